@@ -1,0 +1,18 @@
+"""CPU oracle for the DDA hot path — TEST INFRASTRUCTURE, not part of the product.
+
+Plain, slow, double-precision numpy code written from the paper (Yurkin, Maltsev &
+Hoekstra, "The discrete dipole approximation for simulation of light scattering by
+particles much larger than the wavelength", 2007) and from the literature it cites
+for formulas it uses but does not print.  Only the tests, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the GPU library never
+does, and this package imports nothing from the GPU library.
+
+Modules
+  dda  — lattice, polarizability, Green's tensor, interaction matrix (dense and direct
+         sum), incident field, QMR and Bi-CGSTAB, cross sections, far field, Mueller.
+  mie  — Mie theory for a homogeneous sphere (the exact reference the paper compares to).
+
+Parity status of each function is stated in its docstring ("pinned by ..." or
+"parity unpinned").
+"""
+from . import dda, mie  # noqa: F401

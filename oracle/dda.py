@@ -1,0 +1,499 @@
+"""DDA oracle: plain fp64 numpy implementation of what the GPU hot path computes.
+
+TEST INFRASTRUCTURE ONLY.  Used by tests, the smoke check and the benchmark's CPU
+baseline; never by the product path.
+
+Conventions (the paper fixes none of these beyond eqs. 1-3; each is a stated reading):
+  * Gaussian units, time dependence exp(-i w t), dipole size d = 1, so k stands for kd
+    and cross sections come out in units of d^2; incident amplitude |E0| = 1.
+  * Dipoles sit at the centres of the non-void cells of a grid centred on the origin;
+    the dipole order is the linear cell index x + nx*(y + ny*z) restricted to the mask.
+  * A per-dipole vector is an (N, 3) complex array here (the GPU uses [3][N]).
+
+Section/equation references are to the paper unless a literature source is named.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Lattice-dispersion-relation coefficients (Draine & Goodman 1993, the paper's ref. [13];
+# the paper names LDR as the polarizability used in all its runs, Sec. 3.1, but does not
+# print them).  parity unpinned against the paper itself.
+LDR_B1 = -1.8915316
+LDR_B2 = 0.1648469
+LDR_B3 = -1.7700004
+
+
+# ----------------------------------------------------------------------------- lattice
+def dipoles(mask):
+    """Positions (N, 3) and linear grid indices (N,) of the non-void cells of `mask`.
+
+    `mask` has shape (nz, ny, nx), x fastest.  The paper keeps only non-void dipoles in all
+    work except the FFT (Sec. 2); the order here is the grid's linear order.
+    pinned by: tests compare counts and positions with brute-force loops on tiny grids.
+    """
+    mask = np.asarray(mask)
+    nz, ny, nx = mask.shape
+    lin = np.flatnonzero(mask.reshape(-1))
+    ix = lin % nx
+    iy = (lin // nx) % ny
+    iz = lin // (nx * ny)
+    pos = np.stack([ix + 0.5 - nx / 2.0, iy + 0.5 - ny / 2.0, iz + 0.5 - nz / 2.0], axis=1)
+    return pos.astype(np.float64), lin.astype(np.int64)
+
+
+# ---------------------------------------------------------------------- polarizability
+def alpha_cm(m):
+    """Clausius-Mossotti polarizability of a unit cube: (3/4pi)(m^2-1)/(m^2+2).
+
+    pinned by: alpha = 0 at m = 1; the k -> 0 limit of the LDR polarizability.
+    """
+    m2 = complex(m) ** 2
+    return 3.0 / (4.0 * math.pi) * (m2 - 1.0) / (m2 + 2.0)
+
+
+def ldr_s(prop, pol):
+    """S = sum_mu (a_mu |e_mu|)^2 for unit propagation a and unit polarization e.
+
+    Reading: for a complex (e.g. circular) polarization the squared modulus of each
+    component is used; for linear polarization this is the usual sum (a_mu e_mu)^2.
+    """
+    a = np.asarray(prop, dtype=np.float64)
+    e = np.asarray(pol, dtype=np.complex128)
+    return float(np.sum(a * a * np.abs(e) ** 2))
+
+
+def alpha_ldr(m, k, prop, pol):
+    """LDR polarizability (Draine & Goodman 1993; the paper uses it for every run, Sec. 3.1).
+
+    1/alpha = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 S) k^2 - (2/3) i k^3.
+    pinned by: the CM limit as k -> 0; Im(1/alpha) = -(2/3) k^3 for real m (radiative
+    reaction), which the optical-theorem test checks through the cross sections.
+    The three b coefficients: parity unpinned (not printed in the paper).
+    """
+    m2 = complex(m) ** 2
+    S = ldr_s(prop, pol)
+    inv = 1.0 / alpha_cm(m) + (LDR_B1 + m2 * LDR_B2 + m2 * LDR_B3 * S) * k * k - (2.0 / 3.0) * 1j * k ** 3
+    return 1.0 / inv
+
+
+def beta_of_alpha(alpha):
+    """beta with beta*beta = alpha (Sec. 2, text before eq. 2); principal square root."""
+    return np.sqrt(complex(alpha))
+
+
+# ---------------------------------------------------------------------- Green's tensor
+def green(r, k):
+    """Free-space Green's tensor G(r) of eq. (1): the field at r of a unit dipole at 0.
+
+    G(r) = exp(ikr)/r^3 [k^2 r^2 (I - rr) - (1 - ikr)(I - 3 rr)],  rr = r^ r^ (outer product).
+    `r` has shape (..., 3) and must be non-zero; returns (..., 3, 3) complex.
+    pinned by: G = (k^2 I + grad grad) exp(ikr)/r checked by finite differences; G = G^T.
+    """
+    r = np.asarray(r, dtype=np.float64)
+    rn = np.sqrt(np.sum(r * r, axis=-1))
+    rh = r / rn[..., None]
+    rr = rh[..., :, None] * rh[..., None, :]
+    eye = np.eye(3)
+    kr = np.asarray(k * rn)
+    pref = np.exp(1j * kr) / rn ** 3
+    t1 = (kr * kr)[..., None, None] * (eye - rr)
+    t2 = (1.0 - 1j * kr)[..., None, None] * (eye - 3.0 * rr)
+    return pref[..., None, None] * (t1 - t2)
+
+
+# ------------------------------------------------------------------ interaction matrix
+def interaction_matrix(pos, k, beta):
+    """Dense A of eq. (2): A_ii = I, A_ij = -beta_i G_ij beta_j, as a (3N, 3N) matrix.
+
+    Row/column index 3*i + mu (dipole i, component mu).  `beta` is a scalar or (N,).
+    pinned by: A = A^T exactly; the direct sum below; numpy-FFT convolution on the lattice.
+    """
+    N = pos.shape[0]
+    b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
+    A = np.zeros((N, 3, N, 3), dtype=np.complex128)
+    for i in range(N):
+        d = pos[i][None, :] - pos
+        d[i] = 1.0  # placeholder, overwritten below
+        G = green(d, k)
+        G[i] = 0.0
+        A[i, :, :, :] = -(b[i] * b)[None, :, None] * G.transpose(1, 0, 2)
+        A[i, :, i, :] = np.eye(3)
+    return A.reshape(3 * N, 3 * N)
+
+
+def matvec_rows(pos, k, beta, x, rows):
+    """Eq. (3) left-hand side at the dipoles `rows`: y_i = x_i - beta_i sum_{j!=i} G_ij beta_j x_j.
+
+    Direct O(N) sum per row (matrix-free).  x is (N, 3); returns (len(rows), 3).
+    pinned by: dense assembly (same rows), numpy-FFT convolution on the lattice.
+    """
+    N = pos.shape[0]
+    b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
+    bx = b[:, None] * x
+    out = np.empty((len(rows), 3), dtype=np.complex128)
+    for t, i in enumerate(rows):
+        d = pos[i][None, :] - pos
+        d[i] = 1.0
+        G = green(d, k)
+        G[i] = 0.0
+        s = np.einsum("jab,jb->a", G, bx)
+        out[t] = x[i] - b[i] * s
+    return out
+
+
+def matvec(pos, k, beta, x, chunk=256):
+    """Full direct-sum matvec of eq. (3), processed in row chunks (O(N^2) work)."""
+    N = pos.shape[0]
+    b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
+    bx = b[:, None] * x
+    y = np.empty_like(x, dtype=np.complex128)
+    for s in range(0, N, chunk):
+        rows = np.arange(s, min(N, s + chunk))
+        ar = np.arange(len(rows))
+        d = pos[rows][:, None, :] - pos[None, :, :]
+        d[ar, rows] = 1.0          # self pair excluded (j != i in eq. 3)
+        G = green(d, k)
+        G[ar, rows] = 0.0
+        y[rows] = x[rows] - b[rows, None] * np.einsum("ijab,jb->ia", G, bx)
+    return y
+
+
+# ------------------------------------------------------------------- incident field
+def incident_field(pos, k, prop, pol):
+    """Plane wave E_inc(r) = e exp(i k a.r) at the dipoles (right-hand side of eq. 1)."""
+    a = np.asarray(prop, dtype=np.float64)
+    e = np.asarray(pol, dtype=np.complex128)
+    ph = np.exp(1j * k * (pos @ a))
+    return ph[:, None] * e[None, :]
+
+
+def rhs(pos, k, beta, prop, pol):
+    """Right-hand side of eq. (3): b_i = beta_i E_inc,i."""
+    N = pos.shape[0]
+    b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
+    return b[:, None] * incident_field(pos, k, prop, pol)
+
+
+# ---------------------------------------------------------------------------- solvers
+def _flat(v):
+    return v.reshape(-1)
+
+
+def qmr(apply_A, b, tol, maxit=100000, x0=None, breakdown_eps=1e-12):
+    """Complex-symmetric QMR without look-ahead (Freund 1992, the paper's ref. [16]).
+
+    The paper (Sec. 2) uses QMR and Bi-CG in the form that exploits A = A^T, so one matrix
+    product per iteration suffices.  This is the quasi-minimal-residual iteration built on the
+    complex-symmetric Lanczos process: Lanczos vectors v scaled to unit Euclidean norm, the
+    bilinear form u^T w (no conjugation) in place of an inner product, and the left Lanczos
+    vectors equal to the right ones.  Stops when the recursive residual ||r|| / ||b|| < tol
+    (the paper's stopping criterion, relative residual norm).
+
+    apply_A maps an (N, 3) array to an (N, 3) array.  Returns (x, info) with info keys
+    iters, matvecs, status ('converged' | 'maxit' | 'breakdown'), res_hist (relative recursive
+    residual after each iteration, starting with the initial one), res_rec (recursive relative residual at exit).
+    pinned by: dense LU on small systems; iterates equal the Lanczos least-squares minimizer.
+    """
+    shape = b.shape
+    bn = np.linalg.norm(_flat(b))
+    x = np.zeros(shape, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    nmv = 0
+    if x0 is None:
+        r = b.astype(np.complex128).copy()
+    else:
+        r = b - apply_A(x)
+        nmv += 1
+    hist = [np.linalg.norm(_flat(r)) / bn]
+    info = {"iters": 0, "matvecs": nmv, "status": "maxit", "res_hist": hist}
+    if hist[-1] < tol:
+        info["status"] = "converged"
+        info["res_rec"] = hist[-1]
+        return x, info
+
+    vt = r.copy()                      # unnormalized Lanczos vector
+    rho = np.linalg.norm(_flat(vt))    # its Euclidean norm
+    gamma_prev, theta_prev, eta = 1.0, 0.0, -1.0
+    eps_prev = None
+    p = d = s = None
+    for it in range(1, maxit + 1):
+        v = vt / rho
+        delta = np.dot(_flat(v), _flat(v))          # bilinear v^T v
+        if abs(delta) < breakdown_eps:
+            info["status"] = "breakdown"
+            break
+        if it == 1:
+            p = v.copy()
+        else:
+            p = v - (rho * delta / eps_prev) * p
+        pt = apply_A(p)
+        nmv += 1
+        eps = np.dot(_flat(p), _flat(pt))           # bilinear p^T A p
+        if eps == 0 or not np.isfinite(eps):
+            info["status"] = "breakdown"
+            break
+        beta = eps / delta
+        vt = pt - beta * v
+        rho_new = np.linalg.norm(_flat(vt))
+        theta = rho_new / (gamma_prev * abs(beta))
+        gamma = 1.0 / math.sqrt(1.0 + theta * theta)
+        eta = -eta * rho * gamma * gamma / (beta * gamma_prev * gamma_prev)
+        c = (theta_prev * gamma) ** 2
+        if it == 1:
+            d = eta * p
+            s = eta * pt
+        else:
+            d = eta * p + c * d
+            s = eta * pt + c * s
+        x = x + d
+        r = r - s
+        rho, gamma_prev, theta_prev, eps_prev = rho_new, gamma, theta, eps
+        res = np.linalg.norm(_flat(r)) / bn
+        hist.append(res)
+        info["iters"] = it
+        if res < tol:
+            info["status"] = "converged"
+            break
+        if rho == 0.0:
+            info["status"] = "breakdown"
+            break
+    info["matvecs"] = nmv
+    info["res_rec"] = hist[-1]
+    return x, info
+
+
+def bicgstab(apply_A, b, tol, maxit=100000, x0=None):
+    """Bi-CGSTAB (van der Vorst 1992; one of the paper's four solvers, Sec. 2).
+
+    Hermitian inner products, shadow residual equal to the initial residual; two matrix
+    products per iteration.  Same stopping rule as `qmr`.
+    pinned by: dense LU on small systems; agreement with `qmr` on the solution.
+    """
+    bn = np.linalg.norm(_flat(b))
+    x = np.zeros(b.shape, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    nmv = 0
+    if x0 is None:
+        r = b.astype(np.complex128).copy()
+    else:
+        r = b - apply_A(x)
+        nmv += 1
+    hist = [np.linalg.norm(_flat(r)) / bn]
+    info = {"iters": 0, "matvecs": nmv, "status": "maxit", "res_hist": hist}
+    if hist[-1] < tol:
+        info["status"] = "converged"
+        info["res_rec"] = hist[-1]
+        return x, info
+    rs = r.copy()
+    rho_old = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(r)
+    p = np.zeros_like(r)
+    for it in range(1, maxit + 1):
+        rho = np.vdot(_flat(rs), _flat(r))
+        if rho == 0:
+            info["status"] = "breakdown"
+            break
+        beta = (rho / rho_old) * (alpha / omega)
+        rho_old = rho
+        p = r + beta * (p - omega * v)
+        v = apply_A(p)
+        nmv += 1
+        alpha = rho / np.vdot(_flat(rs), _flat(v))
+        s = r - alpha * v
+        sn = np.linalg.norm(_flat(s)) / bn
+        info["iters"] = it
+        if sn < tol:
+            x = x + alpha * p
+            hist.append(sn)
+            info["status"] = "converged"
+            break
+        t = apply_A(s)
+        nmv += 1
+        omega = np.vdot(_flat(t), _flat(s)) / np.vdot(_flat(t), _flat(t))
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        res = np.linalg.norm(_flat(r)) / bn
+        hist.append(res)
+        if res < tol:
+            info["status"] = "converged"
+            break
+        if omega == 0:
+            info["status"] = "breakdown"
+            break
+    info["matvecs"] = nmv
+    info["res_rec"] = hist[-1]
+    return x, info
+
+
+def solve_dense(pos, k, beta, b):
+    """Exact solution of eq. (3) by dense LU (numpy.linalg.solve); for small systems only."""
+    A = interaction_matrix(pos, k, beta)
+    return np.linalg.solve(A, _flat(b)).reshape(b.shape)
+
+
+# --------------------------------------------------------------------- cross sections
+def cross_sections(pos, k, alpha, P, prop, pol):
+    """Extinction and absorption cross sections from the dipole polarizations P (Draine 1988).
+
+    Cext = 4 pi k sum_i Im(E_inc,i^* . P_i)
+    Cabs = 4 pi k sum_i [ -Im(1/alpha_i) - (2/3) k^3 ] |P_i|^2
+    Units of d^2.  The paper reports Qext (Sec. 3.1) but does not print these formulas.
+    pinned by: optical theorem Cext = Csca(exact) + Cabs; forward-scattering theorem;
+    Cabs = 0 for real m under LDR; agreement with Mie theory.
+    """
+    E = incident_field(pos, k, prop, pol)
+    cext = 4.0 * math.pi * k * float(np.sum(np.imag(np.conj(E) * P)))
+    inv = 1.0 / np.broadcast_to(np.asarray(alpha, dtype=np.complex128), (pos.shape[0],))
+    w = -np.imag(inv) - (2.0 / 3.0) * k ** 3
+    cabs = 4.0 * math.pi * k * float(np.sum(w[:, None] * np.abs(P) ** 2))
+    return cext, cabs
+
+
+def csca_exact(pos, k, P):
+    """Scattering cross section by the exact double sum over dipole pairs.
+
+    Csca = k^4 sum_ij P_i^H M(r_i - r_j) P_j, M(r) = integral over the unit sphere of
+    (I - n n) exp(i k n.r) dOmega = 4 pi [ (2/3 j0 - 1/3 j2)(kr) I + j2(kr) r^ r^ ], M(0) = 8pi/3 I.
+    Independent of the far-field route; used only to check the optical theorem.
+    """
+    N = pos.shape[0]
+    tot = 0.0
+    for s in range(0, N, 512):
+        rows = np.arange(s, min(N, s + 512))
+        d = pos[rows][:, None, :] - pos[None, :, :]
+        rn = np.sqrt(np.sum(d * d, axis=-1))
+        kr = k * rn
+        safe = np.where(kr == 0, 1.0, kr)
+        j0 = np.sin(safe) / safe
+        j1 = np.sin(safe) / safe ** 2 - np.cos(safe) / safe
+        j2 = (3.0 / safe ** 2 - 1.0) * j0 - 3.0 * np.cos(safe) / safe ** 2
+        j0 = np.where(kr == 0, 1.0, j0)
+        j2 = np.where(kr == 0, 0.0, j2)
+        rh = d / np.where(rn == 0, 1.0, rn)[..., None]
+        c_iso = 4.0 * math.pi * ((2.0 / 3.0) * j0 - (1.0 / 3.0) * j2)
+        c_rr = 4.0 * math.pi * j2
+        Pj = P[None, :, :]
+        iso = np.einsum("ij,ija->ia", c_iso, np.broadcast_to(Pj, d.shape))
+        rr = np.einsum("ij,ija,ijb,jb->ia", c_rr, rh, rh, P)
+        tot += float(np.real(np.sum(np.conj(P[rows]) * (iso + rr))))
+        del j1
+    return k ** 4 * tot
+
+
+# ------------------------------------------------------------------ far field, Mueller
+def farfield(pos, k, P, n):
+    """Scattering amplitude vector F(n) = -i k^3 (I - n n) sum_j P_j exp(-i k n.r_j).
+
+    The scattered far field is exp(ikr)/(-ikr) F (Bohren & Huffman convention).  `n` is an
+    (M, 3) array of unit directions; returns (M, 3).
+    pinned by: forward-scattering theorem Cext = (4 pi / k^2) Re(e^* . F(a)); a single dipole
+    reproduces Rayleigh scattering in closed form.
+    """
+    n = np.asarray(n, dtype=np.float64)
+    ph = np.exp(-1j * k * (n @ pos.T))      # (M, N)
+    s = ph @ P                              # (M, 3)
+    s = s - n * np.sum(n * s, axis=1)[:, None]
+    return -1j * k ** 3 * s
+
+
+def beam_frame(prop, pol):
+    """(e1, e2, e3): e3 = propagation, e1 = (real) polarization, e2 = e3 x e1."""
+    e3 = np.asarray(prop, dtype=np.float64)
+    e1 = np.real(np.asarray(pol, dtype=np.complex128))
+    e2 = np.cross(e3, e1)
+    return e1, e2, e3
+
+
+def scattering_directions(prop, pol, theta, phi):
+    """Directions and unit vectors theta^, phi^ in the scattering plane at azimuth phi."""
+    e1, e2, e3 = beam_frame(prop, pol)
+    th = np.asarray(theta, dtype=np.float64)
+    st, ct = np.sin(th), np.cos(th)
+    sp, cp = math.sin(phi), math.cos(phi)
+    n = np.outer(st * cp, e1) + np.outer(st * sp, e2) + np.outer(ct, e3)
+    t_hat = np.outer(ct * cp, e1) + np.outer(ct * sp, e2) - np.outer(st, e3)
+    p_hat = np.broadcast_to(-sp * e1 + cp * e2, n.shape)
+    return n, t_hat, p_hat
+
+
+def amplitude_matrix(F1, F2, t_hat, p_hat, phi):
+    """S1..S4 (Bohren & Huffman) from far fields F1, F2 of incident polarizations e1, e2.
+
+    Incident parallel/perpendicular to the scattering plane: e_par = cos(phi) e1 + sin(phi) e2,
+    e_perp = sin(phi) e1 - cos(phi) e2; by linearity F_par, F_perp follow from F1, F2.
+    S2 = theta^.F_par, S4 = -phi^.F_par, S3 = theta^.F_perp, S1 = -phi^.F_perp.
+    """
+    cp, sp = math.cos(phi), math.sin(phi)
+    Fpar = cp * F1 + sp * F2
+    Fperp = sp * F1 - cp * F2
+    S2 = np.sum(t_hat * Fpar, axis=1)
+    S4 = -np.sum(p_hat * Fpar, axis=1)
+    S3 = np.sum(t_hat * Fperp, axis=1)
+    S1 = -np.sum(p_hat * Fperp, axis=1)
+    return S1, S2, S3, S4
+
+
+def mueller_from_amplitudes(S1, S2, S3, S4):
+    """4x4 Mueller matrix from the amplitude matrix (Bohren & Huffman 1983, eq. 3.16).
+
+    Returns (M, 4, 4), unnormalized (S11 = (|S1|^2+|S2|^2+|S3|^2+|S4|^2)/2).
+    pinned by: Rayleigh single-dipole closed form; S12 = S21 = -S11 sin^2/(1+cos^2) there.
+    """
+    a1, a2, a3, a4 = (np.abs(S) ** 2 for S in (S1, S2, S3, S4))
+    M = np.empty(S1.shape + (4, 4))
+    M[..., 0, 0] = 0.5 * (a2 + a1 + a4 + a3)
+    M[..., 0, 1] = 0.5 * (a2 - a1 + a4 - a3)
+    M[..., 0, 2] = np.real(S2 * np.conj(S3) + S1 * np.conj(S4))
+    M[..., 0, 3] = np.imag(S2 * np.conj(S3) - S1 * np.conj(S4))
+    M[..., 1, 0] = 0.5 * (a2 - a1 - a4 + a3)
+    M[..., 1, 1] = 0.5 * (a2 + a1 - a4 - a3)
+    M[..., 1, 2] = np.real(S2 * np.conj(S3) - S1 * np.conj(S4))
+    M[..., 1, 3] = np.imag(S2 * np.conj(S3) + S1 * np.conj(S4))
+    M[..., 2, 0] = np.real(S2 * np.conj(S4) + S1 * np.conj(S3))
+    M[..., 2, 1] = np.real(S2 * np.conj(S4) - S1 * np.conj(S3))
+    M[..., 2, 2] = np.real(S1 * np.conj(S2) + S3 * np.conj(S4))
+    M[..., 2, 3] = np.imag(S2 * np.conj(S1) + S4 * np.conj(S3))
+    M[..., 3, 0] = np.imag(S4 * np.conj(S2) + S1 * np.conj(S3))
+    M[..., 3, 1] = np.imag(S4 * np.conj(S2) - S1 * np.conj(S3))
+    M[..., 3, 2] = np.imag(S1 * np.conj(S2) - S3 * np.conj(S4))
+    M[..., 3, 3] = np.real(S1 * np.conj(S2) - S3 * np.conj(S4))
+    return M
+
+
+def rotation_about(axis, angle):
+    """Rotation matrix by `angle` about the unit vector `axis` (Rodrigues)."""
+    a = np.asarray(axis, dtype=np.float64)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(angle) * K + (1 - math.cos(angle)) * (K @ K)
+
+
+def mueller(pos, k, prop, pol, P1, P2, theta, phi):
+    """Mueller matrix in the scattering plane at azimuth phi, from the polarizations P1 (incident
+    polarization e1) and P2 (incident polarization e2 = prop x e1).
+
+    If P2 is None, the particle is assumed invariant under a 90-degree rotation about the
+    propagation direction (the paper uses the sphere's symmetry to run one polarization only,
+    Sec. 3.1): then F2(n) = R F1(R^-1 n) with R the +90-degree rotation taking e1 to e2.
+    Returns (len(theta), 4, 4).
+    """
+    n, t_hat, p_hat = scattering_directions(prop, pol, theta, phi)
+    F1 = farfield(pos, k, P1, n)
+    if P2 is not None:
+        F2 = farfield(pos, k, P2, n)
+    else:
+        R = rotation_about(np.asarray(prop, dtype=np.float64), math.pi / 2)
+        F2 = farfield(pos, k, P1, n @ R) @ R.T   # rows: R F1(R^T n)
+    S1, S2, S3, S4 = amplitude_matrix(F1, F2, t_hat, p_hat, phi)
+    return mueller_from_amplitudes(S1, S2, S3, S4)
+
+
+def efficiency(C, n_dipoles):
+    """Q = C / (pi a_eq^2), a_eq = (3N/4pi)^(1/3) d (volume-equivalent radius, Sec. 3.1)."""
+    a_eq = (3.0 * n_dipoles / (4.0 * math.pi)) ** (1.0 / 3.0)
+    return C / (math.pi * a_eq * a_eq)
+
+
+def size_parameter(k, n_dipoles):
+    """Volume-equivalent size parameter x = k a_eq."""
+    return k * (3.0 * n_dipoles / (4.0 * math.pi)) ** (1.0 / 3.0)

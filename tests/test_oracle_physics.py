@@ -1,0 +1,190 @@
+"""Pins of the CPU oracle's building blocks against closed forms, brute force and invariants.
+
+None of these re-type the oracle's formula: each checks it against something the
+mathematics or the physics fixes independently (finite differences, textbook static
+limits, loops over the grid, library FFT convolution, exact symmetries).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dda
+from paper_0704_0037_amd import inputs
+
+
+# ------------------------------------------------------------------------- lattice
+def test_dipoles_match_bruteforce_loops():
+    rng = np.random.default_rng(1)
+    mask = (rng.random((5, 4, 3)) < 0.6).astype(np.uint8)   # (nz, ny, nx)
+    pos, lin = dda.dipoles(mask)
+    exp_pos, exp_lin = [], []
+    for z in range(5):
+        for y in range(4):
+            for x in range(3):
+                if mask[z, y, x]:
+                    exp_lin.append(x + 3 * (y + 4 * z))
+                    exp_pos.append((x + 0.5 - 1.5, y + 0.5 - 2.0, z + 0.5 - 2.5))
+    assert list(lin) == exp_lin
+    np.testing.assert_array_equal(pos, np.array(exp_pos))
+
+
+def test_sphere_counts_bruteforce():
+    # count cells with centre inside the sphere by an explicit loop
+    n = 16
+    cnt = 0
+    for z, y, x in itertools.product(range(n), repeat=3):
+        r2 = (x + 0.5 - n / 2) ** 2 + (y + 0.5 - n / 2) ** 2 + (z + 0.5 - n / 2) ** 2
+        cnt += r2 <= (n / 2) ** 2
+    assert cnt == int(inputs.sphere_mask(n).sum()) == 2176
+
+
+# ------------------------------------------------------------------ Green's tensor
+def _scalar_green(r, k):
+    rn = np.linalg.norm(r)
+    return np.exp(1j * k * rn) / rn
+
+
+def test_green_equals_k2_plus_gradgrad_of_scalar_green():
+    """G = (k^2 I + grad grad) exp(ikr)/r, with the Hessian by 4th-order finite differences."""
+    h = 1e-3
+    for k in (0.3, 1.1):
+        for r in ([1.0, 0.0, 0.0], [0.7, -1.3, 2.1], [3.0, 2.0, -1.0]):
+            r = np.array(r)
+            H = np.zeros((3, 3), dtype=np.complex128)
+            for a in range(3):
+                for b in range(3):
+                    ea, eb = np.eye(3)[a] * h, np.eye(3)[b] * h
+                    if a == b:
+                        f = lambda s: _scalar_green(r + s * ea, k)
+                        H[a, b] = (-f(2) + 16 * f(1) - 30 * f(0) + 16 * f(-1) - f(-2)) / (12 * h * h)
+                    else:
+                        acc = 0
+                        for (sa, sb, w) in [(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)]:
+                            acc += w * _scalar_green(r + sa * ea + sb * eb, k)
+                        H[a, b] = acc / (4 * h * h)
+            expect = k * k * np.eye(3) * _scalar_green(r, k) + H
+            G = dda.green(r, k)
+            assert np.abs(G - expect).max() <= 2e-6 * np.abs(G).max()
+
+
+def test_green_static_limit_is_dipole_field():
+    # textbook static dipole field: E = (3 (p.r^) r^ - p) / r^3
+    G = dda.green(np.array([0.0, 0.0, 2.0]), 0.0)
+    np.testing.assert_allclose(G, np.diag([-1.0, -1.0, 2.0]) / 8.0, atol=1e-15)
+
+
+def test_green_symmetric_and_even():
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal((50, 3))
+    G = dda.green(r, 0.7)
+    assert np.array_equal(G, G.transpose(0, 2, 1))
+    np.testing.assert_allclose(dda.green(-r, 0.7), G, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------------- polarizability
+def test_cm_closed_form_limits():
+    assert dda.alpha_cm(1.0) == 0
+    assert abs(dda.alpha_cm(1e8) - 3 / (4 * math.pi)) < 1e-12
+    # dilute limit: alpha ~ (m^2 - 1)/(4 pi) for m -> 1
+    eps = 1e-6
+    assert abs(dda.alpha_cm(1 + eps) / (((1 + eps) ** 2 - 1) / (4 * math.pi)) - 1) < 1e-5
+
+
+def test_ldr_reduces_to_cm_for_small_k():
+    for m in (1.05, 1.5, 2.0 + 0.3j):
+        a = dda.alpha_ldr(m, 1e-6, (0, 0, 1), (1, 0, 0))
+        assert abs(a / dda.alpha_cm(m) - 1) < 1e-10
+
+
+def test_ldr_radiative_reaction_term():
+    for m in (1.05, 1.5, 2.0):
+        for k in (0.1, 0.3, 0.6):
+            for prop, pol in [((0, 0, 1), (1, 0, 0)), ((0.6, 0, 0.8), (0.8, 0, -0.6))]:
+                a = dda.alpha_ldr(m, k, prop, pol)
+                assert abs((1 / a).imag + 2 / 3 * k ** 3) < 1e-12
+
+
+# ------------------------------------------------------------------ interaction matrix
+def _small_particle(seed=3, shape=(5, 4, 6), fill=0.7):
+    rng = np.random.default_rng(seed)
+    return (rng.random(shape) < fill).astype(np.uint8)
+
+
+def test_interaction_matrix_complex_symmetric():
+    pos, _ = dda.dipoles(_small_particle())
+    A = dda.interaction_matrix(pos, 0.9, np.sqrt(0.05 + 0.01j))
+    assert np.array_equal(A, A.T)
+    assert not np.allclose(A, A.conj().T)
+
+
+def test_direct_sum_equals_dense():
+    pos, _ = dda.dipoles(_small_particle())
+    beta = np.sqrt(0.1 + 0.02j)
+    x = inputs.random_vector(len(pos), 5).T.copy()
+    A = dda.interaction_matrix(pos, 0.5, beta)
+    y_dense = (A @ x.reshape(-1)).reshape(x.shape)
+    y_direct = dda.matvec(pos, 0.5, beta, x, chunk=7)
+    np.testing.assert_allclose(y_direct, y_dense, rtol=0, atol=1e-13 * np.abs(y_dense).max())
+    rows = [0, 3, len(pos) - 1]
+    np.testing.assert_allclose(dda.matvec_rows(pos, 0.5, beta, x, rows), y_dense[rows],
+                               rtol=0, atol=1e-13 * np.abs(y_dense).max())
+
+
+def _fft_convolution_matvec(mask, k, beta, x):
+    """The lattice convolution done with numpy's FFT on a zero-padded circulant grid."""
+    nz, ny, nx = mask.shape
+    L = (2 * nx, 2 * ny, 2 * nz)
+    idx = [np.arange(Lz) for Lz in L]
+    disp = [np.where(i < n, i, i - Ls) for i, n, Ls in zip(idx, (nx, ny, nz), L)]
+    DZ, DY, DX = np.meshgrid(disp[2], disp[1], disp[0], indexing="ij")
+    r = np.stack([DX, DY, DZ], axis=-1).astype(float)
+    zero = (DX == 0) & (DY == 0) & (DZ == 0)
+    r[zero] = 1.0
+    G = dda.green(r, k)
+    G[zero] = 0.0
+    grid = np.zeros((3, L[2], L[1], L[0]), dtype=np.complex128)
+    sel = mask.astype(bool)
+    for c in range(3):
+        g = np.zeros((nz, ny, nx), dtype=np.complex128)
+        g[sel] = beta * x[:, c]
+        grid[c, :nz, :ny, :nx] = g
+    X = np.fft.fftn(grid, axes=(1, 2, 3))
+    Gh = np.fft.fftn(G, axes=(0, 1, 2))
+    Y = np.einsum("zyxab,bzyx->azyx", Gh, X)
+    conv = np.fft.ifftn(Y, axes=(1, 2, 3))[:, :nz, :ny, :nx]
+    return x - beta * np.stack([conv[c][sel] for c in range(3)], axis=1)
+
+
+def test_direct_sum_equals_library_fft_convolution():
+    mask = _small_particle(seed=4, shape=(6, 5, 7))
+    pos, _ = dda.dipoles(mask)
+    beta = np.sqrt(dda.alpha_ldr(1.4 + 0.05j, 0.6, (0, 0, 1), (1, 0, 0)))
+    x = inputs.random_vector(len(pos), 6).T.copy()
+    y = dda.matvec(pos, 0.6, beta, x)
+    y_fft = _fft_convolution_matvec(mask, 0.6, beta, x)
+    assert np.linalg.norm(y - y_fft) / np.linalg.norm(y) < 1e-13
+
+
+def test_ghat_parity_of_components():
+    """Fourier transform of each G component is even/odd along each axis (octant storage)."""
+    n = 4
+    L = 2 * n
+    d = np.where(np.arange(L) < n, np.arange(L), np.arange(L) - L)
+    DZ, DY, DX = np.meshgrid(d, d, d, indexing="ij")
+    r = np.stack([DX, DY, DZ], axis=-1).astype(float)
+    r[L // 2, :, :] = 7.0  # never-used middle planes: any value, 0 used below
+    zero = (DX == 0) & (DY == 0) & (DZ == 0)
+    r[zero] = 1.0
+    G = dda.green(r, 0.8)
+    G[zero] = 0
+    G[n, :, :] = G[:, n, :] = G[:, :, n] = 0
+    Gh = np.fft.fftn(G, axes=(0, 1, 2))
+    flip = lambda a, ax: np.roll(np.flip(a, axis=ax), 1, axis=ax)
+    for a in range(3):
+        for b in range(3):
+            for axis, comp in ((2, 0), (1, 1), (0, 2)):
+                odd = (a == comp) != (b == comp)
+                sgn = -1.0 if odd else 1.0
+                np.testing.assert_allclose(flip(Gh[..., a, b], axis), sgn * Gh[..., a, b], atol=1e-10)

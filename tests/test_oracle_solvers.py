@@ -1,0 +1,108 @@
+"""Pins of the oracle's iterative solvers: dense LU, the Lanczos least-squares characterization
+of QMR, agreement of the two solvers, and the failure modes (breakdown, maxit)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dda
+from paper_0704_0037_amd import inputs
+
+
+def _system(n=6, m=1.5, k=0.5, prop=(0, 0, 1), pol=(1, 0, 0)):
+    mask = inputs.sphere_mask(n)
+    pos, _ = dda.dipoles(mask)
+    alpha = dda.alpha_ldr(m, k, prop, pol)
+    beta = dda.beta_of_alpha(alpha)
+    A = dda.interaction_matrix(pos, k, beta)
+    b = dda.rhs(pos, k, beta, prop, pol)
+    mv = lambda x: (A @ x.reshape(-1)).reshape(x.shape)
+    return pos, alpha, beta, A, b, mv
+
+
+@pytest.mark.parametrize("m", [1.5, 1.33 + 0.1j, 2.0])
+def test_qmr_reaches_lu_solution(m):
+    pos, alpha, beta, A, b, mv = _system(m=m)
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    x, info = dda.qmr(mv, b, 1e-11)
+    assert info["status"] == "converged"
+    true_res = np.linalg.norm(mv(x) - b) / np.linalg.norm(b)
+    assert true_res < 1e-10
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-8
+
+
+@pytest.mark.parametrize("m", [1.5, 1.33 + 0.1j])
+def test_bicgstab_reaches_lu_solution(m):
+    pos, alpha, beta, A, b, mv = _system(m=m)
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    x, info = dda.bicgstab(mv, b, 1e-11)
+    assert info["status"] == "converged"
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-8
+    assert info["matvecs"] <= 2 * info["iters"]
+
+
+def _lanczos_complex_symmetric(A, r0, m):
+    """Complex-symmetric Lanczos with the bilinear form, vectors scaled to unit 2-norm.
+
+    Returns V (n, m+1) and the (m+1, m) Hessenberg H with A V[:, :m] = V H."""
+    n = r0.size
+    V = np.zeros((n, m + 1), dtype=np.complex128)
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    V[:, 0] = r0 / np.linalg.norm(r0)
+    for j in range(m):
+        w = A @ V[:, j]
+        for i in range(max(0, j - 1), j + 1):
+            h = (V[:, i] @ w) / (V[:, i] @ V[:, i])
+            H[i, j] = h
+            w = w - h * V[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V[:, j + 1] = w / H[j + 1, j]
+    return V, H
+
+
+@pytest.mark.parametrize("steps", [1, 2, 5, 9, 12])
+def test_qmr_iterate_is_lanczos_least_squares_minimizer(steps):
+    pos, alpha, beta, A, b, mv = _system(n=6, m=1.6, k=0.6)
+    V, H = _lanczos_complex_symmetric(A, b.reshape(-1), steps)
+    rhs = np.zeros(steps + 1, dtype=np.complex128)
+    rhs[0] = np.linalg.norm(b)
+    z = np.linalg.lstsq(H, rhs, rcond=None)[0]
+    x_ref = V[:, :steps] @ z
+    x, info = dda.qmr(mv, b, 1e-30, maxit=steps)
+    assert info["iters"] == steps
+    assert np.linalg.norm(x.reshape(-1) - x_ref) / np.linalg.norm(x_ref) < 1e-10
+
+
+def test_qmr_true_residual_tracks_recursive():
+    pos, alpha, beta, A, b, mv = _system(n=8, m=1.5, k=0.45)
+    for tol in (1e-5, 1e-8):
+        x, info = dda.qmr(mv, b, tol)
+        true_res = np.linalg.norm(mv(x) - b) / np.linalg.norm(b)
+        assert info["res_rec"] < tol
+        assert true_res < 2 * tol
+
+
+def test_qmr_and_bicgstab_agree():
+    pos, alpha, beta, A, b, mv = _system(n=8, m=1.33 + 0.05j, k=0.5)
+    x1, _ = dda.qmr(mv, b, 1e-10)
+    x2, _ = dda.bicgstab(mv, b, 1e-10)
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) < 1e-8
+
+
+def test_circular_polarization_is_a_breakdown_not_a_nan():
+    # e = (1, i, 0)/sqrt(2) gives b^T b = 0: the bilinear Lanczos breaks down at step 1
+    pol = (1 / math.sqrt(2), 1j / math.sqrt(2), 0)
+    pos, alpha, beta, A, b, mv = _system(pol=pol)
+    x, info = dda.qmr(mv, b, 1e-8)
+    assert info["status"] == "breakdown"
+    assert info["iters"] == 0
+    assert np.all(np.isfinite(x))
+
+
+def test_maxit_and_zero_iterations():
+    pos, alpha, beta, A, b, mv = _system()
+    x, info = dda.qmr(mv, b, 1e-12, maxit=3)
+    assert info["status"] == "maxit" and info["iters"] == 3 and info["matvecs"] == 3
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    x, info = dda.qmr(mv, b, 1e-8, x0=x_lu)
+    assert info["status"] == "converged" and info["iters"] == 0 and info["matvecs"] == 1
