@@ -1,0 +1,209 @@
+/*
+ * dda.h — C-ABI of the MI355X (gfx950) discrete-dipole-approximation hot path.
+ *
+ * The library solves the DDA system of the paper (Yurkin, Maltsev & Hoekstra 2007,
+ * Sec. 2, eqs. 1-3) for a particle given as a mask on a cubic dipole grid:
+ *
+ *     x_i - sum_{j != i} beta_i G_ij beta_j x_j = beta_i E_inc,i ,   P_i = beta_i x_i   (eq. 3)
+ *
+ * with beta_i^2 = alpha_i the dipole polarizability (LDR by default, Sec. 3.1) and G_ij the
+ * free-space Green's tensor.  The interaction-matrix product is applied with zero-padded 3-D
+ * FFTs split into 1-D transforms that skip the zero input and the unused output, the Fourier
+ * transform of the interaction matrix stored symmetry-reduced (Sec. 2), and every operation
+ * other than the FFT touching only the non-void dipoles (Sec. 2).  The iterative solvers are
+ * the complex-symmetric QMR (one product per iteration, Sec. 2) and Bi-CGSTAB (Sec. 2), stopped
+ * at relative residual norm < tol (default 1e-5, Sec. 2).
+ *
+ * Units: dipole size d = 1, so kd is the wavenumber; cross sections are in units of d^2.
+ * Time dependence exp(-i w t).  Incident amplitude |E0| = 1.
+ *
+ * Layouts
+ *   mask      host uint8  [nz][ny][nx], x fastest, nonzero = material.  The dipole order is the
+ *             linear cell index x + nx*(y + ny*z) restricted to the mask; dipole i sits at
+ *             (x + 1/2 - nx/2, y + 1/2 - ny/2, z + 1/2 - nz/2).
+ *   vectors   device, component-major: complex128 (interleaved re, im doubles) [3][N], or
+ *             [n_rhs][3][N] for batches; complex64 for the *_f32 entry points.
+ *
+ * Ownership: the context owns every device buffer it allocates and frees them in dda_free.
+ * Caller vectors are never freed or retained.  Calls on one context are ordered on the
+ * context's stream (the one given to dda_setup, or the default stream) and are not
+ * thread-safe; separate contexts are independent.
+ *
+ * Errors: every entry point returns a dda_status; nothing throws or aborts across the ABI.
+ * dda_last_error() returns a message describing the most recent failure on the calling thread.
+ */
+#ifndef DDA_MI355X_H
+#define DDA_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dda_ctx dda_ctx;
+
+typedef enum {
+    DDA_OK = 0,
+    DDA_EINVAL = -1,       /* bad argument (null pointer, empty mask, size out of range, ...) */
+    DDA_ENOMEM = -2,       /* device allocation failed */
+    DDA_EHIP = -3,         /* a HIP runtime call failed */
+    DDA_ENOTCONV = -4,     /* maxit reached before tol; x_out holds the last iterate */
+    DDA_EBREAKDOWN = -5,   /* Krylov breakdown (e.g. b^T b = 0 for QMR); x_out holds the last iterate */
+    DDA_ESYMMETRY = -6,    /* one-polarization read-out asked for a particle without 90-degree symmetry */
+    DDA_ENOTSUP = -7       /* option not supported by this build */
+} dda_status;
+
+/* Polarizability prescriptions (Sec. 2 lists four; LDR is the one used in Sec. 3). */
+enum { DDA_POL_LDR = 0, DDA_POL_CM = 1 };
+
+/* Iterative solvers (Sec. 2). */
+enum { DDA_QMR = 0, DDA_BICGSTAB = 1 };
+
+/* Arithmetic of the solve: plain double precision everywhere (Sec. 2: all floats double), or
+ * single-precision FFTs, tensor multiply and inner QMR with double-precision residuals, iterate
+ * updates and read-out (iterative refinement). */
+enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1 };
+
+/* Incident plane wave in the particle frame: unit propagation vector and complex unit
+ * polarization (E_inc(r) = pol * exp(i kd prop.r)). */
+typedef struct {
+    double prop[3];
+    double pol_re[3];
+    double pol_im[3];
+} dda_beam;
+
+/* Optional settings of dda_setup (pass NULL for defaults). */
+typedef struct {
+    int32_t pad[3];        /* padded FFT sizes per axis; 0 = smallest supported size >= 2n-1 */
+    int32_t lines_per_block; /* FFT lines per workgroup; 0 = built-in choice */
+    int32_t fp32;          /* nonzero: also build the single-precision tensor for DDA_FP32_REFINE */
+} dda_setup_opts;
+
+/* Options of dda_solve (pass NULL for defaults). */
+typedef struct {
+    int32_t solver;        /* DDA_QMR (default) or DDA_BICGSTAB */
+    int32_t precision;     /* DDA_FP64 (default) or DDA_FP32_REFINE */
+    int32_t maxit;         /* iteration limit; 0 = 100000 */
+    int32_t check_every;   /* iterations between host-side convergence checks; 0 = automatic */
+    double inner_tol;      /* DDA_FP32_REFINE: relative tolerance of each inner solve; 0 = 1e-2 */
+    const void *x0;        /* device initial guess, same layout as x_out; NULL = zero */
+} dda_solve_opts;
+
+/* Per-right-hand-side report of dda_solve. */
+typedef struct {
+    int32_t status;        /* dda_status of this right-hand side */
+    int32_t iters;         /* solver iterations (summed over inner solves for DDA_FP32_REFINE) */
+    int32_t matvecs;       /* interaction-matrix products */
+    int32_t outer;         /* refinement steps (DDA_FP32_REFINE), else 0 */
+    double res_rec;        /* relative recursive residual at exit */
+    double res_true;       /* relative true residual ||b - A x|| / ||b|| computed once at exit */
+    double t_solve_s;      /* wall time of the solve of the whole batch, seconds */
+    double *res_hist;      /* optional host buffer for the relative residual per iteration */
+    int32_t res_hist_cap;  /* its capacity in doubles (0 = none) */
+    int32_t res_hist_len;  /* entries written (initial residual first) */
+} dda_solve_info;
+
+/*
+ * dda_setup — build a context for one particle (Sec. 2: grid of dipoles, non-void list,
+ * polarizability, Fourier transform of the interaction matrix).
+ *   out    receives the context (set to NULL on failure)
+ *   grid   {nx, ny, nz}, each 1..2048
+ *   mask   host uint8 [nz][ny][nx]; at least one nonzero cell
+ *   m      {Re m, Im m}, refractive index of the (homogeneous) material
+ *   kd     wavenumber times dipole size, > 0
+ *   polarizability  DDA_POL_LDR or DDA_POL_CM
+ *   opts   NULL or settings above
+ *   stream hipStream_t the context runs on (NULL = default stream)
+ * Errors: DDA_EINVAL for bad arguments or an unsupported padded size, DDA_ENOMEM, DDA_EHIP.
+ */
+dda_status dda_setup(dda_ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2],
+                     double kd, int32_t polarizability, const dda_setup_opts *opts, void *stream);
+
+/* Release the context and all device memory it owns.  NULL is accepted. */
+dda_status dda_free(dda_ctx *ctx);
+
+/* Number of non-void dipoles N (or -1 for a NULL context). */
+int64_t dda_num_dipoles(const dda_ctx *ctx);
+
+/* Padded FFT grid {Lx, Ly, Lz} chosen at setup. */
+dda_status dda_padded_grid(const dda_ctx *ctx, int32_t out[3]);
+
+/* Polarizability alpha (host {re, im}) the context uses for this beam (LDR depends on the
+ * beam through S = sum_mu (a_mu |e_mu|)^2; Sec. 3.1 names LDR). */
+dda_status dda_polarizability(const dda_ctx *ctx, const dda_beam *beam, double out[2]);
+
+/* Right-hand side of eq. 3, b = beta E_inc, written to device complex128 [3][N]. */
+dda_status dda_rhs(dda_ctx *ctx, const dda_beam *beam, void *b);
+
+/*
+ * dda_matvec — y = A x with A of eq. 2 for the polarizability this beam selects (eq. 3 left side).
+ *   x, y   device complex128 [3][N]; must not overlap
+ * Errors: DDA_EINVAL (null pointers), DDA_EHIP.
+ */
+dda_status dda_matvec(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y);
+
+/* dda_matvec_f32 — the same product in single precision (complex64 [3][N]); needs the context
+ * built with opts.fp32 != 0, else DDA_ENOTSUP. */
+dda_status dda_matvec_f32(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y);
+
+/*
+ * dda_matvec_batch — y_r = A_r x_r for n_rhs vectors sharing the particle: one pass over the
+ * Fourier-space tensor per batch.  beams[n_rhs]; x, y device complex128 [n_rhs][3][N].
+ */
+dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, const void *x, void *y);
+
+/*
+ * dda_solve — solve eq. 3 for n_rhs incident beams (Sec. 2 solvers, stopping rule
+ * ||r|| / ||b|| < tol on the recursive residual, Sec. 2).
+ *   beams   host [n_rhs]
+ *   tol     relative residual threshold (> 0)
+ *   opts    NULL or options
+ *   x_out   device complex128 [n_rhs][3][N]; receives x (P = beta x)
+ *   info    host [n_rhs] or NULL
+ * Returns DDA_OK if every right-hand side converged, else the first failing status
+ * (DDA_ENOTCONV / DDA_EBREAKDOWN); per-RHS statuses are in info.
+ */
+dda_status dda_solve(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, double tol,
+                     const dda_solve_opts *opts, void *x_out, dda_solve_info *info);
+
+/*
+ * dda_cross_sections — out = {Cext, Cabs, Csca = Cext - Cabs} in units of d^2 (Sec. 3.1 reports
+ * extinction efficiencies; formulas of Draine 1988) from the solution x of beam (device
+ * complex128 [3][N]).
+ */
+dda_status dda_cross_sections(dda_ctx *ctx, const dda_beam *beam, const void *x, double out[3]);
+
+/*
+ * dda_farfield — scattering amplitude vectors F(n) = -i k^3 (I - n n) sum_j P_j exp(-i k n.r_j)
+ * (far field = exp(ikr)/(-ikr) F) at n_dir unit directions.
+ *   dirs   host double [n_dir][3];  F  host complex128 [n_dir][3] (interleaved re, im)
+ */
+dda_status dda_farfield(dda_ctx *ctx, const dda_beam *beam, const void *x, int32_t n_dir,
+                        const double *dirs, double *F);
+
+/*
+ * dda_mueller — 4x4 Mueller matrix (Bohren & Huffman eq. 3.16, unnormalized) at n_theta
+ * scattering angles in the scattering plane at azimuth phi (Sec. 3.1: all elements in one
+ * scattering plane).  The beam frame is e3 = beam->prop, e1 = Re(beam->pol), e2 = e3 x e1;
+ * n = sin(theta)(cos(phi) e1 + sin(phi) e2) + cos(theta) e3.
+ *   x1     solution for polarization e1 (device complex128 [3][N])
+ *   x2     solution for polarization e2, or NULL: then the particle must be invariant under the
+ *          90-degree rotation about e3 (checked on the mask; DDA_ESYMMETRY otherwise) and the
+ *          second polarization follows from the first (Sec. 3.1: one polarization suffices)
+ *   theta  host [n_theta] radians;  M  host double [n_theta][4][4] row-major
+ */
+dda_status dda_mueller(dda_ctx *ctx, const dda_beam *beam, const void *x1, const void *x2,
+                       double phi, const double *theta, int32_t n_theta, double *M);
+
+/* Human-readable name of a status code. */
+const char *dda_strerror(dda_status status);
+
+/* Message of the most recent failure on the calling thread ("" if none). */
+const char *dda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDA_MI355X_H */

@@ -124,22 +124,28 @@ def interaction_matrix(pos, k, beta):
     return A.reshape(3 * N, 3 * N)
 
 
-def matvec_rows(pos, k, beta, x, rows):
+def matvec_rows(pos, k, beta, x, rows, chunk=1 << 18):
     """Eq. (3) left-hand side at the dipoles `rows`: y_i = x_i - beta_i sum_{j!=i} G_ij beta_j x_j.
 
-    Direct O(N) sum per row (matrix-free).  x is (N, 3); returns (len(rows), 3).
+    Direct O(N) sum per row (matrix-free), accumulated over `chunk` dipoles at a time so that
+    large particles fit in memory.  x is (N, 3); returns (len(rows), 3).
     pinned by: dense assembly (same rows), numpy-FFT convolution on the lattice.
     """
     N = pos.shape[0]
     b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
-    bx = b[:, None] * x
     out = np.empty((len(rows), 3), dtype=np.complex128)
     for t, i in enumerate(rows):
-        d = pos[i][None, :] - pos
-        d[i] = 1.0
-        G = green(d, k)
-        G[i] = 0.0
-        s = np.einsum("jab,jb->a", G, bx)
+        s = np.zeros(3, dtype=np.complex128)
+        for j0 in range(0, N, chunk):
+            j1 = min(N, j0 + chunk)
+            d = pos[i][None, :] - pos[j0:j1]
+            self_j = i - j0 if j0 <= i < j1 else None
+            if self_j is not None:
+                d[self_j] = 1.0
+            G = green(d, k)
+            if self_j is not None:
+                G[self_j] = 0.0
+            s += np.einsum("jab,jb->a", G, b[j0:j1, None] * x[j0:j1])
         out[t] = x[i] - b[i] * s
     return out
 

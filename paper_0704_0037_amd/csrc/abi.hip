@@ -1,0 +1,174 @@
+// The C-ABI entry points (include/dda.h) that set up contexts, build right-hand sides and apply
+// the interaction matrix.  The solver and the read-out entry points live in solver.hip and
+// readout.hip.
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace dda {
+dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2], double kd, int32_t pol,
+                 const dda_setup_opts *opts, void *stream);
+void destroy(Ctx *c);
+const char *last_error();
+
+// b[c][i] = beta e_c exp(i k a.r_i) for each right-hand side (beta = principal sqrt(alpha))
+template <typename R>
+__global__ void k_rhs(const int *__restrict__ lin, cplx<R> *__restrict__ b, int N, int nx, int ny, int nz, double k,
+                      double a0, double a1, double a2, double e0r, double e0i, double e1r, double e1i, double e2r,
+                      double e2i, double br, double bi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int l = lin[i];
+    const double x = (l % nx) + 0.5 - 0.5 * nx;
+    const double y = ((l / nx) % ny) + 0.5 - 0.5 * ny;
+    const double z = (l / (nx * ny)) + 0.5 - 0.5 * nz;
+    double sn, cs;
+    sincos(k * (a0 * x + a1 * y + a2 * z), &sn, &cs);
+    const double pr = br * cs - bi * sn, pi = br * sn + bi * cs;  // beta * exp(i phase)
+    b[i] = mk<cplx<R>>((R)(pr * e0r - pi * e0i), (R)(pr * e0i + pi * e0r));
+    b[(size_t)N + i] = mk<cplx<R>>((R)(pr * e1r - pi * e1i), (R)(pr * e1i + pi * e1r));
+    b[2 * (size_t)N + i] = mk<cplx<R>>((R)(pr * e2r - pi * e2i), (R)(pr * e2i + pi * e2r));
+}
+
+void beta_of(const Ctx &c, const dda_beam &bm, double &br, double &bi) {
+    double ar, ai;
+    polarizability(c, bm, ar, ai);
+    // principal square root
+    const double mod = std::hypot(ar, ai);
+    br = std::sqrt(0.5 * (mod + ar));
+    bi = std::copysign(std::sqrt(0.5 * (mod - ar)), ai);
+}
+
+template <typename R> dda_status rhs_launch(Ctx &c, const dda_beam &bm, cplx<R> *b, hipStream_t s) {
+    double br, bi;
+    beta_of(c, bm, br, bi);
+    const int N = (int)c.N;
+    hipLaunchKernelGGL(k_rhs<R>, dim3((N + 255) / 256), dim3(256), 0, s, c.lin, b, N, c.nx, c.ny, c.nz, c.kd,
+                       bm.prop[0], bm.prop[1], bm.prop[2], bm.pol_re[0], bm.pol_im[0], bm.pol_re[1], bm.pol_im[1],
+                       bm.pol_re[2], bm.pol_im[2], br, bi);
+    DDA_HIP_CHECK(hipGetLastError());
+    return DDA_OK;
+}
+template dda_status rhs_launch<double>(Ctx &, const dda_beam &, double2 *, hipStream_t);
+template dda_status rhs_launch<float>(Ctx &, const dda_beam &, float2 *, hipStream_t);
+
+bool beam_ok(const dda_beam *b) {
+    if (!b) return false;
+    double a2 = 0, e2 = 0;
+    for (int i = 0; i < 3; ++i) {
+        if (!std::isfinite(b->prop[i]) || !std::isfinite(b->pol_re[i]) || !std::isfinite(b->pol_im[i])) return false;
+        a2 += b->prop[i] * b->prop[i];
+        e2 += b->pol_re[i] * b->pol_re[i] + b->pol_im[i] * b->pol_im[i];
+    }
+    return std::fabs(a2 - 1) < 1e-6 && std::fabs(e2 - 1) < 1e-6;
+}
+
+}  // namespace dda
+
+using namespace dda;
+
+extern "C" {
+
+dda_status dda_setup(dda_ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2], double kd,
+                     int32_t polarizability, const dda_setup_opts *opts, void *stream) {
+    Ctx *c = nullptr;
+    dda_status st = setup(&c, grid, mask, m, kd, polarizability, opts, stream);
+    if (out) *out = reinterpret_cast<dda_ctx *>(c);
+    return st;
+}
+
+dda_status dda_free(dda_ctx *ctx) {
+    destroy(cx(ctx));
+    return DDA_OK;
+}
+
+int64_t dda_num_dipoles(const dda_ctx *ctx) { return ctx ? cx(ctx)->N : -1; }
+
+dda_status dda_padded_grid(const dda_ctx *ctx, int32_t out[3]) {
+    if (!ctx || !out) {
+        set_error("dda_padded_grid: NULL argument");
+        return DDA_EINVAL;
+    }
+    out[0] = cx(ctx)->Lx;
+    out[1] = cx(ctx)->Ly;
+    out[2] = cx(ctx)->Lz;
+    return DDA_OK;
+}
+
+dda_status dda_polarizability(const dda_ctx *ctx, const dda_beam *beam, double out[2]) {
+    if (!ctx || !out || !beam_ok(beam)) {
+        set_error("dda_polarizability: NULL context/output or beam without unit vectors");
+        return DDA_EINVAL;
+    }
+    polarizability(*cx(ctx), *beam, out[0], out[1]);
+    return DDA_OK;
+}
+
+dda_status dda_rhs(dda_ctx *ctx, const dda_beam *beam, void *b) {
+    if (!ctx || !b || !beam_ok(beam)) {
+        set_error("dda_rhs: NULL argument or beam without unit vectors");
+        return DDA_EINVAL;
+    }
+    return rhs_launch<double>(*cx(ctx), *beam, (double2 *)b, cx(ctx)->stream);
+}
+
+static dda_status matvec_common(dda_ctx *h, const dda_beam *beams, int32_t n, const void *x, void *y, bool f32) {
+    Ctx *ctx = cx(h);
+    if (!ctx || !beams || !x || !y || n < 1) {
+        set_error("dda_matvec: NULL argument or n_rhs < 1");
+        return DDA_EINVAL;
+    }
+    if (x == y) {
+        set_error("dda_matvec: x and y must not overlap");
+        return DDA_EINVAL;
+    }
+    std::vector<double> ar(n), ai(n);
+    for (int r = 0; r < n; ++r) {
+        if (!beam_ok(&beams[r])) {
+            set_error("dda_matvec: beam without unit vectors");
+            return DDA_EINVAL;
+        }
+        polarizability(*ctx, beams[r], ar[r], ai[r]);
+    }
+    if (f32) {
+        if (!ctx->ghat32) {
+            set_error("dda_matvec_f32: context built without opts.fp32");
+            return DDA_ENOTSUP;
+        }
+        return matvec_launch<float>(*ctx, (const float2 *)x, (float2 *)y, n, ar.data(), ai.data(), false,
+                                    ctx->stream);
+    }
+    return matvec_launch<double>(*ctx, (const double2 *)x, (double2 *)y, n, ar.data(), ai.data(), false, ctx->stream);
+}
+
+dda_status dda_matvec(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y) {
+    return matvec_common(ctx, beam, 1, x, y, false);
+}
+
+dda_status dda_matvec_f32(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y) {
+    return matvec_common(ctx, beam, 1, x, y, true);
+}
+
+dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, const void *x, void *y) {
+    return matvec_common(ctx, beams, n_rhs, x, y, false);
+}
+
+const char *dda_strerror(dda_status s) {
+    switch (s) {
+        case DDA_OK: return "ok";
+        case DDA_EINVAL: return "invalid argument";
+        case DDA_ENOMEM: return "out of device memory";
+        case DDA_EHIP: return "HIP runtime error";
+        case DDA_ENOTCONV: return "not converged";
+        case DDA_EBREAKDOWN: return "Krylov breakdown";
+        case DDA_ESYMMETRY: return "particle lacks the symmetry the read-out needs";
+        case DDA_ENOTSUP: return "not supported";
+    }
+    return "unknown status";
+}
+
+const char *dda_last_error(void) { return last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal state of one DDA context (one particle on one GPU) and the launch helpers shared by
+// the matvec, solver and read-out translation units.
+#pragma once
+
+#include <numeric>
+#include <vector>
+
+#include "../../include/dda.h"
+#include "fft.hpp"
+
+namespace dda {
+
+// Work buffers of one precision, sized for `nrhs` right-hand sides.
+template <typename R> struct Work {
+    int nrhs = 0;
+    cplx<R> *B1 = nullptr;   // [3 nrhs][nz][Lx][ny]
+    cplx<R> *B2 = nullptr;   // [Ly][Lx][3 nrhs][nz]
+    cplx<R> *scale = nullptr;  // [nrhs] alpha / (Lx Ly Lz)
+    cplx<R> *dots = nullptr;   // per-block partial sums of the matvec epilogue
+    size_t ndots = 0;
+};
+
+struct Ctx {
+    int nx = 0, ny = 0, nz = 0;
+    int Lx = 0, Ly = 0, Lz = 0;
+    int64_t N = 0;
+    double m_re = 0, m_im = 0, kd = 0;
+    int polarizability = DDA_POL_LDR;
+    hipStream_t stream = nullptr;
+    int nl_x = 0, nl_y = 0, nc_z = 0;  // lines per block (x, y passes) and columns per block (z pass)
+
+    std::vector<uint8_t> mask;      // host copy [nz][ny][nx]
+    std::vector<int32_t> lin_host;  // linear cell index of each dipole
+
+    int *gmap = nullptr;            // device [nz][ny][nx] -> dipole index or -1
+    int *lin = nullptr;             // device [N] linear cell index
+    double2 *ghat = nullptr;        // device octant tensor, fp64
+    float2 *ghat32 = nullptr;       // device octant tensor, fp32 (optional)
+    double2 *tw64 = nullptr;        // twiddle tables, fp64
+    float2 *tw32 = nullptr;         // twiddle tables, fp32
+    FftPlan pxf{}, pxi{}, pyf{}, pyi{}, pzf{}, pzi{};
+
+    Work<double> w64;
+    Work<float> w32;
+
+    // solver scratch
+    double2 *vecs = nullptr;    // Krylov vectors, fp64
+    size_t vecs_elems = 0;
+    float2 *vecs32 = nullptr;
+    size_t vecs32_elems = 0;
+    double *sbuf = nullptr;     // device scalar state + reduction partials
+    size_t sbuf_bytes = 0;
+    double *hbuf = nullptr;     // pinned host mirror for convergence checks
+    size_t hbuf_bytes = 0;
+    double2 *red = nullptr;     // read-out partials
+    size_t red_elems = 0;
+};
+
+// alpha of the context's material for a beam (LDR depends on the beam)
+void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im);
+
+// Matvec on nrhs vectors: y = A x; alphas [nrhs] host complex; optionally leaves per-block
+// bilinear partial sums x.y in w.dots (one block range per right-hand side).
+template <typename R>
+dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const double *alpha_re,
+                         const double *alpha_im, bool want_dots, hipStream_t s);
+
+template <typename R> dda_status ensure_work(Ctx &c, int nrhs);
+
+// number of per-block dot partials the x-inverse kernel writes per right-hand side
+inline size_t dots_per_rhs(const Ctx &c) { return (size_t)3 * c.nz * ((c.ny + c.nl_x - 1) / c.nl_x); }
+
+dda_status device_alloc(void **p, size_t bytes);
+
+// the opaque ABI handle is the context itself
+inline Ctx *cx(dda_ctx *p) { return reinterpret_cast<Ctx *>(p); }
+inline const Ctx *cx(const dda_ctx *p) { return reinterpret_cast<const Ctx *>(p); }
+
+}  // namespace dda

@@ -1,0 +1,252 @@
+// Stockham FFT building blocks for lines held in LDS (gfx950, wave64).
+//
+// A length-L transform is split into passes of radix 2, 3, 4, 5, 8 or 16.  Pass p with radix R
+// and stride Ns (product of the radices before it) does L/R butterflies; butterfly j reads the
+// elements j + r*L/R (r < R), multiplies element r by W^(r*k) with W = exp(-+2 pi i/(Ns*R)) and
+// k = j mod Ns, does an R-point DFT and writes output r to (j - k)*R + k + r*Ns (self-sorting,
+// no bit reversal).  The first pass (Ns = 1) needs no twiddles and reads straight from global
+// memory, so zero padding is a predicated-off load; the last pass writes straight to global
+// memory, so the pruned output of an inverse transform is a predicated-off store.
+//
+// DIR = -1 is the forward transform exp(-2 pi i jk/L), DIR = +1 the unnormalized inverse.
+#pragma once
+
+#include "common.hpp"
+
+namespace dda {
+
+constexpr int kMaxPass = 12;
+#ifndef DDA_MAX_THREADS
+#define DDA_MAX_THREADS 256
+#endif
+
+struct FftPlan {
+    int L;                   // transform length
+    int npass;               // number of passes (1 for L = 1, which uses radix 1)
+    int tpl;                 // threads per line = L / smallest radix
+    int tw_off;              // offset of the table exp(-2 pi i m / L), m < L, in the twiddle buffer
+    int radix[kMaxPass];
+    int ns[kMaxPass];        // product of the radices of the preceding passes
+};
+
+// LDS element index with one element of skew every 8, so radix-8 butterflies writing with a
+// stride of 8 elements do not all land in the same banks.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lds_line_stride(int L) { return L + (L >> 3) + 1; }
+
+// ----------------------------------------------------------------------- small DFTs
+template <int DIR, typename C> __device__ __forceinline__ void dft2(C *a) {
+    C t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft3(C *a) {
+    using R = decltype(C::x);
+    const R s3 = (R)0.86602540378443864676;  // sin(2 pi / 3)
+    C s = cadd(a[1], a[2]);
+    C d = csub(a[1], a[2]);
+    C t = mk<C>(a[0].x - (R)0.5 * s.x, a[0].y - (R)0.5 * s.y);
+    C u = mul_i<DIR>(cscale(d, s3));  // -i s3 (a1 - a2) forward
+    a[0] = cadd(a[0], s);
+    a[1] = cadd(t, u);
+    a[2] = csub(t, u);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C *a) {
+    C t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    C t2 = cadd(a[1], a[3]), t3 = mul_i<DIR>(csub(a[1], a[3]));
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft5(C *a) {
+    using R = decltype(C::x);
+    const R c1 = (R)0.30901699437494742410;   // cos(2 pi/5)
+    const R c2 = (R)-0.80901699437494742410;  // cos(4 pi/5)
+    const R s1 = (R)0.95105651629515357212;   // sin(2 pi/5)
+    const R s2 = (R)0.58778525229247312917;   // sin(4 pi/5)
+    C b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]);
+    C d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+    C t1 = mk<C>(a[0].x + c1 * b1.x + c2 * b2.x, a[0].y + c1 * b1.y + c2 * b2.y);
+    C t2 = mk<C>(a[0].x + c2 * b1.x + c1 * b2.x, a[0].y + c2 * b1.y + c1 * b2.y);
+    C u1 = mul_i<DIR>(mk<C>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+    C u2 = mul_i<DIR>(mk<C>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+    a[0] = cadd(a[0], cadd(b1, b2));
+    a[1] = cadd(t1, u1);
+    a[4] = csub(t1, u1);
+    a[2] = cadd(t2, u2);
+    a[3] = csub(t2, u2);
+}
+
+// multiply by exp(DIR * 2 pi i m / 16) for the few m the radix-16 split needs
+template <int DIR, typename C> __device__ __forceinline__ C rot16(C v, int m) {
+    using R = decltype(C::x);
+    const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173;
+    const R h = (R)0.70710678118654752440;
+    R c, s;  // cos, sin of pi m / 8
+    switch (m) {
+        case 1: c = c1; s = s1; break;
+        case 2: c = h; s = h; break;
+        case 3: c = s1; s = c1; break;
+        case 4: c = 0; s = 1; break;
+        case 6: c = -h; s = h; break;
+        default: c = -c1; s = -s1; break;  // m = 9
+    }
+    // forward: (c - i s), inverse: (c + i s)
+    const R ss = DIR < 0 ? -s : s;
+    return mk<C>(v.x * c - v.y * ss, v.x * ss + v.y * c);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C *a) {
+    using R = decltype(C::x);
+    const R h = (R)0.70710678118654752440;
+    C e[4] = {a[0], a[2], a[4], a[6]};
+    C o[4] = {a[1], a[3], a[5], a[7]};
+    dft4<DIR>(e);
+    dft4<DIR>(o);
+    C o1 = o[1], o3 = o[3];
+    if (DIR < 0) {
+        o[1] = mk<C>((o1.x + o1.y) * h, (o1.y - o1.x) * h);
+        o[3] = mk<C>((o3.y - o3.x) * h, -(o3.x + o3.y) * h);
+    } else {
+        o[1] = mk<C>((o1.x - o1.y) * h, (o1.x + o1.y) * h);
+        o[3] = mk<C>(-(o3.x + o3.y) * h, (o3.x - o3.y) * h);
+    }
+    o[2] = mul_i<DIR>(o[2]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = cadd(e[k], o[k]);
+        a[k + 4] = csub(e[k], o[k]);
+    }
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft16(C *a) {
+    // n = 4 n1 + n2: DFT-4 over n1 (stride 4), twiddle W16^(n2 k1), DFT-4 over n2
+    C b[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        C t[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+        dft4<DIR>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) b[n2][k1] = (n2 * k1 == 0) ? t[k1] : rot16<DIR>(t[k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C t[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+        dft4<DIR>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
+    }
+}
+
+template <int DIR, int RADIX, typename C> __device__ __forceinline__ void dftR(C *a) {
+    if constexpr (RADIX == 2) dft2<DIR>(a);
+    else if constexpr (RADIX == 3) dft3<DIR>(a);
+    else if constexpr (RADIX == 4) dft4<DIR>(a);
+    else if constexpr (RADIX == 5) dft5<DIR>(a);
+    else if constexpr (RADIX == 8) dft8<DIR>(a);
+    else if constexpr (RADIX == 16) dft16<DIR>(a);
+}
+
+// ------------------------------------------------------------- butterfly load / store
+// Load the R inputs of butterfly j through ld(index), twiddle, transform (into a[0..R-1]).
+template <int DIR, int RADIX, typename C, class LD>
+__device__ __forceinline__ void bfly_load(C *a, int j, int L, int Ns, const C *__restrict__ tw, LD ld) {
+    const int q = L / RADIX;
+#pragma unroll
+    for (int r = 0; r < RADIX; ++r) a[r] = ld(j + r * q);
+    if (Ns > 1) {
+        const int k = j % Ns;
+        const int step = q / Ns;  // L / (Ns * RADIX)
+#pragma unroll
+        for (int r = 1; r < RADIX; ++r) {
+            C w = tw[r * k * step];
+            a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
+        }
+    }
+    dftR<DIR, RADIX>(a);
+}
+
+// Twiddle and transform values already in registers (for a pass whose inputs a thread holds).
+template <int DIR, int RADIX, typename C>
+__device__ __forceinline__ void bfly_regs(C *a, int j, int L, int Ns, const C *__restrict__ tw) {
+    if (Ns > 1) {
+        const int k = j % Ns;
+        const int step = L / RADIX / Ns;
+#pragma unroll
+        for (int r = 1; r < RADIX; ++r) {
+            C w = tw[r * k * step];
+            a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
+        }
+    }
+    dftR<DIR, RADIX>(a);
+}
+
+template <int RADIX, typename C, class ST>
+__device__ __forceinline__ void bfly_store(const C *a, int j, int Ns, ST st) {
+    const int k = j % Ns;
+    const int base = (j - k) * RADIX + k;
+#pragma unroll
+    for (int r = 0; r < RADIX; ++r) st(base + r * Ns, a[r]);
+}
+
+// Runtime-radix dispatch.  MAXR bounds the radices a kernel supports (register array size).
+template <int DIR, int MAXR, typename C, class LD>
+__device__ __forceinline__ void load_rt(C *a, int R, int j, int L, int Ns, const C *__restrict__ tw, LD ld) {
+    switch (R) {
+        case 1: a[0] = ld(j); break;
+        case 2: bfly_load<DIR, 2>(a, j, L, Ns, tw, ld); break;
+        case 3: bfly_load<DIR, 3>(a, j, L, Ns, tw, ld); break;
+        case 4: bfly_load<DIR, 4>(a, j, L, Ns, tw, ld); break;
+        case 5: bfly_load<DIR, 5>(a, j, L, Ns, tw, ld); break;
+        case 8: if constexpr (MAXR >= 8) bfly_load<DIR, 8>(a, j, L, Ns, tw, ld); break;
+        default: if constexpr (MAXR >= 16) bfly_load<DIR, 16>(a, j, L, Ns, tw, ld); break;
+    }
+}
+
+template <int DIR, int MAXR, typename C>
+__device__ __forceinline__ void regs_rt(C *a, int R, int j, int L, int Ns, const C *__restrict__ tw) {
+    switch (R) {
+        case 1: break;
+        case 2: bfly_regs<DIR, 2>(a, j, L, Ns, tw); break;
+        case 3: bfly_regs<DIR, 3>(a, j, L, Ns, tw); break;
+        case 4: bfly_regs<DIR, 4>(a, j, L, Ns, tw); break;
+        case 5: bfly_regs<DIR, 5>(a, j, L, Ns, tw); break;
+        case 8: if constexpr (MAXR >= 8) bfly_regs<DIR, 8>(a, j, L, Ns, tw); break;
+        default: if constexpr (MAXR >= 16) bfly_regs<DIR, 16>(a, j, L, Ns, tw); break;
+    }
+}
+
+template <int MAXR, typename C, class ST>
+__device__ __forceinline__ void store_rt(const C *a, int R, int j, int Ns, ST st) {
+    switch (R) {
+        case 1: st(j, a[0]); break;
+        case 2: bfly_store<2>(a, j, Ns, st); break;
+        case 3: bfly_store<3>(a, j, Ns, st); break;
+        case 4: bfly_store<4>(a, j, Ns, st); break;
+        case 5: bfly_store<5>(a, j, Ns, st); break;
+        case 8: if constexpr (MAXR >= 8) bfly_store<8>(a, j, Ns, st); break;
+        default: if constexpr (MAXR >= 16) bfly_store<16>(a, j, Ns, st); break;
+    }
+}
+
+// Passes [p0, p1) in place on the LDS line `ln` (stride-skewed).  Every thread of the block
+// must call this (it contains barriers); `active_line` = false threads only take part in them.
+template <int DIR, int MAXR, typename C>
+__device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
+                                           const C *__restrict__ tw) {
+    for (int p = p0; p < p1; ++p) {
+        const int R = pl.radix[p], Ns = pl.ns[p];
+        const bool act = j < pl.L / R;
+        C a[MAXR];
+        if (act) load_rt<DIR, MAXR>(a, R, j, pl.L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
+        __syncthreads();
+        if (act) store_rt<MAXR>(a, R, j, Ns, [&](int i, C v) { ln[pidx(i)] = v; });
+        __syncthreads();
+    }
+}
+
+}  // namespace dda

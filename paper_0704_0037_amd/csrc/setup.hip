@@ -1,0 +1,535 @@
+// Context setup: dipole list, FFT plans and twiddles, the Fourier-transformed interaction tensor
+// (stored for one octant only: every component is even or odd along each axis), work buffers,
+// and the host side of the interaction-matrix product.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+#include "matvec_kernels.hpp"
+
+namespace dda {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error() { return g_last_error.c_str(); }
+
+dda_status device_alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        set_error(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? DDA_ENOMEM : DDA_EHIP;
+    }
+    return DDA_OK;
+}
+
+// ------------------------------------------------------------------------ plans
+static bool five_smooth(int L) {
+    if (L < 1) return false;
+    for (int p : {2, 3, 5})
+        while (L % p == 0) L /= p;
+    return L == 1;
+}
+
+// Radices for length L: 8s first, the leftover power of two as 16 (or 4*4 when maxr = 8), 4 or
+// 2, then 5s and 3s.  Larger radices mean fewer passes over LDS.
+static bool factor(int L, int maxr, std::vector<int> &r) {
+    r.clear();
+    if (L == 1) {
+        r.push_back(1);
+        return true;
+    }
+    int rem = L, p2 = 0, n3 = 0, n5 = 0;
+    while (rem % 2 == 0) rem /= 2, ++p2;
+    while (rem % 5 == 0) rem /= 5, ++n5;
+    while (rem % 3 == 0) rem /= 3, ++n3;
+    if (rem != 1) return false;
+    const int n8 = p2 / 3, left = p2 % 3;
+    for (int i = 0; i < n8; ++i) r.push_back(8);
+    if (left == 1) {
+        if (n8 > 0 && maxr >= 16) r.back() = 16;
+        else if (n8 > 0) { r.back() = 4; r.push_back(4); }
+        else r.push_back(2);
+    } else if (left == 2) {
+        r.push_back(4);
+    }
+    for (int i = 0; i < n5; ++i) r.push_back(5);
+    for (int i = 0; i < n3; ++i) r.push_back(3);
+    return (int)r.size() <= kMaxPass;
+}
+
+static FftPlan make_plan(int L, const std::vector<int> &r, int tw_off) {
+    FftPlan p{};
+    p.L = L;
+    p.npass = (int)r.size();
+    int ns = 1, rmin = 1 << 30;
+    for (int i = 0; i < p.npass; ++i) {
+        p.radix[i] = r[i];
+        p.ns[i] = ns;
+        ns *= r[i];
+        rmin = std::min(rmin, r[i]);
+    }
+    p.tpl = L / rmin;
+    p.tw_off = tw_off;
+    return p;
+}
+
+static int smallest_pad(int n) {
+    int L = std::max(1, 2 * n - 1);
+    while (!five_smooth(L)) ++L;
+    return L;
+}
+
+// lines per block: up to DDA_MAX_THREADS threads, preferably a whole number of waves, LDS <= 64 KiB
+static int pick_lines(int tpl, int line_bytes, int ndim, int want) {
+    const int maxt = DDA_MAX_THREADS;
+    int nl = want > 0 ? want : std::max(1, maxt / tpl);
+    if (want <= 0) {
+        nl = std::min(nl, std::max(ndim, 1));
+        const int g = 64 / std::gcd(tpl, 64);
+        if (g * tpl <= maxt) nl = (nl + g - 1) / g * g;
+    }
+    while (nl > 1 && (nl * tpl > maxt || (size_t)nl * line_bytes > 64 * 1024)) --nl;
+    return nl;
+}
+
+// --------------------------------------------------------------------- kernels
+__device__ __forceinline__ void comp_ab(int comp, int &a, int &b) {
+    const int A[6] = {0, 0, 0, 1, 1, 2}, B[6] = {0, 1, 2, 1, 2, 2};
+    a = A[comp];
+    b = B[comp];
+}
+
+// displacement of circulant index i on an axis of n cells padded to L, or INT_MIN if unused
+__device__ __forceinline__ int disp(int i, int n, int L) {
+    if (i < n) return i;
+    if (i > L - n) return i - L;
+    return -0x40000000;
+}
+
+__global__ void k_gfill(double2 *__restrict__ buf, int comp, int nx, int ny, int nz, int Lx, int Ly, int Lz,
+                        double k) {
+    const size_t total = (size_t)Lx * Ly * Lz;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int ix = (int)(e % Lx);
+    const int iy = (int)((e / Lx) % Ly);
+    const int iz = (int)(e / ((size_t)Lx * Ly));
+    const int dx = disp(ix, nx, Lx), dy = disp(iy, ny, Ly), dz = disp(iz, nz, Lz);
+    double2 out = make_double2(0.0, 0.0);
+    if (dx > -0x40000000 && dy > -0x40000000 && dz > -0x40000000 && (dx | dy | dz) != 0) {
+        // G = exp(ikr)/r^3 [ (k^2 r^2 - 1 + i kr) delta_ab + (3 - k^2 r^2 - 3 i kr) rh_a rh_b ]
+        const double fx = dx, fy = dy, fz = dz;
+        const double r2 = fx * fx + fy * fy + fz * fz;
+        const double r = sqrt(r2);
+        const double kr = k * r;
+        double sn, cs;
+        sincos(kr, &sn, &cs);
+        const double inv_r3 = 1.0 / (r2 * r);
+        int a, b;
+        comp_ab(comp, a, b);
+        const double ra = (a == 0 ? fx : a == 1 ? fy : fz) / r;
+        const double rb = (b == 0 ? fx : b == 1 ? fy : fz) / r;
+        const double rr = ra * rb;
+        const double dlt = (a == b) ? 1.0 : 0.0;
+        const double k2r2 = kr * kr;
+        const double qre = (k2r2 - 1.0) * dlt + (3.0 - k2r2) * rr;
+        const double qim = kr * dlt - 3.0 * kr * rr;
+        out.x = inv_r3 * (cs * qre - sn * qim);
+        out.y = inv_r3 * (sn * qre + cs * qim);
+    }
+    buf[e] = out;
+}
+
+__global__ void __launch_bounds__(DDA_MAX_THREADS) k_fft_axis(double2 *__restrict__ buf, int nu, int nv, long su, long sv,
+                                                   long sp, FftPlan pl, const double2 *__restrict__ twall,
+                                                   int NL, int lanes_over_lines) {
+    using C = double2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const C *tw = twall + pl.tw_off;
+    const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
+    const int utiles = (nu + NL - 1) / NL;
+    const int u0 = (blockIdx.x % utiles) * NL;
+    const int v = blockIdx.x / utiles;
+    const int t = threadIdx.x;
+    const int gline = lanes_over_lines ? t % NL : t / TPL;
+    const int gj = lanes_over_lines ? t / NL : t % TPL;
+    const bool ok = u0 + gline < nu;
+    C *base = buf + (size_t)(ok ? u0 + gline : 0) * su + (size_t)v * sv;
+    {
+        const int R0 = pl.radix[0];
+        if (gj < L / R0) {
+            C a[kMaxRadix];
+            load_rt<-1, kMaxRadix>(a, R0, gj, L, 1, tw,
+                                   [&](int i) -> C { return ok ? base[(size_t)i * sp] : czero<C>(); });
+            C *ln = lds + gline * S;
+            store_rt<kMaxRadix>(a, R0, gj, 1, [&](int i, C val) { ln[pidx(i)] = val; });
+        }
+    }
+    __syncthreads();
+    lds_passes<-1, kMaxRadix>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
+    if (pl.npass >= 2) {
+        const int p = pl.npass - 1, Rp = pl.radix[p], Ns = pl.ns[p];
+        if (gj < L / Rp) {
+            C a[kMaxRadix];
+            const C *ln = lds + gline * S;
+            load_rt<-1, kMaxRadix>(a, Rp, gj, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
+            if (ok) store_rt<kMaxRadix>(a, Rp, gj, Ns, [&](int i, C val) { base[(size_t)i * sp] = val; });
+        }
+    } else if (ok) {
+        for (int i = gj; i < L; i += TPL) base[(size_t)i * sp] = lds[gline * S + pidx(i)];
+    }
+}
+
+__global__ void k_gextract(const double2 *__restrict__ buf, double2 *__restrict__ Gh, int comp, int Lx, int Ly,
+                           int Lz) {
+    const int hx = Lx / 2 + 1, hy = Ly / 2 + 1, hz = Lz / 2 + 1;
+    const size_t total = (size_t)hx * hy * hz;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int kz = (int)(e % hz);
+    const int kx = (int)((e / hz) % hx);
+    const int ky = (int)(e / ((size_t)hz * hx));
+    Gh[e * 6 + comp] = buf[((size_t)kz * Ly + ky) * Lx + kx];
+}
+
+__global__ void k_to_f32(const double2 *__restrict__ a, float2 *__restrict__ b, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+// ------------------------------------------------------------------- host side
+void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
+    // Clausius-Mossotti for a unit cube: (3/4pi)(m^2-1)/(m^2+2)
+    const double mr = c.m_re, mi = c.m_im;
+    const double m2r = mr * mr - mi * mi, m2i = 2 * mr * mi;
+    const double nr = m2r - 1, ni = m2i, dr = m2r + 2, di = m2i;
+    const double den = dr * dr + di * di;
+    const double f = 3.0 / (4.0 * M_PI);
+    const double cmr = f * (nr * dr + ni * di) / den, cmi = f * (ni * dr - nr * di) / den;
+    if (c.polarizability == DDA_POL_CM) {
+        re = cmr;
+        im = cmi;
+        return;
+    }
+    // LDR (Draine & Goodman 1993): 1/alpha = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 S) k^2 - (2/3) i k^3
+    const double b1 = -1.8915316, b2 = 0.1648469, b3 = -1.7700004;
+    double S = 0;
+    for (int a = 0; a < 3; ++a) S += b.prop[a] * b.prop[a] * (b.pol_re[a] * b.pol_re[a] + b.pol_im[a] * b.pol_im[a]);
+    const double k = c.kd;
+    const double cm2 = cmr * cmr + cmi * cmi;
+    double ir = cmr / cm2, ii = -cmi / cm2;  // 1/alpha_CM
+    const double tr = b1 + m2r * b2 + m2r * b3 * S, ti = m2i * b2 + m2i * b3 * S;
+    ir += tr * k * k;
+    ii += ti * k * k - (2.0 / 3.0) * k * k * k;
+    const double n2 = ir * ir + ii * ii;
+    re = ir / n2;
+    im = -ii / n2;
+}
+
+template <typename R> static Work<R> &work_of(Ctx &c);
+template <> Work<double> &work_of<double>(Ctx &c) { return c.w64; }
+template <> Work<float> &work_of<float>(Ctx &c) { return c.w32; }
+
+template <typename R> static void free_work(Work<R> &w) {
+    (void)hipFree(w.B1);
+    (void)hipFree(w.B2);
+    (void)hipFree(w.scale);
+    (void)hipFree(w.dots);
+    w = Work<R>{};
+}
+
+template <typename R> dda_status ensure_work(Ctx &c, int nrhs) {
+    Work<R> &w = work_of<R>(c);
+    if (w.nrhs >= nrhs) return DDA_OK;
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    free_work(w);
+    const size_t nc = (size_t)3 * nrhs;
+    dda_status st;
+    if ((st = device_alloc((void **)&w.B1, nc * c.nz * (size_t)c.Lx * c.ny * sizeof(cplx<R>))) != DDA_OK) return st;
+    if ((st = device_alloc((void **)&w.B2, nc * c.nz * (size_t)c.Lx * c.Ly * sizeof(cplx<R>))) != DDA_OK) return st;
+    if ((st = device_alloc((void **)&w.scale, (size_t)nrhs * sizeof(cplx<R>))) != DDA_OK) return st;
+    w.ndots = dots_per_rhs(c) * nrhs;
+    if ((st = device_alloc((void **)&w.dots, w.ndots * sizeof(cplx<R>))) != DDA_OK) return st;
+    w.nrhs = nrhs;
+    return DDA_OK;
+}
+template dda_status ensure_work<double>(Ctx &, int);
+template dda_status ensure_work<float>(Ctx &, int);
+
+template <typename R> static const cplx<R> *tw_of(const Ctx &c);
+template <> const double2 *tw_of<double>(const Ctx &c) { return c.tw64; }
+template <> const float2 *tw_of<float>(const Ctx &c) { return c.tw32; }
+template <typename R> static const cplx<R> *ghat_of(const Ctx &c);
+template <> const double2 *ghat_of<double>(const Ctx &c) { return c.ghat; }
+template <> const float2 *ghat_of<float>(const Ctx &c) { return c.ghat32; }
+
+template <typename R>
+dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
+                         hipStream_t s) {
+    using C = cplx<R>;
+    Work<R> &w = work_of<R>(c);
+    const C *tw = tw_of<R>(c);
+    const C *gh = ghat_of<R>(c);
+    const int ncomp = 3 * nrhs;
+    const int nlx = c.nl_x, nly = c.nl_y, ncz = c.nc_z;
+    const int ytiles = (c.ny + nlx - 1) / nlx, ztiles = (c.nz + nly - 1) / nly;
+    const size_t lx_bytes = (size_t)nlx * lds_line_stride(c.Lx) * sizeof(C);
+    const size_t ly_bytes = (size_t)nly * lds_line_stride(c.Ly) * sizeof(C);
+    const size_t lz_bytes = (size_t)ncz * 3 * lds_line_stride(c.Lz) * sizeof(C);
+    const int N = (int)c.N;
+    hipLaunchKernelGGL(k_fwd_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, x, w.B1,
+                       c.nx, c.ny, c.nz, N, c.pxf, tw, nlx);
+    hipLaunchKernelGGL(k_fwd_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyf.tpl), ly_bytes, s, w.B1, w.B2, c.ny,
+                       c.nz, c.Lx, ncomp, c.pyf, tw, nly);
+    hipLaunchKernelGGL(k_zmul<R>, dim3((c.Lx * c.Ly + ncz - 1) / ncz, nrhs), dim3(ncz * c.pzf.tpl), lz_bytes, s, w.B2,
+                       gh, c.nz, c.Lx, c.Ly, ncomp, c.pzf, c.pzi, tw, ncz);
+    hipLaunchKernelGGL(k_inv_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyi.tpl), ly_bytes, s, w.B2, w.B1, c.ny,
+                       c.nz, c.Lx, ncomp, c.pyi, tw, nly);
+    hipLaunchKernelGGL(k_inv_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, w.B1, x,
+                       y, c.nx, c.ny, c.nz, N, c.pxi, tw, nlx, scale, dots);
+    DDA_HIP_CHECK(hipGetLastError());
+    return DDA_OK;
+}
+template dda_status matvec_device<double>(Ctx &, const double2 *, double2 *, int, const double2 *, double2 *,
+                                          hipStream_t);
+template dda_status matvec_device<float>(Ctx &, const float2 *, float2 *, int, const float2 *, float2 *, hipStream_t);
+
+template <typename R>
+dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const double *are, const double *aim,
+                         bool want_dots, hipStream_t s) {
+    dda_status st = ensure_work<R>(c, nrhs);
+    if (st != DDA_OK) return st;
+    Work<R> &w = work_of<R>(c);
+    std::vector<cplx<R>> sc(nrhs);
+    const double inv = 1.0 / ((double)c.Lx * c.Ly * c.Lz);
+    for (int r = 0; r < nrhs; ++r) sc[r] = mk<cplx<R>>((R)(are[r] * inv), (R)(aim[r] * inv));
+    DDA_HIP_CHECK(hipMemcpyAsync(w.scale, sc.data(), nrhs * sizeof(cplx<R>), hipMemcpyHostToDevice, s));
+    DDA_HIP_CHECK(hipStreamSynchronize(s));  // the host staging vector goes out of scope
+    return matvec_device<R>(c, x, y, nrhs, w.scale, want_dots ? w.dots : nullptr, s);
+}
+template dda_status matvec_launch<double>(Ctx &, const double2 *, double2 *, int, const double *, const double *, bool,
+                                          hipStream_t);
+template dda_status matvec_launch<float>(Ctx &, const float2 *, float2 *, int, const double *, const double *, bool,
+                                         hipStream_t);
+
+void destroy(Ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_work(c->w64);
+    free_work(c->w32);
+    (void)hipFree(c->gmap);
+    (void)hipFree(c->lin);
+    (void)hipFree(c->ghat);
+    (void)hipFree(c->ghat32);
+    (void)hipFree(c->tw64);
+    (void)hipFree(c->tw32);
+    (void)hipFree(c->vecs);
+    (void)hipFree(c->vecs32);
+    (void)hipFree(c->sbuf);
+    (void)hipFree(c->red);
+    if (c->hbuf) (void)hipHostFree(c->hbuf);
+    delete c;
+}
+
+static dda_status build_ghat(Ctx &c) {
+    const size_t full = (size_t)c.Lx * c.Ly * c.Lz;
+    const size_t oct = (size_t)(c.Lx / 2 + 1) * (c.Ly / 2 + 1) * (c.Lz / 2 + 1);
+    dda_status st;
+    if ((st = device_alloc((void **)&c.ghat, oct * 6 * sizeof(double2))) != DDA_OK) return st;
+    double2 *buf = nullptr;
+    if ((st = device_alloc((void **)&buf, full * sizeof(double2))) != DDA_OK) return st;
+    hipStream_t s = c.stream;
+    const int thr = 256;
+    struct Axis { FftPlan pl; int nu, nv; long su, sv, sp; int lol; };
+    const long Lx = c.Lx, Ly = c.Ly;
+    Axis ax[3] = {{c.pxf, c.Ly, c.Lz, Lx, Lx * Ly, 1, 0},
+                  {c.pyf, c.Lx, c.Lz, 1, Lx * Ly, Lx, 1},
+                  {c.pzf, c.Lx, c.Ly, 1, Lx, Lx * Ly, 1}};
+    int nl[3];
+    for (int a = 0; a < 3; ++a)
+        nl[a] = pick_lines(ax[a].pl.tpl, lds_line_stride(ax[a].pl.L) * (int)sizeof(double2), ax[a].nu, 0);
+    for (int comp = 0; comp < 6; ++comp) {
+        hipLaunchKernelGGL(k_gfill, dim3((unsigned)((full + thr - 1) / thr)), dim3(thr), 0, s, buf, comp, c.nx, c.ny,
+                           c.nz, c.Lx, c.Ly, c.Lz, c.kd);
+        for (int a = 0; a < 3; ++a) {
+            const int utiles = (ax[a].nu + nl[a] - 1) / nl[a];
+            const size_t lds = (size_t)nl[a] * lds_line_stride(ax[a].pl.L) * sizeof(double2);
+            hipLaunchKernelGGL(k_fft_axis, dim3(utiles * ax[a].nv), dim3(nl[a] * ax[a].pl.tpl), lds, s, buf, ax[a].nu,
+                               ax[a].nv, ax[a].su, ax[a].sv, ax[a].sp, ax[a].pl, (const double2 *)c.tw64, nl[a],
+                               ax[a].lol);
+        }
+        hipLaunchKernelGGL(k_gextract, dim3((unsigned)((oct + thr - 1) / thr)), dim3(thr), 0, s, buf, c.ghat, comp,
+                           c.Lx, c.Ly, c.Lz);
+    }
+    hipError_t e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        set_error(std::string("tensor build failed: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        return DDA_EHIP;
+    }
+    return DDA_OK;
+}
+
+dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2], double kd, int32_t pol,
+                 const dda_setup_opts *opts, void *stream) {
+    if (!out) {
+        set_error("dda_setup: out is NULL");
+        return DDA_EINVAL;
+    }
+    *out = nullptr;
+    if (!grid || !mask || !m) {
+        set_error("dda_setup: grid, mask and m must be non-NULL");
+        return DDA_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (grid[a] < 1 || grid[a] > 2048) {
+            set_error("dda_setup: grid sizes must be in 1..2048");
+            return DDA_EINVAL;
+        }
+    if (!(kd > 0) || !std::isfinite(kd) || !std::isfinite(m[0]) || !std::isfinite(m[1])) {
+        set_error("dda_setup: kd must be > 0 and m finite");
+        return DDA_EINVAL;
+    }
+    if (pol != DDA_POL_LDR && pol != DDA_POL_CM) {
+        set_error("dda_setup: unknown polarizability");
+        return DDA_EINVAL;
+    }
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) return DDA_ENOMEM;
+    c->nx = grid[0];
+    c->ny = grid[1];
+    c->nz = grid[2];
+    c->m_re = m[0];
+    c->m_im = m[1];
+    c->kd = kd;
+    c->polarizability = pol;
+    c->stream = (hipStream_t)stream;
+    const size_t ncell = (size_t)c->nx * c->ny * c->nz;
+    c->mask.assign(mask, mask + ncell);
+    std::vector<int32_t> gmap(ncell, -1);
+    for (size_t e = 0; e < ncell; ++e)
+        if (mask[e]) {
+            gmap[e] = (int32_t)c->lin_host.size();
+            c->lin_host.push_back((int32_t)e);
+        }
+    c->N = (int64_t)c->lin_host.size();
+    if (c->N == 0) {
+        set_error("dda_setup: the mask has no non-void cell");
+        delete c;
+        return DDA_EINVAL;
+    }
+    if ((uint64_t)c->N * 3 > 0x7fffffffull) {
+        set_error("dda_setup: too many dipoles");
+        delete c;
+        return DDA_EINVAL;
+    }
+    int Ls[3];
+    const int n[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a) {
+        const int want = opts ? opts->pad[a] : 0;
+        if (want > 0) {
+            if (want < 2 * n[a] - 1 || !five_smooth(want) || want > 4096) {
+                set_error("dda_setup: padded size must be >= 2n-1, 5-smooth and <= 4096");
+                delete c;
+                return DDA_EINVAL;
+            }
+            Ls[a] = want;
+        } else {
+            Ls[a] = smallest_pad(n[a]);
+        }
+    }
+    c->Lx = Ls[0];
+    c->Ly = Ls[1];
+    c->Lz = Ls[2];
+    // plans and twiddle tables (one table per distinct length)
+    std::vector<int> lens;
+    for (int a = 0; a < 3; ++a)
+        if (std::find(lens.begin(), lens.end(), Ls[a]) == lens.end()) lens.push_back(Ls[a]);
+    std::vector<int> offs(lens.size());
+    size_t total = 0;
+    for (size_t i = 0; i < lens.size(); ++i) {
+        offs[i] = (int)total;
+        total += lens[i];
+    }
+    auto off_of = [&](int L) { return offs[std::find(lens.begin(), lens.end(), L) - lens.begin()]; };
+    std::vector<int> r;
+    auto plans = [&](int L, int maxr, FftPlan &f, FftPlan &inv) {
+        if (!factor(L, maxr, r)) return false;
+        f = make_plan(L, r, off_of(L));
+        std::vector<int> rr(r.rbegin(), r.rend());
+        inv = make_plan(L, rr, off_of(L));
+        return true;
+    };
+    if (!plans(c->Lx, kMaxRadix, c->pxf, c->pxi) || !plans(c->Ly, kMaxRadix, c->pyf, c->pyi) ||
+        !plans(c->Lz, kMaxRadixZ, c->pzf, c->pzi)) {
+        set_error("dda_setup: unsupported padded size");
+        delete c;
+        return DDA_EINVAL;
+    }
+    std::vector<double2> tw(total);
+    std::vector<float2> tw32(total);
+    for (size_t i = 0; i < lens.size(); ++i)
+        for (int mm = 0; mm < lens[i]; ++mm) {
+            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * mm / lens[i];
+            tw[offs[i] + mm] = make_double2((double)cosl(ang), (double)sinl(ang));
+            tw32[offs[i] + mm] = make_float2((float)cosl(ang), (float)sinl(ang));
+        }
+    const int want_nl = opts ? opts->lines_per_block : 0;
+    c->nl_x = pick_lines(c->pxf.tpl, lds_line_stride(c->Lx) * 16, c->ny, want_nl);
+    c->nl_y = pick_lines(c->pyf.tpl, lds_line_stride(c->Ly) * 16, c->nz, want_nl);
+    c->nc_z = pick_lines(c->pzf.tpl, 3 * lds_line_stride(c->Lz) * 16, 1 << 20, 0);
+    if (c->nc_z * c->pzf.tpl > DDA_MAX_THREADS || c->nl_x * c->pxf.tpl > DDA_MAX_THREADS ||
+        c->nl_y * c->pyf.tpl > DDA_MAX_THREADS) {
+        set_error("dda_setup: padded size too large for one workgroup per line");
+        delete c;
+        return DDA_EINVAL;
+    }
+    dda_status st;
+    if ((st = device_alloc((void **)&c->gmap, ncell * sizeof(int32_t))) != DDA_OK) goto fail;
+    if ((st = device_alloc((void **)&c->lin, c->N * sizeof(int32_t))) != DDA_OK) goto fail;
+    if ((st = device_alloc((void **)&c->tw64, total * sizeof(double2))) != DDA_OK) goto fail;
+    if ((st = device_alloc((void **)&c->tw32, total * sizeof(float2))) != DDA_OK) goto fail;
+    {
+        hipError_t e = hipMemcpy(c->gmap, gmap.data(), ncell * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->lin, c->lin_host.data(), c->N * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->tw64, tw.data(), total * sizeof(double2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), total * sizeof(float2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            set_error(std::string("dda_setup: upload failed: ") + hipGetErrorString(e));
+            st = DDA_EHIP;
+            goto fail;
+        }
+    }
+    if ((st = build_ghat(*c)) != DDA_OK) goto fail;
+    if (opts && opts->fp32) {
+        const size_t n6 = (size_t)(c->Lx / 2 + 1) * (c->Ly / 2 + 1) * (c->Lz / 2 + 1) * 6;
+        if ((st = device_alloc((void **)&c->ghat32, n6 * sizeof(float2))) != DDA_OK) goto fail;
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n6 + 255) / 256)), dim3(256), 0, c->stream, c->ghat, c->ghat32,
+                           n6);
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            set_error(std::string("dda_setup: fp32 tensor: ") + hipGetErrorString(e));
+            st = DDA_EHIP;
+            goto fail;
+        }
+    }
+    *out = c;
+    return DDA_OK;
+fail:
+    destroy(c);
+    return st;
+}
+
+}  // namespace dda

@@ -1,0 +1,269 @@
+"""Python binding of the DDA C-ABI (include/dda.h): argument marshalling only.
+
+Every computation runs in the HIP library libdda_mi355x.so built next to this file.  Vectors are
+torch tensors on the GPU in the library's component-major layout ([3][N], or [n_rhs][3][N]);
+PyTorch supplies device memory and the stream, nothing else.  Importing this module on a
+machine where the library is missing raises immediately: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdda_mi355x.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESYMMETRY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
+POL_LDR, POL_CM = 0, 1
+QMR, BICGSTAB = 0, 1
+FP64, FP32_REFINE = 0, 1
+
+
+class Beam(ct.Structure):
+    _fields_ = [("prop", ct.c_double * 3), ("pol_re", ct.c_double * 3), ("pol_im", ct.c_double * 3)]
+
+
+class SetupOpts(ct.Structure):
+    _fields_ = [("pad", ct.c_int32 * 3), ("lines_per_block", ct.c_int32), ("fp32", ct.c_int32)]
+
+
+class SolveOpts(ct.Structure):
+    _fields_ = [("solver", ct.c_int32), ("precision", ct.c_int32), ("maxit", ct.c_int32),
+                ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p)]
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("iters", ct.c_int32), ("matvecs", ct.c_int32), ("outer", ct.c_int32),
+                ("res_rec", ct.c_double), ("res_true", ct.c_double), ("t_solve_s", ct.c_double),
+                ("res_hist", ct.POINTER(ct.c_double)), ("res_hist_cap", ct.c_int32),
+                ("res_hist_len", ct.c_int32)]
+
+
+class DDAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+# every symbol include/dda.h declares, with its ctypes signature
+_SIGS = {
+    "dda_setup": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.POINTER(ct.c_int32), ct.c_void_p,
+                             ct.POINTER(ct.c_double), ct.c_double, ct.c_int32, ct.POINTER(SetupOpts), ct.c_void_p]),
+    "dda_free": (ct.c_int, [ct.c_void_p]),
+    "dda_num_dipoles": (ct.c_int64, [ct.c_void_p]),
+    "dda_padded_grid": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int32)]),
+    "dda_polarizability": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.POINTER(ct.c_double)]),
+    "dda_rhs": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
+    "dda_matvec": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
+    "dda_matvec_f32": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
+    "dda_matvec_batch": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_void_p, ct.c_void_p]),
+    "dda_solve": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_double, ct.POINTER(SolveOpts),
+                             ct.c_void_p, ct.POINTER(SolveInfo)]),
+    "dda_cross_sections": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.POINTER(ct.c_double)]),
+    "dda_farfield": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double),
+                                ct.POINTER(ct.c_double)]),
+    "dda_mueller": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p, ct.c_double,
+                               ct.POINTER(ct.c_double), ct.c_int32, ct.POINTER(ct.c_double)]),
+    "dda_strerror": (ct.c_char_p, [ct.c_int]),
+    "dda_last_error": (ct.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {_LIB_PATH} (run __graft_entry__.build())")
+        L = ct.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, what):
+    if status != OK:
+        L = lib()
+        msg = L.dda_last_error().decode() or L.dda_strerror(status).decode()
+        raise DDAError(status, f"{what}: {msg}")
+
+
+def make_beam(prop=(0.0, 0.0, 1.0), pol=(1.0, 0.0, 0.0)):
+    b = Beam()
+    pol = [complex(p) for p in pol]
+    for i in range(3):
+        b.prop[i] = float(prop[i])
+        b.pol_re[i] = pol[i].real
+        b.pol_im[i] = pol[i].imag
+    return b
+
+
+def _beam(obj):
+    if isinstance(obj, Beam):
+        return obj
+    if hasattr(obj, "prop") and hasattr(obj, "pol"):
+        return make_beam(obj.prop, obj.pol)
+    prop, pol = obj
+    return make_beam(prop, pol)
+
+
+def _beams(objs):
+    arr = (Beam * len(objs))()
+    for i, o in enumerate(objs):
+        arr[i] = _beam(o)
+    return arr
+
+
+def _ptr(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ct.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One particle on the current GPU (wraps dda_setup / dda_free)."""
+
+    def __init__(self, mask, m, kd, polarizability=POL_LDR, pad=None, fp32=False, lines_per_block=0,
+                 stream=None):
+        L = lib()
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        if mask.ndim != 3:
+            raise ValueError("mask must be a 3-D array [nz][ny][nx]")
+        nz, ny, nx = mask.shape
+        self.grid = (nx, ny, nz)
+        grid = (ct.c_int32 * 3)(nx, ny, nz)
+        mm = (ct.c_double * 2)(complex(m).real, complex(m).imag)
+        opts = SetupOpts()
+        if pad is not None:
+            for i in range(3):
+                opts.pad[i] = int(pad[i])
+        opts.lines_per_block = int(lines_per_block)
+        opts.fp32 = 1 if fp32 else 0
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ct.c_void_p()
+        _check(L.dda_setup(ct.byref(h), grid, mask.ctypes.data_as(ct.c_void_p), mm, float(kd), int(polarizability),
+                           ct.byref(opts), ct.c_void_p(stream.cuda_stream)), "dda_setup")
+        self._h = h
+        self.n = int(L.dda_num_dipoles(h))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dda_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------ queries
+    def padded_grid(self):
+        out = (ct.c_int32 * 3)()
+        _check(lib().dda_padded_grid(self._h, out), "dda_padded_grid")
+        return tuple(out)
+
+    def polarizability(self, beam):
+        out = (ct.c_double * 2)()
+        _check(lib().dda_polarizability(self._h, ct.byref(_beam(beam)), out), "dda_polarizability")
+        return complex(out[0], out[1])
+
+    def vector(self, n_rhs=None, dtype=torch.complex128):
+        shape = (3, self.n) if n_rhs is None else (n_rhs, 3, self.n)
+        return torch.empty(shape, dtype=dtype, device=self.device)
+
+    # ------------------------------------------------------------------ compute
+    def rhs(self, beam):
+        b = self.vector()
+        _check(lib().dda_rhs(self._h, ct.byref(_beam(beam)), ct.c_void_p(b.data_ptr())), "dda_rhs")
+        return b
+
+    def matvec(self, beam, x, y=None):
+        y = self.vector() if y is None else y
+        _check(lib().dda_matvec(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
+                                _ptr(y, torch.complex128, (3, self.n), "y")), "dda_matvec")
+        return y
+
+    def matvec_f32(self, beam, x, y=None):
+        y = self.vector(dtype=torch.complex64) if y is None else y
+        _check(lib().dda_matvec_f32(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex64, (3, self.n), "x"),
+                                    _ptr(y, torch.complex64, (3, self.n), "y")), "dda_matvec_f32")
+        return y
+
+    def matvec_batch(self, beams, x, y=None):
+        n = len(beams)
+        y = self.vector(n) if y is None else y
+        _check(lib().dda_matvec_batch(self._h, _beams(beams), n, _ptr(x, torch.complex128, (n, 3, self.n), "x"),
+                                      _ptr(y, torch.complex128, (n, 3, self.n), "y")), "dda_matvec_batch")
+        return y
+
+    def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
+              x_out=None, history=0, raise_on_fail=True):
+        n = len(beams)
+        x_out = self.vector(n) if x_out is None else x_out
+        opts = SolveOpts(solver, precision, maxit, check_every, inner_tol,
+                         None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value)
+        infos = (SolveInfo * n)()
+        hists = []
+        for i in range(n):
+            if history:
+                h = (ct.c_double * history)()
+                hists.append(h)
+                infos[i].res_hist = ct.cast(h, ct.POINTER(ct.c_double))
+                infos[i].res_hist_cap = history
+        st = lib().dda_solve(self._h, _beams(beams), n, float(tol), ct.byref(opts),
+                             _ptr(x_out, torch.complex128, (n, 3, self.n), "x_out"), infos)
+        out = []
+        for i in range(n):
+            d = {f: getattr(infos[i], f) for f, _ in SolveInfo._fields_ if f != "res_hist"}
+            if history:
+                d["res_hist"] = list(hists[i][: infos[i].res_hist_len])
+            out.append(d)
+        if raise_on_fail and st not in (OK,):
+            _check(st, "dda_solve")
+        return x_out, out, st
+
+    def cross_sections(self, beam, x):
+        out = (ct.c_double * 3)()
+        _check(lib().dda_cross_sections(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
+                                        out), "dda_cross_sections")
+        return tuple(out)
+
+    def farfield(self, beam, x, dirs):
+        dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        F = np.zeros((len(dirs), 3), dtype=np.complex128)
+        _check(lib().dda_farfield(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
+                                  len(dirs), dirs.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                  F.ctypes.data_as(ct.POINTER(ct.c_double))), "dda_farfield")
+        return F
+
+    def mueller(self, beam, x1, x2, phi, theta):
+        theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        M = np.zeros((len(theta), 4, 4), dtype=np.float64)
+        p2 = ct.c_void_p(0) if x2 is None else _ptr(x2, torch.complex128, (3, self.n), "x2")
+        _check(lib().dda_mueller(self._h, ct.byref(_beam(beam)), _ptr(x1, torch.complex128, (3, self.n), "x1"), p2,
+                                 float(phi), theta.ctypes.data_as(ct.POINTER(ct.c_double)), len(theta),
+                                 M.ctypes.data_as(ct.POINTER(ct.c_double))), "dda_mueller")
+        return M
