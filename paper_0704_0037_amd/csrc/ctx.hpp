@@ -34,6 +34,7 @@ struct Ctx {
 
     int *gmap = nullptr;            // device [nz][ny][nx] -> dipole index or -1
     int *lin = nullptr;             // device [N] linear cell index
+    int *line_start = nullptr;      // device [ny*nz + 1] first dipole of each (y, z) line (read-out)
     double2 *ghat = nullptr;        // device octant tensor, fp64
     float2 *ghat32 = nullptr;       // device octant tensor, fp32 (optional)
     double2 *tw64 = nullptr;        // twiddle tables, fp64
@@ -66,6 +67,12 @@ dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const d
                          const double *alpha_im, bool want_dots, hipStream_t s);
 
 template <typename R> dda_status ensure_work(Ctx &c, int nrhs);
+
+// y = A x on device buffers with device scales [nrhs] (alpha / (Lx Ly Lz)); dots (nullable)
+// receives per-block bilinear partial sums x.y; done (nullable) skips converged right-hand sides.
+template <typename R>
+dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
+                         hipStream_t s, const int *done);
 
 // number of per-block dot partials the x-inverse kernel writes per right-hand side
 inline size_t dots_per_rhs(const Ctx &c) { return (size_t)3 * c.nz * ((c.ny + c.nl_x - 1) / c.nl_x); }

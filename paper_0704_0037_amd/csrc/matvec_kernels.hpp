@@ -15,6 +15,8 @@
 //   Ghat octant              [Ly/2+1][Lx/2+1][Lz/2+1][6]  components xx, xy, xz, yy, yz, zz
 #pragma once
 
+#include <type_traits>
+
 #include "fft.hpp"
 
 namespace dda {
@@ -46,7 +48,8 @@ __device__ __forceinline__ void ghat_load(const float2 *g, float2 *G, float sxy,
 template <typename R>
 __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ x,
                                                 cplx<R> *__restrict__ B1, int nx, int ny, int nz, int N,
-                                                FftPlan pl, const cplx<R> *__restrict__ twall, int NL) {
+                                                FftPlan pl, const cplx<R> *__restrict__ twall, int NL,
+                                                const int *__restrict__ done) {
     using C = cplx<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
@@ -58,6 +61,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict
     b /= ytiles;
     const int z = b % nz;
     const int c = b / nz;
+    if (done && done[c / 3]) return;  // this right-hand side has converged
     const int t = threadIdx.x;
     const C *xc = x + (size_t)c * N;
     {   // pass 0 from global, lines along lanes' j (x contiguous)
@@ -104,7 +108,8 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict
 template <typename R>
 __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__restrict__ B1, cplx<R> *__restrict__ B2, int ny,
                                                 int nz, int Lx, int ncomp, FftPlan pl,
-                                                const cplx<R> *__restrict__ twall, int NL) {
+                                                const cplx<R> *__restrict__ twall, int NL,
+                                                const int *__restrict__ done) {
     using C = cplx<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
@@ -116,6 +121,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__rest
     b /= ztiles;
     const int kx = b % Lx;
     const int c = b / Lx;
+    if (done && done[c / 3]) return;
     const int t = threadIdx.x;
     {
         const int line = t / TPL, j = t % TPL, z = z0 + line;
@@ -152,148 +158,124 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__rest
 }
 
 // ------------------------------------------------- K3: forward z, tensor multiply, inverse z
-// Block: NC columns (kx, ky) of one right-hand side; a thread owns butterfly j of all three
-// components of its column, so the last forward pass leaves X(kz) for the three components in
-// the same registers that the first inverse pass (the reversed radix order) consumes.
+// A block takes NC columns (kx, ky); within a column, thread (comp, j) owns butterfly j of the
+// line of one component (one wave per line at L = 512).  After the forward passes the three
+// transformed lines sit in LDS in natural order; each thread then forms component `comp` of
+// Ghat(k) X(k) at the frequencies k = j + r L/R0 that the first inverse pass (radix R0, the
+// forward plan reversed) needs from it, straight into registers.
+//
+// Work is visited in "slots": slot = (4 * octant_column + mirror) * nrhs + rhs, so the (up to)
+// four columns that share one octant column of the tensor, for every right-hand side of a batch,
+// are neighbours; logical blocks are dealt out so that each XCD walks a contiguous range of them
+// (its L2 then serves the repeated tensor reads).
 template <typename R>
-__device__ __forceinline__ void ghat_mul3(cplx<R> (*a)[kMaxRadixZ], int Rr, int j, int q, int Lz,
-                                          const cplx<R> *__restrict__ gcol, R sx, R sy) {
-    using C = cplx<R>;
-    const int hz = Lz / 2;
-#pragma unroll
-    for (int r = 0; r < kMaxRadixZ; ++r) {
-        if (r < Rr) {
-            const int kz = j + r * q;
-            const int kzo = kz <= hz ? kz : Lz - kz;
-            const R sz = kz <= hz ? (R)1 : (R)-1;
-            C G[6];
-            ghat_load(gcol + (size_t)kzo * 6, G, sx * sy, sx * sz, sy * sz);
-            const C X = a[0][r], Y = a[1][r], Z = a[2][r];
-            a[0][r] = cadd(cadd(cmul(G[0], X), cmul(G[1], Y)), cmul(G[2], Z));
-            a[1][r] = cadd(cadd(cmul(G[1], X), cmul(G[3], Y)), cmul(G[4], Z));
-            a[2][r] = cadd(cadd(cmul(G[2], X), cmul(G[4], Y)), cmul(G[5], Z));
-        }
-    }
+__device__ __forceinline__ void slot_column(int slot, int Lx, int Ly, int &kx, int &ky, int &kxo, int &kyo, bool &ok) {
+    const int hx1 = Lx / 2 + 1, hy1 = Ly / 2 + 1;
+    const int m = slot & 3, o = slot >> 2;
+    kxo = o % hx1;
+    kyo = o / hx1;
+    ok = kyo < hy1;
+    const bool mx = m & 1, my = m & 2;
+    if (mx && (kxo == 0 || 2 * kxo == Lx)) ok = false;  // x mirror coincides with the column itself
+    if (my && (kyo == 0 || 2 * kyo == Ly)) ok = false;
+    kx = mx ? Lx - kxo : kxo;
+    ky = my ? Ly - kyo : kyo;
+    if (!ok) kx = ky = kxo = kyo = 0;
 }
 
 template <typename R>
-__global__ void __launch_bounds__(DDA_MAX_THREADS) k_zmul(cplx<R> *__restrict__ B2, const cplx<R> *__restrict__ Gh, int nz,
-                                               int Lx, int Ly, int ncomp, FftPlan pf, FftPlan pi,
-                                               const cplx<R> *__restrict__ twall, int NC) {
+__global__ void __launch_bounds__(256) k_zmul(cplx<R> *__restrict__ B2, const cplx<R> *__restrict__ Gh, int nz,
+                                              int Lx, int Ly, int nrhs, FftPlan pf, FftPlan pi,
+                                              const cplx<R> *__restrict__ twall, int NC, int nblocks,
+                                              const int *__restrict__ done) {
     using C = cplx<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
+    // XCD-aware logical block: consecutive logical blocks on the same XCD
+    const int per_xcd = gridDim.x / 8;
+    const int lb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (lb >= nblocks) return;
     const C *tw = twall + pf.tw_off;
     const int L = pf.L, TPL = pf.tpl, S = lds_line_stride(L);
     const int t = threadIdx.x;
-    const int col = t / TPL, j = t % TPL;
-    const int cidx = blockIdx.x * NC + col;
-    const int rhs = blockIdx.y;
-    const bool colok = cidx < Lx * Ly;
-    const int kx = colok ? cidx % Lx : 0, ky = colok ? cidx / Lx : 0;
-    const int hx = Lx / 2, hy = Ly / 2;
-    const int kxo = kx <= hx ? kx : Lx - kx, kyo = ky <= hy ? ky : Ly - ky;
+    const int col = t / (3 * TPL), comp = (t / TPL) % 3, j = t % TPL;
+    const int slot = lb * NC + col;
+    const int rhs = slot % nrhs;
+    // blocks hold whole columns of one right-hand side only when NC == 1; with NC > 1 a done
+    // right-hand side still runs (harmless: its buffers are not read afterwards)
+    if (done && NC == 1 && done[rhs]) return;
+    int kx, ky, kxo, kyo;
+    bool ok;
+    slot_column<R>(slot / nrhs, Lx, Ly, kx, ky, kxo, kyo, ok);
+    const int hx = Lx / 2, hy = Ly / 2, hz = L / 2;
     const R sx = kx <= hx ? (R)1 : (R)-1, sy = ky <= hy ? (R)1 : (R)-1;
-    const C *gcol = Gh + ((size_t)kyo * (hx + 1) + kxo) * (size_t)(L / 2 + 1) * 6;
-    C *colp = B2 + ((size_t)cidx * ncomp + rhs * 3) * nz;  // three components, nz each
-    C *ln[3] = {lds + (col * 3 + 0) * S, lds + (col * 3 + 1) * S, lds + (col * 3 + 2) * S};
-    C a[3][kMaxRadixZ];
+    // tensor row `comp`: components (xx,xy,xz), (xy,yy,yz), (xz,yz,zz) and their mirror signs
+    const int g0 = comp == 0 ? 0 : comp == 1 ? 1 : 2;
+    const int g1 = comp == 0 ? 1 : comp == 1 ? 3 : 4;
+    const int g2 = comp == 0 ? 2 : comp == 1 ? 4 : 5;
+    const C *gcol = Gh + ((size_t)kyo * (hx + 1) + kxo) * (size_t)(hz + 1) * 6;
+    C *lcol = lds + (size_t)col * 3 * S;
+    C *ln = lcol + comp * S;
+    const int ncomp = 3 * nrhs;
     const int np = pf.npass;
-    // ---- forward pass 0 from global
     const int R0 = pf.radix[0];
-    if (j < L / R0) {
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            const C *src = colp + (size_t)cc * nz;
-            load_rt<-1, kMaxRadixZ>(a[cc], R0, j, L, 1, tw,
-                                    [&](int i) -> C { return (colok && i < nz) ? src[i] : czero<C>(); });
-        }
-    }
-    if (np >= 2) {
+    const int Ri = pi.radix[0];  // == pf.radix[np - 1]
+    const int qi = L / Ri;
+    {
+        C *line = B2 + (((size_t)ky * Lx + kx) * ncomp + rhs * 3 + comp) * nz;
         if (j < L / R0) {
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc)
-                store_rt<kMaxRadixZ>(a[cc], R0, j, 1, [&](int i, C v) { ln[cc][pidx(i)] = v; });
+            C a[kMaxRadixZ];
+            load_rt<-1, kMaxRadixZ>(a, R0, j, L, 1, tw, [&](int i) -> C { return (ok && i < nz) ? line[i] : czero<C>(); });
+            store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
         __syncthreads();
-        for (int p = 1; p < np - 1; ++p) {  // middle forward passes, in place
-            const int Rp = pf.radix[p], Ns = pf.ns[p];
-            const bool act = j < L / Rp;
-            if (act) {
+        lds_passes<-1, kMaxRadixZ>(ln, pf, 1, np, j, tw);  // natural order in LDS afterwards
+        C a[kMaxRadixZ];
+        const bool act = j < qi;
+        if (act) {
+            // G[comp][d] for d = x, y, z: tensor components and their signs under the mirrors
+            const R s0 = comp == 0 ? (R)1 : comp == 1 ? sx * sy : sx;
+            const R s1 = comp == 0 ? sx * sy : comp == 1 ? (R)1 : sy;
+            const R s2 = comp == 0 ? sx : comp == 1 ? sy : (R)1;
+            auto mul = [&](auto radix_tag) {
+                constexpr int RI = decltype(radix_tag)::value;
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    load_rt<-1, kMaxRadixZ>(a[cc], Rp, j, L, Ns, tw, [&](int i) { return ln[cc][pidx(i)]; });
-            }
-            __syncthreads();
-            if (act) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    store_rt<kMaxRadixZ>(a[cc], Rp, j, Ns, [&](int i, C v) { ln[cc][pidx(i)] = v; });
-            }
-            __syncthreads();
-        }
-        const int Rl = pf.radix[np - 1], Nl = pf.ns[np - 1];
-        if (j < L / Rl) {
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc)
-                load_rt<-1, kMaxRadixZ>(a[cc], Rl, j, L, Nl, tw, [&](int i) { return ln[cc][pidx(i)]; });
-        }
-    }
-    // ---- multiply by the tensor at kz = j + r * L/Rl
-    const int Rl = pf.radix[np - 1];
-    const bool actl = j < L / Rl;
-    if (actl && colok) ghat_mul3<R>(a, Rl, j, L / Rl, L, gcol, sx, sy);
-    // ---- inverse pass 0 on the same registers (pi.radix[0] == Rl, Ns = 1)
-    if (actl) {
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) regs_rt<+1, kMaxRadixZ>(a[cc], Rl, j, L, 1, tw);
-    }
-    if (np >= 2) {
-        __syncthreads();  // all forward reads of LDS are done
-        if (actl) {
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc)
-                store_rt<kMaxRadixZ>(a[cc], Rl, j, 1, [&](int i, C v) { ln[cc][pidx(i)] = v; });
-        }
-        __syncthreads();
-        for (int p = 1; p < np - 1; ++p) {
-            const int Rp = pi.radix[p], Ns = pi.ns[p];
-            const bool act = j < L / Rp;
-            if (act) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    load_rt<+1, kMaxRadixZ>(a[cc], Rp, j, L, Ns, tw, [&](int i) { return ln[cc][pidx(i)]; });
-            }
-            __syncthreads();
-            if (act) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-                    store_rt<kMaxRadixZ>(a[cc], Rp, j, Ns, [&](int i, C v) { ln[cc][pidx(i)] = v; });
-            }
-            __syncthreads();
-        }
-        const int Rq = pi.radix[np - 1], Nq = pi.ns[np - 1];
-        if (j < L / Rq) {
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc)
-                load_rt<+1, kMaxRadixZ>(a[cc], Rq, j, L, Nq, tw, [&](int i) { return ln[cc][pidx(i)]; });
-            if (colok) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    C *dst = colp + (size_t)cc * nz;
-                    store_rt<kMaxRadixZ>(a[cc], Rq, j, Nq, [&](int i, C v) {
-                        if (i < nz) dst[i] = v;
-                    });
+                for (int r = 0; r < RI; ++r) {
+                    const int kz = j + r * qi;
+                    const bool lo = kz <= hz;
+                    const R sz = lo ? (R)1 : (R)-1;
+                    const C *g = gcol + (size_t)(lo ? kz : L - kz) * 6;
+                    // the z-odd components (xz, yz) of row comp pick up sz; so does G[z][x], G[z][y]
+                    const C G0 = cscale(g[g0], comp == 2 ? s0 * sz : s0);
+                    const C G1 = cscale(g[g1], comp == 2 ? s1 * sz : s1);
+                    const C G2 = cscale(g[g2], comp == 2 ? s2 : s2 * sz);
+                    const int p = pidx(kz);
+                    const C X = lcol[p], Y = lcol[S + p], Z = lcol[2 * S + p];
+                    a[r] = cadd(cadd(cmul(G0, X), cmul(G1, Y)), cmul(G2, Z));
                 }
+                dftR<+1, RI>(a);
+            };
+            switch (Ri) {
+                case 1: mul(std::integral_constant<int, 1>{}); break;
+                case 2: mul(std::integral_constant<int, 2>{}); break;
+                case 3: mul(std::integral_constant<int, 3>{}); break;
+                case 4: mul(std::integral_constant<int, 4>{}); break;
+                case 5: mul(std::integral_constant<int, 5>{}); break;
+                default: mul(std::integral_constant<int, 8>{}); break;
             }
         }
-    } else if (actl && colok) {  // single pass: inverse output straight to global
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            C *dst = colp + (size_t)cc * nz;
-            store_rt<kMaxRadixZ>(a[cc], Rl, j, 1, [&](int i, C v) {
-                if (i < nz) dst[i] = v;
-            });
+        __syncthreads();  // every thread has read the three transformed lines
+        if (np == 1) {
+            if (act && ok) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { if (i < nz) line[i] = v; });
+        } else {
+            if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+            __syncthreads();
+            lds_passes<+1, kMaxRadixZ>(ln, pi, 1, np - 1, j, tw);
+            const int Rq = pi.radix[np - 1], Nq = pi.ns[np - 1];
+            if (j < L / Rq) {
+                load_rt<+1, kMaxRadixZ>(a, Rq, j, L, Nq, tw, [&](int i) { return ln[pidx(i)]; });
+                if (ok) store_rt<kMaxRadixZ>(a, Rq, j, Nq, [&](int i, C v) { if (i < nz) line[i] = v; });
+            }
         }
     }
 }
@@ -304,7 +286,8 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_zmul(cplx<R> *__restrict__ 
 template <typename R>
 __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_y(const cplx<R> *__restrict__ B2, cplx<R> *__restrict__ B1, int ny,
                                                 int nz, int Lx, int ncomp, FftPlan pl,
-                                                const cplx<R> *__restrict__ twall, int NL) {
+                                                const cplx<R> *__restrict__ twall, int NL,
+                                                const int *__restrict__ done) {
     using C = cplx<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
@@ -316,6 +299,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_y(const cplx<R> *__rest
     b /= ztiles;
     const int kx = b % Lx;
     const int c = b / Lx;
+    if (done && done[c / 3]) return;
     const int t = threadIdx.x;
     const size_t kystride = (size_t)Lx * ncomp * nz;
     const C *src = B2 + ((size_t)kx * ncomp + c) * nz;
@@ -376,7 +360,8 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_x(const int *__restrict
                                                 const cplx<R> *__restrict__ xin, cplx<R> *__restrict__ yout,
                                                 int nx, int ny, int nz, int N, FftPlan pl,
                                                 const cplx<R> *__restrict__ twall, int NL,
-                                                const cplx<R> *__restrict__ scale, cplx<R> *__restrict__ dots) {
+                                                const cplx<R> *__restrict__ scale, cplx<R> *__restrict__ dots,
+                                                const int *__restrict__ done) {
     using C = cplx<R>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
@@ -388,6 +373,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_x(const int *__restrict
     b /= ytiles;
     const int z = b % nz;
     const int c = b / nz;
+    if (done && done[c / 3]) return;
     const int t = threadIdx.x;
     const C *src = B1 + ((size_t)c * nz + z) * (size_t)L * ny;
     {   // pass 0 from global, lanes over lines (y contiguous in B1)

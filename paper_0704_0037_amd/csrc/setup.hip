@@ -208,6 +208,10 @@ __global__ void k_to_f32(const double2 *__restrict__ a, float2 *__restrict__ b, 
 }
 
 // ------------------------------------------------------------------- host side
+void launch_to_f32(const double2 *a, float2 *b, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+}
+
 void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
     // Clausius-Mossotti for a unit cube: (3/4pi)(m^2-1)/(m^2+2)
     const double mr = c.m_re, mi = c.m_im;
@@ -275,7 +279,7 @@ template <> const float2 *ghat_of<float>(const Ctx &c) { return c.ghat32; }
 
 template <typename R>
 dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
-                         hipStream_t s) {
+                         hipStream_t s, const int *done) {
     using C = cplx<R>;
     Work<R> &w = work_of<R>(c);
     const C *tw = tw_of<R>(c);
@@ -288,21 +292,27 @@ dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const c
     const size_t lz_bytes = (size_t)ncz * 3 * lds_line_stride(c.Lz) * sizeof(C);
     const int N = (int)c.N;
     hipLaunchKernelGGL(k_fwd_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, x, w.B1,
-                       c.nx, c.ny, c.nz, N, c.pxf, tw, nlx);
+                       c.nx, c.ny, c.nz, N, c.pxf, tw, nlx, done);
     hipLaunchKernelGGL(k_fwd_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyf.tpl), ly_bytes, s, w.B1, w.B2, c.ny,
-                       c.nz, c.Lx, ncomp, c.pyf, tw, nly);
-    hipLaunchKernelGGL(k_zmul<R>, dim3((c.Lx * c.Ly + ncz - 1) / ncz, nrhs), dim3(ncz * c.pzf.tpl), lz_bytes, s, w.B2,
-                       gh, c.nz, c.Lx, c.Ly, ncomp, c.pzf, c.pzi, tw, ncz);
+                       c.nz, c.Lx, ncomp, c.pyf, tw, nly, done);
+    {
+        const int slots = 4 * (c.Lx / 2 + 1) * (c.Ly / 2 + 1) * nrhs;
+        const int nb = (slots + ncz - 1) / ncz;
+        const int nb8 = (nb + 7) / 8 * 8;
+        hipLaunchKernelGGL(k_zmul<R>, dim3(nb8), dim3(ncz * 3 * c.pzf.tpl), lz_bytes, s, w.B2, gh, c.nz, c.Lx, c.Ly,
+                           nrhs, c.pzf, c.pzi, tw, ncz, nb, done);
+    }
     hipLaunchKernelGGL(k_inv_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyi.tpl), ly_bytes, s, w.B2, w.B1, c.ny,
-                       c.nz, c.Lx, ncomp, c.pyi, tw, nly);
+                       c.nz, c.Lx, ncomp, c.pyi, tw, nly, done);
     hipLaunchKernelGGL(k_inv_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, w.B1, x,
-                       y, c.nx, c.ny, c.nz, N, c.pxi, tw, nlx, scale, dots);
+                       y, c.nx, c.ny, c.nz, N, c.pxi, tw, nlx, scale, dots, done);
     DDA_HIP_CHECK(hipGetLastError());
     return DDA_OK;
 }
 template dda_status matvec_device<double>(Ctx &, const double2 *, double2 *, int, const double2 *, double2 *,
-                                          hipStream_t);
-template dda_status matvec_device<float>(Ctx &, const float2 *, float2 *, int, const float2 *, float2 *, hipStream_t);
+                                          hipStream_t, const int *);
+template dda_status matvec_device<float>(Ctx &, const float2 *, float2 *, int, const float2 *, float2 *, hipStream_t,
+                                         const int *);
 
 template <typename R>
 dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const double *are, const double *aim,
@@ -315,7 +325,7 @@ dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const d
     for (int r = 0; r < nrhs; ++r) sc[r] = mk<cplx<R>>((R)(are[r] * inv), (R)(aim[r] * inv));
     DDA_HIP_CHECK(hipMemcpyAsync(w.scale, sc.data(), nrhs * sizeof(cplx<R>), hipMemcpyHostToDevice, s));
     DDA_HIP_CHECK(hipStreamSynchronize(s));  // the host staging vector goes out of scope
-    return matvec_device<R>(c, x, y, nrhs, w.scale, want_dots ? w.dots : nullptr, s);
+    return matvec_device<R>(c, x, y, nrhs, w.scale, want_dots ? w.dots : nullptr, s, nullptr);
 }
 template dda_status matvec_launch<double>(Ctx &, const double2 *, double2 *, int, const double *, const double *, bool,
                                           hipStream_t);
@@ -330,6 +340,7 @@ void destroy(Ctx *c) {
     free_work(c->w32);
     (void)hipFree(c->gmap);
     (void)hipFree(c->lin);
+    (void)hipFree(c->line_start);
     (void)hipFree(c->ghat);
     (void)hipFree(c->ghat32);
     (void)hipFree(c->tw64);
@@ -489,8 +500,9 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
     const int want_nl = opts ? opts->lines_per_block : 0;
     c->nl_x = pick_lines(c->pxf.tpl, lds_line_stride(c->Lx) * 16, c->ny, want_nl);
     c->nl_y = pick_lines(c->pyf.tpl, lds_line_stride(c->Ly) * 16, c->nz, want_nl);
-    c->nc_z = pick_lines(c->pzf.tpl, 3 * lds_line_stride(c->Lz) * 16, 1 << 20, 0);
-    if (c->nc_z * c->pzf.tpl > DDA_MAX_THREADS || c->nl_x * c->pxf.tpl > DDA_MAX_THREADS ||
+    c->nc_z = std::max(1, DDA_MAX_THREADS / (3 * c->pzf.tpl));
+    while (c->nc_z > 1 && (size_t)c->nc_z * 3 * lds_line_stride(c->Lz) * 16 > 64 * 1024) --c->nc_z;
+    if (3 * c->pzf.tpl > 768 || c->nl_x * c->pxf.tpl > DDA_MAX_THREADS ||
         c->nl_y * c->pyf.tpl > DDA_MAX_THREADS) {
         set_error("dda_setup: padded size too large for one workgroup per line");
         delete c;

@@ -1,0 +1,1012 @@
+// Iterative solvers of eq. 3 on the device: complex-symmetric QMR (one interaction-matrix
+// product per iteration) and Bi-CGSTAB (two), the two of the paper's four solvers its runs use
+// besides Bi-CG (Sec. 2, Sec. 3.1), plus single-precision inner solves inside double-precision
+// iterative refinement.
+//
+// Every right-hand side of a batch carries its own scalar state on the device; the host only
+// launches kernels and reads the per-RHS "done" flags every few iterations.  A right-hand side
+// that has converged (or broken down) turns every later kernel of its batch into a no-op, so
+// over-launching past convergence never changes its iterate.
+//
+// Vectors are [nrhs][3N] complex (component-major per RHS).  Reductions are per-block partial
+// sums in double precision, summed in a fixed order by one block per right-hand side, so results
+// are bitwise reproducible run to run.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace dda {
+
+template <typename R> dda_status rhs_launch(Ctx &c, const dda_beam &bm, cplx<R> *b, hipStream_t s);
+bool beam_ok(const dda_beam *b);
+void launch_to_f32(const double2 *a, float2 *b, size_t n, hipStream_t s);
+
+enum { ST_RUN = 0, ST_CONV = 1, ST_MAXIT = 2, ST_BREAK = 3 };
+constexpr double kBreakdown = 1e-12;  // |v^T v| below this for unit v: Lanczos breakdown
+constexpr int kVecThreads = 256;
+
+struct SolveState {
+    // QMR
+    double rho, gamma_prev, theta_prev, bnorm, res, c2, tol, snorm;
+    double2 eps, delta, beta, eta, cp;
+    // Bi-CGSTAB
+    double2 rho_b, rho_old, alpha, omega, beta_b;
+    int iter, status, maxit, pending, half, first, pad0, pad1;
+};
+
+// ------------------------------------------------------------------ small helpers
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ double2 ddiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double dabs(double2 a) { return hypot(a.x, a.y); }
+__device__ __forceinline__ bool dfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+template <typename R> __device__ __forceinline__ double2 up(cplx<R> a) { return make_double2((double)a.x, (double)a.y); }
+template <typename R> __device__ __forceinline__ cplx<R> dn(double2 a) { return mk<cplx<R>>((R)a.x, (R)a.y); }
+
+// sum K double2 values over the block (LDS tree, deterministic); result valid in thread 0
+template <int K> __device__ __forceinline__ void block_reduce(double2 (&v)[K], double2 *sh) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < K; ++k) sh[k * kVecThreads + t] = v[k];
+    __syncthreads();
+    for (int h = kVecThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int k = 0; k < K; ++k) {
+                double2 a = sh[k * kVecThreads + t], b = sh[k * kVecThreads + t + h];
+                sh[k * kVecThreads + t] = make_double2(a.x + b.x, a.y + b.y);
+            }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < K; ++k) v[k] = sh[k * kVecThreads];
+}
+
+// sum partials [nb][K] of one right-hand side into out[K]; every thread of the block gets them
+template <int K> __device__ __forceinline__ void sum_partials(const double2 *p, int nb, double2 (&out)[K], double2 *sh) {
+    double2 v[K];
+    for (int k = 0; k < K; ++k) v[k] = make_double2(0, 0);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+        for (int k = 0; k < K; ++k) {
+            v[k].x += p[b * 4 + k].x;
+            v[k].y += p[b * 4 + k].y;
+        }
+    block_reduce<K>(v, sh);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < K; ++k) sh[k] = v[k];
+    __syncthreads();
+    for (int k = 0; k < K; ++k) out[k] = sh[k];
+    __syncthreads();
+}
+
+#define VEC_LOOP(n3) for (size_t i = (size_t)blockIdx.x * kVecThreads + threadIdx.x; i < (n3); i += (size_t)gridDim.x * kVecThreads)
+
+// ============================================================================ QMR
+// r = b - Ax0 (Ax0 given) or b; vt = r; x zeroed when there is no initial guess.
+// partials: (|b|^2, |vt|^2), vt^T vt
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_qmr_init(const cplx<R> *b, const cplx<R> *ax, cplx<R> *x, cplx<R> *r,
+                                                          cplx<R> *vt, size_t n3, double2 *part, int zero_x) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.y;
+    const size_t off = (size_t)rhs * n3;
+    double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const cplx<R> bi = b[off + i];
+        cplx<R> ri = bi;
+        if (ax) ri = csub(bi, ax[off + i]);
+        if (zero_x) x[off + i] = czero<cplx<R>>();
+        r[off + i] = ri;
+        vt[off + i] = ri;
+        const double2 bd = up<R>(bi), rd = up<R>(ri);
+        acc[0].x += bd.x * bd.x + bd.y * bd.y;
+        acc[0].y += rd.x * rd.x + rd.y * rd.y;
+        acc[1].x += rd.x * rd.x - rd.y * rd.y;  // bilinear r^T r
+        acc[1].y += 2 * rd.x * rd.y;
+    }
+    block_reduce<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        double2 *p = part + ((size_t)rhs * gridDim.x + blockIdx.x) * 4;
+        p[0] = acc[0];
+        p[1] = acc[1];
+    }
+}
+
+__global__ void k_qmr_scal_init(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;  // excluded from this solve by the caller
+    double2 s[2];
+    sum_partials<2>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.bnorm = sqrt(s[0].x);
+    S.rho = sqrt(s[0].y);
+    S.res = S.bnorm > 0 ? S.rho / S.bnorm : 0.0;
+    S.gamma_prev = 1.0;
+    S.theta_prev = 0.0;
+    S.eta = make_double2(-1.0, 0.0);
+    S.iter = 0;
+    S.pending = 0;
+    S.first = 1;
+    S.status = ST_RUN;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap] = S.res;
+    if (S.res < S.tol || S.bnorm == 0.0) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+        return;
+    }
+    const double r2 = S.rho * S.rho;
+    S.delta = make_double2(s[1].x / r2, s[1].y / r2);  // v^T v with v = vt / rho
+    if (dabs(S.delta) < kBreakdown || !dfinite(S.delta)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+        return;
+    }
+    S.cp = make_double2(0, 0);
+    done[rhs] = 0;
+}
+
+// first iteration: p = vt / rho
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_qmr_p0(const SolveState *st, const int *done, const cplx<R> *vt,
+                                                        cplx<R> *p, size_t n3) {
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const R inv = (R)(1.0 / st[rhs].rho);
+    VEC_LOOP(n3) p[off + i] = cscale(vt[off + i], inv);
+}
+
+// eps = p^T A p from the matvec epilogue partials; beta = eps / delta
+template <typename R>
+__global__ void k_qmr_scal_eps(SolveState *st, int *done, const cplx<R> *dots, int ndots) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 v[1] = {make_double2(0, 0)};
+    for (int b = threadIdx.x; b < ndots; b += blockDim.x) {
+        const double2 d = up<R>(dots[(size_t)rhs * ndots + b]);
+        v[0].x += d.x;
+        v[0].y += d.y;
+    }
+    block_reduce<1>(v, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.eps = v[0];
+    if ((S.eps.x == 0 && S.eps.y == 0) || !dfinite(S.eps)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+        return;
+    }
+    S.beta = ddiv(S.eps, S.delta);
+}
+
+// vt = pt - (beta / rho) vt; partials |vt|^2, vt^T vt
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_qmr_vt(const SolveState *st, const int *done, const cplx<R> *pt,
+                                                        cplx<R> *vt, size_t n3, double2 *part) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const SolveState &S = st[rhs];
+    const cplx<R> c = dn<R>(make_double2(S.beta.x / S.rho, S.beta.y / S.rho));
+    double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const cplx<R> v = csub(pt[off + i], cmul(c, vt[off + i]));
+        vt[off + i] = v;
+        const double2 d = up<R>(v);
+        acc[0].x += d.x * d.x + d.y * d.y;
+        acc[1].x += d.x * d.x - d.y * d.y;
+        acc[1].y += 2 * d.x * d.y;
+    }
+    block_reduce<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        double2 *p = part + ((size_t)rhs * gridDim.x + blockIdx.x) * 4;
+        p[0] = acc[0];
+        p[1] = acc[1];
+    }
+}
+
+// rho_new, theta, gamma, eta and the coefficients of the update pass
+__global__ void k_qmr_scal_2(SolveState *st, int *done, const double2 *part, int nb) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[2];
+    sum_partials<2>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    const double rho_new = sqrt(s[0].x);
+    const double bmod = dabs(S.beta);
+    const double theta = rho_new / (S.gamma_prev * bmod);
+    const double gamma = 1.0 / sqrt(1.0 + theta * theta);
+    // eta = -eta rho gamma^2 / (beta gamma_prev^2)
+    const double f = S.rho * gamma * gamma / (S.gamma_prev * S.gamma_prev);
+    const double2 q = ddiv(make_double2(S.eta.x * f, S.eta.y * f), S.beta);
+    S.eta = make_double2(-q.x, -q.y);
+    S.c2 = (S.theta_prev * gamma) * (S.theta_prev * gamma);
+    S.theta_prev = theta;
+    S.gamma_prev = gamma;
+    S.rho = rho_new;
+    if (rho_new == 0.0 || !isfinite(rho_new)) {
+        // the Krylov space is exhausted: this update is the last one
+        S.cp = make_double2(0, 0);
+        S.pending = 1;
+        return;
+    }
+    const double r2 = rho_new * rho_new;
+    S.delta = make_double2(s[1].x / r2, s[1].y / r2);
+    if (dabs(S.delta) < kBreakdown || !dfinite(S.delta)) {
+        S.cp = make_double2(0, 0);
+        S.pending = 2;  // breakdown after this update
+        return;
+    }
+    // p_next = vt / rho_new - (rho_new delta / eps) p
+    S.cp = ddiv(make_double2(rho_new * S.delta.x, rho_new * S.delta.y), S.eps);
+}
+
+// d = eta p + c2 d;  s = eta pt + c2 s;  x += d;  r -= s;  p = vt / rho - cp p;  partial |r|^2
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_qmr_update(const SolveState *st, const int *done, cplx<R> *p,
+                                                            const cplx<R> *pt, const cplx<R> *vt, cplx<R> *d,
+                                                            cplx<R> *s, cplx<R> *x, cplx<R> *r, size_t n3,
+                                                            double2 *part) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const SolveState &S = st[rhs];
+    const cplx<R> eta = dn<R>(S.eta), cp = dn<R>(S.cp);
+    const R c2 = (R)S.c2, inv = (R)(S.rho > 0 ? 1.0 / S.rho : 0.0);
+    const bool first = S.first;
+    double2 acc[1] = {make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const cplx<R> pi = p[off + i], pti = pt[off + i];
+        cplx<R> di = cmul(eta, pi), si = cmul(eta, pti);
+        if (!first) {
+            di = cadd(di, cscale(d[off + i], c2));
+            si = cadd(si, cscale(s[off + i], c2));
+        }
+        d[off + i] = di;
+        s[off + i] = si;
+        x[off + i] = cadd(x[off + i], di);
+        const cplx<R> ri = csub(r[off + i], si);
+        r[off + i] = ri;
+        p[off + i] = csub(cscale(vt[off + i], inv), cmul(cp, pi));
+        const double2 rd = up<R>(ri);
+        acc[0].x += rd.x * rd.x + rd.y * rd.y;
+    }
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)rhs * gridDim.x + blockIdx.x) * 4] = acc[0];
+}
+
+__global__ void k_qmr_scal_3(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[1];
+    sum_partials<1>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.first = 0;
+    S.iter += 1;
+    S.res = sqrt(s[0].x) / S.bnorm;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap + (S.iter < hcap ? S.iter : hcap - 1)] = S.res;
+    if (S.res < S.tol || S.pending == 1) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+    } else if (S.pending == 2 || !isfinite(S.res)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+    } else if (S.iter >= S.maxit) {
+        S.status = ST_MAXIT;
+        done[rhs] = 1;
+    }
+}
+
+// ====================================================================== Bi-CGSTAB
+// r = b - Ax0 or b; rs = r; partials (|b|^2, |r|^2)
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_bi_init(const cplx<R> *b, const cplx<R> *ax, cplx<R> *x, cplx<R> *r,
+                                                         cplx<R> *rs, size_t n3, double2 *part, int zero_x) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.y;
+    const size_t off = (size_t)rhs * n3;
+    double2 acc[1] = {make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const cplx<R> bi = b[off + i];
+        cplx<R> ri = bi;
+        if (ax) ri = csub(bi, ax[off + i]);
+        if (zero_x) x[off + i] = czero<cplx<R>>();
+        r[off + i] = ri;
+        rs[off + i] = ri;
+        const double2 bd = up<R>(bi), rd = up<R>(ri);
+        acc[0].x += bd.x * bd.x + bd.y * bd.y;
+        acc[0].y += rd.x * rd.x + rd.y * rd.y;
+    }
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)rhs * gridDim.x + blockIdx.x) * 4] = acc[0];
+}
+
+__global__ void k_bi_scal_init(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[1];
+    sum_partials<1>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.bnorm = sqrt(s[0].x);
+    const double rn = sqrt(s[0].y);
+    S.res = S.bnorm > 0 ? rn / S.bnorm : 0.0;
+    S.rho_b = make_double2(s[0].y, 0.0);  // rs^H r = |r|^2 at the start
+    S.rho_old = S.alpha = S.omega = make_double2(1, 0);
+    S.iter = 0;
+    S.half = 0;
+    S.first = 1;
+    S.status = ST_RUN;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap] = S.res;
+    if (S.res < S.tol || S.bnorm == 0.0) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+        return;
+    }
+    done[rhs] = 0;
+}
+
+// beta = (rho/rho_old)(alpha/omega); p = r + beta (p - omega v)   (p = r at the first iteration)
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_bi_p(SolveState *st, const int *done, const cplx<R> *r, cplx<R> *p,
+                                                      const cplx<R> *v, size_t n3) {
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const SolveState &S = st[rhs];
+    const bool first = S.first;
+    const double2 bd = dmul(ddiv(S.rho_b, S.rho_old), ddiv(S.alpha, S.omega));
+    const cplx<R> beta = dn<R>(bd), om = dn<R>(S.omega);
+    VEC_LOOP(n3) {
+        if (first) p[off + i] = r[off + i];
+        else p[off + i] = cadd(r[off + i], cmul(beta, csub(p[off + i], cmul(om, v[off + i]))));
+    }
+}
+
+// partials of u^H w and (optionally) w^H w over one right-hand side
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_bi_dots(const int *done, const cplx<R> *u, const cplx<R> *w,
+                                                         size_t n3, double2 *part, int with_ww) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const double2 a = up<R>(u[off + i]), b = up<R>(w[off + i]);
+        acc[0].x += a.x * b.x + a.y * b.y;  // conj(a) b
+        acc[0].y += a.x * b.y - a.y * b.x;
+        if (with_ww) acc[1].x += b.x * b.x + b.y * b.y;
+    }
+    block_reduce<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        double2 *p = part + ((size_t)rhs * gridDim.x + blockIdx.x) * 4;
+        p[0] = acc[0];
+        p[1] = acc[1];
+    }
+}
+
+// alpha = rho / (rs^H v)
+__global__ void k_bi_scal_alpha(SolveState *st, int *done, const double2 *part, int nb) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[2];
+    sum_partials<2>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    if ((s[0].x == 0 && s[0].y == 0) || !dfinite(s[0])) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+        return;
+    }
+    S.alpha = ddiv(S.rho_b, s[0]);
+}
+
+// s = r - alpha v; partial |s|^2
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_bi_s(const SolveState *st, const int *done, const cplx<R> *r,
+                                                      const cplx<R> *v, cplx<R> *s, size_t n3, double2 *part) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const cplx<R> a = dn<R>(st[rhs].alpha);
+    double2 acc[1] = {make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const cplx<R> si = csub(r[off + i], cmul(a, v[off + i]));
+        s[off + i] = si;
+        const double2 d = up<R>(si);
+        acc[0].x += d.x * d.x + d.y * d.y;
+    }
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)rhs * gridDim.x + blockIdx.x) * 4] = acc[0];
+}
+
+__global__ void k_bi_scal_s(SolveState *st, const int *done, const double2 *part, int nb) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[1];
+    sum_partials<1>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.snorm = sqrt(s[0].x);
+    S.half = (S.snorm / S.bnorm < S.tol) ? 1 : 0;
+}
+
+// omega = (t^H s) / (t^H t), or 0 when s already met the tolerance
+__global__ void k_bi_scal_omega(SolveState *st, int *done, const double2 *part, int nb) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[2];
+    sum_partials<2>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    if (S.half) {
+        S.omega = make_double2(0, 0);
+        return;
+    }
+    if (s[1].x == 0 || !isfinite(s[1].x)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+        return;
+    }
+    S.omega = make_double2(s[0].x / s[1].x, s[0].y / s[1].x);
+}
+
+// x += alpha p + omega s;  r = s - omega t;  partials |r|^2, rs^H r
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_bi_x(const SolveState *st, const int *done, const cplx<R> *p,
+                                                      const cplx<R> *s, const cplx<R> *t, const cplx<R> *rs,
+                                                      cplx<R> *x, cplx<R> *r, size_t n3, double2 *part) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const SolveState &S = st[rhs];
+    const cplx<R> a = dn<R>(S.alpha), om = dn<R>(S.omega);
+    double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const cplx<R> si = s[off + i];
+        x[off + i] = cadd(x[off + i], cadd(cmul(a, p[off + i]), cmul(om, si)));
+        const cplx<R> ri = csub(si, cmul(om, t[off + i]));
+        r[off + i] = ri;
+        const double2 rd = up<R>(ri), q = up<R>(rs[off + i]);
+        acc[0].x += rd.x * rd.x + rd.y * rd.y;
+        acc[1].x += q.x * rd.x + q.y * rd.y;
+        acc[1].y += q.x * rd.y - q.y * rd.x;
+    }
+    block_reduce<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        double2 *pp = part + ((size_t)rhs * gridDim.x + blockIdx.x) * 4;
+        pp[0] = acc[0];
+        pp[1] = acc[1];
+    }
+}
+
+__global__ void k_bi_scal_end(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[2];
+    sum_partials<2>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.first = 0;
+    S.iter += 1;
+    S.res = S.half ? S.snorm / S.bnorm : sqrt(s[0].x) / S.bnorm;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap + (S.iter < hcap ? S.iter : hcap - 1)] = S.res;
+    S.rho_old = S.rho_b;
+    S.rho_b = s[1];
+    if (S.res < S.tol || S.half) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+    } else if (!isfinite(S.res) || (S.rho_b.x == 0 && S.rho_b.y == 0) || (S.omega.x == 0 && S.omega.y == 0)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+    } else if (S.iter >= S.maxit) {
+        S.status = ST_MAXIT;
+        done[rhs] = 1;
+    }
+}
+
+// ================================================================ refinement helpers
+// r64 = b - ax; partial (|r|^2, |b|^2)
+__global__ void __launch_bounds__(kVecThreads) k_resid(const double2 *b, const double2 *ax, double2 *r, size_t n3,
+                                                       double2 *part) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.y;
+    const size_t off = (size_t)rhs * n3;
+    double2 acc[1] = {make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const double2 bi = b[off + i], ri = make_double2(bi.x - ax[off + i].x, bi.y - ax[off + i].y);
+        if (r) r[off + i] = ri;
+        acc[0].x += ri.x * ri.x + ri.y * ri.y;
+        acc[0].y += bi.x * bi.x + bi.y * bi.y;
+    }
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)rhs * gridDim.x + blockIdx.x) * 4] = acc[0];
+}
+
+// r32 = r64 * scale[rhs]  (scale = 1/|r|)
+__global__ void k_to32(const double2 *r, float2 *r32, size_t n3, const double *scale) {
+    const int rhs = blockIdx.y;
+    const size_t off = (size_t)rhs * n3;
+    const double sc = scale[rhs];
+    VEC_LOOP(n3) r32[off + i] = make_float2((float)(r[off + i].x * sc), (float)(r[off + i].y * sc));
+}
+
+// x64 += e32 * scale[rhs] (only for right-hand sides still refining)
+__global__ void k_addup(double2 *x, const float2 *e, size_t n3, const double *scale, const int *active) {
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const double sc = 1.0 / scale[rhs];
+    VEC_LOOP(n3) {
+        x[off + i].x += (double)e[off + i].x * sc;
+        x[off + i].y += (double)e[off + i].y * sc;
+    }
+}
+
+__global__ void k_sum_part(const double2 *part, int nb, double2 *out) {
+    __shared__ double2 sh[kVecThreads];
+    double2 s[1];
+    sum_partials<1>(part + (size_t)blockIdx.x * nb * 4, nb, s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+__global__ void k_zero(double2 *x, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = make_double2(0, 0);
+}
+
+// ==================================================================== host driver
+struct Bufs {
+    int nrhs = 0;
+    size_t n3 = 0;
+    int nb = 0;
+    SolveState *st = nullptr;
+    int *done = nullptr;
+    double2 *part = nullptr;
+    double *hist = nullptr;
+    int hcap = 0;
+    double2 *scratch = nullptr;  // 4 nrhs + 16 entries of small device scratch
+};
+
+template <typename R> struct Vecs {
+    cplx<R> *b, *r, *vt, *p, *pt, *d, *s, *rs, *v, *t;
+};
+
+template <typename R> static cplx<R> *vec_base(Ctx &c);
+template <> double2 *vec_base<double>(Ctx &c) { return c.vecs; }
+template <> float2 *vec_base<float>(Ctx &c) { return c.vecs32; }
+
+static constexpr int kNumVecs = 9;  // b r vt p pt d s (QMR) / b r rs p v s t (Bi-CGSTAB)
+
+template <typename R> static dda_status ensure_vecs(Ctx &c, int nrhs) {
+    const size_t need = (size_t)kNumVecs * nrhs * 3 * c.N;
+    size_t &have = std::is_same<R, double>::value ? c.vecs_elems : c.vecs32_elems;
+    if (have >= need) return DDA_OK;
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    if (std::is_same<R, double>::value) {
+        (void)hipFree(c.vecs);
+        c.vecs = nullptr;
+        c.vecs_elems = 0;
+        dda_status st = device_alloc((void **)&c.vecs, need * sizeof(double2));
+        if (st != DDA_OK) return st;
+        c.vecs_elems = need;
+    } else {
+        (void)hipFree(c.vecs32);
+        c.vecs32 = nullptr;
+        c.vecs32_elems = 0;
+        dda_status st = device_alloc((void **)&c.vecs32, need * sizeof(float2));
+        if (st != DDA_OK) return st;
+        c.vecs32_elems = need;
+    }
+    return DDA_OK;
+}
+
+template <typename R> static Vecs<R> vecs_of(Ctx &c, int nrhs) {
+    cplx<R> *base = vec_base<R>(c);
+    const size_t L = (size_t)nrhs * 3 * c.N;
+    Vecs<R> v;
+    v.b = base;
+    v.r = base + L;
+    v.vt = base + 2 * L;
+    v.p = base + 3 * L;
+    v.pt = base + 4 * L;
+    v.d = base + 5 * L;
+    v.s = base + 6 * L;
+    v.rs = v.vt;   // Bi-CGSTAB reuses the QMR slots
+    v.v = v.pt;
+    v.t = v.d;
+    return v;
+}
+
+template <typename R> static Work<R> &work(Ctx &c) {
+    if constexpr (std::is_same<R, double>::value) return c.w64;
+    else return c.w32;
+}
+
+// device scales alpha / (Lx Ly Lz) per right-hand side, in the work buffer of precision R
+template <typename R> static dda_status upload_scales(Ctx &c, const std::vector<double> &ar, const std::vector<double> &ai) {
+    dda_status st = ensure_work<R>(c, (int)ar.size());
+    if (st != DDA_OK) return st;
+    Work<R> &w = work<R>(c);
+    std::vector<cplx<R>> sc(ar.size());
+    const double inv = 1.0 / ((double)c.Lx * c.Ly * c.Lz);
+    for (size_t r = 0; r < ar.size(); ++r) sc[r] = mk<cplx<R>>((R)(ar[r] * inv), (R)(ai[r] * inv));
+    DDA_HIP_CHECK(hipMemcpyAsync(w.scale, sc.data(), sc.size() * sizeof(cplx<R>), hipMemcpyHostToDevice, c.stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    return DDA_OK;
+}
+
+static dda_status ensure_bufs(Ctx &c, Bufs &B, int nrhs, int hcap) {
+    B.nrhs = nrhs;
+    B.n3 = (size_t)3 * c.N;
+    B.nb = (int)std::min<size_t>(1024, (B.n3 + kVecThreads * 4 - 1) / (kVecThreads * 4));
+    if (B.nb < 1) B.nb = 1;
+    B.hcap = hcap;
+    const size_t bytes = nrhs * sizeof(SolveState) + 256 + nrhs * sizeof(int) * 2 + 256 +
+                         (size_t)nrhs * B.nb * 4 * sizeof(double2) + 256 + (size_t)nrhs * hcap * sizeof(double) + 256 +
+                         (4 * (size_t)nrhs + 16) * sizeof(double2) + 256;
+    if (c.sbuf_bytes < bytes) {
+        DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+        (void)hipFree(c.sbuf);
+        c.sbuf = nullptr;
+        c.sbuf_bytes = 0;
+        dda_status st = device_alloc((void **)&c.sbuf, bytes);
+        if (st != DDA_OK) return st;
+        c.sbuf_bytes = bytes;
+    }
+    char *p = (char *)c.sbuf;
+    auto take = [&](size_t n) {
+        char *q = p;
+        p += (n + 255) / 256 * 256;
+        return q;
+    };
+    B.st = (SolveState *)take(nrhs * sizeof(SolveState));
+    B.done = (int *)take(nrhs * sizeof(int) * 2);
+    B.part = (double2 *)take((size_t)nrhs * B.nb * 4 * sizeof(double2));
+    B.hist = hcap > 0 ? (double *)take((size_t)nrhs * hcap * sizeof(double)) : nullptr;
+    B.scratch = (double2 *)take((4 * (size_t)nrhs + 16) * sizeof(double2));
+    const size_t hb = 64 + nrhs * (sizeof(SolveState) + 2 * sizeof(int) + 4 * sizeof(double2));
+    if (c.hbuf_bytes < hb) {
+        if (c.hbuf) (void)hipHostFree(c.hbuf);
+        c.hbuf = nullptr;
+        c.hbuf_bytes = 0;
+        DDA_HIP_CHECK(hipHostMalloc((void **)&c.hbuf, hb, hipHostMallocDefault));
+        c.hbuf_bytes = hb;
+    }
+    return DDA_OK;
+}
+
+// Initial states (tolerance, iteration limit) for every right-hand side.
+static dda_status init_states(Ctx &c, Bufs &B, double tol, int maxit, const int *active = nullptr) {
+    std::vector<SolveState> h(B.nrhs);
+    for (auto &s : h) {
+        std::memset(&s, 0, sizeof s);
+        s.tol = tol;
+        s.maxit = maxit;
+    }
+    DDA_HIP_CHECK(hipMemcpyAsync(B.st, h.data(), h.size() * sizeof(SolveState), hipMemcpyHostToDevice, c.stream));
+    std::vector<int> d(B.nrhs, 0);
+    if (active)
+        for (int r = 0; r < B.nrhs; ++r) d[r] = active[r] ? 0 : 1;
+    DDA_HIP_CHECK(hipMemcpyAsync(B.done, d.data(), B.nrhs * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    return DDA_OK;
+}
+
+static dda_status all_done(Ctx &c, Bufs &B, bool &out) {
+    int *hd = (int *)c.hbuf;
+    DDA_HIP_CHECK(hipMemcpyAsync(hd, B.done, B.nrhs * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    out = true;
+    for (int r = 0; r < B.nrhs; ++r) out = out && hd[r];
+    return DDA_OK;
+}
+
+// One Krylov solve on vectors of precision R: x (device, [nrhs][3N]) holds the initial guess if
+// have_x0, else it is zeroed.  b must already be in v.b.  On return the states are on the device.
+template <typename R>
+static dda_status krylov(Ctx &c, Bufs &B, Vecs<R> &v, cplx<R> *x, bool have_x0, int solver, int check_every) {
+    hipStream_t s = c.stream;
+    const dim3 vg(B.nb, B.nrhs), vb(kVecThreads);
+    const int nrhs = B.nrhs;
+    const size_t n3 = B.n3;
+    Work<R> &w = work<R>(c);
+    const int ndots = (int)dots_per_rhs(c);
+    dda_status st;
+    if (have_x0) {
+        if ((st = matvec_device<R>(c, x, v.pt, nrhs, w.scale, nullptr, s, nullptr)) != DDA_OK) return st;
+    }
+    if (solver == DDA_QMR) {
+        hipLaunchKernelGGL(k_qmr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, x, v.r, v.vt, n3, B.part,
+                           have_x0 ? 0 : 1);
+        hipLaunchKernelGGL(k_qmr_scal_init, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+        hipLaunchKernelGGL(k_qmr_p0<R>, vg, vb, 0, s, B.st, B.done, v.vt, v.p, n3);
+    } else {
+        hipLaunchKernelGGL(k_bi_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, x, v.r, v.rs, n3, B.part,
+                           have_x0 ? 0 : 1);
+        hipLaunchKernelGGL(k_bi_scal_init, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+    }
+    DDA_HIP_CHECK(hipGetLastError());
+    bool fin = false;
+    if ((st = all_done(c, B, fin)) != DDA_OK) return st;
+    while (!fin) {
+        for (int k = 0; k < check_every; ++k) {
+            if (solver == DDA_QMR) {
+                if ((st = matvec_device<R>(c, v.p, v.pt, nrhs, w.scale, w.dots, s, B.done)) != DDA_OK) return st;
+                hipLaunchKernelGGL(k_qmr_scal_eps<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
+                hipLaunchKernelGGL(k_qmr_vt<R>, vg, vb, 0, s, B.st, B.done, v.pt, v.vt, n3, B.part);
+                hipLaunchKernelGGL(k_qmr_scal_2, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+                hipLaunchKernelGGL(k_qmr_update<R>, vg, vb, 0, s, B.st, B.done, v.p, v.pt, v.vt, v.d, v.s, x, v.r,
+                                   n3, B.part);
+                hipLaunchKernelGGL(k_qmr_scal_3, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+            } else {
+                hipLaunchKernelGGL(k_bi_p<R>, vg, vb, 0, s, B.st, B.done, v.r, v.p, v.v, n3);
+                if ((st = matvec_device<R>(c, v.p, v.v, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
+                hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.rs, v.v, n3, B.part, 0);
+                hipLaunchKernelGGL(k_bi_scal_alpha, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+                hipLaunchKernelGGL(k_bi_s<R>, vg, vb, 0, s, B.st, B.done, v.r, v.v, v.s, n3, B.part);
+                hipLaunchKernelGGL(k_bi_scal_s, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+                if ((st = matvec_device<R>(c, v.s, v.t, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
+                hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.t, v.s, n3, B.part, 1);
+                hipLaunchKernelGGL(k_bi_scal_omega, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+                hipLaunchKernelGGL(k_bi_x<R>, vg, vb, 0, s, B.st, B.done, v.p, v.s, v.t, v.rs, x, v.r, n3, B.part);
+                hipLaunchKernelGGL(k_bi_scal_end, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+            }
+        }
+        DDA_HIP_CHECK(hipGetLastError());
+        if ((st = all_done(c, B, fin)) != DDA_OK) return st;
+    }
+    return DDA_OK;
+}
+
+static dda_status fetch_states(Ctx &c, Bufs &B, std::vector<SolveState> &h) {
+    h.resize(B.nrhs);
+    DDA_HIP_CHECK(hipMemcpyAsync(h.data(), B.st, B.nrhs * sizeof(SolveState), hipMemcpyDeviceToHost, c.stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    return DDA_OK;
+}
+
+// |b - A x| / |b| per right-hand side (fp64), using v.pt as scratch
+static dda_status true_residual(Ctx &c, Bufs &B, Vecs<double> &v, const double2 *x, double2 *res_r,
+                                std::vector<double> &out) {
+    dda_status st;
+    if ((st = matvec_device<double>(c, x, v.pt, B.nrhs, c.w64.scale, nullptr, c.stream, nullptr)) != DDA_OK)
+        return st;
+    hipLaunchKernelGGL(k_resid, dim3(B.nb, B.nrhs), dim3(kVecThreads), 0, c.stream, v.b, v.pt, res_r, B.n3, B.part);
+    double2 *sums = (double2 *)((char *)c.hbuf + 64);
+    double2 *dsum = B.scratch;
+    hipLaunchKernelGGL(k_sum_part, dim3(B.nrhs), dim3(kVecThreads), 0, c.stream, B.part, B.nb, dsum);
+    DDA_HIP_CHECK(hipMemcpyAsync(sums, dsum, B.nrhs * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    out.resize(B.nrhs);
+    for (int r = 0; r < B.nrhs; ++r) out[r] = sums[r].y > 0 ? std::sqrt(sums[r].x / sums[r].y) : 0.0;
+    return DDA_OK;
+}
+
+static dda_status status_of(int s) {
+    return s == ST_CONV ? DDA_OK : s == ST_MAXIT ? DDA_ENOTCONV : s == ST_BREAK ? DDA_EBREAKDOWN : DDA_ENOTCONV;
+}
+
+// FP64 solve (QMR or Bi-CGSTAB) of all right-hand sides.
+static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
+                             double2 *x, dda_solve_info *info, int check_every) {
+    const int hcap = [&] {
+        int m = 0;
+        if (info)
+            for (int r = 0; r < nrhs; ++r) m = std::max(m, info[r].res_hist_cap);
+        return m;
+    }();
+    Bufs B;
+    dda_status st;
+    if ((st = ensure_vecs<double>(c, nrhs)) != DDA_OK) return st;
+    if ((st = ensure_bufs(c, B, nrhs, hcap)) != DDA_OK) return st;
+    std::vector<double> ar(nrhs), ai(nrhs);
+    for (int r = 0; r < nrhs; ++r) polarizability(c, beams[r], ar[r], ai[r]);
+    if ((st = upload_scales<double>(c, ar, ai)) != DDA_OK) return st;
+    Vecs<double> v = vecs_of<double>(c, nrhs);
+    for (int r = 0; r < nrhs; ++r)
+        if ((st = rhs_launch<double>(c, beams[r], v.b + (size_t)r * B.n3, c.stream)) != DDA_OK) return st;
+    if (o.x0 && o.x0 != x)
+        DDA_HIP_CHECK(hipMemcpyAsync(x, o.x0, (size_t)nrhs * B.n3 * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
+    if ((st = init_states(c, B, tol, o.maxit)) != DDA_OK) return st;
+    if ((st = krylov<double>(c, B, v, x, o.x0 != nullptr, o.solver, check_every)) != DDA_OK) return st;
+    std::vector<SolveState> h;
+    if ((st = fetch_states(c, B, h)) != DDA_OK) return st;
+    std::vector<double> rt;
+    if ((st = true_residual(c, B, v, x, nullptr, rt)) != DDA_OK) return st;
+    std::vector<double> hist;
+    if (hcap > 0) {
+        hist.resize((size_t)nrhs * hcap);
+        DDA_HIP_CHECK(hipMemcpy(hist.data(), B.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    dda_status ret = DDA_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const dda_status sr = status_of(h[r].status);
+        if (ret == DDA_OK && sr != DDA_OK) ret = sr;
+        if (!info) continue;
+        info[r].status = sr;
+        info[r].iters = h[r].iter;
+        const bool bi = o.solver == DDA_BICGSTAB;
+        info[r].matvecs = (bi ? 2 * h[r].iter - (h[r].half ? 1 : 0) : h[r].iter) + (o.x0 ? 1 : 0);
+        info[r].outer = 0;
+        info[r].res_rec = h[r].res;
+        info[r].res_true = rt[r];
+        if (info[r].res_hist && info[r].res_hist_cap > 0) {
+            const int n = std::min(info[r].res_hist_cap, h[r].iter + 1);
+            for (int k = 0; k < n; ++k) info[r].res_hist[k] = hist[(size_t)r * hcap + k];
+            info[r].res_hist_len = n;
+        } else {
+            info[r].res_hist_len = 0;
+        }
+    }
+    return ret;
+}
+
+// Iterative refinement: outer fp64 residual and update, inner fp32 QMR to inner_tol.
+static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
+                               double2 *x, dda_solve_info *info, int check_every) {
+    dda_status st;
+    if (!c.ghat32) {
+        const size_t n6 = (size_t)(c.Lx / 2 + 1) * (c.Ly / 2 + 1) * (c.Lz / 2 + 1) * 6;
+        if ((st = device_alloc((void **)&c.ghat32, n6 * sizeof(float2))) != DDA_OK) return st;
+        launch_to_f32(c.ghat, c.ghat32, n6, c.stream);
+    }
+    Bufs B;
+    if ((st = ensure_vecs<double>(c, nrhs)) != DDA_OK) return st;
+    if ((st = ensure_vecs<float>(c, nrhs)) != DDA_OK) return st;
+    if ((st = ensure_bufs(c, B, nrhs, 0)) != DDA_OK) return st;
+    std::vector<double> ar(nrhs), ai(nrhs);
+    for (int r = 0; r < nrhs; ++r) polarizability(c, beams[r], ar[r], ai[r]);
+    if ((st = upload_scales<double>(c, ar, ai)) != DDA_OK) return st;
+    if ((st = upload_scales<float>(c, ar, ai)) != DDA_OK) return st;
+    Vecs<double> v = vecs_of<double>(c, nrhs);
+    Vecs<float> v32 = vecs_of<float>(c, nrhs);
+    // spare slot 7 of the vector pools: inner fp32 solution and outer fp64 residual
+    float2 *e32 = vec_base<float>(c) + (size_t)7 * nrhs * B.n3;
+    double2 *r64 = vec_base<double>(c) + (size_t)7 * nrhs * B.n3;
+    for (int r = 0; r < nrhs; ++r)
+        if ((st = rhs_launch<double>(c, beams[r], v.b + (size_t)r * B.n3, c.stream)) != DDA_OK) return st;
+    if (o.x0 && o.x0 != x)
+        DDA_HIP_CHECK(hipMemcpyAsync(x, o.x0, (size_t)nrhs * B.n3 * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
+    if (!o.x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, c.stream, x, (size_t)nrhs * B.n3);
+    const double inner = o.inner_tol > 0 ? o.inner_tol : 1e-2;
+    std::vector<int> iters(nrhs, 0), mvs(nrhs, 0), outer(nrhs, 0), active(nrhs, 1);
+    std::vector<double> res(nrhs, 1.0), scale(nrhs, 1.0);
+    std::vector<int> stat(nrhs, ST_RUN);
+    double *dscale = (double *)B.scratch;           // nrhs doubles
+    int *dactive = (int *)(B.scratch + nrhs);       // nrhs ints
+    double2 *dsum = B.scratch + 2 * nrhs;           // nrhs sums
+    const int max_outer = 30;
+    for (int k = 0; k <= max_outer; ++k) {
+        // outer residual in fp64
+        if ((st = matvec_device<double>(c, x, v.pt, nrhs, c.w64.scale, nullptr, c.stream, nullptr)) != DDA_OK)
+            return st;
+        hipLaunchKernelGGL(k_resid, dim3(B.nb, nrhs), dim3(kVecThreads), 0, c.stream, v.b, v.pt, r64, B.n3, B.part);
+        hipLaunchKernelGGL(k_sum_part, dim3(nrhs), dim3(kVecThreads), 0, c.stream, B.part, B.nb, dsum);
+        double2 *hs = (double2 *)((char *)c.hbuf + 64);
+        DDA_HIP_CHECK(hipMemcpyAsync(hs, dsum, nrhs * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+        DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+        bool any = false;
+        for (int r = 0; r < nrhs; ++r) {
+            mvs[r] += 1;
+            if (!active[r]) continue;
+            const double rn = std::sqrt(hs[r].x), bn = std::sqrt(hs[r].y);
+            res[r] = bn > 0 ? rn / bn : 0.0;
+            if (res[r] < tol || bn == 0) {
+                active[r] = 0;
+                stat[r] = ST_CONV;
+            } else if (k == max_outer || iters[r] >= o.maxit) {
+                active[r] = 0;
+                stat[r] = ST_MAXIT;
+            } else {
+                scale[r] = 1.0 / rn;
+                outer[r] += 1;
+                any = true;
+            }
+        }
+        if (!any) break;
+        DDA_HIP_CHECK(hipMemcpyAsync(dscale, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(dactive, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(k_to32, dim3(B.nb, nrhs), dim3(kVecThreads), 0, c.stream, r64, v32.b, B.n3, dscale);
+        // inner fp32 QMR (inactive right-hand sides start as done)
+        if ((st = init_states(c, B, inner, std::max(1, o.maxit), active.data())) != DDA_OK) return st;
+        if ((st = krylov<float>(c, B, v32, e32, false, DDA_QMR, check_every)) != DDA_OK) return st;
+        std::vector<SolveState> h;
+        if ((st = fetch_states(c, B, h)) != DDA_OK) return st;
+        for (int r = 0; r < nrhs; ++r)
+            if (active[r]) {
+                iters[r] += h[r].iter;
+                mvs[r] += h[r].iter;
+                if (h[r].status == ST_BREAK && h[r].iter == 0) {
+                    active[r] = 0;
+                    stat[r] = ST_BREAK;
+                }
+            }
+        DDA_HIP_CHECK(hipMemcpyAsync(dactive, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.stream));
+        hipLaunchKernelGGL(k_addup, dim3(B.nb, nrhs), dim3(kVecThreads), 0, c.stream, x, e32, B.n3, dscale, dactive);
+        DDA_HIP_CHECK(hipGetLastError());
+    }
+    std::vector<double> rt;
+    if ((st = true_residual(c, B, v, x, nullptr, rt)) != DDA_OK) return st;
+    dda_status ret = DDA_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const dda_status sr = status_of(stat[r]);
+        if (ret == DDA_OK && sr != DDA_OK) ret = sr;
+        if (!info) continue;
+        info[r].status = sr;
+        info[r].iters = iters[r];
+        info[r].matvecs = mvs[r];
+        info[r].outer = outer[r];
+        info[r].res_rec = res[r];
+        info[r].res_true = rt[r];
+        info[r].res_hist_len = 0;
+    }
+    return ret;
+}
+
+}  // namespace dda
+
+using namespace dda;
+
+extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, double tol,
+                                const dda_solve_opts *opts, void *x_out, dda_solve_info *info) {
+    Ctx *c = cx(h);
+    if (!c || !beams || !x_out || n_rhs < 1 || !(tol > 0)) {
+        set_error("dda_solve: NULL argument, n_rhs < 1 or tol <= 0");
+        return DDA_EINVAL;
+    }
+    for (int r = 0; r < n_rhs; ++r)
+        if (!beam_ok(&beams[r])) {
+            set_error("dda_solve: beam without unit vectors");
+            return DDA_EINVAL;
+        }
+    dda_solve_opts o{};
+    if (opts) o = *opts;
+    if (o.maxit <= 0) o.maxit = 100000;
+    if (o.solver != DDA_QMR && o.solver != DDA_BICGSTAB) {
+        set_error("dda_solve: unknown solver");
+        return DDA_EINVAL;
+    }
+    if (o.precision != DDA_FP64 && o.precision != DDA_FP32_REFINE) {
+        set_error("dda_solve: unknown precision");
+        return DDA_EINVAL;
+    }
+    if (o.precision == DDA_FP32_REFINE && o.solver != DDA_QMR) {
+        set_error("dda_solve: the refined single-precision solve uses QMR only");
+        return DDA_ENOTSUP;
+    }
+    int check = o.check_every;
+    if (check <= 0) check = c->N * n_rhs > 2000000 ? 1 : c->N * n_rhs > 100000 ? 4 : 16;
+    const auto t0 = std::chrono::steady_clock::now();
+    dda_status st = o.precision == DDA_FP64
+                        ? solve_fp64(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check)
+                        : solve_refine(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check);
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int r = 0; r < n_rhs; ++r) info[r].t_solve_s = dt;
+    return st;
+}
