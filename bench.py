@@ -1,0 +1,180 @@
+"""Benchmark of the DDA hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (default): the 256^3 sphere, x = 40, m = 1.05 (8,783,848 dipoles, FFT grid 512^3, fp64),
+LDR polarizability, incidence along +z.  One step = the whole hot path for one batch: QMR solves of
+both incident polarizations (one batched solve, 2 right-hand sides) to relative residual 1e-5,
+extinction/absorption cross sections of both, and the Mueller matrix on 0..180 degrees in
+0.5-degree steps (361 angles) in the xz plane from the two solutions.
+
+Printed: one JSON line.  value = interaction-matrix products per second over the timed steps
+(whole job: solver vector work and read-out included in the time); roofline = the dominant matvec
+kernel's algorithmic bytes over its mean duration (HIP events on the context's stream);
+cpu_baseline = the CPU oracle's direct-sum product on sampled rows of the same particle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+KERNELS = ["fwd_x", "fwd_y", "zmul", "inv_y", "inv_x"]
+
+
+def alg_bytes(n, N, L, c):
+    """Algorithmic bytes of each matvec kernel on an n^3 grid padded to L^3 (c bytes per complex)."""
+    h = L // 2 + 1
+    return {
+        "fwd_x": c * (3 * N + 3 * L * n * n),                 # read x (non-void), write x-transformed planes
+        "fwd_y": c * (3 * L * n * n + 3 * L * L * n),         # read, write y-transformed
+        "zmul": c * (2 * 3 * L * L * n + 6 * h ** 3),         # read + write the (kx, ky) columns, tensor octant
+        "inv_y": c * (3 * L * L * n + 3 * L * n * n),
+        "inv_x": c * (3 * L * n * n + 3 * N + 3 * N),         # read planes and x, write y (non-void)
+    }
+
+
+def cpu_baseline(w, rows, seed=7):
+    """Oracle direct-sum product on `rows` sampled dipoles; scaled to full products per second."""
+    from oracle import dda as odda
+    pos, _ = odda.dipoles(w.mask)
+    alpha = odda.alpha_ldr(w.m, w.kd, (0, 0, 1), (1, 0, 0))
+    beta = odda.beta_of_alpha(alpha)
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((len(pos), 3)) + 1j * rng.standard_normal((len(pos), 3)))
+    sel = rng.choice(len(pos), rows, replace=False)
+    t0 = time.perf_counter()
+    odda.matvec_rows(pos, w.kd, beta, x, sel)
+    dt = time.perf_counter() - t0
+    per_row = dt / rows
+    return {"value": 1.0 / (per_row * len(pos)), "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows} rows of the {len(pos)}-dipole product by direct summation (numpy, one thread), "
+                      f"{dt:.1f} s; value = 1 / (seconds per row x N)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=12)
+    ap.add_argument("--no-forms", action="store_true", help="skip the fp32-refinement comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0704_0037_amd import dda, inputs
+
+    w = inputs.c2_sphere256()
+    n = w.grid[0]
+    ctx = dda.Context(w.mask, w.m, w.kd, fp32=True)
+    L = ctx.padded_grid()[0]
+    N = ctx.n
+    beams = [inputs.X_POL, inputs.Y_POL]
+    theta = np.radians(np.arange(0.0, 180.0 + 1e-9, 0.5))
+
+    # ---- per-kernel timing of the product (HIP events on the context's stream)
+    x = torch.from_numpy(inputs.random_vector(N, seed=1)).cuda()
+    y = torch.empty_like(x)
+    kms, tot_ms = ctx.matvec_timed(inputs.X_POL, x, y, reps=10)
+    ab = alg_bytes(n, N, L, 16)
+    per_kernel = {k: {"ms": kms[i], "alg_GB": ab[k] / 1e9, "GBps": ab[k] / kms[i] / 1e6,
+                      "frac": ab[k] / kms[i] / 1e6 / HBM_PEAK_GBS} for i, k in enumerate(KERNELS)}
+    dom = max(KERNELS, key=lambda k: per_kernel[k]["ms"])
+    B_mv = sum(ab.values())
+    del x, y
+
+    # ---- steps: the whole hot path
+    def step():
+        xs, info, st = ctx.solve(beams, tol=w.tol)
+        cs = [ctx.cross_sections(b, xs[i].contiguous()) for i, b in enumerate(beams)]
+        M = ctx.mueller(inputs.X_POL, xs[0].contiguous(), xs[1].contiguous(), 0.0, theta)
+        return xs, info, cs, M
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mv = 0
+    iters = []
+    for _ in range(args.steps):
+        xs, info, cs, M = step()
+        mv += sum(i["matvecs"] for i in info)
+        iters = [i["iters"] for i in info]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / args.steps * 1e3
+    res_true = max(i["res_true"] for i in info)
+
+    out = {
+        "metric": "matvecs/s + time-to-1e-5-residual per solve (plain FP64 vs chosen form), 1 GPU",
+        "value": mv / dt,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sphere256_x40_m1.05: 256^3 sphere, x=40, m=1.05, LDR, +z incidence, "
+                               "x and y polarizations, QMR to 1e-5, Cext/Cabs, Mueller at 361 angles",
+                   "grid": n, "padded_grid": L, "n_dipoles": N, "kd": w.kd, "rhs": 2, "tol": w.tol,
+                   "solver": "qmr", "precision": "fp64"},
+        "time_to_tol_s_per_solve": dt / args.steps / len(beams),
+        "iterations": iters,
+        "res_true": res_true,
+        "Cext": [c[0] for c in cs],
+        "matvec_ms": tot_ms,
+        "matvec_only_per_s": 1e3 / tot_ms,
+        "matvec_roofline": {"bound": "hbm", "alg_GB": B_mv / 1e9, "achieved": B_mv / tot_ms / 1e6,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": B_mv / tot_ms / 1e6 / HBM_PEAK_GBS},
+        "kernels": per_kernel,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_kernel[dom]["GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": per_kernel[dom]["frac"], "traffic": None},
+    }
+
+    if not args.no_forms:
+        # chosen form: single-precision inner QMR with double-precision refinement
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x32, i32, st = ctx.solve(beams, tol=w.tol, precision=dda.FP32_REFINE)
+        torch.cuda.synchronize()
+        d32 = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        x64, i64, st = ctx.solve(beams, tol=w.tol)
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - t1
+        c64 = [ctx.cross_sections(b, x64[i].contiguous()) for i, b in enumerate(beams)]
+        c32 = [ctx.cross_sections(b, x32[i].contiguous()) for i, b in enumerate(beams)]
+        M64 = ctx.mueller(inputs.X_POL, x64[0].contiguous(), x64[1].contiguous(), 0.0, theta)
+        M32 = ctx.mueller(inputs.X_POL, x32[0].contiguous(), x32[1].contiguous(), 0.0, theta)
+        out["forms"] = {"fp32_refine": {
+            "time_to_tol_s_per_solve": d32 / len(beams), "fp64_time_to_tol_s_per_solve": d64 / len(beams),
+            "speedup_vs_fp64": d64 / d32, "inner_iterations": [i["iters"] for i in i32],
+            "outer": [i["outer"] for i in i32], "res_true": max(i["res_true"] for i in i32),
+            "rel_err_Cext": max(abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(c32, c64)),
+            "rel_err_S11_max": float(np.max(np.abs(M32[:, 0, 0] / M64[:, 0, 0] - 1)))}}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,47 @@ dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
     return matvec_common(ctx, beams, n_rhs, x, y, false);
 }
 
+dda_status dda_matvec_timed(dda_ctx *h, const dda_beam *beam, const void *x, void *y, int32_t reps,
+                            float kernel_ms[5], float *total_ms) {
+    Ctx *ctx = cx(h);
+    if (!ctx || !beam || !x || !y || reps < 1 || !kernel_ms || !total_ms || x == y || !beam_ok(beam)) {
+        set_error("dda_matvec_timed: bad argument");
+        return DDA_EINVAL;
+    }
+    double ar, ai;
+    polarizability(*ctx, *beam, ar, ai);
+    // first call uploads the scale and settles the work buffers
+    dda_status st = matvec_launch<double>(*ctx, (const double2 *)x, (double2 *)y, 1, &ar, &ai, false, ctx->stream);
+    if (st != DDA_OK) return st;
+    hipEvent_t ev[6];
+    for (int i = 0; i < 6; ++i) DDA_HIP_CHECK(hipEventCreate(&ev[i]));
+    double acc[5] = {0, 0, 0, 0, 0}, tot = 0;
+    for (int r = 0; r < reps && st == DDA_OK; ++r) {
+        st = matvec_device<double>(*ctx, (const double2 *)x, (double2 *)y, 1, ctx->w64.scale, nullptr, ctx->stream,
+                                   nullptr, ev);
+        if (st != DDA_OK) break;
+        hipError_t e = hipEventSynchronize(ev[5]);
+        if (e != hipSuccess) {
+            set_error(std::string("dda_matvec_timed: ") + hipGetErrorString(e));
+            st = DDA_EHIP;
+            break;
+        }
+        for (int k = 0; k < 5; ++k) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            acc[k] += ms;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[5]);
+        tot += ms;
+    }
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    if (st != DDA_OK) return st;
+    for (int k = 0; k < 5; ++k) kernel_ms[k] = (float)(acc[k] / reps);
+    *total_ms = (float)(tot / reps);
+    return DDA_OK;
+}
+
 const char *dda_strerror(dda_status s) {
     switch (s) {
         case DDA_OK: return "ok";

@@ -72,7 +72,7 @@ template <typename R> dda_status ensure_work(Ctx &c, int nrhs);
 // receives per-block bilinear partial sums x.y; done (nullable) skips converged right-hand sides.
 template <typename R>
 dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
-                         hipStream_t s, const int *done);
+                         hipStream_t s, const int *done, hipEvent_t *ev = nullptr);
 
 // number of per-block dot partials the x-inverse kernel writes per right-hand side
 inline size_t dots_per_rhs(const Ctx &c) { return (size_t)3 * c.nz * ((c.ny + c.nl_x - 1) / c.nl_x); }

@@ -279,7 +279,7 @@ template <> const float2 *ghat_of<float>(const Ctx &c) { return c.ghat32; }
 
 template <typename R>
 dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
-                         hipStream_t s, const int *done) {
+                         hipStream_t s, const int *done, hipEvent_t *ev) {
     using C = cplx<R>;
     Work<R> &w = work_of<R>(c);
     const C *tw = tw_of<R>(c);
@@ -291,10 +291,13 @@ dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const c
     const size_t ly_bytes = (size_t)nly * lds_line_stride(c.Ly) * sizeof(C);
     const size_t lz_bytes = (size_t)ncz * 3 * lds_line_stride(c.Lz) * sizeof(C);
     const int N = (int)c.N;
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL(k_fwd_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, x, w.B1,
                        c.nx, c.ny, c.nz, N, c.pxf, tw, nlx, done);
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[1], s));
     hipLaunchKernelGGL(k_fwd_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyf.tpl), ly_bytes, s, w.B1, w.B2, c.ny,
                        c.nz, c.Lx, ncomp, c.pyf, tw, nly, done);
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[2], s));
     {
         const int slots = 4 * (c.Lx / 2 + 1) * (c.Ly / 2 + 1) * nrhs;
         const int nb = (slots + ncz - 1) / ncz;
@@ -302,17 +305,20 @@ dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const c
         hipLaunchKernelGGL(k_zmul<R>, dim3(nb8), dim3(ncz * 3 * c.pzf.tpl), lz_bytes, s, w.B2, gh, c.nz, c.Lx, c.Ly,
                            nrhs, c.pzf, c.pzi, tw, ncz, nb, done);
     }
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[3], s));
     hipLaunchKernelGGL(k_inv_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyi.tpl), ly_bytes, s, w.B2, w.B1, c.ny,
                        c.nz, c.Lx, ncomp, c.pyi, tw, nly, done);
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[4], s));
     hipLaunchKernelGGL(k_inv_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, w.B1, x,
                        y, c.nx, c.ny, c.nz, N, c.pxi, tw, nlx, scale, dots, done);
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[5], s));
     DDA_HIP_CHECK(hipGetLastError());
     return DDA_OK;
 }
 template dda_status matvec_device<double>(Ctx &, const double2 *, double2 *, int, const double2 *, double2 *,
-                                          hipStream_t, const int *);
+                                          hipStream_t, const int *, hipEvent_t *);
 template dda_status matvec_device<float>(Ctx &, const float2 *, float2 *, int, const float2 *, float2 *, hipStream_t,
-                                         const int *);
+                                         const int *, hipEvent_t *);
 
 template <typename R>
 dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const double *are, const double *aim,
@@ -325,7 +331,7 @@ dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const d
     for (int r = 0; r < nrhs; ++r) sc[r] = mk<cplx<R>>((R)(are[r] * inv), (R)(aim[r] * inv));
     DDA_HIP_CHECK(hipMemcpyAsync(w.scale, sc.data(), nrhs * sizeof(cplx<R>), hipMemcpyHostToDevice, s));
     DDA_HIP_CHECK(hipStreamSynchronize(s));  // the host staging vector goes out of scope
-    return matvec_device<R>(c, x, y, nrhs, w.scale, want_dots ? w.dots : nullptr, s, nullptr);
+    return matvec_device<R>(c, x, y, nrhs, w.scale, want_dots ? w.dots : nullptr, s, nullptr, nullptr);
 }
 template dda_status matvec_launch<double>(Ctx &, const double2 *, double2 *, int, const double *, const double *, bool,
                                           hipStream_t);

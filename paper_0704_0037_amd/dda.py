@@ -68,6 +68,8 @@ _SIGS = {
                                 ct.POINTER(ct.c_double)]),
     "dda_mueller": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p, ct.c_double,
                                ct.POINTER(ct.c_double), ct.c_int32, ct.POINTER(ct.c_double)]),
+    "dda_matvec_timed": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p, ct.c_int32,
+                                    ct.POINTER(ct.c_float), ct.POINTER(ct.c_float)]),
     "dda_strerror": (ct.c_char_p, [ct.c_int]),
     "dda_last_error": (ct.c_char_p, []),
 }
@@ -218,6 +220,15 @@ class Context:
         _check(lib().dda_matvec_batch(self._h, _beams(beams), n, _ptr(x, torch.complex128, (n, 3, self.n), "x"),
                                       _ptr(y, torch.complex128, (n, 3, self.n), "y")), "dda_matvec_batch")
         return y
+
+    def matvec_timed(self, beam, x, y, reps):
+        """Mean per-kernel and whole-product durations (ms) of `reps` back-to-back products."""
+        k = (ct.c_float * 5)()
+        tot = ct.c_float()
+        _check(lib().dda_matvec_timed(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
+                                      _ptr(y, torch.complex128, (3, self.n), "y"), int(reps), k, ct.byref(tot)),
+               "dda_matvec_timed")
+        return list(k), tot.value
 
     def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
               x_out=None, history=0, raise_on_fail=True):
