@@ -5,7 +5,7 @@
 #include <numeric>
 #include <vector>
 
-#include "../../include/dda.h"
+#include "dda.h"
 #include "fft.hpp"
 
 namespace dda {
@@ -28,6 +28,7 @@ struct Ctx {
     int polarizability = DDA_POL_LDR;
     hipStream_t stream = nullptr;
     int nl_x = 0, nl_y = 0, nc_z = 0;  // lines per block (x, y passes) and columns per block (z pass)
+    int lnl_x = 0, lnl_y = 0;          // log2 of nl_x, nl_y (powers of two)
 
     std::vector<uint8_t> mask;      // host copy [nz][ny][nx]
     std::vector<int32_t> lin_host;  // linear cell index of each dipole
@@ -73,6 +74,12 @@ template <typename R> dda_status ensure_work(Ctx &c, int nrhs);
 template <typename R>
 dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
                          hipStream_t s, const int *done, hipEvent_t *ev = nullptr);
+template <>
+dda_status matvec_device<double>(Ctx &c, const double2 *x, double2 *y, int nrhs, const double2 *scale, double2 *dots,
+                                 hipStream_t s, const int *done, hipEvent_t *ev);
+template <>
+dda_status matvec_device<float>(Ctx &c, const float2 *x, float2 *y, int nrhs, const float2 *scale, float2 *dots,
+                                hipStream_t s, const int *done, hipEvent_t *ev);
 
 // number of per-block dot partials the x-inverse kernel writes per right-hand side
 inline size_t dots_per_rhs(const Ctx &c) { return (size_t)3 * c.nz * ((c.ny + c.nl_x - 1) / c.nl_x); }

@@ -11,23 +11,97 @@
 // DIR = -1 is the forward transform exp(-2 pi i jk/L), DIR = +1 the unnormalized inverse.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace dda {
 
 constexpr int kMaxPass = 12;
 #ifndef DDA_MAX_THREADS
-#define DDA_MAX_THREADS 256
+#define DDA_MAX_THREADS 512   // block-size bound of the x / y pass kernels
+#endif
+#ifndef DDA_ZMUL_SLOTS
+#define DDA_ZMUL_SLOTS 4      // mirror columns per z-pass block (1, 2 or 4)
+#endif
+#ifndef DDA_ZMUL_THREADS
+#define DDA_ZMUL_THREADS 768  // block-size bound of the fused z-pass kernel
+#endif
+#ifndef DDA_LDS_CAP
+#define DDA_LDS_CAP (96 * 1024)  // LDS bytes a matvec block may take
 #endif
 
 struct FftPlan {
     int L;                   // transform length
-    int npass;               // number of passes (1 for L = 1, which uses radix 1)
+    int npass;               // number of passes (1 for L = 1, which uses radix 1); 0 = length not supported
     int tpl;                 // threads per line = L / smallest radix
     int tw_off;              // offset of the table exp(-2 pi i m / L), m < L, in the twiddle buffer
     int radix[kMaxPass];
     int ns[kMaxPass];        // product of the radices of the preceding passes
 };
+
+// Radix schedule for length L (5-smooth): 8s first, the leftover power of two as 16 (or 4*4 when
+// maxr = 8), 4 or 2, then 5s and 3s; reversed for the inverse of a pass pair whose middle stays in
+// registers.  Larger radices mean fewer passes over LDS.  Used on the host to plan and on the
+// device to specialize kernels for a length known at compile time.
+__host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
+    FftPlan p{};
+    int r[kMaxPass] = {};
+    int n = 0;
+    if (L == 1) {
+        r[n++] = 1;
+    } else {
+        int rem = L, p2 = 0, n3 = 0, n5 = 0;
+        while (rem > 1 && rem % 2 == 0) rem /= 2, ++p2;
+        while (rem > 1 && rem % 5 == 0) rem /= 5, ++n5;
+        while (rem > 1 && rem % 3 == 0) rem /= 3, ++n3;
+        if (rem != 1 || L < 1) return p;  // npass = 0: unsupported
+        const int n8 = p2 / 3, left = p2 % 3;
+        if (n8 + 2 + n3 + n5 > kMaxPass) return p;
+        for (int i = 0; i < n8; ++i) r[n++] = 8;
+        if (left == 1) {
+            if (n8 > 0 && maxr >= 16) r[n - 1] = 16;
+            else if (n8 > 0) { r[n - 1] = 4; r[n++] = 4; }
+            else r[n++] = 2;
+        } else if (left == 2) {
+            r[n++] = 4;
+        }
+        for (int i = 0; i < n5; ++i) r[n++] = 5;
+        for (int i = 0; i < n3; ++i) r[n++] = 3;
+    }
+    if (reverse)
+        for (int i = 0; i < n / 2; ++i) {
+            const int t = r[i];
+            r[i] = r[n - 1 - i];
+            r[n - 1 - i] = t;
+        }
+    int ns = 1, rmin = 1 << 30;
+    for (int i = 0; i < n; ++i) {
+        p.radix[i] = r[i];
+        p.ns[i] = ns;
+        ns *= r[i];
+        rmin = rmin < r[i] ? rmin : r[i];
+    }
+    p.L = L;
+    p.npass = n;
+    p.tpl = L / rmin;
+    return p;
+}
+
+// The plan a kernel uses: the compile-time plan for LC > 0 (all indices fold to constants), else
+// the runtime plan passed as an argument.  tw_off always comes from the runtime plan.
+template <int LC, int MAXR, bool REV>
+__device__ __forceinline__ FftPlan plan_of(const FftPlan &rt) {
+    if constexpr (LC > 0) {
+        constexpr FftPlan P = make_plan(LC, MAXR, REV);  // evaluated by the compiler
+        static_assert(P.npass > 0, "unsupported specialized length");
+        FftPlan p = P;
+        p.tw_off = rt.tw_off;
+        return p;
+    } else {
+        return rt;
+    }
+}
 
 // LDS element index with one element of skew every 8, so radix-8 butterflies writing with a
 // stride of 8 elements do not all land in the same banks.
@@ -143,7 +217,8 @@ template <int DIR, typename C> __device__ __forceinline__ void dft16(C *a) {
 }
 
 template <int DIR, int RADIX, typename C> __device__ __forceinline__ void dftR(C *a) {
-    if constexpr (RADIX == 2) dft2<DIR>(a);
+    if constexpr (RADIX == 1) (void)a;
+    else if constexpr (RADIX == 2) dft2<DIR>(a);
     else if constexpr (RADIX == 3) dft3<DIR>(a);
     else if constexpr (RADIX == 4) dft4<DIR>(a);
     else if constexpr (RADIX == 5) dft5<DIR>(a);
@@ -233,20 +308,73 @@ __device__ __forceinline__ void store_rt(const C *a, int R, int j, int Ns, ST st
     }
 }
 
-// Passes [p0, p1) in place on the LDS line `ln` (stride-skewed).  Every thread of the block
-// must call this (it contains barriers); `active_line` = false threads only take part in them.
-template <int DIR, int MAXR, typename C>
-__device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
-                                           const C *__restrict__ tw) {
-    for (int p = p0; p < p1; ++p) {
-        const int R = pl.radix[p], Ns = pl.ns[p];
-        const bool act = j < pl.L / R;
-        C a[MAXR];
-        if (act) load_rt<DIR, MAXR>(a, R, j, pl.L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-        __syncthreads();
-        if (act) store_rt<MAXR>(a, R, j, Ns, [&](int i, C v) { ln[pidx(i)] = v; });
+template <int B, int E, class F> __device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Ordering point between the read and write phases of an in-place LDS pass.  When every line
+// lives inside one wavefront (WAVE), only that wave's lanes exchange data; LDS instructions of a
+// wave complete in order, so a compiler barrier suffices.  Otherwise the whole block syncs.
+template <bool WAVE> __device__ __forceinline__ void lds_sync() {
+    if constexpr (WAVE) {
+        __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        __asm__ volatile("" ::: "memory");
+    } else {
         __syncthreads();
     }
+}
+
+// lines of a compile-time plan fit in one wavefront when its threads-per-line divides 64
+template <int LC, int MAXR> __host__ __device__ constexpr bool wave_lines() {
+    if constexpr (LC > 0) return 64 % make_plan(LC, MAXR, false).tpl == 0;
+    else return false;
+}
+
+// Passes [p0, p1) in place on the LDS line `ln` (stride-skewed).  Every thread of the block
+// must call this (it may contain barriers).  LC > 0 selects the plan make_plan(LC, MAXR, REV)
+// known at compile time: passes are then unrolled with constant radices and strides, and when a
+// line fits in a wave the passes sync only that wave; LC = 0 runs the runtime plan `pl`.
+template <int DIR, int MAXR, int LC, bool REV, typename C>
+__device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
+                                           const C *__restrict__ tw) {
+    auto ld = [&](int i) { return ln[pidx(i)]; };
+    auto st = [&](int i, C v) { ln[pidx(i)] = v; };
+    if constexpr (LC > 0) {
+        constexpr FftPlan P = make_plan(LC, MAXR, REV);
+        constexpr bool W = wave_lines<LC, MAXR>();
+        static_for<1, P.npass>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int R = P.radix[p], Ns = P.ns[p];
+            if (p >= p0 && p < p1) {
+                const bool act = j < LC / R;
+                C a[R];
+                if (act) bfly_load<DIR, R>(a, j, LC, Ns, tw, ld);
+                lds_sync<W>();
+                if (act) bfly_store<R>(a, j, Ns, st);
+                lds_sync<W>();
+            }
+        });
+    } else {
+        for (int p = p0; p < p1; ++p) {
+            const int R = pl.radix[p], Ns = pl.ns[p];
+            const bool act = j < pl.L / R;
+            C a[MAXR];
+            if (act) load_rt<DIR, MAXR>(a, R, j, pl.L, Ns, tw, ld);
+            __syncthreads();
+            if (act) store_rt<MAXR>(a, R, j, Ns, st);
+            __syncthreads();
+        }
+    }
+}
+
+// compile-time pass count of the specialized plan (0 for the runtime plan)
+template <int LC, int MAXR> __host__ __device__ constexpr int npass_of() {
+    if constexpr (LC > 0) return make_plan(LC, MAXR, false).npass;
+    else return 0;
 }
 
 }  // namespace dda

@@ -12,7 +12,8 @@
 //   gmap                     [nz][ny][nx] int32: dipole index or -1 (void)
 //   B1 (after x pass)        [c][nz][Lx][ny]              y fastest
 //   B2 (after y pass)        [Ly][Lx][c][nz]              z fastest: a (kx, ky) column is contiguous
-//   Ghat octant              [Ly/2+1][Lx/2+1][Lz/2+1][6]  components xx, xy, xz, yy, yz, zz
+//   Ghat octant              [Ly/2+1][Lx/2+1][6][Lz/2+1]  components xx, xy, xz, yy, yz, zz; a column's
+//                            six kz-runs are contiguous so a wave's tensor loads are unit-stride
 #pragma once
 
 #include <type_traits>
@@ -24,38 +25,23 @@ namespace dda {
 constexpr int kMaxRadix = 8;    // x and y passes (radix 16 costs more registers than it saves passes)
 constexpr int kMaxRadixZ = 8;   // the fused z pass keeps three components in registers
 
-// component signs under k -> L - k along each axis: xy, xz flip with x; xy, yz with y; xz, yz with z
-__device__ __forceinline__ void ghat_load(const double2 *g, double2 *G, double sxy, double sxz, double syz) {
-    G[0] = g[0];
-    G[1] = cscale(g[1], sxy);
-    G[2] = cscale(g[2], sxz);
-    G[3] = g[3];
-    G[4] = cscale(g[4], syz);
-    G[5] = g[5];
-}
-__device__ __forceinline__ void ghat_load(const float2 *g, float2 *G, float sxy, float sxz, float syz) {
-    G[0] = g[0];
-    G[1] = cscale(g[1], sxy);
-    G[2] = cscale(g[2], sxz);
-    G[3] = g[3];
-    G[4] = cscale(g[4], syz);
-    G[5] = g[5];
-}
-
 // ---------------------------------------------------------------- K1: forward x pass
 // Block: component c, plane z, NL consecutive lines y.  Gathers x from the compact vector
 // (zero for void cells and for the padding), transforms along x, writes B1[c][z][kx][y].
-template <typename R>
+template <typename R, int LC>
 __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ x,
                                                 cplx<R> *__restrict__ B1, int nx, int ny, int nz, int N,
-                                                FftPlan pl, const cplx<R> *__restrict__ twall, int NL,
+                                                FftPlan pl_rt, const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
     using C = cplx<R>;
+    const FftPlan pl = plan_of<LC, kMaxRadix, false>(pl_rt);
+    const int NL = 1 << lnl;
+    const int NP = pl.npass, R0 = pl.radix[0], RL = pl.radix[NP - 1], NSL = pl.ns[NP - 1];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
-    const C *tw = twall + pl.tw_off;
+    const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
-    const int ytiles = (ny + NL - 1) / NL;
+    const int ytiles = (ny + NL - 1) >> lnl;
     int b = blockIdx.x;
     const int y0 = (b % ytiles) * NL;
     b /= ytiles;
@@ -66,7 +52,6 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict
     const C *xc = x + (size_t)c * N;
     {   // pass 0 from global, lines along lanes' j (x contiguous)
         const int line = t / TPL, j = t % TPL, y = y0 + line;
-        const int R0 = pl.radix[0];
         if (j < L / R0) {
             const int *grow = gmap + ((size_t)z * ny + (y < ny ? y : 0)) * nx;
             const bool yok = y < ny;
@@ -82,12 +67,14 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict
             store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
     }
-    __syncthreads();
-    lds_passes<-1, kMaxRadix>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
+    constexpr bool W = wave_lines<LC, kMaxRadix>();
+    lds_sync<W>();
+    lds_passes<-1, kMaxRadix, LC, false>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
+    if constexpr (W) __syncthreads();  // the store mapping below crosses waves
     C *dstc = B1 + ((size_t)c * nz + z) * (size_t)L * ny;
-    if (pl.npass >= 2) {  // last pass to global, lanes over lines (y contiguous in B1)
-        const int line = t % NL, j = t / NL, y = y0 + line;
-        const int p = pl.npass - 1, Rp = pl.radix[p], Ns = pl.ns[p];
+    if (NP >= 2) {  // last pass to global, lanes over lines (y contiguous in B1)
+        const int line = t & (NL - 1), j = t >> lnl, y = y0 + line;
+        const int Rp = RL, Ns = NSL;
         if (j < L / Rp) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;
@@ -96,7 +83,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict
         }
     } else {
         for (int e = t; e < NL * L; e += blockDim.x) {
-            const int line = e % NL, i = e / NL, y = y0 + line;
+            const int line = e & (NL - 1), i = e >> lnl, y = y0 + line;
             if (y < ny) dstc[(size_t)i * ny + y] = lds[line * S + pidx(i)];
         }
     }
@@ -105,17 +92,20 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict
 // ---------------------------------------------------------------- K2: forward y pass
 // Block: component c, column kx, NL consecutive planes z.  Reads B1 lines along y (n_y
 // nonzero entries), transforms, writes B2[ky][kx][c][z].
-template <typename R>
+template <typename R, int LC>
 __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__restrict__ B1, cplx<R> *__restrict__ B2, int ny,
-                                                int nz, int Lx, int ncomp, FftPlan pl,
-                                                const cplx<R> *__restrict__ twall, int NL,
+                                                int nz, int Lx, int ncomp, FftPlan pl_rt,
+                                                const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
     using C = cplx<R>;
+    const FftPlan pl = plan_of<LC, kMaxRadix, false>(pl_rt);
+    const int NL = 1 << lnl;
+    const int NP = pl.npass, R0 = pl.radix[0], RL = pl.radix[NP - 1], NSL = pl.ns[NP - 1];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
-    const C *tw = twall + pl.tw_off;
+    const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
-    const int ztiles = (nz + NL - 1) / NL;
+    const int ztiles = (nz + NL - 1) >> lnl;
     int b = blockIdx.x;
     const int z0 = (b % ztiles) * NL;
     b /= ztiles;
@@ -125,7 +115,6 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__rest
     const int t = threadIdx.x;
     {
         const int line = t / TPL, j = t % TPL, z = z0 + line;
-        const int R0 = pl.radix[0];
         if (j < L / R0) {
             const bool zok = z < nz;
             const C *src = B1 + (((size_t)c * nz + (zok ? z : 0)) * Lx + kx) * ny;
@@ -136,13 +125,15 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__rest
             store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
     }
-    __syncthreads();
-    lds_passes<-1, kMaxRadix>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
+    constexpr bool W = wave_lines<LC, kMaxRadix>();
+    lds_sync<W>();
+    lds_passes<-1, kMaxRadix, LC, false>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
+    if constexpr (W) __syncthreads();  // the store mapping below crosses waves
     const size_t kystride = (size_t)Lx * ncomp * nz;
     C *dst = B2 + ((size_t)kx * ncomp + c) * nz;
-    if (pl.npass >= 2) {
-        const int line = t % NL, j = t / NL, z = z0 + line;
-        const int p = pl.npass - 1, Rp = pl.radix[p], Ns = pl.ns[p];
+    if (NP >= 2) {
+        const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
+        const int Rp = RL, Ns = NSL;
         if (j < L / Rp) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;
@@ -151,149 +142,149 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__rest
         }
     } else {
         for (int e = t; e < NL * L; e += blockDim.x) {
-            const int line = e % NL, i = e / NL, z = z0 + line;
+            const int line = e & (NL - 1), i = e >> lnl, z = z0 + line;
             if (z < nz) dst[(size_t)i * kystride + z] = lds[line * S + pidx(i)];
         }
     }
 }
 
 // ------------------------------------------------- K3: forward z, tensor multiply, inverse z
-// A block takes NC columns (kx, ky); within a column, thread (comp, j) owns butterfly j of the
-// line of one component (one wave per line at L = 512).  After the forward passes the three
-// transformed lines sit in LDS in natural order; each thread then forms component `comp` of
-// Ghat(k) X(k) at the frequencies k = j + r L/R0 that the first inverse pass (radix R0, the
-// forward plan reversed) needs from it, straight into registers.
+// The (up to) four columns (kx, ky) with kx in {kxo, Lx - kxo}, ky in {kyo, Ly - kyo} share one
+// octant column (kxo, kyo) of the tensor.  A block takes DDA_ZMUL_SLOTS of them (one right-hand
+// side), stages the octant column's six kz-runs in LDS and processes its columns side by side.
 //
-// Work is visited in "slots": slot = (4 * octant_column + mirror) * nrhs + rhs, so the (up to)
-// four columns that share one octant column of the tensor, for every right-hand side of a batch,
-// are neighbours; logical blocks are dealt out so that each XCD walks a contiguous range of them
-// (its L2 then serves the repeated tensor reads).
-template <typename R>
-__device__ __forceinline__ void slot_column(int slot, int Lx, int Ly, int &kx, int &ky, int &kxo, int &kyo, bool &ok) {
-    const int hx1 = Lx / 2 + 1, hy1 = Ly / 2 + 1;
-    const int m = slot & 3, o = slot >> 2;
-    kxo = o % hx1;
-    kyo = o / hx1;
-    ok = kyo < hy1;
-    const bool mx = m & 1, my = m & 2;
-    if (mx && (kxo == 0 || 2 * kxo == Lx)) ok = false;  // x mirror coincides with the column itself
-    if (my && (kyo == 0 || 2 * kyo == Ly)) ok = false;
-    kx = mx ? Lx - kxo : kxo;
-    ky = my ? Ly - kyo : kyo;
-    if (!ok) kx = ky = kxo = kyo = 0;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_zmul(cplx<R> *__restrict__ B2, const cplx<R> *__restrict__ Gh, int nz,
-                                              int Lx, int Ly, int nrhs, FftPlan pf, FftPlan pi,
-                                              const cplx<R> *__restrict__ twall, int NC, int nblocks,
-                                              const int *__restrict__ done) {
+// Within a column, thread (comp, j) owns butterfly j of the line of one component (one wave per
+// line at L = 512).  After the forward passes the three transformed lines sit in LDS in natural
+// order; each thread then forms component `comp` of Ghat(k) X(k) at the frequencies k = j + r L/R0
+// that the first inverse pass (radix R0, the forward plan reversed) needs from it, straight into
+// registers.
+template <typename R, int LC>
+__global__ void __launch_bounds__(DDA_ZMUL_THREADS) k_zmul(cplx<R> *__restrict__ B2, const cplx<R> *__restrict__ Gh,
+                                                          int nz, int Lx, int Ly, int nrhs, FftPlan pf_rt,
+                                                          FftPlan pi_rt, const cplx<R> *__restrict__ twall,
+                                                          const int *__restrict__ done) {
     using C = cplx<R>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *lds = reinterpret_cast<C *>(smem_raw);
-    // XCD-aware logical block: consecutive logical blocks on the same XCD
-    const int per_xcd = gridDim.x / 8;
-    const int lb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (lb >= nblocks) return;
-    const C *tw = twall + pf.tw_off;
+    const FftPlan pf = plan_of<LC, kMaxRadixZ, false>(pf_rt);
+    const FftPlan pi = plan_of<LC, kMaxRadixZ, true>(pi_rt);
+    const int NPZ = pf.npass, RQ = pi.radix[NPZ - 1], NQ = pi.ns[NPZ - 1];
     const int L = pf.L, TPL = pf.tpl, S = lds_line_stride(L);
-    const int t = threadIdx.x;
-    const int col = t / (3 * TPL), comp = (t / TPL) % 3, j = t % TPL;
-    const int slot = lb * NC + col;
-    const int rhs = slot % nrhs;
-    // blocks hold whole columns of one right-hand side only when NC == 1; with NC > 1 a done
-    // right-hand side still runs (harmless: its buffers are not read afterwards)
-    if (done && NC == 1 && done[rhs]) return;
-    int kx, ky, kxo, kyo;
-    bool ok;
-    slot_column<R>(slot / nrhs, Lx, Ly, kx, ky, kxo, kyo, ok);
-    const int hx = Lx / 2, hy = Ly / 2, hz = L / 2;
-    const R sx = kx <= hx ? (R)1 : (R)-1, sy = ky <= hy ? (R)1 : (R)-1;
-    // tensor row `comp`: components (xx,xy,xz), (xy,yy,yz), (xz,yz,zz) and their mirror signs
-    const int g0 = comp == 0 ? 0 : comp == 1 ? 1 : 2;
-    const int g1 = comp == 0 ? 1 : comp == 1 ? 3 : 4;
-    const int g2 = comp == 0 ? 2 : comp == 1 ? 4 : 5;
-    const C *gcol = Gh + ((size_t)kyo * (hx + 1) + kxo) * (size_t)(hz + 1) * 6;
-    C *lcol = lds + (size_t)col * 3 * S;
-    C *ln = lcol + comp * S;
-    const int ncomp = 3 * nrhs;
     const int np = pf.npass;
     const int R0 = pf.radix[0];
     const int Ri = pi.radix[0];  // == pf.radix[np - 1]
     const int qi = L / Ri;
+    const int rhs = blockIdx.y;
+    if (done && done[rhs]) return;  // this right-hand side has converged
+    // XCD-aware block order: consecutive logical blocks (the groups of one octant column) run on
+    // the same XCD, whose L2 then serves the repeated reads of the tensor column
+    const int per_xcd = gridDim.x / 8;
+    const int lb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int ngroups = 4 / DDA_ZMUL_SLOTS;
+    const int oct = lb / ngroups;
+    const int hx = Lx / 2, hy = Ly / 2, hz = L / 2, hz1 = hz + 1;
+    if (oct >= (hx + 1) * (hy + 1)) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const C *tw = twall + pf_rt.tw_off;
+    const int t = threadIdx.x;
+    const int lslot = t / (3 * TPL), comp = (t / TPL) % 3, j = t % TPL;
+    const int slot = (lb % ngroups) * DDA_ZMUL_SLOTS + lslot;  // mirror 0..3 of the octant column
+    const int kxo = oct % (hx + 1), kyo = oct / (hx + 1);
+    const int nmx = (kxo == 0 || 2 * kxo == Lx) ? 1 : 2;  // distinct x mirrors of this column
+    const int nmy = (kyo == 0 || 2 * kyo == Ly) ? 1 : 2;
+    const bool mxs = slot & 1, mys = slot & 2;
+    const bool ok = (!mxs || nmx == 2) && (!mys || nmy == 2);  // slot holds a distinct column
+    const int kx = mxs ? Lx - kxo : kxo, ky = mys ? Ly - kyo : kyo;
+    C *gsh = lds;                            // [6][hz1] tensor runs of this octant column
+    C *lcol = lds + 6 * hz1 + lslot * 3 * S;  // [3][S] the three component lines of this slot
+    C *ln = lcol + comp * S;
     {
-        C *line = B2 + (((size_t)ky * Lx + kx) * ncomp + rhs * 3 + comp) * nz;
-        if (j < L / R0) {
-            C a[kMaxRadixZ];
-            load_rt<-1, kMaxRadixZ>(a, R0, j, L, 1, tw, [&](int i) -> C { return (ok && i < nz) ? line[i] : czero<C>(); });
-            store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
-        }
-        __syncthreads();
-        lds_passes<-1, kMaxRadixZ>(ln, pf, 1, np, j, tw);  // natural order in LDS afterwards
+        const C *gcol = Gh + (size_t)oct * 6 * hz1;
+        for (int e = t; e < 6 * hz1; e += blockDim.x) gsh[e] = gcol[e];
+    }
+    C *line = B2 + (((size_t)(ok ? ky : 0) * Lx + (ok ? kx : 0)) * (3 * nrhs) + rhs * 3 + comp) * nz;
+    if (j < L / R0) {
         C a[kMaxRadixZ];
-        const bool act = j < qi;
-        if (act) {
-            // G[comp][d] for d = x, y, z: tensor components and their signs under the mirrors
-            const R s0 = comp == 0 ? (R)1 : comp == 1 ? sx * sy : sx;
-            const R s1 = comp == 0 ? sx * sy : comp == 1 ? (R)1 : sy;
-            const R s2 = comp == 0 ? sx : comp == 1 ? sy : (R)1;
-            auto mul = [&](auto radix_tag) {
-                constexpr int RI = decltype(radix_tag)::value;
+        load_rt<-1, kMaxRadixZ>(a, R0, j, L, 1, tw, [&](int i) -> C { return (ok && i < nz) ? line[i] : czero<C>(); });
+        store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+    }
+    constexpr bool W = wave_lines<LC, kMaxRadixZ>();
+    lds_sync<W>();
+    lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, tw);  // natural order in LDS afterwards
+    if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
+    C a[kMaxRadixZ];
+    const bool act = j < qi;
+    if (act) {
+        // G[comp][d] for d = x, y, z and their signs under the mirrors: a component is odd along an
+        // axis when exactly one of its indices is that axis; the z-odd ones (xz, yz) pick up sz
+        const R sx = mxs ? (R)-1 : (R)1, sy = mys ? (R)-1 : (R)1;
+        const R s0 = comp == 0 ? (R)1 : comp == 1 ? sx * sy : sx;
+        const R s1 = comp == 0 ? sx * sy : comp == 1 ? (R)1 : sy;
+        const R s2 = comp == 0 ? sx : comp == 1 ? sy : (R)1;
+        const int g0 = comp == 0 ? 0 : comp == 1 ? 1 : 2;  // row comp: (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
+        const int g1 = comp == 0 ? 1 : comp == 1 ? 3 : 4;
+        const int g2 = comp == 0 ? 2 : comp == 1 ? 4 : 5;
+        auto mul = [&](auto radix_tag) {
+            constexpr int RI = decltype(radix_tag)::value;
 #pragma unroll
-                for (int r = 0; r < RI; ++r) {
-                    const int kz = j + r * qi;
-                    const bool lo = kz <= hz;
-                    const R sz = lo ? (R)1 : (R)-1;
-                    const C *g = gcol + (size_t)(lo ? kz : L - kz) * 6;
-                    // the z-odd components (xz, yz) of row comp pick up sz; so does G[z][x], G[z][y]
-                    const C G0 = cscale(g[g0], comp == 2 ? s0 * sz : s0);
-                    const C G1 = cscale(g[g1], comp == 2 ? s1 * sz : s1);
-                    const C G2 = cscale(g[g2], comp == 2 ? s2 : s2 * sz);
-                    const int p = pidx(kz);
-                    const C X = lcol[p], Y = lcol[S + p], Z = lcol[2 * S + p];
-                    a[r] = cadd(cadd(cmul(G0, X), cmul(G1, Y)), cmul(G2, Z));
-                }
-                dftR<+1, RI>(a);
-            };
-            switch (Ri) {
-                case 1: mul(std::integral_constant<int, 1>{}); break;
-                case 2: mul(std::integral_constant<int, 2>{}); break;
-                case 3: mul(std::integral_constant<int, 3>{}); break;
-                case 4: mul(std::integral_constant<int, 4>{}); break;
-                case 5: mul(std::integral_constant<int, 5>{}); break;
-                default: mul(std::integral_constant<int, 8>{}); break;
+            for (int r = 0; r < RI; ++r) {
+                const int kz = j + r * qi;
+                const bool lo = kz <= hz;
+                const R sz = lo ? (R)1 : (R)-1;
+                const C *g = gsh + (lo ? kz : L - kz);
+                const C G0 = cscale(g[g0 * hz1], comp == 2 ? s0 * sz : s0);
+                const C G1 = cscale(g[g1 * hz1], comp == 2 ? s1 * sz : s1);
+                const C G2 = cscale(g[g2 * hz1], comp == 2 ? s2 : s2 * sz);
+                const int p = pidx(kz);
+                const C X = lcol[p], Y = lcol[S + p], Z = lcol[2 * S + p];
+                a[r] = cadd(cadd(cmul(G0, X), cmul(G1, Y)), cmul(G2, Z));
             }
-        }
-        __syncthreads();  // every thread has read the three transformed lines
-        if (np == 1) {
-            if (act && ok) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { if (i < nz) line[i] = v; });
-        } else {
-            if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
-            __syncthreads();
-            lds_passes<+1, kMaxRadixZ>(ln, pi, 1, np - 1, j, tw);
-            const int Rq = pi.radix[np - 1], Nq = pi.ns[np - 1];
-            if (j < L / Rq) {
-                load_rt<+1, kMaxRadixZ>(a, Rq, j, L, Nq, tw, [&](int i) { return ln[pidx(i)]; });
-                if (ok) store_rt<kMaxRadixZ>(a, Rq, j, Nq, [&](int i, C v) { if (i < nz) line[i] = v; });
-            }
+            dftR<+1, RI>(a);
+        };
+        switch (Ri) {
+            case 1: mul(std::integral_constant<int, 1>{}); break;
+            case 2: mul(std::integral_constant<int, 2>{}); break;
+            case 3: mul(std::integral_constant<int, 3>{}); break;
+            case 4: mul(std::integral_constant<int, 4>{}); break;
+            case 5: mul(std::integral_constant<int, 5>{}); break;
+            default: mul(std::integral_constant<int, 8>{}); break;
         }
     }
+    __syncthreads();  // every thread has read the three transformed lines
+    if (np == 1) {
+        if (act && ok) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { if (i < nz) line[i] = v; });
+        return;
+    }
+    if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+    lds_sync<W>();
+    lds_passes<+1, kMaxRadixZ, LC, true>(ln, pi_rt, 1, np - 1, j, tw);
+    if (j < L / RQ) {
+        load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, tw, [&](int i) { return ln[pidx(i)]; });
+        if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) line[i] = v; });
+    }
+}
+
+// LDS elements of the z-pass block: the tensor column and DDA_ZMUL_SLOTS slots of three lines
+__host__ __device__ constexpr size_t zmul_lds_elems(int Lz) {
+    return (size_t)6 * (Lz / 2 + 1) + (size_t)DDA_ZMUL_SLOTS * 3 * lds_line_stride(Lz);
 }
 
 // ---------------------------------------------------------------- K4: inverse y pass
 // Block: component c, column kx, NL consecutive planes z.  Reads B2 along ky (all Ly entries),
 // inverse transform, keeps y < ny, writes B1[c][z][kx][y].
-template <typename R>
+template <typename R, int LC>
 __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_y(const cplx<R> *__restrict__ B2, cplx<R> *__restrict__ B1, int ny,
-                                                int nz, int Lx, int ncomp, FftPlan pl,
-                                                const cplx<R> *__restrict__ twall, int NL,
+                                                int nz, int Lx, int ncomp, FftPlan pl_rt,
+                                                const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
     using C = cplx<R>;
+    const FftPlan pl = plan_of<LC, kMaxRadix, true>(pl_rt);
+    const int NL = 1 << lnl;
+    const int NP = pl.npass, R0 = pl.radix[0], RL = pl.radix[NP - 1], NSL = pl.ns[NP - 1];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
-    const C *tw = twall + pl.tw_off;
+    const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
-    const int ztiles = (nz + NL - 1) / NL;
+    const int ztiles = (nz + NL - 1) >> lnl;
     int b = blockIdx.x;
     const int z0 = (b % ztiles) * NL;
     b /= ztiles;
@@ -304,8 +295,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_y(const cplx<R> *__rest
     const size_t kystride = (size_t)Lx * ncomp * nz;
     const C *src = B2 + ((size_t)kx * ncomp + c) * nz;
     {   // pass 0 from global, lanes over lines (z contiguous in B2)
-        const int line = t % NL, j = t / NL, z = z0 + line;
-        const int R0 = pl.radix[0];
+        const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
         if (j < L / R0) {
             const bool zok = z < nz;
             C a[kMaxRadix];
@@ -316,11 +306,11 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_y(const cplx<R> *__rest
         }
     }
     __syncthreads();
-    lds_passes<+1, kMaxRadix>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
+    lds_passes<+1, kMaxRadix, LC, true>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
     const int line = t / TPL, j = t % TPL, z = z0 + line;
     C *dst = B1 + (((size_t)c * nz + (z < nz ? z : 0)) * Lx + kx) * ny;
-    if (pl.npass >= 2) {
-        const int p = pl.npass - 1, Rp = pl.radix[p], Ns = pl.ns[p];
+    if (NP >= 2) {
+        const int Rp = RL, Ns = NSL;
         if (j < L / Rp) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;
@@ -355,19 +345,22 @@ __device__ __forceinline__ cplx<R> block_sum(cplx<R> v, cplx<R> *scratch) {
     return scratch[0];  // valid in every thread
 }
 
-template <typename R>
+template <typename R, int LC>
 __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ B1,
                                                 const cplx<R> *__restrict__ xin, cplx<R> *__restrict__ yout,
-                                                int nx, int ny, int nz, int N, FftPlan pl,
-                                                const cplx<R> *__restrict__ twall, int NL,
+                                                int nx, int ny, int nz, int N, FftPlan pl_rt,
+                                                const cplx<R> *__restrict__ twall, int lnl,
                                                 const cplx<R> *__restrict__ scale, cplx<R> *__restrict__ dots,
                                                 const int *__restrict__ done) {
     using C = cplx<R>;
+    const FftPlan pl = plan_of<LC, kMaxRadix, true>(pl_rt);
+    const int NL = 1 << lnl;
+    const int NP = pl.npass, R0 = pl.radix[0], RL = pl.radix[NP - 1], NSL = pl.ns[NP - 1];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
-    const C *tw = twall + pl.tw_off;
+    const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
-    const int ytiles = (ny + NL - 1) / NL;
+    const int ytiles = (ny + NL - 1) >> lnl;
     int b = blockIdx.x;
     const int y0 = (b % ytiles) * NL;
     b /= ytiles;
@@ -377,8 +370,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_x(const int *__restrict
     const int t = threadIdx.x;
     const C *src = B1 + ((size_t)c * nz + z) * (size_t)L * ny;
     {   // pass 0 from global, lanes over lines (y contiguous in B1)
-        const int line = t % NL, j = t / NL, y = y0 + line;
-        const int R0 = pl.radix[0];
+        const int line = t & (NL - 1), j = t >> lnl, y = y0 + line;
         if (j < L / R0) {
             const bool yok = y < ny;
             C a[kMaxRadix];
@@ -389,7 +381,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_x(const int *__restrict
         }
     }
     __syncthreads();
-    lds_passes<+1, kMaxRadix>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
+    lds_passes<+1, kMaxRadix, LC, true>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
     const int line = t / TPL, j = t % TPL, y = y0 + line;
     const C sc = scale[c / 3];
     const C *xc = xin + (size_t)c * N;
@@ -407,8 +399,8 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_x(const int *__restrict
             }
         }
     };
-    if (pl.npass >= 2) {
-        const int p = pl.npass - 1, Rp = pl.radix[p], Ns = pl.ns[p];
+    if (NP >= 2) {
+        const int Rp = RL, Ns = NSL;
         if (j < L / Rp) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;

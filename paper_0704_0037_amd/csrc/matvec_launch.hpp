@@ -1,0 +1,100 @@
+// Host side of the interaction-matrix product: picks, for each axis, the kernels specialized for
+// its padded length when one exists (index arithmetic folds to constants) or the general ones.
+// Included by one translation unit per precision.
+#pragma once
+
+#include "ctx.hpp"
+#include "matvec_kernels.hpp"
+
+// padded lengths with specialized kernels (5-smooth sizes the workloads use most)
+#define DDA_SPECIALIZED_LENGTHS(X) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+
+namespace dda {
+
+template <typename R> inline Work<R> &work_of(Ctx &c);
+template <> inline Work<double> &work_of<double>(Ctx &c) { return c.w64; }
+template <> inline Work<float> &work_of<float>(Ctx &c) { return c.w32; }
+template <typename R> inline const cplx<R> *tw_of(const Ctx &c);
+template <> inline const double2 *tw_of<double>(const Ctx &c) { return c.tw64; }
+template <> inline const float2 *tw_of<float>(const Ctx &c) { return c.tw32; }
+template <typename R> inline const cplx<R> *ghat_of(const Ctx &c);
+template <> inline const double2 *ghat_of<double>(const Ctx &c) { return c.ghat; }
+template <> inline const float2 *ghat_of<float>(const Ctx &c) { return c.ghat32; }
+
+// blocks above 64 KiB of dynamic LDS must be allowed explicitly
+template <class K> inline void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
+#define DDA_DISPATCH(LEN, KERNEL, BYTES, ...)                                          \
+    switch (LEN) {                                                                     \
+        DDA_SPECIALIZED_LENGTHS(DDA_CASE_##KERNEL)                                     \
+        default:                                                                       \
+            allow_lds(&KERNEL<R, 0>, BYTES);                                           \
+            hipLaunchKernelGGL((KERNEL<R, 0>), __VA_ARGS__);                           \
+            break;                                                                     \
+    }
+#define DDA_CASE_k_fwd_x(L) case L: allow_lds(&k_fwd_x<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_fwd_x<R, L>), DDA_ARGS); break;
+#define DDA_CASE_k_fwd_y(L) case L: allow_lds(&k_fwd_y<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_fwd_y<R, L>), DDA_ARGS); break;
+#define DDA_CASE_k_zmul(L) case L: allow_lds(&k_zmul<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_zmul<R, L>), DDA_ARGS); break;
+#define DDA_CASE_k_inv_y(L) case L: allow_lds(&k_inv_y<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_inv_y<R, L>), DDA_ARGS); break;
+#define DDA_CASE_k_inv_x(L) case L: allow_lds(&k_inv_x<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_inv_x<R, L>), DDA_ARGS); break;
+
+template <typename R>
+dda_status matvec_device_impl(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
+                              hipStream_t s, const int *done, hipEvent_t *ev) {
+    using C = cplx<R>;
+    Work<R> &w = work_of<R>(c);
+    const C *tw = tw_of<R>(c);
+    const C *gh = ghat_of<R>(c);
+    const int ncomp = 3 * nrhs;
+    const int nlx = c.nl_x, nly = c.nl_y;
+    const int ytiles = (c.ny + nlx - 1) / nlx, ztiles = (c.nz + nly - 1) / nly;
+    const size_t lx_bytes = (size_t)nlx * lds_line_stride(c.Lx) * sizeof(C);
+    const size_t ly_bytes = (size_t)nly * lds_line_stride(c.Ly) * sizeof(C);
+    const size_t lz_bytes = zmul_lds_elems(c.Lz) * sizeof(C);
+    const int N = (int)c.N;
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[0], s));
+#define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, x, w.B1, c.nx, c.ny, c.nz, N, \
+                 c.pxf, tw, c.lnl_x, done
+#define DDA_BYTES lx_bytes
+    DDA_DISPATCH(c.Lx, k_fwd_x, DDA_BYTES, DDA_ARGS)
+#undef DDA_BYTES
+#undef DDA_ARGS
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[1], s));
+#define DDA_ARGS dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyf.tpl), ly_bytes, s, w.B1, w.B2, c.ny, c.nz, c.Lx, ncomp, \
+                 c.pyf, tw, c.lnl_y, done
+#define DDA_BYTES ly_bytes
+    DDA_DISPATCH(c.Ly, k_fwd_y, DDA_BYTES, DDA_ARGS)
+#undef DDA_BYTES
+#undef DDA_ARGS
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[2], s));
+    const int zblocks = (c.Lx / 2 + 1) * (c.Ly / 2 + 1) * (4 / DDA_ZMUL_SLOTS);
+#define DDA_ARGS dim3((zblocks + 7) / 8 * 8, nrhs), dim3(DDA_ZMUL_SLOTS * 3 * c.pzf.tpl), lz_bytes, s, w.B2, gh, c.nz, \
+                 c.Lx, c.Ly, nrhs, c.pzf, c.pzi, tw, done
+#define DDA_BYTES lz_bytes
+    DDA_DISPATCH(c.Lz, k_zmul, DDA_BYTES, DDA_ARGS)
+#undef DDA_BYTES
+#undef DDA_ARGS
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[3], s));
+#define DDA_ARGS dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyi.tpl), ly_bytes, s, w.B2, w.B1, c.ny, c.nz, c.Lx, ncomp, \
+                 c.pyi, tw, c.lnl_y, done
+#define DDA_BYTES ly_bytes
+    DDA_DISPATCH(c.Ly, k_inv_y, DDA_BYTES, DDA_ARGS)
+#undef DDA_BYTES
+#undef DDA_ARGS
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[4], s));
+#define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, w.B1, x, y, c.nx, c.ny, c.nz, \
+                 N, c.pxi, tw, c.lnl_x, scale, dots, done
+#define DDA_BYTES lx_bytes
+    DDA_DISPATCH(c.Lx, k_inv_x, DDA_BYTES, DDA_ARGS)
+#undef DDA_BYTES
+#undef DDA_ARGS
+    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[5], s));
+    DDA_HIP_CHECK(hipGetLastError());
+    return DDA_OK;
+}
+
+}  // namespace dda

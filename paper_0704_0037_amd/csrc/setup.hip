@@ -39,66 +39,24 @@ static bool five_smooth(int L) {
     return L == 1;
 }
 
-// Radices for length L: 8s first, the leftover power of two as 16 (or 4*4 when maxr = 8), 4 or
-// 2, then 5s and 3s.  Larger radices mean fewer passes over LDS.
-static bool factor(int L, int maxr, std::vector<int> &r) {
-    r.clear();
-    if (L == 1) {
-        r.push_back(1);
-        return true;
-    }
-    int rem = L, p2 = 0, n3 = 0, n5 = 0;
-    while (rem % 2 == 0) rem /= 2, ++p2;
-    while (rem % 5 == 0) rem /= 5, ++n5;
-    while (rem % 3 == 0) rem /= 3, ++n3;
-    if (rem != 1) return false;
-    const int n8 = p2 / 3, left = p2 % 3;
-    for (int i = 0; i < n8; ++i) r.push_back(8);
-    if (left == 1) {
-        if (n8 > 0 && maxr >= 16) r.back() = 16;
-        else if (n8 > 0) { r.back() = 4; r.push_back(4); }
-        else r.push_back(2);
-    } else if (left == 2) {
-        r.push_back(4);
-    }
-    for (int i = 0; i < n5; ++i) r.push_back(5);
-    for (int i = 0; i < n3; ++i) r.push_back(3);
-    return (int)r.size() <= kMaxPass;
-}
-
-static FftPlan make_plan(int L, const std::vector<int> &r, int tw_off) {
-    FftPlan p{};
-    p.L = L;
-    p.npass = (int)r.size();
-    int ns = 1, rmin = 1 << 30;
-    for (int i = 0; i < p.npass; ++i) {
-        p.radix[i] = r[i];
-        p.ns[i] = ns;
-        ns *= r[i];
-        rmin = std::min(rmin, r[i]);
-    }
-    p.tpl = L / rmin;
-    p.tw_off = tw_off;
-    return p;
-}
-
 static int smallest_pad(int n) {
     int L = std::max(1, 2 * n - 1);
     while (!five_smooth(L)) ++L;
     return L;
 }
 
-// lines per block: up to DDA_MAX_THREADS threads, preferably a whole number of waves, LDS <= 64 KiB
-static int pick_lines(int tpl, int line_bytes, int ndim, int want) {
+// lines per block (a power of two, returned as its log2): up to DDA_MAX_THREADS threads,
+// preferably a whole number of waves, LDS within DDA_LDS_CAP
+static int pick_lines_log2(int tpl, int line_bytes, int ndim, int want) {
     const int maxt = DDA_MAX_THREADS;
     int nl = want > 0 ? want : std::max(1, maxt / tpl);
-    if (want <= 0) {
-        nl = std::min(nl, std::max(ndim, 1));
-        const int g = 64 / std::gcd(tpl, 64);
-        if (g * tpl <= maxt) nl = (nl + g - 1) / g * g;
-    }
-    while (nl > 1 && (nl * tpl > maxt || (size_t)nl * line_bytes > 64 * 1024)) --nl;
-    return nl;
+    if (want <= 0) nl = std::min(nl, std::max(ndim, 1));
+    int l = 0;
+    while ((2 << l) <= nl) ++l;  // round down to a power of two
+    if (want <= 0)
+        while ((((1 << l) * tpl) % 64) != 0 && ((2 << l) * tpl) <= maxt) ++l;  // whole waves if possible
+    while (l > 0 && (((1 << l) * tpl) > maxt || (size_t)(1 << l) * line_bytes > DDA_LDS_CAP)) --l;
+    return l;
 }
 
 // --------------------------------------------------------------------- kernels
@@ -176,7 +134,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fft_axis(double2 *__restric
         }
     }
     __syncthreads();
-    lds_passes<-1, kMaxRadix>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
+    lds_passes<-1, kMaxRadix, 0, false>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
     if (pl.npass >= 2) {
         const int p = pl.npass - 1, Rp = pl.radix[p], Ns = pl.ns[p];
         if (gj < L / Rp) {
@@ -199,7 +157,8 @@ __global__ void k_gextract(const double2 *__restrict__ buf, double2 *__restrict_
     const int kz = (int)(e % hz);
     const int kx = (int)((e / hz) % hx);
     const int ky = (int)(e / ((size_t)hz * hx));
-    Gh[e * 6 + comp] = buf[((size_t)kz * Ly + ky) * Lx + kx];
+    // [ky][kx][comp][kz]
+    Gh[(((size_t)ky * hx + kx) * 6 + comp) * hz + kz] = buf[((size_t)kz * Ly + ky) * Lx + kx];
 }
 
 __global__ void k_to_f32(const double2 *__restrict__ a, float2 *__restrict__ b, size_t n) {
@@ -270,56 +229,6 @@ template <typename R> dda_status ensure_work(Ctx &c, int nrhs) {
 template dda_status ensure_work<double>(Ctx &, int);
 template dda_status ensure_work<float>(Ctx &, int);
 
-template <typename R> static const cplx<R> *tw_of(const Ctx &c);
-template <> const double2 *tw_of<double>(const Ctx &c) { return c.tw64; }
-template <> const float2 *tw_of<float>(const Ctx &c) { return c.tw32; }
-template <typename R> static const cplx<R> *ghat_of(const Ctx &c);
-template <> const double2 *ghat_of<double>(const Ctx &c) { return c.ghat; }
-template <> const float2 *ghat_of<float>(const Ctx &c) { return c.ghat32; }
-
-template <typename R>
-dda_status matvec_device(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
-                         hipStream_t s, const int *done, hipEvent_t *ev) {
-    using C = cplx<R>;
-    Work<R> &w = work_of<R>(c);
-    const C *tw = tw_of<R>(c);
-    const C *gh = ghat_of<R>(c);
-    const int ncomp = 3 * nrhs;
-    const int nlx = c.nl_x, nly = c.nl_y, ncz = c.nc_z;
-    const int ytiles = (c.ny + nlx - 1) / nlx, ztiles = (c.nz + nly - 1) / nly;
-    const size_t lx_bytes = (size_t)nlx * lds_line_stride(c.Lx) * sizeof(C);
-    const size_t ly_bytes = (size_t)nly * lds_line_stride(c.Ly) * sizeof(C);
-    const size_t lz_bytes = (size_t)ncz * 3 * lds_line_stride(c.Lz) * sizeof(C);
-    const int N = (int)c.N;
-    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL(k_fwd_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, x, w.B1,
-                       c.nx, c.ny, c.nz, N, c.pxf, tw, nlx, done);
-    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL(k_fwd_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyf.tpl), ly_bytes, s, w.B1, w.B2, c.ny,
-                       c.nz, c.Lx, ncomp, c.pyf, tw, nly, done);
-    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[2], s));
-    {
-        const int slots = 4 * (c.Lx / 2 + 1) * (c.Ly / 2 + 1) * nrhs;
-        const int nb = (slots + ncz - 1) / ncz;
-        const int nb8 = (nb + 7) / 8 * 8;
-        hipLaunchKernelGGL(k_zmul<R>, dim3(nb8), dim3(ncz * 3 * c.pzf.tpl), lz_bytes, s, w.B2, gh, c.nz, c.Lx, c.Ly,
-                           nrhs, c.pzf, c.pzi, tw, ncz, nb, done);
-    }
-    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[3], s));
-    hipLaunchKernelGGL(k_inv_y<R>, dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyi.tpl), ly_bytes, s, w.B2, w.B1, c.ny,
-                       c.nz, c.Lx, ncomp, c.pyi, tw, nly, done);
-    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[4], s));
-    hipLaunchKernelGGL(k_inv_x<R>, dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, w.B1, x,
-                       y, c.nx, c.ny, c.nz, N, c.pxi, tw, nlx, scale, dots, done);
-    if (ev) DDA_HIP_CHECK(hipEventRecord(ev[5], s));
-    DDA_HIP_CHECK(hipGetLastError());
-    return DDA_OK;
-}
-template dda_status matvec_device<double>(Ctx &, const double2 *, double2 *, int, const double2 *, double2 *,
-                                          hipStream_t, const int *, hipEvent_t *);
-template dda_status matvec_device<float>(Ctx &, const float2 *, float2 *, int, const float2 *, float2 *, hipStream_t,
-                                         const int *, hipEvent_t *);
-
 template <typename R>
 dda_status matvec_launch(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const double *are, const double *aim,
                          bool want_dots, hipStream_t s) {
@@ -375,13 +284,16 @@ static dda_status build_ghat(Ctx &c) {
                   {c.pzf, c.Lx, c.Ly, 1, Lx, Lx * Ly, 1}};
     int nl[3];
     for (int a = 0; a < 3; ++a)
-        nl[a] = pick_lines(ax[a].pl.tpl, lds_line_stride(ax[a].pl.L) * (int)sizeof(double2), ax[a].nu, 0);
+        nl[a] = 1 << pick_lines_log2(ax[a].pl.tpl, lds_line_stride(ax[a].pl.L) * (int)sizeof(double2), ax[a].nu, 0);
     for (int comp = 0; comp < 6; ++comp) {
         hipLaunchKernelGGL(k_gfill, dim3((unsigned)((full + thr - 1) / thr)), dim3(thr), 0, s, buf, comp, c.nx, c.ny,
                            c.nz, c.Lx, c.Ly, c.Lz, c.kd);
         for (int a = 0; a < 3; ++a) {
             const int utiles = (ax[a].nu + nl[a] - 1) / nl[a];
             const size_t lds = (size_t)nl[a] * lds_line_stride(ax[a].pl.L) * sizeof(double2);
+            if (lds > 64 * 1024)
+                (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_axis),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(k_fft_axis, dim3(utiles * ax[a].nv), dim3(nl[a] * ax[a].pl.tpl), lds, s, buf, ax[a].nu,
                                ax[a].nv, ax[a].su, ax[a].sv, ax[a].sp, ax[a].pl, (const double2 *)c.tw64, nl[a],
                                ax[a].lol);
@@ -481,13 +393,11 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
         total += lens[i];
     }
     auto off_of = [&](int L) { return offs[std::find(lens.begin(), lens.end(), L) - lens.begin()]; };
-    std::vector<int> r;
     auto plans = [&](int L, int maxr, FftPlan &f, FftPlan &inv) {
-        if (!factor(L, maxr, r)) return false;
-        f = make_plan(L, r, off_of(L));
-        std::vector<int> rr(r.rbegin(), r.rend());
-        inv = make_plan(L, rr, off_of(L));
-        return true;
+        f = make_plan(L, maxr, false);
+        inv = make_plan(L, maxr, true);
+        f.tw_off = inv.tw_off = off_of(L);
+        return f.npass > 0 && inv.npass > 0;
     };
     if (!plans(c->Lx, kMaxRadix, c->pxf, c->pxi) || !plans(c->Ly, kMaxRadix, c->pyf, c->pyi) ||
         !plans(c->Lz, kMaxRadixZ, c->pzf, c->pzi)) {
@@ -504,11 +414,13 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
             tw32[offs[i] + mm] = make_float2((float)cosl(ang), (float)sinl(ang));
         }
     const int want_nl = opts ? opts->lines_per_block : 0;
-    c->nl_x = pick_lines(c->pxf.tpl, lds_line_stride(c->Lx) * 16, c->ny, want_nl);
-    c->nl_y = pick_lines(c->pyf.tpl, lds_line_stride(c->Ly) * 16, c->nz, want_nl);
-    c->nc_z = std::max(1, DDA_MAX_THREADS / (3 * c->pzf.tpl));
-    while (c->nc_z > 1 && (size_t)c->nc_z * 3 * lds_line_stride(c->Lz) * 16 > 64 * 1024) --c->nc_z;
-    if (3 * c->pzf.tpl > 768 || c->nl_x * c->pxf.tpl > DDA_MAX_THREADS ||
+    c->lnl_x = pick_lines_log2(c->pxf.tpl, lds_line_stride(c->Lx) * 16, c->ny, want_nl);
+    c->lnl_y = pick_lines_log2(c->pyf.tpl, lds_line_stride(c->Ly) * 16, c->nz, want_nl);
+    c->nl_x = 1 << c->lnl_x;
+    c->nl_y = 1 << c->lnl_y;
+    c->nc_z = 1;
+    if (DDA_ZMUL_SLOTS * 3 * c->pzf.tpl > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 ||
+        c->nl_x * c->pxf.tpl > DDA_MAX_THREADS ||
         c->nl_y * c->pyf.tpl > DDA_MAX_THREADS) {
         set_error("dda_setup: padded size too large for one workgroup per line");
         delete c;
