@@ -88,6 +88,7 @@ typedef struct {
     int32_t check_every;   /* iterations between host-side convergence checks; 0 = automatic */
     double inner_tol;      /* DDA_FP32_REFINE: relative tolerance of each inner solve; 0 = 1e-2 */
     const void *x0;        /* device initial guess, same layout as x_out; NULL = zero */
+    int32_t graph;         /* iterations replayed as a captured hipGraph: 0 = automatic, 1 = on, -1 = off */
 } dda_solve_opts;
 
 /* Per-right-hand-side report of dda_solve. */
@@ -166,6 +167,19 @@ dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
  */
 dda_status dda_solve(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, double tol,
                      const dda_solve_opts *opts, void *x_out, dda_solve_info *info);
+
+/*
+ * dda_solve_many — one right-hand side on each of n_ctx particles (contexts), solved concurrently:
+ * every context advances on its own stream (the paper runs independent orientations or particles
+ * as separate simulations, Sec. 2; here they share the GPU).  Double precision, zero initial guess.
+ *   ctxs    host [n_ctx] distinct contexts;  beams  host [n_ctx]
+ *   x_out   host [n_ctx] device pointers, each complex128 [3][N_i]
+ *   info    host [n_ctx] or NULL
+ * Returns DDA_OK if every particle converged, else the first failing status; DDA_ENOTSUP for
+ * DDA_FP32_REFINE or an initial guess.
+ */
+dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const dda_beam *beams, double tol,
+                          const dda_solve_opts *opts, void *const *x_out, dda_solve_info *info);
 
 /*
  * dda_cross_sections — out = {Cext, Cabs, Csca = Cext - Cabs} in units of d^2 (Sec. 3.1 reports

@@ -26,7 +26,8 @@ struct Ctx {
     int64_t N = 0;
     double m_re = 0, m_im = 0, kd = 0;
     int polarizability = DDA_POL_LDR;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;      // the caller's stream (all calls are ordered on it)
+    hipStream_t own_stream = nullptr;  // the context's own stream: solves run (and graphs capture) here
     int nl_x = 0, nl_y = 0, nc_z = 0;  // lines per block (x, y passes) and columns per block (z pass)
     int lnl_x = 0, lnl_y = 0;          // log2 of nl_x, nl_y (powers of two)
 

@@ -3,6 +3,10 @@
 // Included by one translation unit per precision.
 #pragma once
 
+#include <mutex>
+#include <set>
+#include <tuple>
+
 #include "ctx.hpp"
 #include "matvec_kernels.hpp"
 
@@ -21,11 +25,18 @@ template <typename R> inline const cplx<R> *ghat_of(const Ctx &c);
 template <> inline const double2 *ghat_of<double>(const Ctx &c) { return c.ghat; }
 template <> inline const float2 *ghat_of<float>(const Ctx &c) { return c.ghat32; }
 
-// blocks above 64 KiB of dynamic LDS must be allowed explicitly
+// blocks above 64 KiB of dynamic LDS must be allowed explicitly; done once per kernel, device and
+// size, so that launches recorded into a graph later make no attribute calls
 template <class K> inline void allow_lds(K kernel, size_t bytes) {
-    if (bytes > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bytes);
+    if (bytes <= 64 * 1024) return;
+    static std::mutex mu;
+    static std::set<std::tuple<const void *, int, size_t>> seen;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const void *f = reinterpret_cast<const void *>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    if (seen.insert(std::make_tuple(f, dev, bytes)).second)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 #define DDA_DISPATCH(LEN, KERNEL, BYTES, ...)                                          \

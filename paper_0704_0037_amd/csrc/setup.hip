@@ -265,6 +265,7 @@ void destroy(Ctx *c) {
     (void)hipFree(c->sbuf);
     (void)hipFree(c->red);
     if (c->hbuf) (void)hipHostFree(c->hbuf);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
 
@@ -427,6 +428,12 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
         return DDA_EINVAL;
     }
     dda_status st;
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        set_error("dda_setup: stream creation failed");
+        c->own_stream = nullptr;
+        st = DDA_EHIP;
+        goto fail;
+    }
     if ((st = device_alloc((void **)&c->gmap, ncell * sizeof(int32_t))) != DDA_OK) goto fail;
     if ((st = device_alloc((void **)&c->lin, c->N * sizeof(int32_t))) != DDA_OK) goto fail;
     if ((st = device_alloc((void **)&c->tw64, total * sizeof(double2))) != DDA_OK) goto fail;

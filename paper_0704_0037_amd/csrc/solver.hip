@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -717,70 +718,168 @@ static dda_status init_states(Ctx &c, Bufs &B, double tol, int maxit, const int 
     return DDA_OK;
 }
 
-static dda_status all_done(Ctx &c, Bufs &B, bool &out) {
-    int *hd = (int *)c.hbuf;
-    DDA_HIP_CHECK(hipMemcpyAsync(hd, B.done, B.nrhs * sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
-    out = true;
-    for (int r = 0; r < B.nrhs; ++r) out = out && hd[r];
-    return DDA_OK;
-}
+// One Krylov solve in flight on a context: its buffers, the chunk of `check_every` iterations it
+// launches between convergence checks, and (optionally) that chunk captured once as a hipGraph
+// and replayed.  A right-hand side that is done turns every later kernel into a no-op, so
+// launching whole chunks past convergence never changes its iterate.
+template <typename R> struct Run {
+    Ctx *c = nullptr;
+    Bufs B;
+    Vecs<R> v{};
+    cplx<R> *x = nullptr;
+    int solver = DDA_QMR;
+    int check_every = 1;
+    bool graph = false;
+    int chunks = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipEvent_t ev = nullptr;
+    bool fin = false;
+    bool pending = false;
+};
 
-// One Krylov solve on vectors of precision R: x (device, [nrhs][3N]) holds the initial guess if
-// have_x0, else it is zeroed.  b must already be in v.b.  On return the states are on the device.
-template <typename R>
-static dda_status krylov(Ctx &c, Bufs &B, Vecs<R> &v, cplx<R> *x, bool have_x0, int solver, int check_every) {
+// enqueue `count` solver iterations on the context's stream
+template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count) {
+    Ctx &c = *k.c;
+    Bufs &B = k.B;
+    Vecs<R> &v = k.v;
     hipStream_t s = c.stream;
     const dim3 vg(B.nb, B.nrhs), vb(kVecThreads);
     const int nrhs = B.nrhs;
     const size_t n3 = B.n3;
     Work<R> &w = work<R>(c);
     const int ndots = (int)dots_per_rhs(c);
+    cplx<R> *x = k.x;
     dda_status st;
-    if (have_x0) {
-        if ((st = matvec_device<R>(c, x, v.pt, nrhs, w.scale, nullptr, s, nullptr)) != DDA_OK) return st;
-    }
-    if (solver == DDA_QMR) {
-        hipLaunchKernelGGL(k_qmr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, x, v.r, v.vt, n3, B.part,
-                           have_x0 ? 0 : 1);
-        hipLaunchKernelGGL(k_qmr_scal_init, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
-        hipLaunchKernelGGL(k_qmr_p0<R>, vg, vb, 0, s, B.st, B.done, v.vt, v.p, n3);
-    } else {
-        hipLaunchKernelGGL(k_bi_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, x, v.r, v.rs, n3, B.part,
-                           have_x0 ? 0 : 1);
-        hipLaunchKernelGGL(k_bi_scal_init, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+    for (int it = 0; it < count; ++it) {
+        if (k.solver == DDA_QMR) {
+            if ((st = matvec_device<R>(c, v.p, v.pt, nrhs, w.scale, w.dots, s, B.done)) != DDA_OK) return st;
+            hipLaunchKernelGGL(k_qmr_scal_eps<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
+            hipLaunchKernelGGL(k_qmr_vt<R>, vg, vb, 0, s, B.st, B.done, v.pt, v.vt, n3, B.part);
+            hipLaunchKernelGGL(k_qmr_scal_2, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+            hipLaunchKernelGGL(k_qmr_update<R>, vg, vb, 0, s, B.st, B.done, v.p, v.pt, v.vt, v.d, v.s, x, v.r, n3,
+                               B.part);
+            hipLaunchKernelGGL(k_qmr_scal_3, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+        } else {
+            hipLaunchKernelGGL(k_bi_p<R>, vg, vb, 0, s, B.st, B.done, v.r, v.p, v.v, n3);
+            if ((st = matvec_device<R>(c, v.p, v.v, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
+            hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.rs, v.v, n3, B.part, 0);
+            hipLaunchKernelGGL(k_bi_scal_alpha, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+            hipLaunchKernelGGL(k_bi_s<R>, vg, vb, 0, s, B.st, B.done, v.r, v.v, v.s, n3, B.part);
+            hipLaunchKernelGGL(k_bi_scal_s, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+            if ((st = matvec_device<R>(c, v.s, v.t, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
+            hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.t, v.s, n3, B.part, 1);
+            hipLaunchKernelGGL(k_bi_scal_omega, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
+            hipLaunchKernelGGL(k_bi_x<R>, vg, vb, 0, s, B.st, B.done, v.p, v.s, v.t, v.rs, x, v.r, n3, B.part);
+            hipLaunchKernelGGL(k_bi_scal_end, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+        }
     }
     DDA_HIP_CHECK(hipGetLastError());
-    bool fin = false;
-    if ((st = all_done(c, B, fin)) != DDA_OK) return st;
-    while (!fin) {
-        for (int k = 0; k < check_every; ++k) {
-            if (solver == DDA_QMR) {
-                if ((st = matvec_device<R>(c, v.p, v.pt, nrhs, w.scale, w.dots, s, B.done)) != DDA_OK) return st;
-                hipLaunchKernelGGL(k_qmr_scal_eps<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
-                hipLaunchKernelGGL(k_qmr_vt<R>, vg, vb, 0, s, B.st, B.done, v.pt, v.vt, n3, B.part);
-                hipLaunchKernelGGL(k_qmr_scal_2, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
-                hipLaunchKernelGGL(k_qmr_update<R>, vg, vb, 0, s, B.st, B.done, v.p, v.pt, v.vt, v.d, v.s, x, v.r,
-                                   n3, B.part);
-                hipLaunchKernelGGL(k_qmr_scal_3, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
-            } else {
-                hipLaunchKernelGGL(k_bi_p<R>, vg, vb, 0, s, B.st, B.done, v.r, v.p, v.v, n3);
-                if ((st = matvec_device<R>(c, v.p, v.v, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
-                hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.rs, v.v, n3, B.part, 0);
-                hipLaunchKernelGGL(k_bi_scal_alpha, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
-                hipLaunchKernelGGL(k_bi_s<R>, vg, vb, 0, s, B.st, B.done, v.r, v.v, v.s, n3, B.part);
-                hipLaunchKernelGGL(k_bi_scal_s, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
-                if ((st = matvec_device<R>(c, v.s, v.t, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
-                hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.t, v.s, n3, B.part, 1);
-                hipLaunchKernelGGL(k_bi_scal_omega, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
-                hipLaunchKernelGGL(k_bi_x<R>, vg, vb, 0, s, B.st, B.done, v.p, v.s, v.t, v.rs, x, v.r, n3, B.part);
-                hipLaunchKernelGGL(k_bi_scal_end, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
-            }
-        }
-        DDA_HIP_CHECK(hipGetLastError());
-        if ((st = all_done(c, B, fin)) != DDA_OK) return st;
-    }
     return DDA_OK;
+}
+
+// copy the done flags to the pinned host mirror and mark the point to wait for
+template <typename R> static dda_status post_check(Run<R> &k) {
+    Ctx &c = *k.c;
+    DDA_HIP_CHECK(hipMemcpyAsync(c.hbuf, k.B.done, k.B.nrhs * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    DDA_HIP_CHECK(hipEventRecord(k.ev, c.stream));
+    k.pending = true;
+    return DDA_OK;
+}
+
+// initial residual and scalars (x holds the initial guess if have_x0, else it is zeroed)
+template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
+    Ctx &c = *k.c;
+    Bufs &B = k.B;
+    Vecs<R> &v = k.v;
+    hipStream_t s = c.stream;
+    const dim3 vg(B.nb, B.nrhs), vb(kVecThreads);
+    const size_t n3 = B.n3;
+    Work<R> &w = work<R>(c);
+    dda_status st;
+    DDA_HIP_CHECK(hipEventCreateWithFlags(&k.ev, hipEventDisableTiming));
+    if (have_x0) {
+        if ((st = matvec_device<R>(c, k.x, v.pt, B.nrhs, w.scale, nullptr, s, nullptr)) != DDA_OK) return st;
+    }
+    if (k.solver == DDA_QMR) {
+        hipLaunchKernelGGL(k_qmr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, k.x, v.r, v.vt, n3, B.part,
+                           have_x0 ? 0 : 1);
+        hipLaunchKernelGGL(k_qmr_scal_init, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+        hipLaunchKernelGGL(k_qmr_p0<R>, vg, vb, 0, s, B.st, B.done, v.vt, v.p, n3);
+    } else {
+        hipLaunchKernelGGL(k_bi_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, k.x, v.r, v.rs, n3, B.part,
+                           have_x0 ? 0 : 1);
+        hipLaunchKernelGGL(k_bi_scal_init, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+    }
+    DDA_HIP_CHECK(hipGetLastError());
+    return post_check(k);
+}
+
+// launch one chunk of iterations: eagerly the first time, then as a replayed graph if enabled
+template <typename R> static dda_status run_issue(Run<R> &k) {
+    Ctx &c = *k.c;
+    dda_status st;
+    if (k.graph && k.chunks > 0) {
+        if (!k.ge) {
+            DDA_HIP_CHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+            st = enqueue_iterations(k, k.check_every);
+            hipError_t e = hipStreamEndCapture(c.stream, &k.g);
+            if (st != DDA_OK) return st;
+            if (e != hipSuccess) {
+                set_error(std::string("solver graph capture: ") + hipGetErrorString(e));
+                return DDA_EHIP;
+            }
+            DDA_HIP_CHECK(hipGraphInstantiate(&k.ge, k.g, nullptr, nullptr, 0));
+        }
+        DDA_HIP_CHECK(hipGraphLaunch(k.ge, c.stream));
+    } else if ((st = enqueue_iterations(k, k.check_every)) != DDA_OK) {
+        return st;
+    }
+    ++k.chunks;
+    return post_check(k);
+}
+
+template <typename R> static dda_status run_poll(Run<R> &k) {
+    if (!k.pending) return DDA_OK;
+    DDA_HIP_CHECK(hipEventSynchronize(k.ev));
+    k.pending = false;
+    const int *hd = (const int *)k.c->hbuf;
+    bool all = true;
+    for (int r = 0; r < k.B.nrhs; ++r) all = all && hd[r];
+    k.fin = all;
+    return DDA_OK;
+}
+
+template <typename R> static void run_end(Run<R> &k) {
+    if (k.ge) (void)hipGraphExecDestroy(k.ge);
+    if (k.g) (void)hipGraphDestroy(k.g);
+    if (k.ev) (void)hipEventDestroy(k.ev);
+    k.ge = nullptr;
+    k.g = nullptr;
+    k.ev = nullptr;
+}
+
+// One Krylov solve to completion (x holds the initial guess if have_x0, else it is zeroed; b must
+// already be in v.b; on return the states are on the device).
+template <typename R>
+static dda_status krylov(Ctx &c, Bufs &B, Vecs<R> &v, cplx<R> *x, bool have_x0, int solver, int check_every,
+                         bool graph = false) {
+    Run<R> k;
+    k.c = &c;
+    k.B = B;
+    k.v = v;
+    k.x = x;
+    k.solver = solver;
+    k.check_every = check_every;
+    k.graph = graph;
+    dda_status st = run_begin(k, have_x0);
+    if (st == DDA_OK) st = run_poll(k);
+    while (st == DDA_OK && !k.fin) {
+        if ((st = run_issue(k)) != DDA_OK) break;
+        st = run_poll(k);
+    }
+    run_end(k);
+    return st;
 }
 
 static dda_status fetch_states(Ctx &c, Bufs &B, std::vector<SolveState> &h) {
@@ -812,36 +911,49 @@ static dda_status status_of(int s) {
 }
 
 // FP64 solve (QMR or Bi-CGSTAB) of all right-hand sides.
-static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
-                             double2 *x, dda_solve_info *info, int check_every) {
-    const int hcap = [&] {
-        int m = 0;
-        if (info)
-            for (int r = 0; r < nrhs; ++r) m = std::max(m, info[r].res_hist_cap);
-        return m;
-    }();
-    Bufs B;
+static int hist_cap(const dda_solve_info *info, int nrhs) {
+    int m = 0;
+    if (info)
+        for (int r = 0; r < nrhs; ++r) m = std::max(m, info[r].res_hist_cap);
+    return m;
+}
+
+// fp64 solve, first half: buffers, scales, right-hand sides, initial guess, states, begin
+static dda_status prepare_fp64(Ctx &c, Run<double> &k, const dda_beam *beams, int nrhs, double tol,
+                               const dda_solve_opts &o, double2 *x, int hcap) {
     dda_status st;
     if ((st = ensure_vecs<double>(c, nrhs)) != DDA_OK) return st;
-    if ((st = ensure_bufs(c, B, nrhs, hcap)) != DDA_OK) return st;
+    if ((st = ensure_bufs(c, k.B, nrhs, hcap)) != DDA_OK) return st;
     std::vector<double> ar(nrhs), ai(nrhs);
     for (int r = 0; r < nrhs; ++r) polarizability(c, beams[r], ar[r], ai[r]);
     if ((st = upload_scales<double>(c, ar, ai)) != DDA_OK) return st;
-    Vecs<double> v = vecs_of<double>(c, nrhs);
+    k.c = &c;
+    k.v = vecs_of<double>(c, nrhs);
+    k.x = x;
+    k.solver = o.solver;
     for (int r = 0; r < nrhs; ++r)
-        if ((st = rhs_launch<double>(c, beams[r], v.b + (size_t)r * B.n3, c.stream)) != DDA_OK) return st;
+        if ((st = rhs_launch<double>(c, beams[r], k.v.b + (size_t)r * k.B.n3, c.stream)) != DDA_OK) return st;
     if (o.x0 && o.x0 != x)
-        DDA_HIP_CHECK(hipMemcpyAsync(x, o.x0, (size_t)nrhs * B.n3 * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
-    if ((st = init_states(c, B, tol, o.maxit)) != DDA_OK) return st;
-    if ((st = krylov<double>(c, B, v, x, o.x0 != nullptr, o.solver, check_every)) != DDA_OK) return st;
+        DDA_HIP_CHECK(hipMemcpyAsync(x, o.x0, (size_t)nrhs * k.B.n3 * sizeof(double2), hipMemcpyDeviceToDevice,
+                                     c.stream));
+    if ((st = init_states(c, k.B, tol, o.maxit)) != DDA_OK) return st;
+    return run_begin(k, o.x0 != nullptr);
+}
+
+// fp64 solve, second half: states, true residual, report
+static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_opts &o, dda_solve_info *info,
+                              int hcap) {
+    dda_status st;
     std::vector<SolveState> h;
-    if ((st = fetch_states(c, B, h)) != DDA_OK) return st;
+    if ((st = fetch_states(c, k.B, h)) != DDA_OK) return st;
     std::vector<double> rt;
-    if ((st = true_residual(c, B, v, x, nullptr, rt)) != DDA_OK) return st;
+    if ((st = true_residual(c, k.B, k.v, k.x, nullptr, rt)) != DDA_OK) return st;
     std::vector<double> hist;
     if (hcap > 0) {
         hist.resize((size_t)nrhs * hcap);
-        DDA_HIP_CHECK(hipMemcpy(hist.data(), B.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost));
+        DDA_HIP_CHECK(hipMemcpyAsync(hist.data(), k.B.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                     c.stream));
+        DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
     }
     dda_status ret = DDA_OK;
     for (int r = 0; r < nrhs; ++r) {
@@ -857,7 +969,7 @@ static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol
         info[r].res_true = rt[r];
         if (info[r].res_hist && info[r].res_hist_cap > 0) {
             const int n = std::min(info[r].res_hist_cap, h[r].iter + 1);
-            for (int k = 0; k < n; ++k) info[r].res_hist[k] = hist[(size_t)r * hcap + k];
+            for (int q = 0; q < n; ++q) info[r].res_hist[q] = hist[(size_t)r * hcap + q];
             info[r].res_hist_len = n;
         } else {
             info[r].res_hist_len = 0;
@@ -866,9 +978,26 @@ static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol
     return ret;
 }
 
+static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
+                             double2 *x, dda_solve_info *info, int check_every, bool graph) {
+    const int hcap = hist_cap(info, nrhs);
+    Run<double> k;
+    k.check_every = check_every;
+    k.graph = graph;
+    dda_status st = prepare_fp64(c, k, beams, nrhs, tol, o, x, hcap);
+    if (st == DDA_OK) st = run_poll(k);
+    while (st == DDA_OK && !k.fin) {
+        if ((st = run_issue(k)) != DDA_OK) break;
+        st = run_poll(k);
+    }
+    run_end(k);
+    if (st != DDA_OK) return st;
+    return finish_fp64(c, k, nrhs, o, info, hcap);
+}
+
 // Iterative refinement: outer fp64 residual and update, inner fp32 QMR to inner_tol.
 static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
-                               double2 *x, dda_solve_info *info, int check_every) {
+                               double2 *x, dda_solve_info *info, int check_every, bool graph) {
     dda_status st;
     if (!c.ghat32) {
         const size_t n6 = (size_t)(c.Lx / 2 + 1) * (c.Ly / 2 + 1) * (c.Lz / 2 + 1) * 6;
@@ -934,7 +1063,7 @@ static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double t
         hipLaunchKernelGGL(k_to32, dim3(B.nb, nrhs), dim3(kVecThreads), 0, c.stream, r64, v32.b, B.n3, dscale);
         // inner fp32 QMR (inactive right-hand sides start as done)
         if ((st = init_states(c, B, inner, std::max(1, o.maxit), active.data())) != DDA_OK) return st;
-        if ((st = krylov<float>(c, B, v32, e32, false, DDA_QMR, check_every)) != DDA_OK) return st;
+        if ((st = krylov<float>(c, B, v32, e32, false, DDA_QMR, check_every, graph)) != DDA_OK) return st;
         std::vector<SolveState> h;
         if ((st = fetch_states(c, B, h)) != DDA_OK) return st;
         for (int r = 0; r < nrhs; ++r)
@@ -972,19 +1101,27 @@ static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double t
 
 using namespace dda;
 
-extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, double tol,
-                                const dda_solve_opts *opts, void *x_out, dda_solve_info *info) {
-    Ctx *c = cx(h);
-    if (!c || !beams || !x_out || n_rhs < 1 || !(tol > 0)) {
-        set_error("dda_solve: NULL argument, n_rhs < 1 or tol <= 0");
-        return DDA_EINVAL;
+// Runs a solve on the context's own stream, ordered after the caller's stream, and restores it.
+namespace dda {
+struct StreamSwap {
+    Ctx &c;
+    hipStream_t user;
+    bool ok = false;
+    explicit StreamSwap(Ctx &cc) : c(cc), user(cc.stream) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+        ok = hipEventRecord(e, user) == hipSuccess && hipStreamWaitEvent(c.own_stream, e, 0) == hipSuccess;
+        (void)hipEventDestroy(e);
+        if (ok) c.stream = c.own_stream;
     }
-    for (int r = 0; r < n_rhs; ++r)
-        if (!beam_ok(&beams[r])) {
-            set_error("dda_solve: beam without unit vectors");
-            return DDA_EINVAL;
-        }
-    dda_solve_opts o{};
+    ~StreamSwap() {
+        if (ok) (void)hipStreamSynchronize(c.own_stream);
+        c.stream = user;
+    }
+};
+
+static dda_status check_opts(const dda_solve_opts *opts, dda_solve_opts &o) {
+    o = dda_solve_opts{};
     if (opts) o = *opts;
     if (o.maxit <= 0) o.maxit = 100000;
     if (o.solver != DDA_QMR && o.solver != DDA_BICGSTAB) {
@@ -999,14 +1136,119 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
         set_error("dda_solve: the refined single-precision solve uses QMR only");
         return DDA_ENOTSUP;
     }
-    int check = o.check_every;
-    if (check <= 0) check = c->N * n_rhs > 2000000 ? 1 : c->N * n_rhs > 100000 ? 4 : 16;
+    return DDA_OK;
+}
+
+// host-side convergence check cadence and graph use: big problems check every iteration (the
+// check is cheap next to an iteration); small ones launch chunks, replayed as a graph
+static void cadence(const Ctx &c, int nrhs, const dda_solve_opts &o, int &check, bool &graph) {
+    const int64_t work = c.N * (int64_t)nrhs;
+    check = o.check_every > 0 ? o.check_every : work > 2000000 ? 1 : work > 100000 ? 4 : 16;
+    graph = o.graph > 0 || (o.graph == 0 && work <= 2000000);
+}
+}  // namespace dda
+
+extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, double tol,
+                                const dda_solve_opts *opts, void *x_out, dda_solve_info *info) {
+    Ctx *c = cx(h);
+    if (!c || !beams || !x_out || n_rhs < 1 || !(tol > 0)) {
+        set_error("dda_solve: NULL argument, n_rhs < 1 or tol <= 0");
+        return DDA_EINVAL;
+    }
+    for (int r = 0; r < n_rhs; ++r)
+        if (!beam_ok(&beams[r])) {
+            set_error("dda_solve: beam without unit vectors");
+            return DDA_EINVAL;
+        }
+    dda_solve_opts o;
+    dda_status st = check_opts(opts, o);
+    if (st != DDA_OK) return st;
+    int check;
+    bool graph;
+    cadence(*c, n_rhs, o, check, graph);
     const auto t0 = std::chrono::steady_clock::now();
-    dda_status st = o.precision == DDA_FP64
-                        ? solve_fp64(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check)
-                        : solve_refine(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check);
+    {
+        StreamSwap sw(*c);
+        if (!sw.ok) {
+            set_error("dda_solve: could not order the solve after the caller's stream");
+            return DDA_EHIP;
+        }
+        st = o.precision == DDA_FP64 ? solve_fp64(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph)
+                                     : solve_refine(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
+    }
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)
         for (int r = 0; r < n_rhs; ++r) info[r].t_solve_s = dt;
     return st;
+}
+
+extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const dda_beam *beams, double tol,
+                                     const dda_solve_opts *opts, void *const *x_out, dda_solve_info *info) {
+    if (!ctxs || !beams || !x_out || n_ctx < 1 || !(tol > 0)) {
+        set_error("dda_solve_many: NULL argument, n_ctx < 1 or tol <= 0");
+        return DDA_EINVAL;
+    }
+    for (int i = 0; i < n_ctx; ++i) {
+        if (!ctxs[i] || !x_out[i] || !beam_ok(&beams[i])) {
+            set_error("dda_solve_many: NULL context/output or beam without unit vectors");
+            return DDA_EINVAL;
+        }
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) {
+                set_error("dda_solve_many: a context appears twice");
+                return DDA_EINVAL;
+            }
+    }
+    dda_solve_opts o;
+    dda_status st = check_opts(opts, o);
+    if (st != DDA_OK) return st;
+    if (o.precision != DDA_FP64 || o.x0) {
+        set_error("dda_solve_many: double precision without an initial guess only");
+        return DDA_ENOTSUP;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::unique_ptr<StreamSwap>> sw;
+    std::vector<Run<double>> runs(n_ctx);
+    std::vector<int> hcaps(n_ctx);
+    for (int i = 0; i < n_ctx && st == DDA_OK; ++i) {
+        Ctx &c = *cx(ctxs[i]);
+        sw.emplace_back(new StreamSwap(c));
+        if (!sw.back()->ok) {
+            set_error("dda_solve_many: could not order a solve after the caller's stream");
+            st = DDA_EHIP;
+            break;
+        }
+        int check;
+        bool graph;
+        cadence(c, 1, o, check, graph);
+        runs[i].check_every = check;
+        runs[i].graph = graph;
+        hcaps[i] = hist_cap(info ? info + i : nullptr, 1);
+        st = prepare_fp64(c, runs[i], &beams[i], 1, tol, o, (double2 *)x_out[i], hcaps[i]);
+    }
+    // all particles advance concurrently, each on its own stream
+    bool busy = st == DDA_OK;
+    while (busy && st == DDA_OK) {
+        busy = false;
+        for (int i = 0; i < n_ctx && st == DDA_OK; ++i) st = run_poll(runs[i]);
+        for (int i = 0; i < n_ctx && st == DDA_OK; ++i)
+            if (!runs[i].fin) {
+                busy = true;
+                st = run_issue(runs[i]);
+            }
+    }
+    dda_status ret = st;
+    for (int i = 0; i < n_ctx; ++i) {
+        run_end(runs[i]);
+        if (ret == DDA_OK || ret == DDA_ENOTCONV || ret == DDA_EBREAKDOWN) {
+            const dda_status si = finish_fp64(*cx(ctxs[i]), runs[i], 1, o, info ? info + i : nullptr, hcaps[i]);
+            if (si == DDA_EHIP || si == DDA_ENOMEM) ret = si;
+            else if (ret == DDA_OK && si != DDA_OK) ret = si;
+        }
+    }
+    sw.clear();
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int i = 0; i < n_ctx; ++i) info[i].t_solve_s = dt;
+    return ret;
 }

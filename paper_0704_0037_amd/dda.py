@@ -31,7 +31,8 @@ class SetupOpts(ct.Structure):
 
 class SolveOpts(ct.Structure):
     _fields_ = [("solver", ct.c_int32), ("precision", ct.c_int32), ("maxit", ct.c_int32),
-                ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p)]
+                ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p),
+                ("graph", ct.c_int32)]
 
 
 class SolveInfo(ct.Structure):
@@ -63,6 +64,8 @@ _SIGS = {
     "dda_matvec_batch": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_void_p, ct.c_void_p]),
     "dda_solve": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_double, ct.POINTER(SolveOpts),
                              ct.c_void_p, ct.POINTER(SolveInfo)]),
+    "dda_solve_many": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.c_int32, ct.POINTER(Beam), ct.c_double,
+                                  ct.POINTER(SolveOpts), ct.POINTER(ct.c_void_p), ct.POINTER(SolveInfo)]),
     "dda_cross_sections": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.POINTER(ct.c_double)]),
     "dda_farfield": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double),
                                 ct.POINTER(ct.c_double)]),
@@ -231,11 +234,11 @@ class Context:
         return list(k), tot.value
 
     def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
-              x_out=None, history=0, raise_on_fail=True):
+              x_out=None, history=0, raise_on_fail=True, graph=0):
         n = len(beams)
         x_out = self.vector(n) if x_out is None else x_out
         opts = SolveOpts(solver, precision, maxit, check_every, inner_tol,
-                         None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value)
+                         None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value, graph)
         infos = (SolveInfo * n)()
         hists = []
         for i in range(n):
@@ -278,3 +281,24 @@ class Context:
                                  float(phi), theta.ctypes.data_as(ct.POINTER(ct.c_double)), len(theta),
                                  M.ctypes.data_as(ct.POINTER(ct.c_double))), "dda_mueller")
         return M
+
+
+def _info_dict(inf):
+    return {f: getattr(inf, f) for f, _ in SolveInfo._fields_ if f != "res_hist"}
+
+
+def solve_many(contexts, beams, tol=1e-5, solver=QMR, maxit=0, check_every=0, graph=0, x_out=None,
+               raise_on_fail=True):
+    """One right-hand side per context, all solved concurrently (dda_solve_many)."""
+    n = len(contexts)
+    if len(beams) != n:
+        raise ValueError("one beam per context")
+    xs = [c.vector() for c in contexts] if x_out is None else list(x_out)
+    hs = (ct.c_void_p * n)(*[c._h.value for c in contexts])
+    ps = (ct.c_void_p * n)(*[_ptr(x, torch.complex128, (3, c.n), "x_out").value for x, c in zip(xs, contexts)])
+    opts = SolveOpts(solver, FP64, maxit, check_every, 0.0, None, graph)
+    infos = (SolveInfo * n)()
+    st = lib().dda_solve_many(hs, n, _beams(beams), float(tol), ct.byref(opts), ps, infos)
+    if raise_on_fail and st != OK:
+        _check(st, "dda_solve_many")
+    return xs, [_info_dict(infos[i]) for i in range(n)], st

@@ -185,3 +185,47 @@ def test_mueller_two_polarizations_equal_symmetry_route():
         with pytest.raises(dda.DDAError) as e:
             ctx.mueller(inputs.X_POL, x[0].contiguous(), None, 0.0, th)
         assert e.value.status == dda.ESYMMETRY
+
+
+@pytest.mark.parametrize("solver", ["qmr", "bicgstab"])
+def test_graph_replay_equals_eager(solver):
+    """Iterations replayed from a captured graph give bitwise the eager result."""
+    dda = _dda()
+    sv = dda.QMR if solver == "qmr" else dda.BICGSTAB
+    mask = inputs.ellipsoid_mask((14, 12, 9), (7, 5.5, 4))
+    beams = inputs.beams_for_orientations(2, seed=5)
+    with dda.Context(mask, 1.4 + 0.02j, 0.4) as ctx:
+        xe, ie, st = ctx.solve(beams, tol=1e-9, solver=sv, check_every=3, graph=-1)
+        assert st == 0
+        for _ in range(2):
+            xg, ig, st = ctx.solve(beams, tol=1e-9, solver=sv, check_every=3, graph=1)
+            assert st == 0
+            assert [i["iters"] for i in ig] == [i["iters"] for i in ie]
+            assert torch.equal(xg, xe)
+        if sv == dda.QMR:
+            xr, ir, st = ctx.solve(beams, tol=1e-9, precision=dda.FP32_REFINE, check_every=3, graph=-1)
+            xq, iq, st2 = ctx.solve(beams, tol=1e-9, precision=dda.FP32_REFINE, check_every=3, graph=1)
+            assert st == 0 and st2 == 0 and torch.equal(xr, xq)
+
+
+def test_solve_many_equals_single():
+    """Particles of different shapes solved concurrently give bitwise their one-at-a-time results."""
+    dda = _dda()
+    shapes = [(inputs.sphere_mask(9), 1.5, 0.5), (inputs.ellipsoid_mask((16, 11, 7), (8, 5.5, 3.5)), 1.33, 0.35),
+              (inputs.cluster_mask((14, 10, 10), [(-3.5, 0, 0), (3.5, 0.5, 0)], [3.2, 4.0]), 1.6 + 0.05j, 0.45)]
+    beams = inputs.beams_for_orientations(3, seed=9)[::2]
+    ctxs = [dda.Context(mk, m, kd) for mk, m, kd in shapes]
+    try:
+        xs, infos, st = dda.solve_many(ctxs, beams, tol=1e-8)
+        assert st == 0
+        for c, b, x, inf in zip(ctxs, beams, xs, infos):
+            x1, i1, s1 = c.solve([b], tol=1e-8)
+            assert s1 == 0 and inf["status"] == 0
+            assert inf["iters"] == i1[0]["iters"] and inf["res_true"] < 2e-8
+            assert torch.equal(x1[0], x)
+        with pytest.raises(dda.DDAError) as e:
+            dda.solve_many([ctxs[0], ctxs[0]], beams[:2], tol=1e-8)
+        assert e.value.status == dda.EINVAL
+    finally:
+        for c in ctxs:
+            c.close()
