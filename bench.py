@@ -31,16 +31,44 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 KERNELS = ["fwd_x", "fwd_y", "zmul", "inv_y", "inv_x"]
 
 
-def alg_bytes(n, N, L, c):
-    """Algorithmic bytes of each matvec kernel on an n^3 grid padded to L^3 (c bytes per complex)."""
+def alg_bytes(n, N, L, c, nrhs=1):
+    """Algorithmic bytes of one launch of each matvec kernel on an n^3 grid padded to L^3 for a
+    batch of nrhs vectors (c bytes per complex); the tensor octant is read once per batch."""
     h = L // 2 + 1
     return {
-        "fwd_x": c * (3 * N + 3 * L * n * n),                 # read x (non-void), write x-transformed planes
-        "fwd_y": c * (3 * L * n * n + 3 * L * L * n),         # read, write y-transformed
-        "zmul": c * (2 * 3 * L * L * n + 6 * h ** 3),         # read + write the (kx, ky) columns, tensor octant
-        "inv_y": c * (3 * L * L * n + 3 * L * n * n),
-        "inv_x": c * (3 * L * n * n + 3 * N + 3 * N),         # read planes and x, write y (non-void)
+        "fwd_x": c * nrhs * (3 * N + 3 * L * n * n),          # read x (non-void), write x-transformed planes
+        "fwd_y": c * nrhs * (3 * L * n * n + 3 * L * L * n),  # read, write y-transformed
+        "zmul": c * (nrhs * 2 * 3 * L * L * n + 6 * h ** 3),  # read + write the (kx, ky) columns, tensor octant
+        "inv_y": c * nrhs * (3 * L * L * n + 3 * L * n * n),
+        "inv_x": c * nrhs * (3 * L * n * n + 3 * N + 3 * N),  # read planes and x, write y (non-void)
     }
+
+
+def kernel_sources_digest():
+    """Digest of the matvec kernel sources, to tell whether recorded byte counters still apply."""
+    import hashlib
+    d = hashlib.sha256()
+    for f in ("fft.hpp", "matvec_kernels.hpp", "matvec_launch.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_0704_0037_amd", "csrc", f), "rb") as fh:
+            d.update(fh.read())
+    return d.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed byte-counter summary, or None when the
+    summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("record:"):
+            for kv in line[len("record:"):].split():
+                k, _, v = kv.partition("=")
+                rec[k] = v
+    if rec.get("sources") != kernel_sources_digest() or f"{kernel}_bytes" not in rec:
+        return None
+    return float(rec[f"{kernel}_bytes"])
 
 
 def cpu_baseline(w, rows, seed=7):
@@ -61,6 +89,10 @@ def cpu_baseline(w, rows, seed=7):
                       f"{dt:.1f} s; value = 1 / (seconds per row x N)"}
 
 
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=12)
     ap.add_argument("--no-forms", action="store_true", help="skip the fp32-refinement comparison")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for byte-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -77,24 +111,42 @@ def main():
     import torch
     from paper_0704_0037_amd import dda, inputs
 
+    if args.calibration_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
+
     w = inputs.c2_sphere256()
     n = w.grid[0]
     ctx = dda.Context(w.mask, w.m, w.kd, fp32=True)
     L = ctx.padded_grid()[0]
     N = ctx.n
+    log(f"context ready: {N} dipoles, padded grid {L}^3")
     beams = [inputs.X_POL, inputs.Y_POL]
     theta = np.radians(np.arange(0.0, 180.0 + 1e-9, 0.5))
 
-    # ---- per-kernel timing of the product (HIP events on the context's stream)
-    x = torch.from_numpy(inputs.random_vector(N, seed=1)).cuda()
+    # ---- per-kernel timing of the product, in the launch configuration of the solve (both
+    # polarizations in one batch); HIP events on the context's stream
+    nb = len(beams)
+    x = torch.from_numpy(inputs.random_vector(N, seed=1, n_rhs=nb)).cuda()
     y = torch.empty_like(x)
-    kms, tot_ms = ctx.matvec_timed(inputs.X_POL, x, y, reps=10)
-    ab = alg_bytes(n, N, L, 16)
+    kms, tot_ms = ctx.matvec_timed(beams, x, y, reps=10)
+    ab = alg_bytes(n, N, L, 16, nb)
     per_kernel = {k: {"ms": kms[i], "alg_GB": ab[k] / 1e9, "GBps": ab[k] / kms[i] / 1e6,
                       "frac": ab[k] / kms[i] / 1e6 / HBM_PEAK_GBS} for i, k in enumerate(KERNELS)}
     dom = max(KERNELS, key=lambda k: per_kernel[k]["ms"])
     B_mv = sum(ab.values())
     del x, y
+    x32 = torch.from_numpy(inputs.random_vector(N, seed=1, n_rhs=nb).astype(np.complex64)).cuda()
+    y32 = torch.empty_like(x32)
+    kms32, tot32 = ctx.matvec_timed(beams, x32, y32, reps=10, precision=dda.FP32_REFINE)
+    ab32 = alg_bytes(n, N, L, 8, nb)
+    per_kernel32 = {k: {"ms": kms32[i], "GBps": ab32[k] / kms32[i] / 1e6,
+                        "frac": ab32[k] / kms32[i] / 1e6 / HBM_PEAK_GBS} for i, k in enumerate(KERNELS)}
+    del x32, y32
+    traffic = recorded_traffic(dom, "sphere256_fp64_2rhs")
+    log(f"product timed: {tot_ms:.2f} ms per fp64 batch of {nb}, {tot32:.2f} ms fp32")
 
     # ---- steps: the whole hot path
     def step():
@@ -103,8 +155,9 @@ def main():
         M = ctx.mueller(inputs.X_POL, xs[0].contiguous(), xs[1].contiguous(), 0.0, theta)
         return xs, info, cs, M
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        log(f"warmup step {i} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mv = 0
@@ -113,6 +166,7 @@ def main():
         xs, info, cs, M = step()
         mv += sum(i["matvecs"] for i in info)
         iters = [i["iters"] for i in info]
+        log(f"step done: iterations {iters}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt / args.steps * 1e3
@@ -139,13 +193,17 @@ def main():
         "iterations": iters,
         "res_true": res_true,
         "Cext": [c[0] for c in cs],
-        "matvec_ms": tot_ms,
-        "matvec_only_per_s": 1e3 / tot_ms,
+        "matvec_ms_per_batch": tot_ms,
+        "matvec_batch": nb,
+        "matvec_only_per_s": nb * 1e3 / tot_ms,
         "matvec_roofline": {"bound": "hbm", "alg_GB": B_mv / 1e9, "achieved": B_mv / tot_ms / 1e6,
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": B_mv / tot_ms / 1e6 / HBM_PEAK_GBS},
         "kernels": per_kernel,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_kernel[dom]["GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": per_kernel[dom]["frac"], "traffic": None},
+                     "unit": "GB/s", "frac": per_kernel[dom]["frac"],
+                     "traffic": traffic, "alg_bytes": ab[dom], "launch": f"{nb} right-hand sides, fp64"},
+        "fp32_matvec": {"ms_per_batch": tot32, "matvec_only_per_s": nb * 1e3 / tot32,
+                        "frac": sum(ab32.values()) / tot32 / 1e6 / HBM_PEAK_GBS, "kernels": per_kernel32},
     }
 
     if not args.no_forms:
@@ -171,6 +229,7 @@ def main():
             "rel_err_S11_max": float(np.max(np.abs(M32[:, 0, 0] / M64[:, 0, 0] - 1)))}}
 
     if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
     ctx.close()
     print(json.dumps(out), flush=True)

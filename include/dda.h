@@ -211,13 +211,16 @@ dda_status dda_mueller(dda_ctx *ctx, const dda_beam *beam, const void *x1, const
                        double phi, const double *theta, int32_t n_theta, double *M);
 
 /*
- * dda_matvec_timed — measurement aid: runs dda_matvec `reps` times back to back on the context's
- * stream with HIP events around each of its kernels, and returns the mean duration in
- * milliseconds of each kernel (kernel_ms[5]: forward x, forward y, z + tensor multiply, inverse y,
- * inverse x) and of a whole product (total_ms).  Same arguments and layouts as dda_matvec.
+ * dda_matvec_timed — measurement aid: runs the product of n_rhs vectors (as dda_matvec_batch, or
+ * as dda_matvec_f32 per vector when precision = DDA_FP32_REFINE) `reps` times back to back on the
+ * context's stream with HIP events around each of its kernels, and returns the mean duration in
+ * milliseconds of each kernel launch (kernel_ms[5]: forward x, forward y, z + tensor multiply,
+ * inverse y, inverse x) and of a whole product (total_ms).
+ *   x, y   device [n_rhs][3][N], complex128 (DDA_FP64) or complex64 (DDA_FP32_REFINE; the context
+ *          must have been set up with opts.fp32)
  */
-dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y, int32_t reps,
-                            float kernel_ms[5], float *total_ms);
+dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, int32_t precision,
+                            const void *x, void *y, int32_t reps, float kernel_ms[5], float *total_ms);
 
 /* Human-readable name of a status code. */
 const char *dda_strerror(dda_status status);

@@ -155,24 +155,20 @@ dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
     return matvec_common(ctx, beams, n_rhs, x, y, false);
 }
 
-dda_status dda_matvec_timed(dda_ctx *h, const dda_beam *beam, const void *x, void *y, int32_t reps,
-                            float kernel_ms[5], float *total_ms) {
-    Ctx *ctx = cx(h);
-    if (!ctx || !beam || !x || !y || reps < 1 || !kernel_ms || !total_ms || x == y || !beam_ok(beam)) {
-        set_error("dda_matvec_timed: bad argument");
-        return DDA_EINVAL;
-    }
-    double ar, ai;
-    polarizability(*ctx, *beam, ar, ai);
-    // first call uploads the scale and settles the work buffers
-    dda_status st = matvec_launch<double>(*ctx, (const double2 *)x, (double2 *)y, 1, &ar, &ai, false, ctx->stream);
+}  // extern "C"
+
+template <typename R>
+static dda_status matvec_timed(Ctx &c, int n, const std::vector<double> &ar, const std::vector<double> &ai,
+                               const cplx<R> *x, cplx<R> *y, int reps, float kernel_ms[5], float *total_ms) {
+    // first call uploads the scales and settles the work buffers
+    dda_status st = matvec_launch<R>(c, x, y, n, ar.data(), ai.data(), false, c.stream);
     if (st != DDA_OK) return st;
+    Work<R> &w = work_of<R>(c);
     hipEvent_t ev[6];
     for (int i = 0; i < 6; ++i) DDA_HIP_CHECK(hipEventCreate(&ev[i]));
     double acc[5] = {0, 0, 0, 0, 0}, tot = 0;
     for (int r = 0; r < reps && st == DDA_OK; ++r) {
-        st = matvec_device<double>(*ctx, (const double2 *)x, (double2 *)y, 1, ctx->w64.scale, nullptr, ctx->stream,
-                                   nullptr, ev);
+        st = matvec_device<R>(c, x, y, n, w.scale, nullptr, c.stream, nullptr, ev);
         if (st != DDA_OK) break;
         hipError_t e = hipEventSynchronize(ev[5]);
         if (e != hipSuccess) {
@@ -194,6 +190,36 @@ dda_status dda_matvec_timed(dda_ctx *h, const dda_beam *beam, const void *x, voi
     for (int k = 0; k < 5; ++k) kernel_ms[k] = (float)(acc[k] / reps);
     *total_ms = (float)(tot / reps);
     return DDA_OK;
+}
+
+extern "C" {
+
+dda_status dda_matvec_timed(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, int32_t precision, const void *x,
+                            void *y, int32_t reps, float kernel_ms[5], float *total_ms) {
+    Ctx *ctx = cx(h);
+    if (!ctx || !beams || n_rhs < 1 || !x || !y || reps < 1 || !kernel_ms || !total_ms || x == y) {
+        set_error("dda_matvec_timed: bad argument");
+        return DDA_EINVAL;
+    }
+    if (precision != DDA_FP64 && precision != DDA_FP32_REFINE) {
+        set_error("dda_matvec_timed: unknown precision");
+        return DDA_EINVAL;
+    }
+    std::vector<double> ar(n_rhs), ai(n_rhs);
+    for (int r = 0; r < n_rhs; ++r) {
+        if (!beam_ok(&beams[r])) {
+            set_error("dda_matvec_timed: beam without unit vectors");
+            return DDA_EINVAL;
+        }
+        polarizability(*ctx, beams[r], ar[r], ai[r]);
+    }
+    if (precision == DDA_FP64)
+        return matvec_timed<double>(*ctx, n_rhs, ar, ai, (const double2 *)x, (double2 *)y, reps, kernel_ms, total_ms);
+    if (!ctx->ghat32) {
+        set_error("dda_matvec_timed: context built without opts.fp32");
+        return DDA_ENOTSUP;
+    }
+    return matvec_timed<float>(*ctx, n_rhs, ar, ai, (const float2 *)x, (float2 *)y, reps, kernel_ms, total_ms);
 }
 
 const char *dda_strerror(dda_status s) {

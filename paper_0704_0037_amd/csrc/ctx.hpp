@@ -2,6 +2,8 @@
 // the matvec, solver and read-out translation units.
 #pragma once
 
+#include <type_traits>
+
 #include <numeric>
 #include <vector>
 
@@ -58,6 +60,12 @@ struct Ctx {
     double2 *red = nullptr;     // read-out partials
     size_t red_elems = 0;
 };
+
+// the work buffers of precision R
+template <typename R> inline Work<R> &work_of(Ctx &c) {
+    if constexpr (std::is_same<R, double>::value) return c.w64;
+    else return c.w32;
+}
 
 // alpha of the context's material for a beam (LDR depends on the beam)
 void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im);

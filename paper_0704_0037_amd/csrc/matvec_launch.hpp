@@ -15,9 +15,6 @@
 
 namespace dda {
 
-template <typename R> inline Work<R> &work_of(Ctx &c);
-template <> inline Work<double> &work_of<double>(Ctx &c) { return c.w64; }
-template <> inline Work<float> &work_of<float>(Ctx &c) { return c.w32; }
 template <typename R> inline const cplx<R> *tw_of(const Ctx &c);
 template <> inline const double2 *tw_of<double>(const Ctx &c) { return c.tw64; }
 template <> inline const float2 *tw_of<float>(const Ctx &c) { return c.tw32; }

@@ -199,10 +199,6 @@ void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
     im = -ii / n2;
 }
 
-template <typename R> static Work<R> &work_of(Ctx &c);
-template <> Work<double> &work_of<double>(Ctx &c) { return c.w64; }
-template <> Work<float> &work_of<float>(Ctx &c) { return c.w32; }
-
 template <typename R> static void free_work(Work<R> &w) {
     (void)hipFree(w.B1);
     (void)hipFree(w.B2);

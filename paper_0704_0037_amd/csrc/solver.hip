@@ -643,16 +643,11 @@ template <typename R> static Vecs<R> vecs_of(Ctx &c, int nrhs) {
     return v;
 }
 
-template <typename R> static Work<R> &work(Ctx &c) {
-    if constexpr (std::is_same<R, double>::value) return c.w64;
-    else return c.w32;
-}
-
 // device scales alpha / (Lx Ly Lz) per right-hand side, in the work buffer of precision R
 template <typename R> static dda_status upload_scales(Ctx &c, const std::vector<double> &ar, const std::vector<double> &ai) {
     dda_status st = ensure_work<R>(c, (int)ar.size());
     if (st != DDA_OK) return st;
-    Work<R> &w = work<R>(c);
+    Work<R> &w = work_of<R>(c);
     std::vector<cplx<R>> sc(ar.size());
     const double inv = 1.0 / ((double)c.Lx * c.Ly * c.Lz);
     for (size_t r = 0; r < ar.size(); ++r) sc[r] = mk<cplx<R>>((R)(ar[r] * inv), (R)(ai[r] * inv));
@@ -747,7 +742,7 @@ template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count)
     const dim3 vg(B.nb, B.nrhs), vb(kVecThreads);
     const int nrhs = B.nrhs;
     const size_t n3 = B.n3;
-    Work<R> &w = work<R>(c);
+    Work<R> &w = work_of<R>(c);
     const int ndots = (int)dots_per_rhs(c);
     cplx<R> *x = k.x;
     dda_status st;
@@ -795,7 +790,7 @@ template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
     hipStream_t s = c.stream;
     const dim3 vg(B.nb, B.nrhs), vb(kVecThreads);
     const size_t n3 = B.n3;
-    Work<R> &w = work<R>(c);
+    Work<R> &w = work_of<R>(c);
     dda_status st;
     DDA_HIP_CHECK(hipEventCreateWithFlags(&k.ev, hipEventDisableTiming));
     if (have_x0) {

@@ -71,8 +71,8 @@ _SIGS = {
                                 ct.POINTER(ct.c_double)]),
     "dda_mueller": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p, ct.c_double,
                                ct.POINTER(ct.c_double), ct.c_int32, ct.POINTER(ct.c_double)]),
-    "dda_matvec_timed": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p, ct.c_int32,
-                                    ct.POINTER(ct.c_float), ct.POINTER(ct.c_float)]),
+    "dda_matvec_timed": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_int32, ct.c_void_p,
+                                    ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_float), ct.POINTER(ct.c_float)]),
     "dda_strerror": (ct.c_char_p, [ct.c_int]),
     "dda_last_error": (ct.c_char_p, []),
 }
@@ -224,12 +224,17 @@ class Context:
                                       _ptr(y, torch.complex128, (n, 3, self.n), "y")), "dda_matvec_batch")
         return y
 
-    def matvec_timed(self, beam, x, y, reps):
-        """Mean per-kernel and whole-product durations (ms) of `reps` back-to-back products."""
+    def matvec_timed(self, beams, x, y, reps, precision=FP64):
+        """Mean per-kernel and whole-product durations (ms) of `reps` back-to-back products of the
+        [n][3][N] batch x (one beam per vector; complex64 for FP32_REFINE)."""
+        if isinstance(beams, Beam) or hasattr(beams, "prop"):
+            beams = [beams]
+        n = len(beams)
+        dt = torch.complex128 if precision == FP64 else torch.complex64
         k = (ct.c_float * 5)()
         tot = ct.c_float()
-        _check(lib().dda_matvec_timed(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
-                                      _ptr(y, torch.complex128, (3, self.n), "y"), int(reps), k, ct.byref(tot)),
+        _check(lib().dda_matvec_timed(self._h, _beams(beams), n, int(precision), _ptr(x, dt, (n, 3, self.n), "x"),
+                                      _ptr(y, dt, (n, 3, self.n), "y"), int(reps), k, ct.byref(tot)),
                "dda_matvec_timed")
         return list(k), tot.value
 

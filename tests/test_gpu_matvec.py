@@ -149,3 +149,21 @@ def test_full_size_sphere256_sampled_rows():
     ref = odda.matvec_rows(pos, w.kd, odda.beta_of_alpha(alpha), x.T, rows)
     got = y[:, rows].T
     assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12
+
+
+def test_matvec_timed_returns_the_product():
+    """The measurement entry point computes the same product it times (fp64 batch and fp32)."""
+    from paper_0704_0037_amd import dda
+    mask = inputs.ellipsoid_mask((18, 14, 11), (9, 6.5, 5))
+    beams = inputs.beams_for_orientations(1, seed=4)
+    with dda.Context(mask, 1.3 + 0.02j, 0.4, fp32=True) as ctx:
+        x = torch.from_numpy(inputs.random_vector(ctx.n, seed=3, n_rhs=2)).cuda()
+        y = torch.empty_like(x)
+        kms, tot = ctx.matvec_timed(beams, x, y, reps=3)
+        assert all(k > 0 for k in kms) and tot >= 0.5 * sum(kms)
+        assert torch.equal(y, ctx.matvec_batch(beams, x))
+        x32 = x.to(torch.complex64)
+        y32 = torch.empty_like(x32)
+        kms, tot = ctx.matvec_timed(beams, x32, y32, reps=2, precision=dda.FP32_REFINE)
+        for r in range(2):
+            assert torch.equal(y32[r], ctx.matvec_f32(beams[r], x32[r].contiguous()))
