@@ -22,6 +22,11 @@ template <typename R> struct Work {
     size_t ndots = 0;
 };
 
+// lines per block of the x and y passes (powers of two) and their log2
+struct Tiles {
+    int nl_x = 0, nl_y = 0, lnl_x = 0, lnl_y = 0;
+};
+
 struct Ctx {
     int nx = 0, ny = 0, nz = 0;
     int Lx = 0, Ly = 0, Lz = 0;
@@ -30,8 +35,8 @@ struct Ctx {
     int polarizability = DDA_POL_LDR;
     hipStream_t stream = nullptr;      // the caller's stream (all calls are ordered on it)
     hipStream_t own_stream = nullptr;  // the context's own stream: solves run (and graphs capture) here
-    int nl_x = 0, nl_y = 0, nc_z = 0;  // lines per block (x, y passes) and columns per block (z pass)
-    int lnl_x = 0, lnl_y = 0;          // log2 of nl_x, nl_y (powers of two)
+    Tiles tl64, tl32;                  // lines per block of the x / y passes, per precision
+    int nc_z = 0;                      // columns per block (z pass)
 
     std::vector<uint8_t> mask;      // host copy [nz][ny][nx]
     std::vector<int32_t> lin_host;  // linear cell index of each dipole
@@ -91,7 +96,11 @@ dda_status matvec_device<float>(Ctx &c, const float2 *x, float2 *y, int nrhs, co
                                 hipStream_t s, const int *done, hipEvent_t *ev);
 
 // number of per-block dot partials the x-inverse kernel writes per right-hand side
-inline size_t dots_per_rhs(const Ctx &c) { return (size_t)3 * c.nz * ((c.ny + c.nl_x - 1) / c.nl_x); }
+template <typename R> inline const Tiles &tiles_of(const Ctx &c) { return sizeof(R) == 8 ? c.tl64 : c.tl32; }
+template <typename R> inline size_t dots_per_rhs(const Ctx &c) {
+    const Tiles &t = tiles_of<R>(c);
+    return (size_t)3 * c.nz * ((c.ny + t.nl_x - 1) / t.nl_x);
+}
 
 dda_status device_alloc(void **p, size_t bytes);
 

@@ -21,11 +21,17 @@ constexpr int kMaxPass = 12;
 #ifndef DDA_MAX_THREADS
 #define DDA_MAX_THREADS 512   // block-size bound of the x / y pass kernels
 #endif
+// block-size bound of the x / y pass kernels per precision: single-precision lines need twice the
+// lines per block for the same 128-byte runs on their transposed side, and fit the registers
+template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_MAX_THREADS : 2 * DDA_MAX_THREADS; }
 #ifndef DDA_ZMUL_SLOTS
-#define DDA_ZMUL_SLOTS 4      // mirror columns per z-pass block (1, 2 or 4)
+#define DDA_ZMUL_SLOTS 1      // mirror columns processed side by side in a z-pass block (1, 2 or 4)
 #endif
 #ifndef DDA_ZMUL_THREADS
-#define DDA_ZMUL_THREADS 768  // block-size bound of the fused z-pass kernel
+#define DDA_ZMUL_THREADS (DDA_ZMUL_SLOTS * 3 * 64)  // block-size bound of the fused z-pass kernel
+#endif
+#ifndef DDA_ZMUL_WAVES_PER_EU
+#define DDA_ZMUL_WAVES_PER_EU 3  // register budget of the z pass: three 3-wave blocks per CU at fp64
 #endif
 #ifndef DDA_LDS_CAP
 #define DDA_LDS_CAP (96 * 1024)  // LDS bytes a matvec block may take

@@ -29,7 +29,7 @@ constexpr int kMaxRadixZ = 8;   // the fused z pass keeps three components in re
 // Block: component c, plane z, NL consecutive lines y.  Gathers x from the compact vector
 // (zero for void cells and for the padding), transforms along x, writes B1[c][z][kx][y].
 template <typename R, int LC>
-__global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ x,
+__global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ x,
                                                 cplx<R> *__restrict__ B1, int nx, int ny, int nz, int N,
                                                 FftPlan pl_rt, const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_x(const int *__restrict
 // Block: component c, column kx, NL consecutive planes z.  Reads B1 lines along y (n_y
 // nonzero entries), transforms, writes B2[ky][kx][c][z].
 template <typename R, int LC>
-__global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__restrict__ B1, cplx<R> *__restrict__ B2, int ny,
+__global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__restrict__ B1, cplx<R> *__restrict__ B2, int ny,
                                                 int nz, int Lx, int ncomp, FftPlan pl_rt,
                                                 const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
@@ -150,8 +150,9 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__rest
 
 // ------------------------------------------------- K3: forward z, tensor multiply, inverse z
 // The (up to) four columns (kx, ky) with kx in {kxo, Lx - kxo}, ky in {kyo, Ly - kyo} share one
-// octant column (kxo, kyo) of the tensor.  A block takes DDA_ZMUL_SLOTS of them (one right-hand
-// side), stages the octant column's six kz-runs in LDS and processes its columns side by side.
+// octant column (kxo, kyo) of the tensor.  A block owns one octant column: it stages the column's
+// six kz-runs in LDS once and then runs, for every right-hand side, its mirror columns through
+// the z pass, DDA_ZMUL_SLOTS of them side by side per round.  The tensor is read once per batch.
 //
 // Within a column, thread (comp, j) owns butterfly j of the line of one component (one wave per
 // line at L = 512).  After the forward passes the three transformed lines sit in LDS in natural
@@ -159,7 +160,7 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fwd_y(const cplx<R> *__rest
 // that the first inverse pass (radix R0, the forward plan reversed) needs from it, straight into
 // registers.
 template <typename R, int LC>
-__global__ void __launch_bounds__(DDA_ZMUL_THREADS) k_zmul(cplx<R> *__restrict__ B2, const cplx<R> *__restrict__ Gh,
+__global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmul(cplx<R> *__restrict__ B2, const cplx<R> *__restrict__ Gh,
                                                           int nz, int Lx, int Ly, int nrhs, FftPlan pf_rt,
                                                           FftPlan pi_rt, const cplx<R> *__restrict__ twall,
                                                           const int *__restrict__ done) {
@@ -172,14 +173,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS) k_zmul(cplx<R> *__restrict__
     const int R0 = pf.radix[0];
     const int Ri = pi.radix[0];  // == pf.radix[np - 1]
     const int qi = L / Ri;
-    const int rhs = blockIdx.y;
-    if (done && done[rhs]) return;  // this right-hand side has converged
-    // XCD-aware block order: consecutive logical blocks (the groups of one octant column) run on
-    // the same XCD, whose L2 then serves the repeated reads of the tensor column
+    // XCD-aware block order: neighbouring octant columns run on the same XCD
     const int per_xcd = gridDim.x / 8;
-    const int lb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    const int ngroups = 4 / DDA_ZMUL_SLOTS;
-    const int oct = lb / ngroups;
+    const int oct = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int hx = Lx / 2, hy = Ly / 2, hz = L / 2, hz1 = hz + 1;
     if (oct >= (hx + 1) * (hy + 1)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -187,13 +183,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS) k_zmul(cplx<R> *__restrict__
     const C *tw = twall + pf_rt.tw_off;
     const int t = threadIdx.x;
     const int lslot = t / (3 * TPL), comp = (t / TPL) % 3, j = t % TPL;
-    const int slot = (lb % ngroups) * DDA_ZMUL_SLOTS + lslot;  // mirror 0..3 of the octant column
     const int kxo = oct % (hx + 1), kyo = oct / (hx + 1);
     const int nmx = (kxo == 0 || 2 * kxo == Lx) ? 1 : 2;  // distinct x mirrors of this column
     const int nmy = (kyo == 0 || 2 * kyo == Ly) ? 1 : 2;
-    const bool mxs = slot & 1, mys = slot & 2;
-    const bool ok = (!mxs || nmx == 2) && (!mys || nmy == 2);  // slot holds a distinct column
-    const int kx = mxs ? Lx - kxo : kxo, ky = mys ? Ly - kyo : kyo;
     C *gsh = lds;                            // [6][hz1] tensor runs of this octant column
     C *lcol = lds + 6 * hz1 + lslot * 3 * S;  // [3][S] the three component lines of this slot
     C *ln = lcol + comp * S;
@@ -201,65 +193,91 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS) k_zmul(cplx<R> *__restrict__
         const C *gcol = Gh + (size_t)oct * 6 * hz1;
         for (int e = t; e < 6 * hz1; e += blockDim.x) gsh[e] = gcol[e];
     }
-    C *line = B2 + (((size_t)(ok ? ky : 0) * Lx + (ok ? kx : 0)) * (3 * nrhs) + rhs * 3 + comp) * nz;
-    if (j < L / R0) {
-        C a[kMaxRadixZ];
-        load_rt<-1, kMaxRadixZ>(a, R0, j, L, 1, tw, [&](int i) -> C { return (ok && i < nz) ? line[i] : czero<C>(); });
-        store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
-    }
     constexpr bool W = wave_lines<LC, kMaxRadixZ>();
-    lds_sync<W>();
-    lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, tw);  // natural order in LDS afterwards
-    if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
-    C a[kMaxRadixZ];
+    constexpr int ngroups = 4 / DDA_ZMUL_SLOTS;
     const bool act = j < qi;
-    if (act) {
-        // G[comp][d] for d = x, y, z and their signs under the mirrors: a component is odd along an
-        // axis when exactly one of its indices is that axis; the z-odd ones (xz, yz) pick up sz
-        const R sx = mxs ? (R)-1 : (R)1, sy = mys ? (R)-1 : (R)1;
-        const R s0 = comp == 0 ? (R)1 : comp == 1 ? sx * sy : sx;
-        const R s1 = comp == 0 ? sx * sy : comp == 1 ? (R)1 : sy;
-        const R s2 = comp == 0 ? sx : comp == 1 ? sy : (R)1;
-        const int g0 = comp == 0 ? 0 : comp == 1 ? 1 : 2;  // row comp: (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
-        const int g1 = comp == 0 ? 1 : comp == 1 ? 3 : 4;
-        const int g2 = comp == 0 ? 2 : comp == 1 ? 4 : 5;
-        auto mul = [&](auto radix_tag) {
-            constexpr int RI = decltype(radix_tag)::value;
-#pragma unroll
-            for (int r = 0; r < RI; ++r) {
-                const int kz = j + r * qi;
-                const bool lo = kz <= hz;
-                const R sz = lo ? (R)1 : (R)-1;
-                const C *g = gsh + (lo ? kz : L - kz);
-                const C G0 = cscale(g[g0 * hz1], comp == 2 ? s0 * sz : s0);
-                const C G1 = cscale(g[g1 * hz1], comp == 2 ? s1 * sz : s1);
-                const C G2 = cscale(g[g2 * hz1], comp == 2 ? s2 : s2 * sz);
-                const int p = pidx(kz);
-                const C X = lcol[p], Y = lcol[S + p], Z = lcol[2 * S + p];
-                a[r] = cadd(cadd(cmul(G0, X), cmul(G1, Y)), cmul(G2, Z));
-            }
-            dftR<+1, RI>(a);
-        };
-        switch (Ri) {
-            case 1: mul(std::integral_constant<int, 1>{}); break;
-            case 2: mul(std::integral_constant<int, 2>{}); break;
-            case 3: mul(std::integral_constant<int, 3>{}); break;
-            case 4: mul(std::integral_constant<int, 4>{}); break;
-            case 5: mul(std::integral_constant<int, 5>{}); break;
-            default: mul(std::integral_constant<int, 8>{}); break;
+    // G[comp][d] for d = x, y, z: row comp of the symmetric tensor is (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
+    const int g0 = comp == 0 ? 0 : comp == 1 ? 1 : 2;
+    const int g1 = comp == 0 ? 1 : comp == 1 ? 3 : 4;
+    const int g2 = comp == 0 ? 2 : comp == 1 ? 4 : 5;
+    // rounds q = rhs * ngroups + grp; a round is skipped when its right-hand side has converged or
+    // its group holds no distinct column
+    const int Q = nrhs * ngroups;
+    auto next_round = [&](int q) {
+        for (; q < Q; ++q) {
+            const int rhs = q / ngroups, slot0 = (q % ngroups) * DDA_ZMUL_SLOTS;
+            if (done && done[rhs]) continue;
+            if (((slot0 & 1) && nmx == 1) || ((slot0 & 2) && nmy == 1)) continue;
+            break;
         }
-    }
-    __syncthreads();  // every thread has read the three transformed lines
-    if (np == 1) {
-        if (act && ok) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { if (i < nz) line[i] = v; });
-        return;
-    }
-    if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
-    lds_sync<W>();
-    lds_passes<+1, kMaxRadixZ, LC, true>(ln, pi_rt, 1, np - 1, j, tw);
-    if (j < L / RQ) {
-        load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, tw, [&](int i) { return ln[pidx(i)]; });
-        if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) line[i] = v; });
+        return q;
+    };
+    const int q0 = L / R0;
+    for (int q = next_round(0); q < Q; q = next_round(q + 1)) {
+        const int rhs = q / ngroups, grp = q % ngroups;
+        {
+            const int slot = grp * DDA_ZMUL_SLOTS + lslot;  // mirror 0..3 of the octant column
+            const bool mxs = slot & 1, mys = slot & 2;
+            const bool ok = (!mxs || nmx == 2) && (!mys || nmy == 2);  // slot holds a distinct column
+            const int kx = mxs ? Lx - kxo : kxo, ky = mys ? Ly - kyo : kyo;
+            C *line = B2 + (((size_t)(ok ? ky : 0) * Lx + (ok ? kx : 0)) * (3 * nrhs) + rhs * 3 + comp) * nz;
+            if (j < q0) {
+                C a[kMaxRadixZ];
+                load_rt<-1, kMaxRadixZ>(a, R0, j, L, 1, tw,
+                                        [&](int i) -> C { return (ok && i < nz) ? line[i] : czero<C>(); });
+                store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+            }
+            lds_sync<W>();
+            lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, tw);  // natural order in LDS afterwards
+            if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
+            C a[kMaxRadixZ];
+            if (act) {
+                // signs under the mirrors: a component is odd along an axis when exactly one of its
+                // indices is that axis; the z-odd ones (xz, yz) pick up sz
+                const R sx = mxs ? (R)-1 : (R)1, sy = mys ? (R)-1 : (R)1;
+                const R s0 = comp == 0 ? (R)1 : comp == 1 ? sx * sy : sx;
+                const R s1 = comp == 0 ? sx * sy : comp == 1 ? (R)1 : sy;
+                const R s2 = comp == 0 ? sx : comp == 1 ? sy : (R)1;
+                auto mul = [&](auto radix_tag) {
+                    constexpr int RI = decltype(radix_tag)::value;
+#pragma unroll
+                    for (int r = 0; r < RI; ++r) {
+                        const int kz = j + r * qi;
+                        const bool lo = kz <= hz;
+                        const R sz = lo ? (R)1 : (R)-1;
+                        const C *g = gsh + (lo ? kz : L - kz);
+                        const C G0 = cscale(g[g0 * hz1], comp == 2 ? s0 * sz : s0);
+                        const C G1 = cscale(g[g1 * hz1], comp == 2 ? s1 * sz : s1);
+                        const C G2 = cscale(g[g2 * hz1], comp == 2 ? s2 : s2 * sz);
+                        const int p = pidx(kz);
+                        const C X = lcol[p], Y = lcol[S + p], Z = lcol[2 * S + p];
+                        a[r] = cadd(cadd(cmul(G0, X), cmul(G1, Y)), cmul(G2, Z));
+                    }
+                    dftR<+1, RI>(a);
+                };
+                switch (Ri) {
+                    case 1: mul(std::integral_constant<int, 1>{}); break;
+                    case 2: mul(std::integral_constant<int, 2>{}); break;
+                    case 3: mul(std::integral_constant<int, 3>{}); break;
+                    case 4: mul(std::integral_constant<int, 4>{}); break;
+                    case 5: mul(std::integral_constant<int, 5>{}); break;
+                    default: mul(std::integral_constant<int, 8>{}); break;
+                }
+            }
+            __syncthreads();  // every thread has read the three transformed lines
+            if (np == 1) {
+                if (act && ok) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { if (i < nz) line[i] = v; });
+            } else {
+                if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+                lds_sync<W>();
+                lds_passes<+1, kMaxRadixZ, LC, true>(ln, pi_rt, 1, np - 1, j, tw);
+                if (j < L / RQ) {
+                    load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, tw, [&](int i) { return ln[pidx(i)]; });
+                    if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) line[i] = v; });
+                }
+            }
+            lds_sync<W>();  // the slot's lines are rewritten by the next round
+        }
     }
 }
 
@@ -272,7 +290,7 @@ __host__ __device__ constexpr size_t zmul_lds_elems(int Lz) {
 // Block: component c, column kx, NL consecutive planes z.  Reads B2 along ky (all Ly entries),
 // inverse transform, keeps y < ny, writes B1[c][z][kx][y].
 template <typename R, int LC>
-__global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_y(const cplx<R> *__restrict__ B2, cplx<R> *__restrict__ B1, int ny,
+__global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__restrict__ B2, cplx<R> *__restrict__ B1, int ny,
                                                 int nz, int Lx, int ncomp, FftPlan pl_rt,
                                                 const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
@@ -346,7 +364,7 @@ __device__ __forceinline__ cplx<R> block_sum(cplx<R> v, cplx<R> *scratch) {
 }
 
 template <typename R, int LC>
-__global__ void __launch_bounds__(DDA_MAX_THREADS) k_inv_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ B1,
+__global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ B1,
                                                 const cplx<R> *__restrict__ xin, cplx<R> *__restrict__ yout,
                                                 int nx, int ny, int nz, int N, FftPlan pl_rt,
                                                 const cplx<R> *__restrict__ twall, int lnl,

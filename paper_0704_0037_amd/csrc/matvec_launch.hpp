@@ -58,7 +58,8 @@ dda_status matvec_device_impl(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, co
     const C *tw = tw_of<R>(c);
     const C *gh = ghat_of<R>(c);
     const int ncomp = 3 * nrhs;
-    const int nlx = c.nl_x, nly = c.nl_y;
+    const Tiles &tl = tiles_of<R>(c);
+    const int nlx = tl.nl_x, nly = tl.nl_y;
     const int ytiles = (c.ny + nlx - 1) / nlx, ztiles = (c.nz + nly - 1) / nly;
     const size_t lx_bytes = (size_t)nlx * lds_line_stride(c.Lx) * sizeof(C);
     const size_t ly_bytes = (size_t)nly * lds_line_stride(c.Ly) * sizeof(C);
@@ -66,21 +67,21 @@ dda_status matvec_device_impl(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, co
     const int N = (int)c.N;
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[0], s));
 #define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, x, w.B1, c.nx, c.ny, c.nz, N, \
-                 c.pxf, tw, c.lnl_x, done
+                 c.pxf, tw, tl.lnl_x, done
 #define DDA_BYTES lx_bytes
     DDA_DISPATCH(c.Lx, k_fwd_x, DDA_BYTES, DDA_ARGS)
 #undef DDA_BYTES
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[1], s));
 #define DDA_ARGS dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyf.tpl), ly_bytes, s, w.B1, w.B2, c.ny, c.nz, c.Lx, ncomp, \
-                 c.pyf, tw, c.lnl_y, done
+                 c.pyf, tw, tl.lnl_y, done
 #define DDA_BYTES ly_bytes
     DDA_DISPATCH(c.Ly, k_fwd_y, DDA_BYTES, DDA_ARGS)
 #undef DDA_BYTES
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[2], s));
-    const int zblocks = (c.Lx / 2 + 1) * (c.Ly / 2 + 1) * (4 / DDA_ZMUL_SLOTS);
-#define DDA_ARGS dim3((zblocks + 7) / 8 * 8, nrhs), dim3(DDA_ZMUL_SLOTS * 3 * c.pzf.tpl), lz_bytes, s, w.B2, gh, c.nz, \
+    const int zblocks = (c.Lx / 2 + 1) * (c.Ly / 2 + 1);  // one block per octant column
+#define DDA_ARGS dim3((zblocks + 7) / 8 * 8), dim3(DDA_ZMUL_SLOTS * 3 * c.pzf.tpl), lz_bytes, s, w.B2, gh, c.nz, \
                  c.Lx, c.Ly, nrhs, c.pzf, c.pzi, tw, done
 #define DDA_BYTES lz_bytes
     DDA_DISPATCH(c.Lz, k_zmul, DDA_BYTES, DDA_ARGS)
@@ -88,14 +89,14 @@ dda_status matvec_device_impl(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, co
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[3], s));
 #define DDA_ARGS dim3(ncomp * c.Lx * ztiles), dim3(nly * c.pyi.tpl), ly_bytes, s, w.B2, w.B1, c.ny, c.nz, c.Lx, ncomp, \
-                 c.pyi, tw, c.lnl_y, done
+                 c.pyi, tw, tl.lnl_y, done
 #define DDA_BYTES ly_bytes
     DDA_DISPATCH(c.Ly, k_inv_y, DDA_BYTES, DDA_ARGS)
 #undef DDA_BYTES
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[4], s));
 #define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, w.B1, x, y, c.nx, c.ny, c.nz, \
-                 N, c.pxi, tw, c.lnl_x, scale, dots, done
+                 N, c.pxi, tw, tl.lnl_x, scale, dots, done
 #define DDA_BYTES lx_bytes
     DDA_DISPATCH(c.Lx, k_inv_x, DDA_BYTES, DDA_ARGS)
 #undef DDA_BYTES

@@ -47,8 +47,7 @@ static int smallest_pad(int n) {
 
 // lines per block (a power of two, returned as its log2): up to DDA_MAX_THREADS threads,
 // preferably a whole number of waves, LDS within DDA_LDS_CAP
-static int pick_lines_log2(int tpl, int line_bytes, int ndim, int want) {
-    const int maxt = DDA_MAX_THREADS;
+static int pick_lines_log2(int tpl, int line_bytes, int ndim, int want, int maxt = DDA_MAX_THREADS) {
     int nl = want > 0 ? want : std::max(1, maxt / tpl);
     if (want <= 0) nl = std::min(nl, std::max(ndim, 1));
     int l = 0;
@@ -217,7 +216,7 @@ template <typename R> dda_status ensure_work(Ctx &c, int nrhs) {
     if ((st = device_alloc((void **)&w.B1, nc * c.nz * (size_t)c.Lx * c.ny * sizeof(cplx<R>))) != DDA_OK) return st;
     if ((st = device_alloc((void **)&w.B2, nc * c.nz * (size_t)c.Lx * c.Ly * sizeof(cplx<R>))) != DDA_OK) return st;
     if ((st = device_alloc((void **)&w.scale, (size_t)nrhs * sizeof(cplx<R>))) != DDA_OK) return st;
-    w.ndots = dots_per_rhs(c) * nrhs;
+    w.ndots = dots_per_rhs<R>(c) * nrhs;
     if ((st = device_alloc((void **)&w.dots, w.ndots * sizeof(cplx<R>))) != DDA_OK) return st;
     w.nrhs = nrhs;
     return DDA_OK;
@@ -411,14 +410,19 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
             tw32[offs[i] + mm] = make_float2((float)cosl(ang), (float)sinl(ang));
         }
     const int want_nl = opts ? opts->lines_per_block : 0;
-    c->lnl_x = pick_lines_log2(c->pxf.tpl, lds_line_stride(c->Lx) * 16, c->ny, want_nl);
-    c->lnl_y = pick_lines_log2(c->pyf.tpl, lds_line_stride(c->Ly) * 16, c->nz, want_nl);
-    c->nl_x = 1 << c->lnl_x;
-    c->nl_y = 1 << c->lnl_y;
+    auto tiles = [&](Tiles &t, int cb, int maxt) {
+        // fp32 at the automatic setting: twice the lines, so the transposed side still moves
+        // 128-byte runs
+        const int want = want_nl > 0 ? want_nl : 0;
+        t.lnl_x = pick_lines_log2(c->pxf.tpl, lds_line_stride(c->Lx) * cb, c->ny, want, maxt);
+        t.lnl_y = pick_lines_log2(c->pyf.tpl, lds_line_stride(c->Ly) * cb, c->nz, want, maxt);
+        t.nl_x = 1 << t.lnl_x;
+        t.nl_y = 1 << t.lnl_y;
+        return t.nl_x * c->pxf.tpl <= maxt && t.nl_y * c->pyf.tpl <= maxt;
+    };
+    const bool tiles_ok = tiles(c->tl64, 16, max_threads<double>()) && tiles(c->tl32, 8, max_threads<float>());
     c->nc_z = 1;
-    if (DDA_ZMUL_SLOTS * 3 * c->pzf.tpl > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 ||
-        c->nl_x * c->pxf.tpl > DDA_MAX_THREADS ||
-        c->nl_y * c->pyf.tpl > DDA_MAX_THREADS) {
+    if (DDA_ZMUL_SLOTS * 3 * c->pzf.tpl > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 || !tiles_ok) {
         set_error("dda_setup: padded size too large for one workgroup per line");
         delete c;
         return DDA_EINVAL;

@@ -743,7 +743,7 @@ template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count)
     const int nrhs = B.nrhs;
     const size_t n3 = B.n3;
     Work<R> &w = work_of<R>(c);
-    const int ndots = (int)dots_per_rhs(c);
+    const int ndots = (int)dots_per_rhs<R>(c);
     cplx<R> *x = k.x;
     dda_status st;
     for (int it = 0; it < count; ++it) {
