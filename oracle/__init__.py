@@ -11,8 +11,10 @@ Modules
   dda  — lattice, polarizability, Green's tensor, interaction matrix (dense and direct
          sum), incident field, QMR and Bi-CGSTAB, cross sections, far field, Mueller.
   mie  — Mie theory for a homogeneous sphere (the exact reference the paper compares to).
+  convnet — the learned-initial-guess network: forward, masked loss, exact gradient, and the
+         features / target / guess maps between a DDA solution and the network's grid.
 
 Parity status of each function is stated in its docstring ("pinned by ..." or
 "parity unpinned").
 """
-from . import dda, mie  # noqa: F401
+from . import convnet, dda, mie  # noqa: F401
