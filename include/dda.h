@@ -89,6 +89,7 @@ typedef struct {
     double inner_tol;      /* DDA_FP32_REFINE: relative tolerance of each inner solve; 0 = 1e-2 */
     const void *x0;        /* device initial guess, same layout as x_out; NULL = zero */
     int32_t graph;         /* iterations replayed as a captured hipGraph: 0 = automatic, 1 = on, -1 = off */
+    int32_t x0_check;      /* 1: keep x0 for a right-hand side only if |b - A x0| < |b|, else start from 0 */
 } dda_solve_opts;
 
 /* Per-right-hand-side report of dda_solve. */
@@ -221,6 +222,64 @@ dda_status dda_mueller(dda_ctx *ctx, const dda_beam *beam, const void *x1, const
  */
 dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, int32_t precision,
                             const void *x, void *y, int32_t reps, float kernel_ms[5], float *total_ms);
+
+/* ------------------------------------------------------------------ learned initial guess
+ * A small 3-D convolutional network supplies QMR's starting vector (the paper's iteration starts
+ * from an initial guess it leaves open, Sec. 2; plain QMR from x0 = 0 stays the fallback and the
+ * judge of convergence, see dda_solve_opts.x0_check).  The particle is placed at the centre of a
+ * G^3 box (G a multiple of 8, each particle grid side <= G).
+ *
+ * Network, on channels-last tensors [batch][z][y][x][c]:
+ *   e0 = relu(conv(f, W0) + b0)         G    16 -> 16     d2 = relu(conv(up(e3), W4) + b4 + e2)  G/4  64 -> 48
+ *   e1 = relu(conv(pool(e0), W1) + b1)  G/2  16 -> 32     d1 = relu(conv(up(d2), W5) + b5 + e1)  G/2  48 -> 32
+ *   e2 = relu(conv(pool(e1), W2) + b2)  G/4  32 -> 48     d0 = relu(conv(up(d1), W6) + b6 + e0)  G    32 -> 16
+ *   e3 = relu(conv(pool(e2), W3) + b3)  G/8  48 -> 64     out = conv(d0, W7) + b7                 G    16 -> 6
+ * conv = 3x3x3 zero-padded cross-correlation with W[t][co][ci], t = 9(dz+1) + 3(dy+1) + (dx+1);
+ * pool = 2x2x2 mean; up = nearest-neighbour doubling.  Weights are kept as fp32 masters and used as
+ * bfloat16; activations and stored gradients are bfloat16; products accumulate in fp32.
+ * Parameters (host float32, dda_net_num_params() of them): per layer in order W (27*Cout*Cin,
+ * tap-major, then Cout, then Cin) then b (Cout).
+ * Features (device bfloat16 [G^3][16]): 0 mask, 1 (Re m - 1) mask, 2 Im m mask, 3 kd, 4..9 Re/Im
+ * of E_inc = e exp(i kd a.r) for x, y, z at every box cell (r the particle-frame position of the
+ * cell), 10..15 Re/Im of (m^2 - 1) E_inc mask for x, y, z.  Output / target (device float32 [G^3][6]): Re/Im of
+ * E_exc - E_inc at the dipoles (E_exc = x / beta, P = beta x, eq. 3); zero elsewhere.
+ * Loss: mean over dipole cells of the squared output error summed over the 6 channels.
+ */
+typedef struct dda_net dda_net;
+
+int64_t dda_net_num_params(void);
+
+/* Network for a G^3 box and batches of up to max_batch particles; params host float32.  Work runs
+ * on `stream` (a hipStream_t, NULL = default). */
+dda_status dda_net_create(dda_net **out, int32_t grid, int32_t max_batch, const float *params, void *stream);
+dda_status dda_net_free(dda_net *net);
+/* Replace the parameters (and reset the optimizer state) / read them back (host float32). */
+dda_status dda_net_set_params(dda_net *net, const float *params);
+dda_status dda_net_get_params(dda_net *net, float *params);
+
+/* Features of the context's particle for one beam into feat (device bfloat16 [G^3][16]). */
+dda_status dda_net_features(dda_net *net, dda_ctx *ctx, const dda_beam *beam, void *feat);
+
+/* Training target from a solution x (device complex128 [3][N]) into tgt (device float32 [G^3][6]). */
+dda_status dda_net_target(dda_net *net, dda_ctx *ctx, const dda_beam *beam, const void *x, void *tgt);
+
+/* out (device float32 [batch][G^3][6]) = network(feat [batch][G^3][16]). */
+dda_status dda_net_forward(dda_net *net, const void *feat, int32_t batch, void *out);
+
+/* Loss of a batch and its gradient (host float32 [num_params] in the parameter layout, or NULL). */
+dda_status dda_net_grad(dda_net *net, const void *feat, const void *tgt, int32_t batch, double *loss,
+                        float *grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on a batch; returns the loss
+ * before the step. */
+dda_status dda_net_train_step(dda_net *net, const void *feat, const void *tgt, int32_t batch, double lr,
+                              double *loss);
+
+/* Initial guesses x0 = beta (E_inc + out) for n_rhs beams on one particle (feat: their features,
+ * device bfloat16 [n_rhs][G^3][16]); x0 device complex128 [n_rhs][3][N], ready for
+ * dda_solve_opts.x0. */
+dda_status dda_guess(dda_ctx *ctx, dda_net *net, const dda_beam *beams, int32_t n_rhs, const void *feat,
+                     void *x0);
 
 /* Human-readable name of a status code. */
 const char *dda_strerror(dda_status status);

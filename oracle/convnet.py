@@ -9,7 +9,7 @@ reference the GPU kernels must reproduce.
 
 Network (grid G per side, G a multiple of 8; channels-last arrays [G][G][G][C], z slowest):
 
-    e0 = relu(conv(f,  W0) + b0)              G,    10 -> 16
+    e0 = relu(conv(f,  W0) + b0)              G,    16 -> 16
     e1 = relu(conv(pool(e0), W1) + b1)        G/2,  16 -> 32
     e2 = relu(conv(pool(e1), W2) + b2)        G/4,  32 -> 48
     e3 = relu(conv(pool(e2), W3) + b3)        G/8,  48 -> 64
@@ -25,11 +25,13 @@ pool: mean over 2x2x2 blocks; up: nearest-neighbour doubling.
 Parameters, canonical flat layout (float32): for each layer in order, W (27*Cout*Cin, tap-major,
 then Cout, then Cin) followed by b (Cout).
 
-Input features (10 channels) for a particle on an n = (nx, ny, nz) grid placed in the G^3 box at
+Input features (16 channels) for a particle on an n = (nx, ny, nz) grid placed in the G^3 box at
 offset o = (G - n) // 2 per axis, at box cell (X, Y, Z) with particle-frame position
 r = (X - ox + 1/2 - nx/2, ...):
     0 mask, 1 (Re m - 1) mask, 2 (Im m) mask, 3 kd (everywhere),
-    4..9 Re/Im of the incident field E_inc(r) = e exp(i kd a.r) components x, y, z (everywhere).
+    4..9 Re/Im of the incident field E_inc(r) = e exp(i kd a.r) components x, y, z (everywhere),
+    10..15 Re/Im of (m^2 - 1) E_inc(r) mask, components x, y, z (the product a ReLU network
+    cannot form from the other channels).
 Output / target (6 channels): Re/Im of delta = E_exc - E_inc per component at the dipoles, with
 E_exc = x / beta the exciting field of the solution x of A x = b (P = beta x, eq. 3).  The guess
 is x0 = beta (E_inc + delta).
@@ -48,7 +50,7 @@ from __future__ import annotations
 
 import numpy as np
 
-N_IN, N_OUT = 10, 6
+N_IN, N_OUT = 16, 6
 LEVELS = (16, 32, 48, 64)
 # (cin, cout, level, input kind, skip)
 LAYERS = (
@@ -261,8 +263,11 @@ def features(mask, m, kd, prop, pol, G):
     f[..., 1] = (np.real(m) - 1.0) * mk
     f[..., 2] = np.imag(m) * mk
     f[..., 3] = kd
-    f[..., 4::2] = E.real
-    f[..., 5::2] = E.imag
+    f[..., 4:10:2] = E.real
+    f[..., 5:10:2] = E.imag
+    P = (m * m - 1.0) * E * mk[..., None]
+    f[..., 10::2] = P.real
+    f[..., 11::2] = P.imag
     return f
 
 

@@ -901,6 +901,18 @@ static dda_status true_residual(Ctx &c, Bufs &B, Vecs<double> &v, const double2 
     return DDA_OK;
 }
 
+// Initial-guess check: a right-hand side whose guess does not lower the residual below |b|
+// starts from zero instead (b must be in v.b).
+static dda_status check_x0(Ctx &c, Bufs &B, Vecs<double> &v, double2 *x, int nrhs) {
+    std::vector<double> r0;
+    dda_status st = true_residual(c, B, v, x, nullptr, r0);
+    if (st != DDA_OK) return st;
+    for (int r = 0; r < nrhs; ++r)
+        if (!(r0[r] < 1.0)) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, c.stream, x + (size_t)r * B.n3, B.n3);
+    DDA_HIP_CHECK(hipGetLastError());
+    return DDA_OK;
+}
+
 static dda_status status_of(int s) {
     return s == ST_CONV ? DDA_OK : s == ST_MAXIT ? DDA_ENOTCONV : s == ST_BREAK ? DDA_EBREAKDOWN : DDA_ENOTCONV;
 }
@@ -931,6 +943,7 @@ static dda_status prepare_fp64(Ctx &c, Run<double> &k, const dda_beam *beams, in
     if (o.x0 && o.x0 != x)
         DDA_HIP_CHECK(hipMemcpyAsync(x, o.x0, (size_t)nrhs * k.B.n3 * sizeof(double2), hipMemcpyDeviceToDevice,
                                      c.stream));
+    if (o.x0 && o.x0_check && (st = check_x0(c, k.B, k.v, x, nrhs)) != DDA_OK) return st;
     if ((st = init_states(c, k.B, tol, o.maxit)) != DDA_OK) return st;
     return run_begin(k, o.x0 != nullptr);
 }
@@ -958,7 +971,7 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
         info[r].status = sr;
         info[r].iters = h[r].iter;
         const bool bi = o.solver == DDA_BICGSTAB;
-        info[r].matvecs = (bi ? 2 * h[r].iter - (h[r].half ? 1 : 0) : h[r].iter) + (o.x0 ? 1 : 0);
+        info[r].matvecs = (bi ? 2 * h[r].iter - (h[r].half ? 1 : 0) : h[r].iter) + (o.x0 ? 1 + (o.x0_check ? 1 : 0) : 0);
         info[r].outer = 0;
         info[r].res_rec = h[r].res;
         info[r].res_true = rt[r];
@@ -1017,6 +1030,7 @@ static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double t
     if (o.x0 && o.x0 != x)
         DDA_HIP_CHECK(hipMemcpyAsync(x, o.x0, (size_t)nrhs * B.n3 * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
     if (!o.x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, c.stream, x, (size_t)nrhs * B.n3);
+    if (o.x0 && o.x0_check && (st = check_x0(c, B, v, x, nrhs)) != DDA_OK) return st;
     const double inner = o.inner_tol > 0 ? o.inner_tol : 1e-2;
     std::vector<int> iters(nrhs, 0), mvs(nrhs, 0), outer(nrhs, 0), active(nrhs, 1);
     std::vector<double> res(nrhs, 1.0), scale(nrhs, 1.0);

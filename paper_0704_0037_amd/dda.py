@@ -32,7 +32,7 @@ class SetupOpts(ct.Structure):
 class SolveOpts(ct.Structure):
     _fields_ = [("solver", ct.c_int32), ("precision", ct.c_int32), ("maxit", ct.c_int32),
                 ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p),
-                ("graph", ct.c_int32)]
+                ("graph", ct.c_int32), ("x0_check", ct.c_int32)]
 
 
 class SolveInfo(ct.Structure):
@@ -73,6 +73,19 @@ _SIGS = {
                                ct.POINTER(ct.c_double), ct.c_int32, ct.POINTER(ct.c_double)]),
     "dda_matvec_timed": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_int32, ct.c_void_p,
                                     ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_float), ct.POINTER(ct.c_float)]),
+    "dda_net_num_params": (ct.c_int64, []),
+    "dda_net_create": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p]),
+    "dda_net_free": (ct.c_int, [ct.c_void_p]),
+    "dda_net_set_params": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "dda_net_get_params": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "dda_net_features": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
+    "dda_net_target": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
+    "dda_net_forward": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p]),
+    "dda_net_grad": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double),
+                                ct.c_void_p]),
+    "dda_net_train_step": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_double,
+                                      ct.POINTER(ct.c_double)]),
+    "dda_guess": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_void_p, ct.c_void_p]),
     "dda_strerror": (ct.c_char_p, [ct.c_int]),
     "dda_last_error": (ct.c_char_p, []),
 }
@@ -239,11 +252,12 @@ class Context:
         return list(k), tot.value
 
     def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
-              x_out=None, history=0, raise_on_fail=True, graph=0):
+              x_out=None, history=0, raise_on_fail=True, graph=0, x0_check=False):
         n = len(beams)
         x_out = self.vector(n) if x_out is None else x_out
         opts = SolveOpts(solver, precision, maxit, check_every, inner_tol,
-                         None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value, graph)
+                         None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value, graph,
+                         1 if x0_check else 0)
         infos = (SolveInfo * n)()
         hists = []
         for i in range(n):
@@ -301,9 +315,108 @@ def solve_many(contexts, beams, tol=1e-5, solver=QMR, maxit=0, check_every=0, gr
     xs = [c.vector() for c in contexts] if x_out is None else list(x_out)
     hs = (ct.c_void_p * n)(*[c._h.value for c in contexts])
     ps = (ct.c_void_p * n)(*[_ptr(x, torch.complex128, (3, c.n), "x_out").value for x, c in zip(xs, contexts)])
-    opts = SolveOpts(solver, FP64, maxit, check_every, 0.0, None, graph)
+    opts = SolveOpts(solver, FP64, maxit, check_every, 0.0, None, graph, 0)
     infos = (SolveInfo * n)()
     st = lib().dda_solve_many(hs, n, _beams(beams), float(tol), ct.byref(opts), ps, infos)
     if raise_on_fail and st != OK:
         _check(st, "dda_solve_many")
     return xs, [_info_dict(infos[i]) for i in range(n)], st
+
+
+class Net:
+    """The learned-initial-guess network on a G^3 box (wraps dda_net_*)."""
+
+    def __init__(self, grid, params, max_batch=8, device="cuda"):
+        params = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if params.size != num_params():
+            raise ValueError(f"expected {num_params()} parameters, got {params.size}")
+        self.grid = int(grid)
+        self.max_batch = int(max_batch)
+        self.device = torch.device(device)
+        h = ct.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().dda_net_create(ct.byref(h), self.grid, self.max_batch, params.ctypes.data, ct.c_void_p(stream)),
+               "dda_net_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dda_net_free(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def cells(self):
+        return self.grid ** 3
+
+    def params(self):
+        out = np.empty(num_params(), dtype=np.float32)
+        _check(lib().dda_net_get_params(self._h, out.ctypes.data), "dda_net_get_params")
+        return out
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        _check(lib().dda_net_set_params(self._h, params.ctypes.data), "dda_net_set_params")
+
+    def features(self, ctx, beam, out=None):
+        out = torch.empty((self.cells, 16), dtype=torch.bfloat16, device=self.device) if out is None else out
+        _check(lib().dda_net_features(self._h, ctx._h, ct.byref(_beam(beam)),
+                                      _ptr(out, torch.bfloat16, (self.cells, 16), "feat")), "dda_net_features")
+        return out
+
+    def target(self, ctx, beam, x, out=None):
+        out = torch.empty((self.cells, 6), dtype=torch.float32, device=self.device) if out is None else out
+        _check(lib().dda_net_target(self._h, ctx._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, ctx.n), "x"),
+                                    _ptr(out, torch.float32, (self.cells, 6), "tgt")), "dda_net_target")
+        return out
+
+    def forward(self, feat):
+        b = feat.shape[0]
+        out = torch.empty((b, self.cells, 6), dtype=torch.float32, device=self.device)
+        _check(lib().dda_net_forward(self._h, _ptr(feat, torch.bfloat16, (b, self.cells, 16), "feat"), b,
+                                     _ptr(out, torch.float32, (b, self.cells, 6), "out")), "dda_net_forward")
+        return out
+
+    def grad(self, feat, tgt):
+        b = feat.shape[0]
+        loss = ct.c_double()
+        g = np.empty(num_params(), dtype=np.float32)
+        _check(lib().dda_net_grad(self._h, _ptr(feat, torch.bfloat16, (b, self.cells, 16), "feat"),
+                                  _ptr(tgt, torch.float32, (b, self.cells, 6), "tgt"), b, ct.byref(loss),
+                                  g.ctypes.data), "dda_net_grad")
+        return loss.value, g
+
+    def train_step(self, feat, tgt, lr):
+        b = feat.shape[0]
+        loss = ct.c_double()
+        _check(lib().dda_net_train_step(self._h, _ptr(feat, torch.bfloat16, (b, self.cells, 16), "feat"),
+                                        _ptr(tgt, torch.float32, (b, self.cells, 6), "tgt"), b, float(lr),
+                                        ct.byref(loss)), "dda_net_train_step")
+        return loss.value
+
+    def guess(self, ctx, beams, feat=None):
+        """Initial guesses [n][3][N] for the beams on ctx's particle."""
+        n = len(beams)
+        if feat is None:
+            feat = torch.empty((n, self.cells, 16), dtype=torch.bfloat16, device=self.device)
+            for i, b in enumerate(beams):
+                self.features(ctx, b, feat[i])
+        x0 = ctx.vector(n)
+        _check(lib().dda_guess(ctx._h, self._h, _beams(beams), n, _ptr(feat, torch.bfloat16, (n, self.cells, 16), "feat"),
+                               _ptr(x0, torch.complex128, (n, 3, ctx.n), "x0")), "dda_guess")
+        return x0
+
+
+def num_params():
+    return int(lib().dda_net_num_params())

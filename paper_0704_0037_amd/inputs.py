@@ -185,3 +185,35 @@ def c4b_sphere_batch(count=32, seed=4002, kd=0.3):
 
 def small_sphere(n, m=1.5 + 0j, kd=0.4):
     return Workload(f"sphere{n}", (n, n, n), sphere_mask(n), complex(m), kd, [X_POL], 1e-8)
+
+
+def c5_particle(seed, G=48):
+    """One particle of the learned-initial-guess workload, on a cubic grid of side n <= G.
+
+    Family (uniform): a sphere, a randomly rotated ellipsoid (semi-axes n/2 times sorted uniform
+    [0.4, 1] factors) or a cluster of 2-4 spheres (radii in [n/8, n/4], centres uniform inside the
+    cube).  n uniform in [G/3, G]; m real, uniform in [1.05, 2]; size parameter x of the
+    circumscribing sphere (radius n/2) uniform in [1, min(8, 0.8 n / (2 m))], so |m| kd <= 0.8;
+    incidence direction and polarization of a random orientation.
+    """
+    rng = np.random.default_rng(seed)
+    fam = int(rng.integers(3))
+    n = int(rng.integers(G // 3, G + 1))
+    grid = (n, n, n)
+    if fam == 1:
+        axes = (n / 2.0) * np.sort(rng.uniform(0.4, 1.0, 3))[::-1]
+        mask = rotated_ellipsoid_mask(grid, axes, zyz_matrix(*random_rotation_zyz(rng)))
+    elif fam == 2:
+        k = int(rng.integers(2, 5))
+        radii = rng.uniform(n / 8.0, n / 4.0, k)
+        centers = [rng.uniform(-(n / 2.0 - r), n / 2.0 - r, 3) for r in radii]
+        mask = cluster_mask(grid, centers, radii)
+    else:
+        mask = sphere_mask(n)
+    if not mask.any():
+        mask = sphere_mask(n)
+    m = float(rng.uniform(1.05, 2.0))
+    x = float(rng.uniform(1.0, min(8.0, 0.8 * n / (2.0 * m))))
+    kd = x / (n / 2.0)
+    beam = beams_for_orientations(1, seed=int(rng.integers(1 << 31)))[int(rng.integers(2))]
+    return mask, complex(m), kd, beam

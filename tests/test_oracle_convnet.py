@@ -79,6 +79,7 @@ def test_gradient_matches_finite_differences():
     h = 1e-6
     for s in range(3):
         d = rng.standard_normal(p.size)
+        d /= np.linalg.norm(d)  # a unit step, so that h stays far below the distance to a relu kink
         fd = (cn.loss_and_grad(p + h * d, feats, targets, masks)[0]
               - cn.loss_and_grad(p - h * d, feats, targets, masks)[0]) / (2 * h)
         assert abs(fd - g @ d) < 1e-6 * max(1.0, abs(fd))
@@ -119,7 +120,9 @@ def test_features_target_guess_against_dda_oracle():
     ff = f.reshape(-1, cn.N_IN)
     assert ff[:, 0].sum() == len(pos) and np.all(ff[idx, 0] == 1)
     E = odda.incident_field(pos, kd, beam.prop, beam.pol)
-    assert np.abs(ff[idx, 4::2] + 1j * ff[idx, 5::2] - E).max() < 1e-14
+    assert np.abs(ff[idx, 4:10:2] + 1j * ff[idx, 5:10:2] - E).max() < 1e-14
+    assert np.abs(ff[idx, 10::2] + 1j * ff[idx, 11::2] - (m * m - 1) * E).max() < 1e-14
+    assert not ff[ff[:, 0] == 0, 10:].any()
     assert np.allclose(ff[idx, 1], 0.5) and np.allclose(ff[idx, 2], 0.02) and np.all(ff[:, 3] == kd)
     # the box cells next to a dipole are one lattice step away
     pb = cn.box_positions((10, 8, 6), G).reshape(-1, 3)
