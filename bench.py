@@ -1,6 +1,6 @@
 """Benchmark of the DDA hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
 
 Workload (default): the 256^3 sphere, x = 40, m = 1.05 (8,783,848 dipoles, FFT grid 512^3, fp64),
 LDR polarizability, incidence along +z.  One step = the whole hot path for one batch: QMR solves of
@@ -12,6 +12,10 @@ Printed: one JSON line.  value = interaction-matrix products per second over the
 (whole job: solver vector work and read-out included in the time); roofline = the dominant matvec
 kernel's algorithmic bytes over its mean duration (HIP events on the context's stream);
 cpu_baseline = the CPU oracle's direct-sum product on sampled rows of the same particle.
+forms = the extensions against the plain fp64 solve on their own workloads: fp32 inner solves with
+fp64 refinement (this sphere; the m = 2, 160^3 sphere), 128 orientations x polarizations of a
+64^3 ellipsoid in one batch, 32 spheres of 24..96 cells solved concurrently, and the learned
+initial guess on random particles in a 48^3 box (trained in the run).
 """
 from __future__ import annotations
 
@@ -89,6 +93,96 @@ def cpu_baseline(w, rows, seed=7):
                       f"{dt:.1f} s; value = 1 / (seconds per row x N)"}
 
 
+def _timed(torch, f):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = f()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def forms(ctx, w, beams, theta, dda, inputs, torch):
+    """The extensions, each against the plain fp64 GPU solve at the same residual."""
+    res = {}
+    # (1) fp32 inner solves + fp64 refinement on this sphere
+    (x32, i32, _), d32 = _timed(torch, lambda: ctx.solve(beams, tol=w.tol, precision=dda.FP32_REFINE))
+    (x64, i64, _), d64 = _timed(torch, lambda: ctx.solve(beams, tol=w.tol))
+    c64 = [ctx.cross_sections(b, x64[i].contiguous()) for i, b in enumerate(beams)]
+    c32 = [ctx.cross_sections(b, x32[i].contiguous()) for i, b in enumerate(beams)]
+    M64 = ctx.mueller(inputs.X_POL, x64[0].contiguous(), x64[1].contiguous(), 0.0, theta)
+    M32 = ctx.mueller(inputs.X_POL, x32[0].contiguous(), x32[1].contiguous(), 0.0, theta)
+    res["fp32_refine"] = {
+        "workload": "sphere256_x40_m1.05, both polarizations, tol 1e-5",
+        "time_to_tol_s_per_solve": d32 / len(beams), "fp64_time_to_tol_s_per_solve": d64 / len(beams),
+        "speedup_vs_fp64": d64 / d32, "inner_iterations": [i["iters"] for i in i32],
+        "fp64_iterations": [i["iters"] for i in i64], "outer": [i["outer"] for i in i32],
+        "res_true": max(i["res_true"] for i in i32),
+        "rel_err_Cext": max(abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(c32, c64)),
+        "rel_err_Cabs_abs": max(abs(a[1] - b[1]) / abs(b[0]) for a, b in zip(c32, c64)),
+        "rel_err_S11_max": float(np.max(np.abs(M32[:, 0, 0] / M64[:, 0, 0] - 1)))}
+    del x32, x64
+    log("form fp32_refine done")
+    # (1b) the strongly scattering sphere: m = 2, x = 20, 160^3 (QMR needs >20000 iterations to
+    # 1e-5 there; both forms are timed to 1e-2)
+    w3 = inputs.c3_sphere160()
+    with dda.Context(w3.mask, w3.m, w3.kd, fp32=True) as c3:
+        c3.tune(dda.FP64)
+        c3.tune(dda.FP32_REFINE)
+        tol3 = 1e-2
+        (xa, ia, sa), ta = _timed(torch, lambda: c3.solve(w3.beams, tol=tol3, raise_on_fail=False))
+        (xb, ib, sb), tb = _timed(torch, lambda: c3.solve(w3.beams, tol=tol3, precision=dda.FP32_REFINE,
+                                                             raise_on_fail=False))
+        ca = c3.cross_sections(w3.beams[0], xa[0].contiguous())
+        cb = c3.cross_sections(w3.beams[0], xb[0].contiguous())
+        res["fp32_refine_m2"] = {
+            "workload": "sphere160_x20_m2 (2,144,432 dipoles, 320^3 grid), x-pol, tol 1e-2",
+            "fp64_s": ta, "refine_s": tb, "speedup_vs_fp64": ta / tb, "fp64_iterations": ia[0]["iters"],
+            "inner_iterations": ib[0]["iters"], "outer": ib[0]["outer"], "status": [sa, sb],
+            "res_true": [ia[0]["res_true"], ib[0]["res_true"]], "Cext": [ca[0], cb[0]]}
+        del xa, xb
+    log("form fp32_refine_m2 done")
+    # (2a) 64 orientations x 2 polarizations of a 64^3 ellipsoid in one batch
+    w4 = inputs.c4a_ellipsoid64()
+    with dda.Context(w4.mask, w4.m, w4.kd, fp32=True) as c4:
+        c4.tune(dda.FP64)
+        c4.tune(dda.FP32_REFINE)
+        c4.solve(w4.beams[:2], tol=w4.tol)
+        (_, iseq, _), tseq = _timed(torch, lambda: [c4.solve([b], tol=w4.tol) for b in w4.beams][-1])
+        (_, ib64, _), tb64 = _timed(torch, lambda: c4.solve(w4.beams, tol=w4.tol))
+        (_, ib32, _), tb32 = _timed(torch, lambda: c4.solve(w4.beams, tol=w4.tol, precision=dda.FP32_REFINE))
+        res["batched_orientations"] = {
+            "workload": "ellipsoid64_m1.33+0.01i_kd0.3 (48,072 dipoles), 64 orientations x 2 pols = 128 RHS, tol 1e-5",
+            "sequential_fp64_s": tseq, "batched_fp64_s": tb64, "batched_refine_s": tb32,
+            "speedup_batched_fp64": tseq / tb64, "speedup_batched_refine": tseq / tb32,
+            "iterations_fp64": [min(i["iters"] for i in ib64), max(i["iters"] for i in ib64)]}
+    log("form batched_orientations done")
+    # (2b) 32 spheres of 24..96 cells, solved concurrently
+    ws = inputs.c4b_sphere_batch()
+    cs = [dda.Context(x.mask, x.m, x.kd) for x in ws]
+    try:
+        for c in cs:
+            c.solve([inputs.X_POL], tol=1e-1)
+        _, tseq = _timed(torch, lambda: [c.solve([inputs.X_POL], tol=1e-5) for c in cs])
+        (_, infos, st), tm = _timed(torch, lambda: dda.solve_many(cs, [inputs.X_POL] * len(cs), tol=1e-5))
+        res["many_particles"] = {
+            "workload": "32 spheres n ~ U{24..96}, m ~ U[1.05, 1.6], kd 0.3, x-pol, tol 1e-5 (fp64)",
+            "dipoles": int(sum(c.n for c in cs)), "sequential_fp64_s": tseq, "concurrent_fp64_s": tm,
+            "speedup": tseq / tm, "iterations": [int(i["iters"]) for i in infos]}
+    finally:
+        for c in cs:
+            c.close()
+    log("form many_particles done")
+    # (4) learned initial guess, trained in this run on solver output
+    from paper_0704_0037_amd import learned_guess as lg
+    ev, _ = lg.run(grid=48, n_train=600, n_eval=32, epochs=30, batch=8, lr=1e-3, seed=5000, quiet=True)
+    ev.pop("rows")
+    res["learned_guess"] = {"workload": "random spheres / ellipsoids / clusters in a 48^3 box, m in [1.05, 2], "
+                                        "x <= 8; 600 training particles, 32 held out, tol 1e-5",
+                            "speedup_vs_zero_guess": ev["speedup"], **ev}
+    log("form learned_guess done")
+    return res
+
+
 def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -100,7 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=12)
-    ap.add_argument("--no-forms", action="store_true", help="skip the fp32-refinement comparison")
+    ap.add_argument("--no-forms", action="store_true", help="skip the extension forms")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for byte-counter runs)")
     args = ap.parse_args()
@@ -123,6 +217,8 @@ def main():
     L = ctx.padded_grid()[0]
     N = ctx.n
     log(f"context ready: {N} dipoles, padded grid {L}^3")
+    tiles = {"fp64": ctx.tune(dda.FP64), "fp32": ctx.tune(dda.FP32_REFINE)}
+    log(f"tile schedule (lines per block, x / y pass): {tiles}")
     beams = [inputs.X_POL, inputs.Y_POL]
     theta = np.radians(np.arange(0.0, 180.0 + 1e-9, 0.5))
 
@@ -188,7 +284,7 @@ def main():
         "config": {"workload": "sphere256_x40_m1.05: 256^3 sphere, x=40, m=1.05, LDR, +z incidence, "
                                "x and y polarizations, QMR to 1e-5, Cext/Cabs, Mueller at 361 angles",
                    "grid": n, "padded_grid": L, "n_dipoles": N, "kd": w.kd, "rhs": 2, "tol": w.tol,
-                   "solver": "qmr", "precision": "fp64"},
+                   "solver": "qmr", "precision": "fp64", "tiles": tiles},
         "time_to_tol_s_per_solve": dt / args.steps / len(beams),
         "iterations": iters,
         "res_true": res_true,
@@ -207,27 +303,7 @@ def main():
     }
 
     if not args.no_forms:
-        # chosen form: single-precision inner QMR with double-precision refinement
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        x32, i32, st = ctx.solve(beams, tol=w.tol, precision=dda.FP32_REFINE)
-        torch.cuda.synchronize()
-        d32 = time.perf_counter() - t1
-        t1 = time.perf_counter()
-        x64, i64, st = ctx.solve(beams, tol=w.tol)
-        torch.cuda.synchronize()
-        d64 = time.perf_counter() - t1
-        c64 = [ctx.cross_sections(b, x64[i].contiguous()) for i, b in enumerate(beams)]
-        c32 = [ctx.cross_sections(b, x32[i].contiguous()) for i, b in enumerate(beams)]
-        M64 = ctx.mueller(inputs.X_POL, x64[0].contiguous(), x64[1].contiguous(), 0.0, theta)
-        M32 = ctx.mueller(inputs.X_POL, x32[0].contiguous(), x32[1].contiguous(), 0.0, theta)
-        out["forms"] = {"fp32_refine": {
-            "time_to_tol_s_per_solve": d32 / len(beams), "fp64_time_to_tol_s_per_solve": d64 / len(beams),
-            "speedup_vs_fp64": d64 / d32, "inner_iterations": [i["iters"] for i in i32],
-            "outer": [i["outer"] for i in i32], "res_true": max(i["res_true"] for i in i32),
-            "rel_err_Cext": max(abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(c32, c64)),
-            "rel_err_S11_max": float(np.max(np.abs(M32[:, 0, 0] / M64[:, 0, 0] - 1)))}}
-
+        out["forms"] = forms(ctx, w, beams, theta, dda, inputs, torch)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)

@@ -86,7 +86,8 @@ typedef struct {
     int32_t precision;     /* DDA_FP64 (default) or DDA_FP32_REFINE */
     int32_t maxit;         /* iteration limit; 0 = 100000 */
     int32_t check_every;   /* iterations between host-side convergence checks; 0 = automatic */
-    double inner_tol;      /* DDA_FP32_REFINE: relative tolerance of each inner solve; 0 = 1e-2 */
+    double inner_tol;      /* DDA_FP32_REFINE: relative tolerance of each inner solve; 0 = automatic:
+                              half of tol over the current residual, at least 1e-5 */
     const void *x0;        /* device initial guess, same layout as x_out; NULL = zero */
     int32_t graph;         /* iterations replayed as a captured hipGraph: 0 = automatic, 1 = on, -1 = off */
     int32_t x0_check;      /* 1: keep x0 for a right-hand side only if |b - A x0| < |b|, else start from 0 */
@@ -222,6 +223,19 @@ dda_status dda_mueller(dda_ctx *ctx, const dda_beam *beam, const void *x1, const
  */
 dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, int32_t precision,
                             const void *x, void *y, int32_t reps, float kernel_ms[5], float *total_ms);
+
+/*
+ * dda_tune — autotuner of the tile schedule of the x and y passes: for the given precision
+ * (DDA_FP64 or DDA_FP32_REFINE) it times `reps` products for every admissible number of lines per
+ * block (powers of two within the block-size and LDS limits) and keeps, for each axis, the
+ * fastest.  tiles_out (optional) receives {lines per block of the x pass, of the y pass}.
+ * dda_get_tiles / dda_set_tiles read / impose a schedule (e.g. one cached from an earlier run;
+ * DDA_EINVAL for an inadmissible one).  Results of products do not depend on the schedule except
+ * through the order of the bilinear-dot partial sums.
+ */
+dda_status dda_tune(dda_ctx *ctx, int32_t precision, int32_t reps, int32_t tiles_out[2]);
+dda_status dda_get_tiles(const dda_ctx *ctx, int32_t precision, int32_t tiles[2]);
+dda_status dda_set_tiles(dda_ctx *ctx, int32_t precision, const int32_t tiles[2]);
 
 /* ------------------------------------------------------------------ learned initial guess
  * A small 3-D convolutional network supplies QMR's starting vector (the paper's iteration starts

@@ -222,6 +222,109 @@ dda_status dda_matvec_timed(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, in
     return matvec_timed<float>(*ctx, n_rhs, ar, ai, (const float2 *)x, (float2 *)y, reps, kernel_ms, total_ms);
 }
 
+}  // extern "C"
+
+namespace dda {
+template <typename R> static Tiles &tiles_ref(Ctx &c) { return sizeof(R) == 8 ? c.tl64 : c.tl32; }
+
+static int log2i(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+template <typename R> static void set_tiles(Ctx &c, int nlx, int nly) {
+    Tiles &t = tiles_ref<R>(c);
+    t.nl_x = nlx;
+    t.nl_y = nly;
+    t.lnl_x = log2i(nlx);
+    t.lnl_y = log2i(nly);
+}
+
+// Tile-schedule autotuner: every admissible lines-per-block count of the x and of the y pass is
+// timed on products of a zero vector (HIP events around each kernel); each axis keeps its fastest.
+template <typename R> static dda_status tune(Ctx &c, int reps, int32_t out[2]) {
+    const Tiles saved = tiles_ref<R>(c);
+    cplx<R> *x = nullptr, *y = nullptr;
+    const size_t bytes = (size_t)3 * c.N * sizeof(cplx<R>);
+    dda_status st = device_alloc((void **)&x, bytes);
+    if (st == DDA_OK) st = device_alloc((void **)&y, bytes);
+    if (st == DDA_OK && hipMemsetAsync(x, 0, bytes, c.stream) != hipSuccess) st = DDA_EHIP;
+    std::vector<double> ar(1, 0.0), ai(1, 0.0);
+    double best_x = 1e300, best_y = 1e300;
+    int nlx = saved.nl_x, nly = saved.nl_y;
+    for (int nl = 1; nl <= 64 && st == DDA_OK; nl *= 2) {
+        const bool okx = tiles_valid<R>(c, 0, nl) && nl <= std::max(1, c.ny);
+        const bool oky = tiles_valid<R>(c, 1, nl) && nl <= std::max(1, c.nz);
+        if (!okx && !oky) continue;
+        set_tiles<R>(c, okx ? nl : saved.nl_x, oky ? nl : saved.nl_y);
+        float k[5], tot;
+        st = matvec_timed<R>(c, 1, ar, ai, x, y, reps, k, &tot);
+        if (st != DDA_OK) break;
+        if (okx && k[0] + k[4] < best_x) best_x = k[0] + k[4], nlx = nl;
+        if (oky && k[1] + k[3] < best_y) best_y = k[1] + k[3], nly = nl;
+    }
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (st != DDA_OK) {
+        tiles_ref<R>(c) = saved;
+        return st;
+    }
+    set_tiles<R>(c, nlx, nly);
+    if (out) {
+        out[0] = nlx;
+        out[1] = nly;
+    }
+    return DDA_OK;
+}
+}  // namespace dda
+
+extern "C" {
+
+dda_status dda_tune(dda_ctx *h, int32_t precision, int32_t reps, int32_t tiles_out[2]) {
+    Ctx *c = cx(h);
+    if (!c || reps < 1 || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
+        set_error("dda_tune: NULL context, reps < 1 or unknown precision");
+        return DDA_EINVAL;
+    }
+    if (precision == DDA_FP32_REFINE && !c->ghat32) {
+        set_error("dda_tune: context built without opts.fp32");
+        return DDA_ENOTSUP;
+    }
+    return precision == DDA_FP64 ? tune<double>(*c, reps, tiles_out) : tune<float>(*c, reps, tiles_out);
+}
+
+dda_status dda_get_tiles(const dda_ctx *h, int32_t precision, int32_t tiles[2]) {
+    const Ctx *c = cx(h);
+    if (!c || !tiles || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
+        set_error("dda_get_tiles: bad argument");
+        return DDA_EINVAL;
+    }
+    const Tiles &t = precision == DDA_FP64 ? c->tl64 : c->tl32;
+    tiles[0] = t.nl_x;
+    tiles[1] = t.nl_y;
+    return DDA_OK;
+}
+
+dda_status dda_set_tiles(dda_ctx *h, int32_t precision, const int32_t tiles[2]) {
+    Ctx *c = cx(h);
+    if (!c || !tiles || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
+        set_error("dda_set_tiles: bad argument");
+        return DDA_EINVAL;
+    }
+    const bool f64 = precision == DDA_FP64;
+    const bool ok = f64 ? tiles_valid<double>(*c, 0, tiles[0]) && tiles_valid<double>(*c, 1, tiles[1])
+                        : tiles_valid<float>(*c, 0, tiles[0]) && tiles_valid<float>(*c, 1, tiles[1]);
+    if (!ok) {
+        set_error("dda_set_tiles: lines per block must be powers of two within the block and LDS limits");
+        return DDA_EINVAL;
+    }
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (f64) set_tiles<double>(*c, tiles[0], tiles[1]);
+    else set_tiles<float>(*c, tiles[0], tiles[1]);
+    return DDA_OK;
+}
+
 const char *dda_strerror(dda_status s) {
     switch (s) {
         case DDA_OK: return "ok";

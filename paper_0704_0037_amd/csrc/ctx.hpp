@@ -97,6 +97,8 @@ dda_status matvec_device<float>(Ctx &c, const float2 *x, float2 *y, int nrhs, co
 
 // number of per-block dot partials the x-inverse kernel writes per right-hand side
 template <typename R> inline const Tiles &tiles_of(const Ctx &c) { return sizeof(R) == 8 ? c.tl64 : c.tl32; }
+inline size_t max_dots_per_rhs(const Ctx &c) { return (size_t)3 * c.nz * c.ny; }
+template <typename R> bool tiles_valid(const Ctx &c, int axis, int nl);
 template <typename R> inline size_t dots_per_rhs(const Ctx &c) {
     const Tiles &t = tiles_of<R>(c);
     return (size_t)3 * c.nz * ((c.ny + t.nl_x - 1) / t.nl_x);

@@ -24,6 +24,10 @@ constexpr int kMaxPass = 12;
 // block-size bound of the x / y pass kernels per precision: single-precision lines need twice the
 // lines per block for the same 128-byte runs on their transposed side, and fit the registers
 template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_MAX_THREADS : 2 * DDA_MAX_THREADS; }
+// padded lengths with kernels specialized at compile time (5-smooth sizes the workloads use most)
+#define DDA_SPECIALIZED_LENGTHS(X) \
+    X(32) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+
 #ifndef DDA_ZMUL_SLOTS
 #define DDA_ZMUL_SLOTS 1      // mirror columns processed side by side in a z-pass block (1, 2 or 4)
 #endif

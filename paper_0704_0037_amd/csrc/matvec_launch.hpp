@@ -10,8 +10,6 @@
 #include "ctx.hpp"
 #include "matvec_kernels.hpp"
 
-// padded lengths with specialized kernels (5-smooth sizes the workloads use most)
-#define DDA_SPECIALIZED_LENGTHS(X) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
 
 namespace dda {
 

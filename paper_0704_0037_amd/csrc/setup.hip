@@ -39,9 +39,26 @@ static bool five_smooth(int L) {
     return L == 1;
 }
 
+// Padded length of an axis of n cells: at least 2n - 1 (the circulant embedding of the Toeplitz
+// interaction), 5-smooth, with at most 64 threads per line (the z pass runs one column of three
+// lines per block); a length with compile-time specialized kernels is preferred when it costs at
+// most 25 % more than the smallest admissible one.
+static bool admissible(int L) {
+    if (!five_smooth(L)) return false;
+    const FftPlan p = make_plan(L, kMaxRadixZ, false);
+    return p.npass > 0 && p.tpl <= 64;
+}
 static int smallest_pad(int n) {
     int L = std::max(1, 2 * n - 1);
-    while (!five_smooth(L)) ++L;
+    while (!admissible(L)) ++L;
+#define DDA_SPEC_ITEM(S) S,
+    static const int spec[] = {DDA_SPECIALIZED_LENGTHS(DDA_SPEC_ITEM)};
+#undef DDA_SPEC_ITEM
+    for (int S : spec)
+        if (S >= L) {
+            if (4 * S <= 5 * L) L = S;
+            break;
+        }
     return L;
 }
 
@@ -198,6 +215,16 @@ void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
     im = -ii / n2;
 }
 
+// whether nl lines per block (a power of two) fit the x (axis 0) or y (axis 1) pass of precision R
+template <typename R> bool tiles_valid(const Ctx &c, int axis, int nl) {
+    if (nl < 1 || (nl & (nl - 1))) return false;
+    const FftPlan &p = axis == 0 ? c.pxf : c.pyf;
+    const int L = axis == 0 ? c.Lx : c.Ly;
+    return nl * p.tpl <= max_threads<R>() && (size_t)nl * lds_line_stride(L) * sizeof(cplx<R>) <= DDA_LDS_CAP;
+}
+template bool tiles_valid<double>(const Ctx &, int, int);
+template bool tiles_valid<float>(const Ctx &, int, int);
+
 template <typename R> static void free_work(Work<R> &w) {
     (void)hipFree(w.B1);
     (void)hipFree(w.B2);
@@ -216,7 +243,7 @@ template <typename R> dda_status ensure_work(Ctx &c, int nrhs) {
     if ((st = device_alloc((void **)&w.B1, nc * c.nz * (size_t)c.Lx * c.ny * sizeof(cplx<R>))) != DDA_OK) return st;
     if ((st = device_alloc((void **)&w.B2, nc * c.nz * (size_t)c.Lx * c.Ly * sizeof(cplx<R>))) != DDA_OK) return st;
     if ((st = device_alloc((void **)&w.scale, (size_t)nrhs * sizeof(cplx<R>))) != DDA_OK) return st;
-    w.ndots = dots_per_rhs<R>(c) * nrhs;
+    w.ndots = max_dots_per_rhs(c) * nrhs;  // enough for any tile schedule (the tuner may change it)
     if ((st = device_alloc((void **)&w.dots, w.ndots * sizeof(cplx<R>))) != DDA_OK) return st;
     w.nrhs = nrhs;
     return DDA_OK;

@@ -697,11 +697,13 @@ static dda_status ensure_bufs(Ctx &c, Bufs &B, int nrhs, int hcap) {
 }
 
 // Initial states (tolerance, iteration limit) for every right-hand side.
-static dda_status init_states(Ctx &c, Bufs &B, double tol, int maxit, const int *active = nullptr) {
+static dda_status init_states(Ctx &c, Bufs &B, double tol, int maxit, const int *active = nullptr,
+                              const double *tols = nullptr) {
     std::vector<SolveState> h(B.nrhs);
-    for (auto &s : h) {
+    for (int r = 0; r < B.nrhs; ++r) {
+        SolveState &s = h[r];
         std::memset(&s, 0, sizeof s);
-        s.tol = tol;
+        s.tol = tols ? tols[r] : tol;
         s.maxit = maxit;
     }
     DDA_HIP_CHECK(hipMemcpyAsync(B.st, h.data(), h.size() * sizeof(SolveState), hipMemcpyHostToDevice, c.stream));
@@ -1031,7 +1033,10 @@ static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double t
         DDA_HIP_CHECK(hipMemcpyAsync(x, o.x0, (size_t)nrhs * B.n3 * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
     if (!o.x0) hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, c.stream, x, (size_t)nrhs * B.n3);
     if (o.x0 && o.x0_check && (st = check_x0(c, B, v, x, nrhs)) != DDA_OK) return st;
-    const double inner = o.inner_tol > 0 ? o.inner_tol : 1e-2;
+    // inner tolerance: as given, else what brings each right-hand side to the outer tolerance in
+    // one inner solve (half of tol / current residual), floored where single precision stalls
+    const double kInnerFloor = 1e-5;
+    std::vector<double> inner_tols(nrhs, 1e-2);
     std::vector<int> iters(nrhs, 0), mvs(nrhs, 0), outer(nrhs, 0), active(nrhs, 1);
     std::vector<double> res(nrhs, 1.0), scale(nrhs, 1.0);
     std::vector<int> stat(nrhs, ST_RUN);
@@ -1064,6 +1069,7 @@ static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double t
                 scale[r] = 1.0 / rn;
                 outer[r] += 1;
                 any = true;
+                inner_tols[r] = o.inner_tol > 0 ? o.inner_tol : std::min(0.5, std::max(0.5 * tol / res[r], kInnerFloor));
             }
         }
         if (!any) break;
@@ -1071,7 +1077,7 @@ static dda_status solve_refine(Ctx &c, const dda_beam *beams, int nrhs, double t
         DDA_HIP_CHECK(hipMemcpyAsync(dactive, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.stream));
         hipLaunchKernelGGL(k_to32, dim3(B.nb, nrhs), dim3(kVecThreads), 0, c.stream, r64, v32.b, B.n3, dscale);
         // inner fp32 QMR (inactive right-hand sides start as done)
-        if ((st = init_states(c, B, inner, std::max(1, o.maxit), active.data())) != DDA_OK) return st;
+        if ((st = init_states(c, B, 0.0, std::max(1, o.maxit), active.data(), inner_tols.data())) != DDA_OK) return st;
         if ((st = krylov<float>(c, B, v32, e32, false, DDA_QMR, check_every, graph)) != DDA_OK) return st;
         std::vector<SolveState> h;
         if ((st = fetch_states(c, B, h)) != DDA_OK) return st;

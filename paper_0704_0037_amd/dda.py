@@ -73,6 +73,9 @@ _SIGS = {
                                ct.POINTER(ct.c_double), ct.c_int32, ct.POINTER(ct.c_double)]),
     "dda_matvec_timed": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_int32, ct.c_void_p,
                                     ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_float), ct.POINTER(ct.c_float)]),
+    "dda_tune": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
+    "dda_get_tiles": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32)]),
+    "dda_set_tiles": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "dda_net_num_params": (ct.c_int64, []),
     "dda_net_create": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p]),
     "dda_net_free": (ct.c_int, [ct.c_void_p]),
@@ -250,6 +253,38 @@ class Context:
                                       _ptr(y, dt, (n, 3, self.n), "y"), int(reps), k, ct.byref(tot)),
                "dda_matvec_timed")
         return list(k), tot.value
+
+    def tiles(self, precision=FP64):
+        t = (ct.c_int32 * 2)()
+        _check(lib().dda_get_tiles(self._h, int(precision), t), "dda_get_tiles")
+        return [t[0], t[1]]
+
+    def set_tiles(self, tiles, precision=FP64):
+        t = (ct.c_int32 * 2)(*[int(v) for v in tiles])
+        _check(lib().dda_set_tiles(self._h, int(precision), t), "dda_set_tiles")
+
+    def tune(self, precision=FP64, reps=3, cache=None):
+        """Autotune the x/y tile schedule (dda_tune).  With a cache file (JSON; default: the
+        DDA_TUNE_CACHE environment variable, if set) a schedule found earlier for the same grid,
+        padded grid and precision is reused instead of timed again."""
+        import json
+        cache = cache if cache is not None else os.environ.get("DDA_TUNE_CACHE")
+        key = f"{self.grid}|{tuple(self.padded_grid())}|{int(precision)}"
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tiles(table[key], precision)
+                return list(table[key])
+        t = (ct.c_int32 * 2)()
+        _check(lib().dda_tune(self._h, int(precision), int(reps), t), "dda_tune")
+        res = [t[0], t[1]]
+        if cache:
+            table[key] = res
+            with open(cache, "w") as f:
+                json.dump(table, f)
+        return res
 
     def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
               x_out=None, history=0, raise_on_fail=True, graph=0, x0_check=False):

@@ -48,6 +48,8 @@ CASES = [
     ("single_dipole", np.ones((1, 1, 1), dtype=np.uint8), 1.5, 0.4, None),
     ("ellipsoid20_pad40_radix5", inputs.ellipsoid_mask((20, 14, 10), (10, 7, 5)), 1.33 + 0.01j, 0.3, (40, 30, 20)),
     ("sphere12_radix3", inputs.sphere_mask(12), 1.6, 0.45, (24, 48, 36)),
+    # automatic padding onto the specialized lengths 60 / 72 / 80 (x, y, z of 25, 33, 38 cells)
+    ("sparse_auto_pad_60_72_80", _random_mask((38, 33, 25), 14, 0.05), 1.3, 0.3, None),
 ]
 
 
@@ -167,3 +169,42 @@ def test_matvec_timed_returns_the_product():
         kms, tot = ctx.matvec_timed(beams, x32, y32, reps=2, precision=dda.FP32_REFINE)
         for r in range(2):
             assert torch.equal(y32[r], ctx.matvec_f32(beams[r], x32[r].contiguous()))
+
+
+def test_tuner_keeps_products_and_caches(tmp_path):
+    """The tile schedule changes how lines are grouped into blocks, never the product."""
+    import json
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((20, 16, 12), (10, 8, 6))
+    with dda.Context(mask, 1.3 + 0.01j, 0.4, fp32=True) as ctx:
+        x = torch.from_numpy(inputs.random_vector(ctx.n, seed=5)).cuda()
+        y0 = ctx.matvec(inputs.X_POL, x).clone()
+        y32 = ctx.matvec_f32(inputs.X_POL, x.to(torch.complex64)).clone()
+        _, i0, _ = ctx.solve([inputs.X_POL], tol=1e-9)
+        t = ctx.tune(dda.FP64, reps=2)
+        assert ctx.tiles(dda.FP64) == t
+        assert torch.equal(ctx.matvec(inputs.X_POL, x), y0)
+        ctx.tune(dda.FP32_REFINE, reps=2)
+        assert torch.equal(ctx.matvec_f32(inputs.X_POL, x.to(torch.complex64)), y32)
+        for tiles in ([1, 1], [2, 4], [8, 2]):
+            ctx.set_tiles(tiles, dda.FP64)
+            assert ctx.tiles(dda.FP64) == tiles
+            assert torch.equal(ctx.matvec(inputs.X_POL, x), y0)
+            _, i1, st = ctx.solve([inputs.X_POL], tol=1e-9)
+            assert st == 0 and abs(i1[0]["iters"] - i0[0]["iters"]) <= 1
+        with pytest.raises(dda.DDAError):
+            ctx.set_tiles([3, 1], dda.FP64)
+        cache = str(tmp_path / "tiles.json")
+        tc = ctx.tune(dda.FP64, reps=2, cache=cache)
+        assert list(json.load(open(cache)).values()) == [tc]
+        ctx.set_tiles([1, 1], dda.FP64)
+        assert ctx.tune(dda.FP64, cache=cache) == tc and ctx.tiles(dda.FP64) == tc
+
+
+def test_many_sphere_sizes_set_up():
+    """Every sphere of 24..96 cells gets an admissible padded grid (the multi-particle workload)."""
+    dda = _dda()
+    for n in range(24, 97, 1):
+        with dda.Context(inputs.sphere_mask(n), 1.2, 0.3) as ctx:
+            L = ctx.padded_grid()
+            assert L[0] >= 2 * n - 1 and L[0] == L[1] == L[2]

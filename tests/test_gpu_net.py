@@ -144,7 +144,7 @@ def test_trained_guess_against_zero_guess():
     residual on held-out particles than the untrained network's (x0 = b), and QMR from it needs no
     more iterations than from zero (plain QMR stays the fallback and the convergence judge)."""
     from paper_0704_0037_amd import learned_guess as lg
-    ev, _ = lg.run(grid=32, n_train=384, n_eval=24, epochs=40, batch=8, lr=1e-3, seed=700, quiet=True)
+    ev, _ = lg.run(grid=48, n_train=600, n_eval=16, epochs=30, batch=8, lr=1e-3, seed=5000, quiet=True)
     assert all(r["status"] == [0, 0, 0] for r in ev["rows"])
-    assert ev["mean_res0_guess"] < 0.9 * ev["mean_res0_b"], ev
+    assert ev["mean_res0_guess"] < 0.85 * ev["mean_res0_b"], ev
     assert ev["mean_iters_guess"] <= ev["mean_iters_zero"] + 0.5, ev
