@@ -144,8 +144,8 @@ def forms(ctx, w, beams, theta, dda, inputs, torch):
     # (2a) 64 orientations x 2 polarizations of a 64^3 ellipsoid in one batch
     w4 = inputs.c4a_ellipsoid64()
     with dda.Context(w4.mask, w4.m, w4.kd, fp32=True) as c4:
-        c4.tune(dda.FP64)
-        c4.tune(dda.FP32_REFINE)
+        c4.tune(dda.FP64, n_rhs=len(w4.beams))
+        c4.tune(dda.FP32_REFINE, n_rhs=len(w4.beams))
         c4.solve(w4.beams[:2], tol=w4.tol)
         (_, iseq, _), tseq = _timed(torch, lambda: [c4.solve([b], tol=w4.tol) for b in w4.beams][-1])
         (_, ib64, _), tb64 = _timed(torch, lambda: c4.solve(w4.beams, tol=w4.tol))
@@ -217,7 +217,7 @@ def main():
     L = ctx.padded_grid()[0]
     N = ctx.n
     log(f"context ready: {N} dipoles, padded grid {L}^3")
-    tiles = {"fp64": ctx.tune(dda.FP64), "fp32": ctx.tune(dda.FP32_REFINE)}
+    tiles = {"fp64": ctx.tune(dda.FP64, n_rhs=2), "fp32": ctx.tune(dda.FP32_REFINE, n_rhs=2)}
     log(f"tile schedule (lines per block, x / y pass): {tiles}")
     beams = [inputs.X_POL, inputs.Y_POL]
     theta = np.radians(np.arange(0.0, 180.0 + 1e-9, 0.5))

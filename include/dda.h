@@ -226,14 +226,14 @@ dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
 
 /*
  * dda_tune — autotuner of the tile schedule of the x and y passes: for the given precision
- * (DDA_FP64 or DDA_FP32_REFINE) it times `reps` products for every admissible number of lines per
- * block (powers of two within the block-size and LDS limits) and keeps, for each axis, the
- * fastest.  tiles_out (optional) receives {lines per block of the x pass, of the y pass}.
+ * (DDA_FP64 or DDA_FP32_REFINE) it times `reps` products of a batch of n_rhs vectors (the batch
+ * size the solves will use) for every admissible number of lines per block (powers of two within
+ * the block-size and LDS limits) and keeps, for each axis, the fastest.  tiles_out (optional) receives {lines per block of the x pass, of the y pass}.
  * dda_get_tiles / dda_set_tiles read / impose a schedule (e.g. one cached from an earlier run;
  * DDA_EINVAL for an inadmissible one).  Results of products do not depend on the schedule except
  * through the order of the bilinear-dot partial sums.
  */
-dda_status dda_tune(dda_ctx *ctx, int32_t precision, int32_t reps, int32_t tiles_out[2]);
+dda_status dda_tune(dda_ctx *ctx, int32_t precision, int32_t n_rhs, int32_t reps, int32_t tiles_out[2]);
 dda_status dda_get_tiles(const dda_ctx *ctx, int32_t precision, int32_t tiles[2]);
 dda_status dda_set_tiles(dda_ctx *ctx, int32_t precision, const int32_t tiles[2]);
 

@@ -242,15 +242,16 @@ template <typename R> static void set_tiles(Ctx &c, int nlx, int nly) {
 }
 
 // Tile-schedule autotuner: every admissible lines-per-block count of the x and of the y pass is
-// timed on products of a zero vector (HIP events around each kernel); each axis keeps its fastest.
-template <typename R> static dda_status tune(Ctx &c, int reps, int32_t out[2]) {
+// timed on products of a batch of n_rhs zero vectors (HIP events around each kernel); each axis
+// keeps its fastest.
+template <typename R> static dda_status tune(Ctx &c, int nrhs, int reps, int32_t out[2]) {
     const Tiles saved = tiles_ref<R>(c);
     cplx<R> *x = nullptr, *y = nullptr;
-    const size_t bytes = (size_t)3 * c.N * sizeof(cplx<R>);
+    const size_t bytes = (size_t)3 * nrhs * c.N * sizeof(cplx<R>);
     dda_status st = device_alloc((void **)&x, bytes);
     if (st == DDA_OK) st = device_alloc((void **)&y, bytes);
     if (st == DDA_OK && hipMemsetAsync(x, 0, bytes, c.stream) != hipSuccess) st = DDA_EHIP;
-    std::vector<double> ar(1, 0.0), ai(1, 0.0);
+    std::vector<double> ar(nrhs, 0.0), ai(nrhs, 0.0);
     double best_x = 1e300, best_y = 1e300;
     int nlx = saved.nl_x, nly = saved.nl_y;
     for (int nl = 1; nl <= 64 && st == DDA_OK; nl *= 2) {
@@ -259,7 +260,7 @@ template <typename R> static dda_status tune(Ctx &c, int reps, int32_t out[2]) {
         if (!okx && !oky) continue;
         set_tiles<R>(c, okx ? nl : saved.nl_x, oky ? nl : saved.nl_y);
         float k[5], tot;
-        st = matvec_timed<R>(c, 1, ar, ai, x, y, reps, k, &tot);
+        st = matvec_timed<R>(c, nrhs, ar, ai, x, y, reps, k, &tot);
         if (st != DDA_OK) break;
         if (okx && k[0] + k[4] < best_x) best_x = k[0] + k[4], nlx = nl;
         if (oky && k[1] + k[3] < best_y) best_y = k[1] + k[3], nly = nl;
@@ -281,17 +282,17 @@ template <typename R> static dda_status tune(Ctx &c, int reps, int32_t out[2]) {
 
 extern "C" {
 
-dda_status dda_tune(dda_ctx *h, int32_t precision, int32_t reps, int32_t tiles_out[2]) {
+dda_status dda_tune(dda_ctx *h, int32_t precision, int32_t n_rhs, int32_t reps, int32_t tiles_out[2]) {
     Ctx *c = cx(h);
-    if (!c || reps < 1 || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
-        set_error("dda_tune: NULL context, reps < 1 or unknown precision");
+    if (!c || reps < 1 || n_rhs < 1 || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
+        set_error("dda_tune: NULL context, reps < 1, n_rhs < 1 or unknown precision");
         return DDA_EINVAL;
     }
     if (precision == DDA_FP32_REFINE && !c->ghat32) {
         set_error("dda_tune: context built without opts.fp32");
         return DDA_ENOTSUP;
     }
-    return precision == DDA_FP64 ? tune<double>(*c, reps, tiles_out) : tune<float>(*c, reps, tiles_out);
+    return precision == DDA_FP64 ? tune<double>(*c, n_rhs, reps, tiles_out) : tune<float>(*c, n_rhs, reps, tiles_out);
 }
 
 dda_status dda_get_tiles(const dda_ctx *h, int32_t precision, int32_t tiles[2]) {

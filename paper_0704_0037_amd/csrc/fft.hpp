@@ -23,7 +23,10 @@ constexpr int kMaxPass = 12;
 #endif
 // block-size bound of the x / y pass kernels per precision: single-precision lines need twice the
 // lines per block for the same 128-byte runs on their transposed side, and fit the registers
-template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_MAX_THREADS : 2 * DDA_MAX_THREADS; }
+#ifndef DDA_MAX_THREADS_F64
+#define DDA_MAX_THREADS_F64 DDA_MAX_THREADS
+#endif
+template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_MAX_THREADS_F64 : 2 * DDA_MAX_THREADS; }
 // padded lengths with kernels specialized at compile time (5-smooth sizes the workloads use most)
 #define DDA_SPECIALIZED_LENGTHS(X) \
     X(32) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
@@ -33,6 +36,12 @@ template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_
 #endif
 #ifndef DDA_ZMUL_THREADS
 #define DDA_ZMUL_THREADS (DDA_ZMUL_SLOTS * 3 * 64)  // block-size bound of the fused z-pass kernel
+#endif
+#ifndef DDA_TW_DERIVED
+#define DDA_TW_DERIVED 1  // radix-8 twiddles w^3, w^5, w^6, w^7 formed from w, w^2, w^4 (0: all from the table)
+#endif
+#ifndef DDA_ZMUL_OWN
+#define DDA_ZMUL_OWN 1  // the fp64 z pass multiplies each thread's own component from registers
 #endif
 #ifndef DDA_ZMUL_WAVES_PER_EU
 #define DDA_ZMUL_WAVES_PER_EU 3  // register budget of the z pass: three 3-wave blocks per CU at fp64
@@ -237,36 +246,40 @@ template <int DIR, int RADIX, typename C> __device__ __forceinline__ void dftR(C
 }
 
 // ------------------------------------------------------------- butterfly load / store
+// a[r] *= w^(r k) (conjugated for the inverse), w = exp(-2 pi i step / L), from the table tw.
+// With DDA_TW_DERIVED, radix 8 loads w, w^2, w^4 and forms the other four by products (fewer
+// cached loads per butterfly, ~2 ulps more rounding).
+template <int DIR, int RADIX, typename C>
+__device__ __forceinline__ void twiddle(C *a, int k, int step, const C *__restrict__ tw) {
+    if constexpr (DDA_TW_DERIVED && RADIX == 8) {
+        const C w1 = tw[k * step], w2 = tw[2 * k * step], w4 = tw[4 * k * step];
+        const C w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+        const C w[8] = {w1, w1, w2, w3, w4, w5, w6, w7};
+#pragma unroll
+        for (int r = 1; r < 8; ++r) a[r] = cmul(a[r], DIR < 0 ? w[r] : cconj(w[r]));
+    } else {
+#pragma unroll
+        for (int r = 1; r < RADIX; ++r) {
+            C w = tw[r * k * step];
+            a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
+        }
+    }
+}
+
 // Load the R inputs of butterfly j through ld(index), twiddle, transform (into a[0..R-1]).
 template <int DIR, int RADIX, typename C, class LD>
 __device__ __forceinline__ void bfly_load(C *a, int j, int L, int Ns, const C *__restrict__ tw, LD ld) {
     const int q = L / RADIX;
 #pragma unroll
     for (int r = 0; r < RADIX; ++r) a[r] = ld(j + r * q);
-    if (Ns > 1) {
-        const int k = j % Ns;
-        const int step = q / Ns;  // L / (Ns * RADIX)
-#pragma unroll
-        for (int r = 1; r < RADIX; ++r) {
-            C w = tw[r * k * step];
-            a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
-        }
-    }
+    if (Ns > 1) twiddle<DIR, RADIX>(a, j % Ns, q / Ns, tw);  // step = L / (Ns * RADIX)
     dftR<DIR, RADIX>(a);
 }
 
 // Twiddle and transform values already in registers (for a pass whose inputs a thread holds).
 template <int DIR, int RADIX, typename C>
 __device__ __forceinline__ void bfly_regs(C *a, int j, int L, int Ns, const C *__restrict__ tw) {
-    if (Ns > 1) {
-        const int k = j % Ns;
-        const int step = L / RADIX / Ns;
-#pragma unroll
-        for (int r = 1; r < RADIX; ++r) {
-            C w = tw[r * k * step];
-            a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
-        }
-    }
+    if (Ns > 1) twiddle<DIR, RADIX>(a, j % Ns, L / RADIX / Ns, tw);
     dftR<DIR, RADIX>(a);
 }
 

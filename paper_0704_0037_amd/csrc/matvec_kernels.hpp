@@ -188,11 +188,11 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     const int nmy = (kyo == 0 || 2 * kyo == Ly) ? 1 : 2;
     C *gsh = lds;                            // [6][hz1] tensor runs of this octant column
     C *lcol = lds + 6 * hz1 + lslot * 3 * S;  // [3][S] the three component lines of this slot
-    C *ln = lcol + comp * S;
     {
         const C *gcol = Gh + (size_t)oct * 6 * hz1;
         for (int e = t; e < 6 * hz1; e += blockDim.x) gsh[e] = gcol[e];
     }
+    C *ln = lcol + comp * S;
     constexpr bool W = wave_lines<LC, kMaxRadixZ>();
     constexpr int ngroups = 4 / DDA_ZMUL_SLOTS;
     const bool act = j < qi;
@@ -228,9 +228,27 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                 store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
             }
             lds_sync<W>();
-            lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, tw);  // natural order in LDS afterwards
-            if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
+            // own-component path (double precision): all forward passes but the last through LDS;
+            // the last one keeps this thread's outputs (its own component at kz = j + r qi) in
+            // registers and also stores them, in natural order, for the two other components
+            constexpr bool OWN = DDA_ZMUL_OWN && sizeof(R) == 8;
             C a[kMaxRadixZ];
+            if constexpr (OWN) {
+                if (np >= 2) {
+                    lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np - 1, j, tw);
+                    const int NsL = L / Ri;  // Ns of the last forward pass
+                    if (act) load_rt<-1, kMaxRadixZ>(a, Ri, j, L, NsL, tw, [&](int i) { return ln[pidx(i)]; });
+                    lds_sync<W>();
+                    if (act) store_rt<kMaxRadixZ>(a, Ri, j, NsL, [&](int i, C v) { ln[pidx(i)] = v; });
+                } else if (act) {
+#pragma unroll
+                    for (int r = 0; r < kMaxRadixZ; ++r) a[r] = ln[pidx(j + r * qi)];
+                }
+                __syncthreads();  // the multiply reads the other two lines and the staged tensor
+            } else {
+                lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, tw);  // natural order in LDS afterwards
+                if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
+            }
             if (act) {
                 // signs under the mirrors: a component is odd along an axis when exactly one of its
                 // indices is that axis; the z-odd ones (xz, yz) pick up sz
@@ -240,19 +258,29 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                 const R s2 = comp == 0 ? sx : comp == 1 ? sy : (R)1;
                 auto mul = [&](auto radix_tag) {
                     constexpr int RI = decltype(radix_tag)::value;
+                    // the component is uniform per wave: one code path per component; on the
+                    // own-component path each reads only the two other lines
+                    auto rows = [&](auto comp_tag) {
+                        constexpr int CP = decltype(comp_tag)::value;
 #pragma unroll
-                    for (int r = 0; r < RI; ++r) {
-                        const int kz = j + r * qi;
-                        const bool lo = kz <= hz;
-                        const R sz = lo ? (R)1 : (R)-1;
-                        const C *g = gsh + (lo ? kz : L - kz);
-                        const C G0 = cscale(g[g0 * hz1], comp == 2 ? s0 * sz : s0);
-                        const C G1 = cscale(g[g1 * hz1], comp == 2 ? s1 * sz : s1);
-                        const C G2 = cscale(g[g2 * hz1], comp == 2 ? s2 : s2 * sz);
-                        const int p = pidx(kz);
-                        const C X = lcol[p], Y = lcol[S + p], Z = lcol[2 * S + p];
-                        a[r] = cadd(cadd(cmul(G0, X), cmul(G1, Y)), cmul(G2, Z));
-                    }
+                        for (int r = 0; r < RI; ++r) {
+                            const int kz = j + r * qi;
+                            const bool lo = kz <= hz;
+                            const R sz = lo ? (R)1 : (R)-1;
+                            const C *g = gsh + (lo ? kz : L - kz);
+                            const C G0 = cscale(g[g0 * hz1], CP == 2 ? s0 * sz : s0);
+                            const C G1 = cscale(g[g1 * hz1], CP == 2 ? s1 * sz : s1);
+                            const C G2 = cscale(g[g2 * hz1], CP == 2 ? s2 : s2 * sz);
+                            const int p = pidx(kz);
+                            const C X = OWN && CP == 0 ? a[r] : lcol[p];
+                            const C Y = OWN && CP == 1 ? a[r] : lcol[S + p];
+                            const C Z = OWN && CP == 2 ? a[r] : lcol[2 * S + p];
+                            a[r] = cadd(cadd(cmul(G0, X), cmul(G1, Y)), cmul(G2, Z));
+                        }
+                    };
+                    if (comp == 0) rows(std::integral_constant<int, 0>{});
+                    else if (comp == 1) rows(std::integral_constant<int, 1>{});
+                    else rows(std::integral_constant<int, 2>{});
                     dftR<+1, RI>(a);
                 };
                 switch (Ri) {

@@ -73,7 +73,7 @@ _SIGS = {
                                ct.POINTER(ct.c_double), ct.c_int32, ct.POINTER(ct.c_double)]),
     "dda_matvec_timed": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_int32, ct.c_void_p,
                                     ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_float), ct.POINTER(ct.c_float)]),
-    "dda_tune": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
+    "dda_tune": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "dda_get_tiles": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "dda_set_tiles": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "dda_net_num_params": (ct.c_int64, []),
@@ -263,13 +263,13 @@ class Context:
         t = (ct.c_int32 * 2)(*[int(v) for v in tiles])
         _check(lib().dda_set_tiles(self._h, int(precision), t), "dda_set_tiles")
 
-    def tune(self, precision=FP64, reps=3, cache=None):
+    def tune(self, precision=FP64, reps=3, cache=None, n_rhs=1):
         """Autotune the x/y tile schedule (dda_tune).  With a cache file (JSON; default: the
         DDA_TUNE_CACHE environment variable, if set) a schedule found earlier for the same grid,
         padded grid and precision is reused instead of timed again."""
         import json
         cache = cache if cache is not None else os.environ.get("DDA_TUNE_CACHE")
-        key = f"{self.grid}|{tuple(self.padded_grid())}|{int(precision)}"
+        key = f"{self.grid}|{tuple(self.padded_grid())}|{int(precision)}|{int(n_rhs)}"
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
@@ -278,7 +278,7 @@ class Context:
                 self.set_tiles(table[key], precision)
                 return list(table[key])
         t = (ct.c_int32 * 2)()
-        _check(lib().dda_tune(self._h, int(precision), int(reps), t), "dda_tune")
+        _check(lib().dda_tune(self._h, int(precision), int(n_rhs), int(reps), t), "dda_tune")
         res = [t[0], t[1]]
         if cache:
             table[key] = res
