@@ -1,6 +1,6 @@
 """GPU parity of the interaction-matrix product (eq. 3) against the CPU oracle.
 
-Tolerance: the benchmark spec's bound for the fp64 product is 1e-12 relative; it is applied to the
+Tolerance: the required bound for the fp64 product is 1e-12 relative; it is applied to the
 largest componentwise error divided by the largest |y| (rounding of the FFT route is a few ulps
 times log L of the data's scale).  The fp32 product is held to 2e-5 of the same scale.
 """

@@ -1,6 +1,6 @@
 """GPU parity of the solvers and the read-out with the CPU oracle.
 
-Bars: Cext within 1e-9 relative of the oracle's QMR at the same tolerance (spec bound);
+Bars: Cext within 1e-9 relative of the oracle's QMR at the same tolerance (the required bound);
 the solution within a few times tol of the oracle's; Mueller elements within 1e-9 of the largest
 |S11| when computed from the same solution vector (phase recurrences add ~1e-14).
 """
