@@ -107,6 +107,8 @@ def forms(ctx, w, beams, theta, dda, inputs, torch):
     # (1) fp32 inner solves + fp64 refinement on this sphere
     (x32, i32, _), d32 = _timed(torch, lambda: ctx.solve(beams, tol=w.tol, precision=dda.FP32_REFINE))
     (x64, i64, _), d64 = _timed(torch, lambda: ctx.solve(beams, tol=w.tol))
+    (xp, ip, _), dp = _timed(torch, lambda: ctx.solve(beams, tol=w.tol, precision=dda.FP32_PRODUCT))
+    cp = [ctx.cross_sections(b, xp[i].contiguous()) for i, b in enumerate(beams)]
     c64 = [ctx.cross_sections(b, x64[i].contiguous()) for i, b in enumerate(beams)]
     c32 = [ctx.cross_sections(b, x32[i].contiguous()) for i, b in enumerate(beams)]
     M64 = ctx.mueller(inputs.X_POL, x64[0].contiguous(), x64[1].contiguous(), 0.0, theta)
@@ -120,7 +122,15 @@ def forms(ctx, w, beams, theta, dda, inputs, torch):
         "rel_err_Cext": max(abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(c32, c64)),
         "rel_err_Cabs_abs": max(abs(a[1] - b[1]) / abs(b[0]) for a, b in zip(c32, c64)),
         "rel_err_S11_max": float(np.max(np.abs(M32[:, 0, 0] / M64[:, 0, 0] - 1)))}
-    del x32, x64
+    Mp = ctx.mueller(inputs.X_POL, xp[0].contiguous(), xp[1].contiguous(), 0.0, theta)
+    res["fp32_products"] = {
+        "workload": "sphere256_x40_m1.05, both polarizations, tol 1e-5",
+        "time_to_tol_s_per_solve": dp / len(beams), "speedup_vs_fp64": d64 / dp,
+        "iterations": [i["iters"] for i in ip], "fp64_finish": [i["outer"] for i in ip],
+        "res_true": max(i["res_true"] for i in ip),
+        "rel_err_Cext": max(abs(a[0] - b[0]) / abs(b[0]) for a, b in zip(cp, c64)),
+        "rel_err_S11_max": float(np.max(np.abs(Mp[:, 0, 0] / M64[:, 0, 0] - 1)))}
+    del x32, x64, xp
     log("form fp32_refine done")
     # (1b) the strongly scattering sphere: m = 2, x = 20, 160^3 (QMR needs >20000 iterations to
     # 1e-5 there; both forms are timed to 1e-2)
@@ -132,14 +142,19 @@ def forms(ctx, w, beams, theta, dda, inputs, torch):
         (xa, ia, sa), ta = _timed(torch, lambda: c3.solve(w3.beams, tol=tol3, raise_on_fail=False))
         (xb, ib, sb), tb = _timed(torch, lambda: c3.solve(w3.beams, tol=tol3, precision=dda.FP32_REFINE,
                                                              raise_on_fail=False))
+        (xc, ic, sc), tc = _timed(torch, lambda: c3.solve(w3.beams, tol=tol3, precision=dda.FP32_PRODUCT,
+                                                             raise_on_fail=False))
         ca = c3.cross_sections(w3.beams[0], xa[0].contiguous())
         cb = c3.cross_sections(w3.beams[0], xb[0].contiguous())
+        cc = c3.cross_sections(w3.beams[0], xc[0].contiguous())
         res["fp32_refine_m2"] = {
             "workload": "sphere160_x20_m2 (2,144,432 dipoles, 320^3 grid), x-pol, tol 1e-2",
             "fp64_s": ta, "refine_s": tb, "speedup_vs_fp64": ta / tb, "fp64_iterations": ia[0]["iters"],
             "inner_iterations": ib[0]["iters"], "outer": ib[0]["outer"], "status": [sa, sb],
-            "res_true": [ia[0]["res_true"], ib[0]["res_true"]], "Cext": [ca[0], cb[0]]}
-        del xa, xb
+            "res_true": [ia[0]["res_true"], ib[0]["res_true"]], "Cext": [ca[0], cb[0]],
+            "fp32_products_s": tc, "speedup_fp32_products": ta / tc, "fp32_products_iterations": ic[0]["iters"],
+            "fp32_products_res_true": ic[0]["res_true"], "fp32_products_Cext": cc[0]}
+        del xa, xb, xc
     log("form fp32_refine_m2 done")
     # (2a) 64 orientations x 2 polarizations of a 64^3 ellipsoid in one batch
     w4 = inputs.c4a_ellipsoid64()

@@ -63,7 +63,13 @@ enum { DDA_QMR = 0, DDA_BICGSTAB = 1 };
 /* Arithmetic of the solve: plain double precision everywhere (Sec. 2: all floats double), or
  * single-precision FFTs, tensor multiply and inner QMR with double-precision residuals, iterate
  * updates and read-out (iterative refinement). */
-enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1 };
+/* DDA_FP64: everything in double precision.  DDA_FP32_REFINE: single-precision inner QMR solves
+ * (products, vectors, scalars) on the double-precision residual, double-precision residual and
+ * update (iterative refinement).  DDA_FP32_PRODUCT: the double-precision solver whose products run
+ * the FFTs and the tensor multiply in single precision (x, y and the epilogue in double), to
+ * max(tol, 1e-6); a right-hand side whose true residual misses tol afterwards is finished in
+ * DDA_FP64 from there (from zero if that iterate is no better than zero). */
+enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1, DDA_FP32_PRODUCT = 2 };
 
 /* Incident plane wave in the particle frame: unit propagation vector and complex unit
  * polarization (E_inc(r) = pol * exp(i kd prop.r)). */
@@ -77,13 +83,13 @@ typedef struct {
 typedef struct {
     int32_t pad[3];        /* padded FFT sizes per axis; 0 = smallest supported size >= 2n-1 */
     int32_t lines_per_block; /* FFT lines per workgroup; 0 = built-in choice */
-    int32_t fp32;          /* nonzero: also build the single-precision tensor for DDA_FP32_REFINE */
+    int32_t fp32;          /* nonzero: also build the single-precision tensor (DDA_FP32_REFINE, _PRODUCT) */
 } dda_setup_opts;
 
 /* Options of dda_solve (pass NULL for defaults). */
 typedef struct {
     int32_t solver;        /* DDA_QMR (default) or DDA_BICGSTAB */
-    int32_t precision;     /* DDA_FP64 (default) or DDA_FP32_REFINE */
+    int32_t precision;     /* DDA_FP64 (default), DDA_FP32_REFINE or DDA_FP32_PRODUCT */
     int32_t maxit;         /* iteration limit; 0 = 100000 */
     int32_t check_every;   /* iterations between host-side convergence checks; 0 = automatic */
     double inner_tol;      /* DDA_FP32_REFINE: relative tolerance of each inner solve; 0 = automatic:
@@ -98,7 +104,8 @@ typedef struct {
     int32_t status;        /* dda_status of this right-hand side */
     int32_t iters;         /* solver iterations (summed over inner solves for DDA_FP32_REFINE) */
     int32_t matvecs;       /* interaction-matrix products */
-    int32_t outer;         /* refinement steps (DDA_FP32_REFINE), else 0 */
+    int32_t outer;         /* refinement steps (DDA_FP32_REFINE); 1 if DDA_FP32_PRODUCT needed the
+                              double-precision finish; else 0 */
     double res_rec;        /* relative recursive residual at exit */
     double res_true;       /* relative true residual ||b - A x|| / ||b|| computed once at exit */
     double t_solve_s;      /* wall time of the solve of the whole batch, seconds */

@@ -37,6 +37,10 @@ template <int DIR, typename C> __host__ __device__ __forceinline__ C mul_i(C a) 
     return DIR < 0 ? mk<C>(a.y, -a.x) : mk<C>(-a.y, a.x);
 }
 template <typename C> __host__ __device__ __forceinline__ C czero() { return mk<C>(0, 0); }
+// complex value converted between precisions
+template <typename D, typename S> __host__ __device__ __forceinline__ D ccast(S v) {
+    return mk<D>((decltype(D::x))v.x, (decltype(D::x))v.y);
+}
 
 // Thread-local last error message, set by the ABI layer.
 void set_error(const std::string &msg);

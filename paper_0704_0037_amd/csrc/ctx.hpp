@@ -94,6 +94,9 @@ dda_status matvec_device<double>(Ctx &c, const double2 *x, double2 *y, int nrhs,
 template <>
 dda_status matvec_device<float>(Ctx &c, const float2 *x, float2 *y, int nrhs, const float2 *scale, float2 *dots,
                                 hipStream_t s, const int *done, hipEvent_t *ev);
+// double-precision x, y, scale and dots through single-precision transforms (context with fp32)
+dda_status matvec_device_mixed(Ctx &c, const double2 *x, double2 *y, int nrhs, const double2 *scale, double2 *dots,
+                               hipStream_t s, const int *done, hipEvent_t *ev = nullptr);
 
 // number of per-block dot partials the x-inverse kernel writes per right-hand side
 template <typename R> inline const Tiles &tiles_of(const Ctx &c) { return sizeof(R) == 8 ? c.tl64 : c.tl32; }

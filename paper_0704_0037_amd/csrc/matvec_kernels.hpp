@@ -28,8 +28,10 @@ constexpr int kMaxRadixZ = 8;   // the fused z pass keeps three components in re
 // ---------------------------------------------------------------- K1: forward x pass
 // Block: component c, plane z, NL consecutive lines y.  Gathers x from the compact vector
 // (zero for void cells and for the padding), transforms along x, writes B1[c][z][kx][y].
-template <typename R, int LC>
-__global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ x,
+// RX: precision of the input vector (the transform runs in R; a double vector may feed a single-
+// precision transform)
+template <typename R, int LC, typename RX = R>
+__global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restrict__ gmap, const cplx<RX> *__restrict__ x,
                                                 cplx<R> *__restrict__ B1, int nx, int ny, int nz, int N,
                                                 FftPlan pl_rt, const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
@@ -49,7 +51,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
     const int c = b / nz;
     if (done && done[c / 3]) return;  // this right-hand side has converged
     const int t = threadIdx.x;
-    const C *xc = x + (size_t)c * N;
+    const cplx<RX> *xc = x + (size_t)c * N;
     {   // pass 0 from global, lines along lanes' j (x contiguous)
         const int line = t / TPL, j = t % TPL, y = y0 + line;
         if (j < L / R0) {
@@ -59,7 +61,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
             load_rt<-1, kMaxRadix>(a, R0, j, L, 1, tw, [&](int i) -> C {
                 if (yok && i < nx) {
                     const int id = grow[i];
-                    if (id >= 0) return xc[id];
+                    if (id >= 0) return ccast<C>(xc[id]);
                 }
                 return czero<C>();
             });
@@ -391,14 +393,17 @@ __device__ __forceinline__ cplx<R> block_sum(cplx<R> v, cplx<R> *scratch) {
     return scratch[0];  // valid in every thread
 }
 
-template <typename R, int LC>
+// RX: precision of x, y, the scale and the dots (the transform runs in R; with R = float and
+// RX = double the epilogue y = x - s v and the dot sums are formed in double)
+template <typename R, int LC, typename RX = R>
 __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ B1,
-                                                const cplx<R> *__restrict__ xin, cplx<R> *__restrict__ yout,
+                                                const cplx<RX> *__restrict__ xin, cplx<RX> *__restrict__ yout,
                                                 int nx, int ny, int nz, int N, FftPlan pl_rt,
                                                 const cplx<R> *__restrict__ twall, int lnl,
-                                                const cplx<R> *__restrict__ scale, cplx<R> *__restrict__ dots,
+                                                const cplx<RX> *__restrict__ scale, cplx<RX> *__restrict__ dots,
                                                 const int *__restrict__ done) {
     using C = cplx<R>;
+    using CX = cplx<RX>;
     const FftPlan pl = plan_of<LC, kMaxRadix, true>(pl_rt);
     const int NL = 1 << lnl;
     const int NP = pl.npass, R0 = pl.radix[0], RL = pl.radix[NP - 1], NSL = pl.ns[NP - 1];
@@ -429,17 +434,17 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     __syncthreads();
     lds_passes<+1, kMaxRadix, LC, true>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
     const int line = t / TPL, j = t % TPL, y = y0 + line;
-    const C sc = scale[c / 3];
-    const C *xc = xin + (size_t)c * N;
-    C *yc = yout + (size_t)c * N;
+    const CX sc = scale[c / 3];
+    const CX *xc = xin + (size_t)c * N;
+    CX *yc = yout + (size_t)c * N;
     const int *grow = gmap + ((size_t)z * ny + (y < ny ? y : 0)) * nx;
-    C acc = czero<C>();
+    CX acc = czero<CX>();
     auto emit = [&](int i, C v) {
         if (y < ny && i < nx) {
             const int id = grow[i];
             if (id >= 0) {
-                const C xv = xc[id];
-                const C out = csub(xv, cmul(sc, v));
+                const CX xv = xc[id];
+                const CX out = csub(xv, cmul(sc, ccast<CX>(v)));
                 yc[id] = out;
                 acc = cadd(acc, cmul(xv, out));
             }
@@ -457,7 +462,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
         for (int i = j; i < nx; i += TPL) emit(i, lds[line * S + pidx(i)]);
     }
     if (dots) {
-        C s = block_sum<R>(acc, lds);  // LDS reused as scratch: all FFT reads are done
+        CX s = block_sum<RX>(acc, reinterpret_cast<CX *>(lds));  // LDS reused as scratch: all FFT reads are done
         if (t == 0) dots[blockIdx.x] = s;
     }
 }

@@ -42,15 +42,25 @@ template <class K> inline void allow_lds(K kernel, size_t bytes) {
             hipLaunchKernelGGL((KERNEL<R, 0>), __VA_ARGS__);                           \
             break;                                                                     \
     }
-#define DDA_CASE_k_fwd_x(L) case L: allow_lds(&k_fwd_x<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_fwd_x<R, L>), DDA_ARGS); break;
+// the x passes also carry the precision of the vectors
+#define DDA_DISPATCH_X(LEN, KERNEL, BYTES, ...)                                        \
+    switch (LEN) {                                                                     \
+        DDA_SPECIALIZED_LENGTHS(DDA_CASE_##KERNEL)                                     \
+        default:                                                                       \
+            allow_lds(&KERNEL<R, 0, RX>, BYTES);                                       \
+            hipLaunchKernelGGL((KERNEL<R, 0, RX>), __VA_ARGS__);                       \
+            break;                                                                     \
+    }
+#define DDA_CASE_k_fwd_x(L) case L: allow_lds(&k_fwd_x<R, L, RX>, DDA_BYTES); hipLaunchKernelGGL((k_fwd_x<R, L, RX>), DDA_ARGS); break;
 #define DDA_CASE_k_fwd_y(L) case L: allow_lds(&k_fwd_y<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_fwd_y<R, L>), DDA_ARGS); break;
 #define DDA_CASE_k_zmul(L) case L: allow_lds(&k_zmul<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_zmul<R, L>), DDA_ARGS); break;
 #define DDA_CASE_k_inv_y(L) case L: allow_lds(&k_inv_y<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_inv_y<R, L>), DDA_ARGS); break;
-#define DDA_CASE_k_inv_x(L) case L: allow_lds(&k_inv_x<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_inv_x<R, L>), DDA_ARGS); break;
+#define DDA_CASE_k_inv_x(L) case L: allow_lds(&k_inv_x<R, L, RX>, DDA_BYTES); hipLaunchKernelGGL((k_inv_x<R, L, RX>), DDA_ARGS); break;
 
-template <typename R>
-dda_status matvec_device_impl(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, const cplx<R> *scale, cplx<R> *dots,
-                              hipStream_t s, const int *done, hipEvent_t *ev) {
+// Transforms in precision R on the work buffers of precision R; x, y, scale and dots in RX.
+template <typename R, typename RX = R>
+dda_status matvec_device_impl(Ctx &c, const cplx<RX> *x, cplx<RX> *y, int nrhs, const cplx<RX> *scale,
+                              cplx<RX> *dots, hipStream_t s, const int *done, hipEvent_t *ev) {
     using C = cplx<R>;
     Work<R> &w = work_of<R>(c);
     const C *tw = tw_of<R>(c);
@@ -67,7 +77,7 @@ dda_status matvec_device_impl(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, co
 #define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, x, w.B1, c.nx, c.ny, c.nz, N, \
                  c.pxf, tw, tl.lnl_x, done
 #define DDA_BYTES lx_bytes
-    DDA_DISPATCH(c.Lx, k_fwd_x, DDA_BYTES, DDA_ARGS)
+    DDA_DISPATCH_X(c.Lx, k_fwd_x, DDA_BYTES, DDA_ARGS)
 #undef DDA_BYTES
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[1], s));
@@ -96,7 +106,7 @@ dda_status matvec_device_impl(Ctx &c, const cplx<R> *x, cplx<R> *y, int nrhs, co
 #define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, w.B1, x, y, c.nx, c.ny, c.nz, \
                  N, c.pxi, tw, tl.lnl_x, scale, dots, done
 #define DDA_BYTES lx_bytes
-    DDA_DISPATCH(c.Lx, k_inv_x, DDA_BYTES, DDA_ARGS)
+    DDA_DISPATCH_X(c.Lx, k_inv_x, DDA_BYTES, DDA_ARGS)
 #undef DDA_BYTES
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[5], s));

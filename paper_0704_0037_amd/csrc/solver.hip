@@ -381,10 +381,10 @@ __global__ void __launch_bounds__(kVecThreads) k_bi_p(SolveState *st, const int 
     }
 }
 
-// partials of u^H w and (optionally) w^H w over one right-hand side
+// partials of u^H w and (optionally) u^H u over one right-hand side
 template <typename R>
 __global__ void __launch_bounds__(kVecThreads) k_bi_dots(const int *done, const cplx<R> *u, const cplx<R> *w,
-                                                         size_t n3, double2 *part, int with_ww) {
+                                                         size_t n3, double2 *part, int with_uu) {
     __shared__ double2 sh[2 * kVecThreads];
     const int rhs = blockIdx.y;
     if (done[rhs]) return;
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(kVecThreads) k_bi_dots(const int *done, const 
         const double2 a = up<R>(u[off + i]), b = up<R>(w[off + i]);
         acc[0].x += a.x * b.x + a.y * b.y;  // conj(a) b
         acc[0].y += a.x * b.y - a.y * b.x;
-        if (with_ww) acc[1].x += b.x * b.x + b.y * b.y;
+        if (with_uu) acc[1].x += a.x * a.x + a.y * a.y;
     }
     block_reduce<2>(acc, sh);
     if (threadIdx.x == 0) {
@@ -733,7 +733,19 @@ template <typename R> struct Run {
     hipEvent_t ev = nullptr;
     bool fin = false;
     bool pending = false;
+    bool mixed = false;  // double-precision Krylov vectors, single-precision transforms (R = double)
 };
+
+// the product a run applies: plain precision R, or double vectors through single-precision
+// transforms
+template <typename R>
+static dda_status run_matvec(Run<R> &k, const cplx<R> *x, cplx<R> *y, cplx<R> *dots, const int *done) {
+    Ctx &c = *k.c;
+    Work<R> &w = work_of<R>(c);
+    if constexpr (std::is_same<R, double>::value)
+        if (k.mixed) return matvec_device_mixed(c, x, y, k.B.nrhs, w.scale, dots, c.stream, done);
+    return matvec_device<R>(c, x, y, k.B.nrhs, w.scale, dots, c.stream, done);
+}
 
 // enqueue `count` solver iterations on the context's stream
 template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count) {
@@ -745,12 +757,12 @@ template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count)
     const int nrhs = B.nrhs;
     const size_t n3 = B.n3;
     Work<R> &w = work_of<R>(c);
-    const int ndots = (int)dots_per_rhs<R>(c);
+    const int ndots = (int)(k.mixed ? dots_per_rhs<float>(c) : dots_per_rhs<R>(c));
     cplx<R> *x = k.x;
     dda_status st;
     for (int it = 0; it < count; ++it) {
         if (k.solver == DDA_QMR) {
-            if ((st = matvec_device<R>(c, v.p, v.pt, nrhs, w.scale, w.dots, s, B.done)) != DDA_OK) return st;
+            if ((st = run_matvec(k, v.p, v.pt, w.dots, B.done)) != DDA_OK) return st;
             hipLaunchKernelGGL(k_qmr_scal_eps<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
             hipLaunchKernelGGL(k_qmr_vt<R>, vg, vb, 0, s, B.st, B.done, v.pt, v.vt, n3, B.part);
             hipLaunchKernelGGL(k_qmr_scal_2, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
@@ -759,12 +771,12 @@ template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count)
             hipLaunchKernelGGL(k_qmr_scal_3, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
         } else {
             hipLaunchKernelGGL(k_bi_p<R>, vg, vb, 0, s, B.st, B.done, v.r, v.p, v.v, n3);
-            if ((st = matvec_device<R>(c, v.p, v.v, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
+            if ((st = run_matvec(k, v.p, v.v, nullptr, B.done)) != DDA_OK) return st;
             hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.rs, v.v, n3, B.part, 0);
             hipLaunchKernelGGL(k_bi_scal_alpha, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
             hipLaunchKernelGGL(k_bi_s<R>, vg, vb, 0, s, B.st, B.done, v.r, v.v, v.s, n3, B.part);
             hipLaunchKernelGGL(k_bi_scal_s, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
-            if ((st = matvec_device<R>(c, v.s, v.t, nrhs, w.scale, nullptr, s, B.done)) != DDA_OK) return st;
+            if ((st = run_matvec(k, v.s, v.t, nullptr, B.done)) != DDA_OK) return st;
             hipLaunchKernelGGL(k_bi_dots<R>, vg, vb, 0, s, B.done, v.t, v.s, n3, B.part, 1);
             hipLaunchKernelGGL(k_bi_scal_omega, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb);
             hipLaunchKernelGGL(k_bi_x<R>, vg, vb, 0, s, B.st, B.done, v.p, v.s, v.t, v.rs, x, v.r, n3, B.part);
@@ -796,7 +808,7 @@ template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
     dda_status st;
     DDA_HIP_CHECK(hipEventCreateWithFlags(&k.ev, hipEventDisableTiming));
     if (have_x0) {
-        if ((st = matvec_device<R>(c, k.x, v.pt, B.nrhs, w.scale, nullptr, s, nullptr)) != DDA_OK) return st;
+        if ((st = run_matvec(k, k.x, v.pt, nullptr, nullptr)) != DDA_OK) return st;
     }
     if (k.solver == DDA_QMR) {
         hipLaunchKernelGGL(k_qmr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, k.x, v.r, v.vt, n3, B.part,
@@ -940,6 +952,7 @@ static dda_status prepare_fp64(Ctx &c, Run<double> &k, const dda_beam *beams, in
     k.v = vecs_of<double>(c, nrhs);
     k.x = x;
     k.solver = o.solver;
+    k.mixed = o.precision == DDA_FP32_PRODUCT;
     for (int r = 0; r < nrhs; ++r)
         if ((st = rhs_launch<double>(c, beams[r], k.v.b + (size_t)r * k.B.n3, c.stream)) != DDA_OK) return st;
     if (o.x0 && o.x0 != x)
@@ -1003,6 +1016,56 @@ static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol
     run_end(k);
     if (st != DDA_OK) return st;
     return finish_fp64(c, k, nrhs, o, info, hcap);
+}
+
+// Double-precision Krylov iteration whose products run their transforms and tensor multiply in
+// single precision, to max(tol, 1e-6) (below that the single-precision products' rounding makes
+// the residual stagnate); a right-hand side whose true (double-precision) residual then misses
+// tol is finished by the double-precision solver, started from that iterate when it lowers the
+// residual below |b| and from zero otherwise.
+static dda_status solve_products32(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
+                                   double2 *x, dda_solve_info *info, int check_every, bool graph) {
+    if (!c.ghat32) {
+        set_error("dda_solve: DDA_FP32_PRODUCT needs a context set up with opts.fp32");
+        return DDA_ENOTSUP;
+    }
+    std::vector<dda_solve_info> first(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        first[r] = dda_solve_info{};
+        if (info) {
+            first[r].res_hist = info[r].res_hist;
+            first[r].res_hist_cap = info[r].res_hist_cap;
+        }
+    }
+    const double kProductFloor = 1e-6;
+    dda_status st = solve_fp64(c, beams, nrhs, std::max(tol, kProductFloor), o, x, first.data(), check_every, graph);
+    if (st != DDA_OK && st != DDA_ENOTCONV && st != DDA_EBREAKDOWN) return st;
+    bool again = false;
+    for (int r = 0; r < nrhs; ++r) again = again || !(first[r].res_true < tol);
+    std::vector<dda_solve_info> second(nrhs);
+    if (again) {
+        dda_solve_opts o2 = o;
+        o2.precision = DDA_FP64;
+        o2.x0 = x;
+        o2.x0_check = 1;
+        for (auto &i : second) i = dda_solve_info{};
+        st = solve_fp64(c, beams, nrhs, tol, o2, x, second.data(), check_every, graph);
+        if (st != DDA_OK && st != DDA_ENOTCONV && st != DDA_EBREAKDOWN) return st;
+    }
+    dda_status ret = DDA_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const dda_solve_info &f = again ? second[r] : first[r];
+        if (ret == DDA_OK && f.status != DDA_OK) ret = (dda_status)f.status;
+        if (!info) continue;
+        info[r].status = f.status;
+        info[r].iters = first[r].iters + (again ? second[r].iters : 0);
+        info[r].matvecs = first[r].matvecs + (again ? second[r].matvecs : 0);
+        info[r].outer = again ? 1 : 0;
+        info[r].res_rec = f.res_rec;
+        info[r].res_true = f.res_true;
+        info[r].res_hist_len = first[r].res_hist_len;
+    }
+    return ret;
 }
 
 // Iterative refinement: outer fp64 residual and update, inner fp32 QMR to inner_tol.
@@ -1143,7 +1206,7 @@ static dda_status check_opts(const dda_solve_opts *opts, dda_solve_opts &o) {
         set_error("dda_solve: unknown solver");
         return DDA_EINVAL;
     }
-    if (o.precision != DDA_FP64 && o.precision != DDA_FP32_REFINE) {
+    if (o.precision != DDA_FP64 && o.precision != DDA_FP32_REFINE && o.precision != DDA_FP32_PRODUCT) {
         set_error("dda_solve: unknown precision");
         return DDA_EINVAL;
     }
@@ -1188,8 +1251,12 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
             set_error("dda_solve: could not order the solve after the caller's stream");
             return DDA_EHIP;
         }
-        st = o.precision == DDA_FP64 ? solve_fp64(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph)
-                                     : solve_refine(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
+        if (o.precision == DDA_FP64)
+            st = solve_fp64(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
+        else if (o.precision == DDA_FP32_REFINE)
+            st = solve_refine(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
+        else
+            st = solve_products32(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
     }
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)

@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdda_mi3
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESYMMETRY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 POL_LDR, POL_CM = 0, 1
 QMR, BICGSTAB = 0, 1
-FP64, FP32_REFINE = 0, 1
+FP64, FP32_REFINE, FP32_PRODUCT = 0, 1, 2
 
 
 class Beam(ct.Structure):

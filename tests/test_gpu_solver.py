@@ -229,3 +229,55 @@ def test_solve_many_equals_single():
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_fp32_products_solve():
+    """Double-precision QMR / Bi-CGSTAB with single-precision transforms: reaches the tolerance in
+    the true residual (finishing in double precision when needed) and tracks the fp64 solve."""
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((14, 12, 10), (7, 6, 5))
+    beams = [inputs.X_POL, inputs.Y_POL]
+    with dda.Context(mask, 1.6, 0.45, fp32=True) as ctx:
+        for solver in (dda.QMR, dda.BICGSTAB):
+            x64, i64, _ = ctx.solve(beams, tol=1e-9, solver=solver)
+            xp, ip, st = ctx.solve(beams, tol=1e-9, solver=solver, precision=dda.FP32_PRODUCT)
+            assert st == 0 and all(i["res_true"] < 1e-9 for i in ip), ip
+            assert (torch.linalg.norm(xp - x64) / torch.linalg.norm(x64)).item() < 1e-7
+            for r, b in enumerate(beams):
+                c64 = ctx.cross_sections(b, x64[r].contiguous())[0]
+                cp = ctx.cross_sections(b, xp[r].contiguous())[0]
+                assert abs(cp - c64) < 1e-8 * abs(c64)
+        # at 1e-5 the single-precision products alone suffice, in about the fp64 iteration count
+        x64, i64, _ = ctx.solve(beams, tol=1e-5)
+        xq, iq, st = ctx.solve(beams, tol=1e-5, precision=dda.FP32_PRODUCT)
+        assert st == 0 and all(i["outer"] == 0 and i["res_true"] < 1e-5 for i in iq)
+        assert all(abs(a["iters"] - b["iters"]) <= 2 for a, b in zip(iq, i64))
+    with dda.Context(mask, 1.6, 0.45) as ctx:
+        with pytest.raises(dda.DDAError) as e:
+            ctx.solve(beams, tol=1e-5, precision=dda.FP32_PRODUCT)
+        assert e.value.status == dda.ENOTSUP
+
+
+def test_bicgstab_iterates_track_oracle():
+    """Same algorithm, same order: residual histories agree with the oracle's Bi-CGSTAB, from a
+    zero guess and from a perturbed guess (a wrong step length shows up at the first iteration)."""
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((14, 12, 10), (7, 6, 5))
+    beam = inputs.X_POL
+    pos, alpha, beta, A, b = _oracle_system(mask, 1.6, 0.45, beam)
+    apply = lambda v: (A @ v.reshape(-1)).reshape(v.shape)
+    xs = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    rng = np.random.default_rng(3)
+    x0 = xs + 1e-6 * np.abs(xs).max() * (rng.standard_normal(xs.shape) + 1j * rng.standard_normal(xs.shape))
+    with dda.Context(mask, 1.6, 0.45) as ctx:
+        for guess in (None, x0):
+            xo, io = odda.bicgstab(apply, b, 1e-9, x0=guess)
+            x0t = None if guess is None else torch.from_numpy(guess.T.copy()).reshape(1, 3, ctx.n).cuda()
+            x, info, st = ctx.solve([beam], tol=1e-9, solver=dda.BICGSTAB, x0=x0t, history=200)
+            assert st == 0 and info[0]["iters"] == io["iters"], (info[0]["iters"], io["iters"])
+            h = np.array(info[0]["res_hist"])
+            ho = np.array(io["res_hist"])
+            assert len(h) == len(ho)
+            assert np.abs(h[:4] / ho[:4] - 1).max() < 1e-8
+            assert np.abs(h / ho - 1).max() < 1e-3
+            assert np.linalg.norm(x[0].cpu().numpy().T - xo) / np.linalg.norm(xo) < 1e-8
