@@ -42,6 +42,7 @@ struct Ctx {
     std::vector<int32_t> lin_host;  // linear cell index of each dipole
 
     int *gmap = nullptr;            // device [nz][ny][nx] -> dipole index or -1
+    int2 *rows = nullptr;           // device [nz][ny] single-run descriptors of the rows (x passes)
     int *lin = nullptr;             // device [N] linear cell index
     int *line_start = nullptr;      // device [ny*nz + 1] first dipole of each (y, z) line (read-out)
     double2 *ghat = nullptr;        // device octant tensor, fp64

@@ -40,6 +40,9 @@ template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_
 #ifndef DDA_TW_DERIVED
 #define DDA_TW_DERIVED 1  // radix-8 twiddles w^3, w^5, w^6, w^7 formed from w, w^2, w^4 (0: all from the table)
 #endif
+#ifndef DDA_B2_COLMAJOR
+#define DDA_B2_COLMAJOR 1  // y-pass output [Lx][c][Ly][nz] (0: [Ly][Lx][c][nz])
+#endif
 #ifndef DDA_ZMUL_OWN
 #define DDA_ZMUL_OWN 1  // the fp64 z pass multiplies each thread's own component from registers
 #endif

@@ -30,8 +30,20 @@ constexpr int kMaxRadixZ = 8;   // the fused z pass keeps three components in re
 // (zero for void cells and for the padding), transforms along x, writes B1[c][z][kx][y].
 // RX: precision of the input vector (the transform runs in R; a double vector may feed a single-
 // precision transform)
+// rows: per (y, z) row of the grid, {x0 | x1 << 16, first dipole} when the row's non-void cells are
+// the single run x0 <= x < x1 (dipole indices then follow from x without a lookup), x0 = 0xFFFF
+// when they are not (the cell map gmap is used)
+__device__ __forceinline__ bool row_run(const int2 *__restrict__ rows, int row, int &x0, int &x1, int &id0) {
+    const int2 rr = rows[row];
+    x0 = rr.x & 0xFFFF;
+    x1 = (rr.x >> 16) & 0xFFFF;
+    id0 = rr.y;
+    return x0 != 0xFFFF;
+}
+
 template <typename R, int LC, typename RX = R>
-__global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restrict__ gmap, const cplx<RX> *__restrict__ x,
+__global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restrict__ gmap, const int2 *__restrict__ rows,
+                                                const cplx<RX> *__restrict__ x,
                                                 cplx<R> *__restrict__ B1, int nx, int ny, int nz, int N,
                                                 FftPlan pl_rt, const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
@@ -57,14 +69,21 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
         if (j < L / R0) {
             const int *grow = gmap + ((size_t)z * ny + (y < ny ? y : 0)) * nx;
             const bool yok = y < ny;
+            int rx0, rx1, id0;
+            const bool run = row_run(rows, z * ny + (y < ny ? y : 0), rx0, rx1, id0);
             C a[kMaxRadix];
-            load_rt<-1, kMaxRadix>(a, R0, j, L, 1, tw, [&](int i) -> C {
-                if (yok && i < nx) {
-                    const int id = grow[i];
-                    if (id >= 0) return ccast<C>(xc[id]);
-                }
-                return czero<C>();
-            });
+            if (run)
+                load_rt<-1, kMaxRadix>(a, R0, j, L, 1, tw, [&](int i) -> C {
+                    return (yok && i >= rx0 && i < rx1) ? ccast<C>(xc[id0 + i - rx0]) : czero<C>();
+                });
+            else
+                load_rt<-1, kMaxRadix>(a, R0, j, L, 1, tw, [&](int i) -> C {
+                    if (yok && i < nx) {
+                        const int id = grow[i];
+                        if (id >= 0) return ccast<C>(xc[id]);
+                    }
+                    return czero<C>();
+                });
             C *ln = lds + line * S;
             store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
@@ -131,8 +150,13 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
     lds_sync<W>();
     lds_passes<-1, kMaxRadix, LC, false>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
     if constexpr (W) __syncthreads();  // the store mapping below crosses waves
+#if DDA_B2_COLMAJOR
+    const size_t kystride = (size_t)nz;
+    C *dst = B2 + ((size_t)kx * ncomp + c) * (size_t)L * nz;
+#else
     const size_t kystride = (size_t)Lx * ncomp * nz;
     C *dst = B2 + ((size_t)kx * ncomp + c) * nz;
+#endif
     if (NP >= 2) {
         const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
         const int Rp = RL, Ns = NSL;
@@ -222,7 +246,11 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             const bool mxs = slot & 1, mys = slot & 2;
             const bool ok = (!mxs || nmx == 2) && (!mys || nmy == 2);  // slot holds a distinct column
             const int kx = mxs ? Lx - kxo : kxo, ky = mys ? Ly - kyo : kyo;
+#if DDA_B2_COLMAJOR
+            C *line = B2 + (((size_t)(ok ? kx : 0) * (3 * nrhs) + rhs * 3 + comp) * Ly + (ok ? ky : 0)) * nz;
+#else
             C *line = B2 + (((size_t)(ok ? ky : 0) * Lx + (ok ? kx : 0)) * (3 * nrhs) + rhs * 3 + comp) * nz;
+#endif
             if (j < q0) {
                 C a[kMaxRadixZ];
                 load_rt<-1, kMaxRadixZ>(a, R0, j, L, 1, tw,
@@ -340,8 +368,13 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
     const int c = b / Lx;
     if (done && done[c / 3]) return;
     const int t = threadIdx.x;
+#if DDA_B2_COLMAJOR
+    const size_t kystride = (size_t)nz;
+    const C *src = B2 + ((size_t)kx * ncomp + c) * (size_t)L * nz;
+#else
     const size_t kystride = (size_t)Lx * ncomp * nz;
     const C *src = B2 + ((size_t)kx * ncomp + c) * nz;
+#endif
     {   // pass 0 from global, lanes over lines (z contiguous in B2)
         const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
         if (j < L / R0) {
@@ -396,7 +429,8 @@ __device__ __forceinline__ cplx<R> block_sum(cplx<R> v, cplx<R> *scratch) {
 // RX: precision of x, y, the scale and the dots (the transform runs in R; with R = float and
 // RX = double the epilogue y = x - s v and the dot sums are formed in double)
 template <typename R, int LC, typename RX = R>
-__global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restrict__ gmap, const cplx<R> *__restrict__ B1,
+__global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restrict__ gmap, const int2 *__restrict__ rows,
+                                                const cplx<R> *__restrict__ B1,
                                                 const cplx<RX> *__restrict__ xin, cplx<RX> *__restrict__ yout,
                                                 int nx, int ny, int nz, int N, FftPlan pl_rt,
                                                 const cplx<R> *__restrict__ twall, int lnl,
@@ -438,10 +472,12 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     const CX *xc = xin + (size_t)c * N;
     CX *yc = yout + (size_t)c * N;
     const int *grow = gmap + ((size_t)z * ny + (y < ny ? y : 0)) * nx;
+    int rx0, rx1, id0;
+    const bool run = row_run(rows, z * ny + (y < ny ? y : 0), rx0, rx1, id0);
     CX acc = czero<CX>();
     auto emit = [&](int i, C v) {
         if (y < ny && i < nx) {
-            const int id = grow[i];
+            const int id = run ? (i >= rx0 && i < rx1 ? id0 + i - rx0 : -1) : grow[i];
             if (id >= 0) {
                 const CX xv = xc[id];
                 const CX out = csub(xv, cmul(sc, ccast<CX>(v)));

@@ -276,6 +276,7 @@ void destroy(Ctx *c) {
     free_work(c->w64);
     free_work(c->w32);
     (void)hipFree(c->gmap);
+    (void)hipFree(c->rows);
     (void)hipFree(c->lin);
     (void)hipFree(c->line_start);
     (void)hipFree(c->ghat);
@@ -462,11 +463,31 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
         goto fail;
     }
     if ((st = device_alloc((void **)&c->gmap, ncell * sizeof(int32_t))) != DDA_OK) goto fail;
+    if ((st = device_alloc((void **)&c->rows, (size_t)c->ny * c->nz * sizeof(int2))) != DDA_OK) goto fail;
     if ((st = device_alloc((void **)&c->lin, c->N * sizeof(int32_t))) != DDA_OK) goto fail;
     if ((st = device_alloc((void **)&c->tw64, total * sizeof(double2))) != DDA_OK) goto fail;
     if ((st = device_alloc((void **)&c->tw32, total * sizeof(float2))) != DDA_OK) goto fail;
     {
+        // rows whose non-void cells form one run x0 <= x < x1 (or none) need no cell-map lookups
+        std::vector<int2> rows((size_t)c->ny * c->nz);
+        for (size_t row = 0; row < rows.size(); ++row) {
+            const int32_t *g = gmap.data() + row * c->nx;
+            int x0 = -1, x1 = -1, runs = 0;
+            for (int xx = 0; xx < c->nx; ++xx)
+                if (g[xx] >= 0 && (xx == 0 || g[xx - 1] < 0)) {
+                    ++runs;
+                    x0 = xx;
+                }
+            if (runs == 1) {
+                x1 = x0;
+                while (x1 < c->nx && g[x1] >= 0) ++x1;
+                rows[row] = make_int2(x0 | (x1 << 16), g[x0]);
+            } else {
+                rows[row] = make_int2(runs == 0 ? 0 : 0xFFFF, 0);
+            }
+        }
         hipError_t e = hipMemcpy(c->gmap, gmap.data(), ncell * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->rows, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->lin, c->lin_host.data(), c->N * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->tw64, tw.data(), total * sizeof(double2), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), total * sizeof(float2), hipMemcpyHostToDevice);
