@@ -270,11 +270,13 @@ __device__ __forceinline__ void twiddle(C *a, int k, int step, const C *__restri
 }
 
 // Load the R inputs of butterfly j through ld(index), twiddle, transform (into a[0..R-1]).
-template <int DIR, int RADIX, typename C, class LD>
+// UPPER_ZERO: the first pass of a zero-padded line (L >= 2n - 1, so every index >= L/2 is
+// padding): inputs j + r L/R with r >= ceil(R/2) are zero without being loaded.
+template <int DIR, int RADIX, typename C, class LD, bool UPPER_ZERO = false>
 __device__ __forceinline__ void bfly_load(C *a, int j, int L, int Ns, const C *__restrict__ tw, LD ld) {
     const int q = L / RADIX;
 #pragma unroll
-    for (int r = 0; r < RADIX; ++r) a[r] = ld(j + r * q);
+    for (int r = 0; r < RADIX; ++r) a[r] = (UPPER_ZERO && 2 * r >= RADIX) ? czero<C>() : ld(j + r * q);
     if (Ns > 1) twiddle<DIR, RADIX>(a, j % Ns, q / Ns, tw);  // step = L / (Ns * RADIX)
     dftR<DIR, RADIX>(a);
 }
@@ -295,16 +297,16 @@ __device__ __forceinline__ void bfly_store(const C *a, int j, int Ns, ST st) {
 }
 
 // Runtime-radix dispatch.  MAXR bounds the radices a kernel supports (register array size).
-template <int DIR, int MAXR, typename C, class LD>
+template <int DIR, int MAXR, bool UPPER_ZERO = false, typename C, class LD>
 __device__ __forceinline__ void load_rt(C *a, int R, int j, int L, int Ns, const C *__restrict__ tw, LD ld) {
     switch (R) {
         case 1: a[0] = ld(j); break;
-        case 2: bfly_load<DIR, 2>(a, j, L, Ns, tw, ld); break;
-        case 3: bfly_load<DIR, 3>(a, j, L, Ns, tw, ld); break;
-        case 4: bfly_load<DIR, 4>(a, j, L, Ns, tw, ld); break;
-        case 5: bfly_load<DIR, 5>(a, j, L, Ns, tw, ld); break;
-        case 8: if constexpr (MAXR >= 8) bfly_load<DIR, 8>(a, j, L, Ns, tw, ld); break;
-        default: if constexpr (MAXR >= 16) bfly_load<DIR, 16>(a, j, L, Ns, tw, ld); break;
+        case 2: bfly_load<DIR, 2, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 3: bfly_load<DIR, 3, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 4: bfly_load<DIR, 4, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 5: bfly_load<DIR, 5, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 8: if constexpr (MAXR >= 8) bfly_load<DIR, 8, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        default: if constexpr (MAXR >= 16) bfly_load<DIR, 16, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
     }
 }
 

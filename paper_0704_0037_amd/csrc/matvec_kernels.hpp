@@ -73,11 +73,11 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
             const bool run = row_run(rows, z * ny + (y < ny ? y : 0), rx0, rx1, id0);
             C a[kMaxRadix];
             if (run)
-                load_rt<-1, kMaxRadix>(a, R0, j, L, 1, tw, [&](int i) -> C {
+                load_rt<-1, kMaxRadix, true>(a, R0, j, L, 1, tw, [&](int i) -> C {
                     return (yok && i >= rx0 && i < rx1) ? ccast<C>(xc[id0 + i - rx0]) : czero<C>();
                 });
             else
-                load_rt<-1, kMaxRadix>(a, R0, j, L, 1, tw, [&](int i) -> C {
+                load_rt<-1, kMaxRadix, true>(a, R0, j, L, 1, tw, [&](int i) -> C {
                     if (yok && i < nx) {
                         const int id = grow[i];
                         if (id >= 0) return ccast<C>(xc[id]);
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
             const bool zok = z < nz;
             const C *src = B1 + (((size_t)c * nz + (zok ? z : 0)) * Lx + kx) * ny;
             C a[kMaxRadix];
-            load_rt<-1, kMaxRadix>(a, R0, j, L, 1, tw,
+            load_rt<-1, kMaxRadix, true>(a, R0, j, L, 1, tw,
                                    [&](int i) -> C { return (zok && i < ny) ? src[i] : czero<C>(); });
             C *ln = lds + line * S;
             store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
 #endif
             if (j < q0) {
                 C a[kMaxRadixZ];
-                load_rt<-1, kMaxRadixZ>(a, R0, j, L, 1, tw,
+                load_rt<-1, kMaxRadixZ, true>(a, R0, j, L, 1, tw,
                                         [&](int i) -> C { return (ok && i < nz) ? line[i] : czero<C>(); });
                 store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
             }
