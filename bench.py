@@ -173,16 +173,23 @@ def forms(ctx, w, beams, theta, dda, inputs, torch):
     log("form batched_orientations done")
     # (2b) 32 spheres of 24..96 cells, solved concurrently
     ws = inputs.c4b_sphere_batch()
-    cs = [dda.Context(x.mask, x.m, x.kd) for x in ws]
+    cs = [dda.Context(x.mask, x.m, x.kd, fp32=True) for x in ws]
     try:
         for c in cs:
+            c.tune(dda.FP64)
+            c.tune(dda.FP32_REFINE)
             c.solve([inputs.X_POL], tol=1e-1)
+            c.solve([inputs.X_POL], tol=1e-1, precision=dda.FP32_PRODUCT)
+        pol = [inputs.X_POL] * len(cs)
         _, tseq = _timed(torch, lambda: [c.solve([inputs.X_POL], tol=1e-5) for c in cs])
-        (_, infos, st), tm = _timed(torch, lambda: dda.solve_many(cs, [inputs.X_POL] * len(cs), tol=1e-5))
+        (_, infos, st), tm = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5))
+        (_, i32, st32), tm32 = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5, precision=dda.FP32_PRODUCT))
         res["many_particles"] = {
-            "workload": "32 spheres n ~ U{24..96}, m ~ U[1.05, 1.6], kd 0.3, x-pol, tol 1e-5 (fp64)",
+            "workload": "32 spheres n ~ U{24..96}, m ~ U[1.05, 1.6], kd 0.3, x-pol, tol 1e-5",
             "dipoles": int(sum(c.n for c in cs)), "sequential_fp64_s": tseq, "concurrent_fp64_s": tm,
-            "speedup": tseq / tm, "iterations": [int(i["iters"]) for i in infos]}
+            "concurrent_fp32_products_s": tm32, "speedup": tseq / tm, "speedup_fp32_products": tseq / tm32,
+            "iterations": [int(i["iters"]) for i in infos], "fp64_finish": sum(int(i["outer"]) for i in i32),
+            "res_true_max_fp32_products": max(i["res_true"] for i in i32)}
     finally:
         for c in cs:
             c.close()

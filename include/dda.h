@@ -180,10 +180,12 @@ dda_status dda_solve(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, double 
 /*
  * dda_solve_many — one right-hand side on each of n_ctx particles (contexts), solved concurrently:
  * every context advances on its own stream (the paper runs independent orientations or particles
- * as separate simulations, Sec. 2; here they share the GPU).  Double precision, zero initial guess.
+ * as separate simulations, Sec. 2; here they share the GPU).  Zero initial guess.
  *   ctxs    host [n_ctx] distinct contexts;  beams  host [n_ctx]
  *   x_out   host [n_ctx] device pointers, each complex128 [3][N_i]
  *   info    host [n_ctx] or NULL
+ * opts->precision DDA_FP64 or DDA_FP32_PRODUCT (contexts set up with opts.fp32; particles whose
+ * true residual misses tol are finished in double precision one after another).
  * Returns DDA_OK if every particle converged, else the first failing status; DDA_ENOTSUP for
  * DDA_FP32_REFINE or an initial guess.
  */

@@ -1284,9 +1284,24 @@ extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const 
     dda_solve_opts o;
     dda_status st = check_opts(opts, o);
     if (st != DDA_OK) return st;
-    if (o.precision != DDA_FP64 || o.x0) {
-        set_error("dda_solve_many: double precision without an initial guess only");
+    if ((o.precision != DDA_FP64 && o.precision != DDA_FP32_PRODUCT) || o.x0) {
+        set_error("dda_solve_many: DDA_FP64 or DDA_FP32_PRODUCT, without an initial guess");
         return DDA_ENOTSUP;
+    }
+    const bool mixed = o.precision == DDA_FP32_PRODUCT;
+    for (int i = 0; i < n_ctx && mixed; ++i)
+        if (!cx(ctxs[i])->ghat32) {
+            set_error("dda_solve_many: DDA_FP32_PRODUCT needs contexts set up with opts.fp32");
+            return DDA_ENOTSUP;
+        }
+    const double tol_run = mixed ? std::max(tol, 1e-6) : tol;  // single-precision products stall below 1e-6
+    std::vector<dda_solve_info> local(n_ctx);
+    for (int i = 0; i < n_ctx; ++i) {
+        local[i] = dda_solve_info{};
+        if (info) {
+            local[i].res_hist = info[i].res_hist;
+            local[i].res_hist_cap = info[i].res_hist_cap;
+        }
     }
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<std::unique_ptr<StreamSwap>> sw;
@@ -1305,8 +1320,8 @@ extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const 
         cadence(c, 1, o, check, graph);
         runs[i].check_every = check;
         runs[i].graph = graph;
-        hcaps[i] = hist_cap(info ? info + i : nullptr, 1);
-        st = prepare_fp64(c, runs[i], &beams[i], 1, tol, o, (double2 *)x_out[i], hcaps[i]);
+        hcaps[i] = hist_cap(&local[i], 1);
+        st = prepare_fp64(c, runs[i], &beams[i], 1, tol_run, o, (double2 *)x_out[i], hcaps[i]);
     }
     // all particles advance concurrently, each on its own stream
     bool busy = st == DDA_OK;
@@ -1323,11 +1338,51 @@ extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const 
     for (int i = 0; i < n_ctx; ++i) {
         run_end(runs[i]);
         if (ret == DDA_OK || ret == DDA_ENOTCONV || ret == DDA_EBREAKDOWN) {
-            const dda_status si = finish_fp64(*cx(ctxs[i]), runs[i], 1, o, info ? info + i : nullptr, hcaps[i]);
+            const dda_status si = finish_fp64(*cx(ctxs[i]), runs[i], 1, o, &local[i], hcaps[i]);
             if (si == DDA_EHIP || si == DDA_ENOMEM) ret = si;
             else if (ret == DDA_OK && si != DDA_OK) ret = si;
         }
     }
+    // single-precision products: particles whose true residual missed tol are finished in double
+    // precision from their iterate (one after another; the remaining work is short)
+    if (mixed && (ret == DDA_OK || ret == DDA_ENOTCONV || ret == DDA_EBREAKDOWN)) {
+        ret = DDA_OK;
+        for (int i = 0; i < n_ctx; ++i) {
+            if (local[i].res_true < tol) {
+                if (ret == DDA_OK && local[i].status != DDA_OK) ret = (dda_status)local[i].status;
+                continue;
+            }
+            Ctx &c = *cx(ctxs[i]);
+            dda_solve_opts o2 = o;
+            o2.precision = DDA_FP64;
+            o2.x0 = x_out[i];
+            o2.x0_check = 1;
+            dda_solve_info f = dda_solve_info{};
+            int check;
+            bool graph;
+            cadence(c, 1, o2, check, graph);
+            const dda_status si = solve_fp64(c, &beams[i], 1, tol, o2, (double2 *)x_out[i], &f, check, graph);
+            if (si == DDA_EHIP || si == DDA_ENOMEM) {
+                ret = si;
+                break;
+            }
+            local[i].status = f.status;
+            local[i].iters += f.iters;
+            local[i].matvecs += f.matvecs;
+            local[i].outer = 1;
+            local[i].res_rec = f.res_rec;
+            local[i].res_true = f.res_true;
+            if (ret == DDA_OK && f.status != DDA_OK) ret = (dda_status)f.status;
+        }
+    }
+    if (info)
+        for (int i = 0; i < n_ctx; ++i) {
+            double *hp = info[i].res_hist;
+            const int hc = info[i].res_hist_cap;
+            info[i] = local[i];
+            info[i].res_hist = hp;
+            info[i].res_hist_cap = hc;
+        }
     sw.clear();
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)

@@ -342,7 +342,7 @@ def _info_dict(inf):
 
 
 def solve_many(contexts, beams, tol=1e-5, solver=QMR, maxit=0, check_every=0, graph=0, x_out=None,
-               raise_on_fail=True):
+               raise_on_fail=True, precision=FP64):
     """One right-hand side per context, all solved concurrently (dda_solve_many)."""
     n = len(contexts)
     if len(beams) != n:
@@ -350,7 +350,7 @@ def solve_many(contexts, beams, tol=1e-5, solver=QMR, maxit=0, check_every=0, gr
     xs = [c.vector() for c in contexts] if x_out is None else list(x_out)
     hs = (ct.c_void_p * n)(*[c._h.value for c in contexts])
     ps = (ct.c_void_p * n)(*[_ptr(x, torch.complex128, (3, c.n), "x_out").value for x, c in zip(xs, contexts)])
-    opts = SolveOpts(solver, FP64, maxit, check_every, 0.0, None, graph, 0)
+    opts = SolveOpts(solver, precision, maxit, check_every, 0.0, None, graph, 0)
     infos = (SolveInfo * n)()
     st = lib().dda_solve_many(hs, n, _beams(beams), float(tol), ct.byref(opts), ps, infos)
     if raise_on_fail and st != OK:

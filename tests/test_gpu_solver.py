@@ -226,6 +226,22 @@ def test_solve_many_equals_single():
         with pytest.raises(dda.DDAError) as e:
             dda.solve_many([ctxs[0], ctxs[0]], beams[:2], tol=1e-8)
         assert e.value.status == dda.EINVAL
+        with pytest.raises(dda.DDAError) as e:
+            dda.solve_many(ctxs, beams, tol=1e-8, precision=dda.FP32_PRODUCT)  # no fp32 tensors
+        assert e.value.status == dda.ENOTSUP
+    finally:
+        for c in ctxs:
+            c.close()
+    # single-precision products, finished in double precision where needed
+    ctxs = [dda.Context(mk, m, kd, fp32=True) for mk, m, kd in shapes]
+    try:
+        xs, infos, st = dda.solve_many(ctxs, beams, tol=1e-8, precision=dda.FP32_PRODUCT)
+        assert st == 0
+        for c, b, x, inf in zip(ctxs, beams, xs, infos):
+            x1, i1, s1 = c.solve([b], tol=1e-8, precision=dda.FP32_PRODUCT)
+            assert s1 == 0 and inf["status"] == 0 and inf["res_true"] < 1e-8
+            assert inf["iters"] == i1[0]["iters"] and inf["outer"] == i1[0]["outer"]
+            assert torch.equal(x1[0], x)
     finally:
         for c in ctxs:
             c.close()
