@@ -136,21 +136,35 @@ def test_invalid_arguments_are_reported():
             ctx.matvec_f32(inputs.X_POL, torch.zeros((3, ctx.n), dtype=torch.complex64, device="cuda"))
 
 
+FULL = [
+    # workload, batch of right-hand sides as the benchmark launches them, rows sampled per vector
+    ("sphere256_x40_m1.05", inputs.c2_sphere256, 2, 4),
+    ("sphere160_x20_m2", inputs.c3_sphere160, 1, 6),
+    ("ellipsoid64_128rhs", inputs.c4a_ellipsoid64, 128, 3),
+]
+
+
 @pytest.mark.slow
-def test_full_size_sphere256_sampled_rows():
-    """The 256^3 sphere (x = 40, m = 1.05) at its real size: sampled rows by direct summation."""
+@pytest.mark.parametrize("name,make,nrhs,nrows", FULL, ids=[f[0] for f in FULL])
+def test_full_size_sampled_rows(name, make, nrhs, nrows):
+    """The benchmark workloads at their real sizes, in the launch configuration the benchmark
+    times (batch size, tuned tile schedule): sampled rows against the oracle's direct sums."""
     dda = _dda()
-    w = inputs.c2_sphere256()
+    w = make()
+    beams = (w.beams * nrhs)[:nrhs] if len(w.beams) < nrhs else w.beams[:nrhs]
     with dda.Context(w.mask, w.m, w.kd) as ctx:
-        assert ctx.n == 8783848 and ctx.padded_grid() == (512, 512, 512)
-        x = inputs.random_vector(ctx.n, seed=2024)
-        y = ctx.matvec(inputs.X_POL, torch.from_numpy(x).cuda()).cpu().numpy()
+        ctx.tune(dda.FP64, n_rhs=nrhs)
+        x = inputs.random_vector(ctx.n, seed=2024, n_rhs=nrhs)
+        y = ctx.matvec_batch(beams, torch.from_numpy(x).cuda()).cpu().numpy()
     pos, _ = odda.dipoles(w.mask)
-    alpha = odda.alpha_ldr(w.m, w.kd, (0, 0, 1), (1, 0, 0))
-    rows = np.random.default_rng(5).choice(len(pos), 4, replace=False)
-    ref = odda.matvec_rows(pos, w.kd, odda.beta_of_alpha(alpha), x.T, rows)
-    got = y[:, rows].T
-    assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12
+    rng = np.random.default_rng(5)
+    for r in sorted(set([0, nrhs - 1, nrhs // 2])):
+        b = beams[r]
+        beta = odda.beta_of_alpha(odda.alpha_ldr(w.m, w.kd, b.prop, b.pol))
+        rows = rng.choice(len(pos), nrows, replace=False)
+        ref = odda.matvec_rows(pos, w.kd, beta, x[r].T, rows)
+        got = y[r][:, rows].T
+        assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12, (name, r)
 
 
 def test_matvec_timed_returns_the_product():

@@ -297,3 +297,23 @@ def test_bicgstab_iterates_track_oracle():
             assert np.abs(h[:4] / ho[:4] - 1).max() < 1e-8
             assert np.abs(h / ho - 1).max() < 1e-3
             assert np.linalg.norm(x[0].cpu().numpy().T - xo) / np.linalg.norm(xo) < 1e-8
+
+
+@pytest.mark.slow
+def test_full_size_sphere256_solve():
+    """The benchmark's solve at its real size (8,783,848 dipoles, both polarizations in one batch):
+    the true residual meets the tolerance, the sphere's two polarizations give the same Cext, and
+    Qext agrees with Mie theory within the accuracy the paper reports for DDA (a few percent)."""
+    from oracle import mie
+    dda = _dda()
+    w = inputs.c2_sphere256()
+    with dda.Context(w.mask, w.m, w.kd) as ctx:
+        x, info, st = ctx.solve(w.beams, tol=w.tol)
+        assert st == 0 and all(i["res_true"] < w.tol for i in info)
+        c = [ctx.cross_sections(b, x[r].contiguous()) for r, b in enumerate(w.beams)]
+        n = ctx.n
+    assert abs(c[0][0] - c[1][0]) < 1e-8 * abs(c[0][0])
+    assert abs(c[0][1]) < 1e-10 * c[0][0]  # real m: no absorption
+    qext = odda.efficiency(c[0][0], n)
+    q_mie = mie.efficiencies(odda.size_parameter(w.kd, n), w.m)[0]
+    assert abs(qext / q_mie - 1) < 0.05, (qext, q_mie)
