@@ -97,7 +97,17 @@ typedef struct {
     const void *x0;        /* device initial guess, same layout as x_out; NULL = zero */
     int32_t graph;         /* iterations replayed as a captured hipGraph: 0 = automatic, 1 = on, -1 = off */
     int32_t x0_check;      /* 1: keep x0 for a right-hand side only if |b - A x0| < |b|, else start from 0 */
+    int32_t on_breakdown;  /* DDA_BREAKDOWN_REPORT (default) or DDA_BREAKDOWN_RECOVER, below */
 } dda_solve_opts;
+
+/* What dda_solve does when QMR breaks down for a right-hand side (the paper does not say):
+ * DDA_BREAKDOWN_REPORT stops that right-hand side with DDA_EBREAKDOWN and its last iterate.
+ * DDA_BREAKDOWN_RECOVER solves it again from its current iterate: QMR restarted (a fresh Lanczos
+ * sequence on the current residual) at most twice, then Bi-CGSTAB; a breakdown before the first
+ * step (b^T b = 0, e.g. a circularly polarized beam, for which the bilinear form vanishes) goes
+ * to Bi-CGSTAB at once.  The attempts share opts.maxit; iters, matvecs and the residual history
+ * (concatenated) cover all of them.  Ignored by dda_solve_many. */
+enum { DDA_BREAKDOWN_REPORT = 0, DDA_BREAKDOWN_RECOVER = 1 };
 
 /* Per-right-hand-side report of dda_solve. */
 typedef struct {

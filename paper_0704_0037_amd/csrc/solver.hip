@@ -1214,6 +1214,10 @@ static dda_status check_opts(const dda_solve_opts *opts, dda_solve_opts &o) {
         set_error("dda_solve: the refined single-precision solve uses QMR only");
         return DDA_ENOTSUP;
     }
+    if (o.on_breakdown != DDA_BREAKDOWN_REPORT && o.on_breakdown != DDA_BREAKDOWN_RECOVER) {
+        set_error("dda_solve: unknown breakdown policy");
+        return DDA_EINVAL;
+    }
     return DDA_OK;
 }
 
@@ -1223,6 +1227,60 @@ static void cadence(const Ctx &c, int nrhs, const dda_solve_opts &o, int &check,
     const int64_t work = c.N * (int64_t)nrhs;
     check = o.check_every > 0 ? o.check_every : work > 2000000 ? 1 : work > 100000 ? 4 : 16;
     graph = o.graph > 0 || (o.graph == 0 && work <= 2000000);
+}
+}  // namespace dda
+
+namespace dda {
+static dda_status solve_with(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
+                             double2 *x, dda_solve_info *info, int check, bool graph) {
+    if (o.precision == DDA_FP64) return solve_fp64(c, beams, nrhs, tol, o, x, info, check, graph);
+    if (o.precision == DDA_FP32_REFINE) return solve_refine(c, beams, nrhs, tol, o, x, info, check, graph);
+    return solve_products32(c, beams, nrhs, tol, o, x, info, check, graph);
+}
+
+// Breakdown recovery (DDA_BREAKDOWN_RECOVER): every right-hand side that stopped on a QMR
+// breakdown is solved again, alone, from its current iterate: QMR restarted on the current
+// residual (new Lanczos vectors) at most twice, Bi-CGSTAB after that or at once when the
+// breakdown came before the first step (the bilinear form b^T b of the start vector vanishes, and
+// so it would again).  The refined single-precision form recovers in double precision.
+static dda_status recover_breakdowns(Ctx &c, const dda_beam *beams, int nrhs, double tol,
+                                     const dda_solve_opts &o, double2 *x, dda_solve_info *inf, int check,
+                                     bool graph) {
+    const size_t n3 = (size_t)3 * c.N;
+    for (int r = 0; r < nrhs; ++r) {
+        int restarts = 0, last_iters = inf[r].iters;
+        bool bicg = o.solver == DDA_BICGSTAB;
+        while (inf[r].status == DDA_EBREAKDOWN && !bicg) {
+            bicg = last_iters == 0 || restarts >= 2;
+            dda_solve_opts s = o;
+            s.solver = bicg ? DDA_BICGSTAB : DDA_QMR;
+            s.precision = o.precision == DDA_FP32_REFINE ? DDA_FP64 : o.precision;
+            s.x0 = x + r * n3;  // the solve starts from, and overwrites, the current iterate
+            s.x0_check = 0;
+            s.maxit = o.maxit - inf[r].iters;
+            if (s.maxit <= 0) {
+                inf[r].status = DDA_ENOTCONV;
+                break;
+            }
+            dda_solve_info si{};
+            if (inf[r].res_hist && inf[r].res_hist_cap > inf[r].res_hist_len) {
+                si.res_hist = inf[r].res_hist + inf[r].res_hist_len;
+                si.res_hist_cap = inf[r].res_hist_cap - inf[r].res_hist_len;
+            }
+            const dda_status st = solve_with(c, beams + r, 1, tol, s, x + r * n3, &si, check, graph);
+            if (st != DDA_OK && st != DDA_ENOTCONV && st != DDA_EBREAKDOWN) return st;
+            inf[r].status = si.status;
+            inf[r].iters += si.iters;
+            inf[r].matvecs += si.matvecs;
+            inf[r].outer += si.outer;
+            inf[r].res_rec = si.res_rec;
+            inf[r].res_true = si.res_true;
+            inf[r].res_hist_len += si.res_hist_len;
+            last_iters = si.iters;
+            if (!bicg) ++restarts;
+        }
+    }
+    return DDA_OK;
 }
 }  // namespace dda
 
@@ -1251,12 +1309,19 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
             set_error("dda_solve: could not order the solve after the caller's stream");
             return DDA_EHIP;
         }
-        if (o.precision == DDA_FP64)
-            st = solve_fp64(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
-        else if (o.precision == DDA_FP32_REFINE)
-            st = solve_refine(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
-        else
-            st = solve_products32(*c, beams, n_rhs, tol, o, (double2 *)x_out, info, check, graph);
+        // the breakdown recovery needs the per-RHS report even when the caller passes none
+        std::vector<dda_solve_info> own;
+        dda_solve_info *inf = info;
+        if (!inf && o.on_breakdown == DDA_BREAKDOWN_RECOVER) {
+            own.assign(n_rhs, dda_solve_info{});
+            inf = own.data();
+        }
+        st = solve_with(*c, beams, n_rhs, tol, o, (double2 *)x_out, inf, check, graph);
+        if ((st == DDA_EBREAKDOWN || st == DDA_ENOTCONV) && o.on_breakdown == DDA_BREAKDOWN_RECOVER) {
+            st = recover_breakdowns(*c, beams, n_rhs, tol, o, (double2 *)x_out, inf, check, graph);
+            for (int r = 0; r < n_rhs && st == DDA_OK; ++r)
+                if (inf[r].status != DDA_OK) st = (dda_status)inf[r].status;
+        }
     }
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)

@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESYMMETRY, ENOTSUP = 0, -1, -2, 
 POL_LDR, POL_CM = 0, 1
 QMR, BICGSTAB = 0, 1
 FP64, FP32_REFINE, FP32_PRODUCT = 0, 1, 2
+BREAKDOWN_REPORT, BREAKDOWN_RECOVER = 0, 1
 
 
 class Beam(ct.Structure):
@@ -32,7 +33,7 @@ class SetupOpts(ct.Structure):
 class SolveOpts(ct.Structure):
     _fields_ = [("solver", ct.c_int32), ("precision", ct.c_int32), ("maxit", ct.c_int32),
                 ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p),
-                ("graph", ct.c_int32), ("x0_check", ct.c_int32)]
+                ("graph", ct.c_int32), ("x0_check", ct.c_int32), ("on_breakdown", ct.c_int32)]
 
 
 class SolveInfo(ct.Structure):
@@ -287,12 +288,12 @@ class Context:
         return res
 
     def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
-              x_out=None, history=0, raise_on_fail=True, graph=0, x0_check=False):
+              x_out=None, history=0, raise_on_fail=True, graph=0, x0_check=False, on_breakdown=BREAKDOWN_REPORT):
         n = len(beams)
         x_out = self.vector(n) if x_out is None else x_out
         opts = SolveOpts(solver, precision, maxit, check_every, inner_tol,
                          None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value, graph,
-                         1 if x0_check else 0)
+                         1 if x0_check else 0, on_breakdown)
         infos = (SolveInfo * n)()
         hists = []
         for i in range(n):

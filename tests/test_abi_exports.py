@@ -51,3 +51,33 @@ def test_host_only_entry_points_without_a_gpu():
     m = (ctypes.c_double * 2)(1.5, 0.0)
     assert L.dda_setup(ctypes.byref(h), grid, None, m, 0.4, 0, None, None) == dda.EINVAL
     assert h.value is None
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    # compile a probe against include/dda.h with the host C compiler and compare every struct's
+    # size and field offsets with the ctypes mirrors of the binding
+    import shutil
+    import subprocess
+    import pytest
+    from paper_0704_0037_amd import dda
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"dda_beam": dda.Beam, "dda_setup_opts": dda.SetupOpts, "dda_solve_opts": dda.SolveOpts,
+               "dda_solve_info": dda.SolveInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dda.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

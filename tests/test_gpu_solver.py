@@ -159,6 +159,37 @@ def test_breakdown_maxit_and_exact_guess():
         assert st == 0 and info[0]["iters"] == 0
 
 
+@pytest.mark.parametrize("precision", ["FP64", "FP32_PRODUCT", "FP32_REFINE"])
+def test_breakdown_recovery_reaches_the_dense_solution(precision):
+    # a circularly polarized beam along z: b^T b = 0, so QMR breaks down before its first step and
+    # the recovery goes to Bi-CGSTAB; batched with a linear polarization that QMR solves directly
+    # (S = 0 for both, one matrix), each compared with the oracle's dense solve
+    dda = _dda()
+    mask = inputs.sphere_mask(6)
+    circ = inputs.Beam((0.0, 0.0, 1.0), (1 / math.sqrt(2), 1j / math.sqrt(2), 0j))
+    beams = [inputs.X_POL, circ]
+    with dda.Context(mask, 1.5, 0.5, fp32=precision != "FP64") as ctx:
+        x, info, st = ctx.solve(beams, tol=1e-10, history=400, precision=getattr(dda, precision),
+                                on_breakdown=dda.BREAKDOWN_RECOVER)
+        assert st == 0, info
+        for r, beam in enumerate(beams):
+            *_, A, b = _oracle_system(mask, 1.5, 0.5, beam)
+            x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+            xg = x[r].cpu().numpy().T
+            assert np.linalg.norm(xg - x_lu) / np.linalg.norm(x_lu) < 1e-8
+            assert info[r]["res_true"] < 2e-10
+        if precision == "FP64":
+            assert info[0]["res_hist_len"] == info[0]["iters"] + 1
+            # the broken-down attempt gives its initial residual, the Bi-CGSTAB attempt the rest
+            # (starting again from 1: the current iterate is still zero)
+            h = info[1]["res_hist"]
+            assert len(h) == info[1]["iters"] + 2 and h[0] == h[1] and abs(h[0] - 1.0) < 1e-14
+            assert h[-1] < 1e-10
+        # the default policy still reports the breakdown
+        x, info, st = ctx.solve([circ], tol=1e-10, raise_on_fail=False)
+        assert st == dda.EBREAKDOWN and info[0]["iters"] == 0
+
+
 def test_fp32_refinement_reaches_fp64_tolerance(sphere16):
     w, ctx = sphere16
     x64, i64, _ = ctx.solve([inputs.X_POL], tol=1e-8)
