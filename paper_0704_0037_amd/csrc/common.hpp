@@ -37,6 +37,21 @@ template <int DIR, typename C> __host__ __device__ __forceinline__ C mul_i(C a) 
     return DIR < 0 ? mk<C>(a.y, -a.x) : mk<C>(-a.y, a.x);
 }
 template <typename C> __host__ __device__ __forceinline__ C czero() { return mk<C>(0, 0); }
+
+// Streaming (non-temporal) global load and store of one complex value: the FFT passes read and
+// write each intermediate element exactly once, so they bypass cache retention
+template <typename C> __device__ __forceinline__ C ld_stream(const C *p) {
+    typedef decltype(C::x) V2 __attribute__((ext_vector_type(2)));
+    const V2 w = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(p));
+    return mk<C>(w.x, w.y);
+}
+template <typename C> __device__ __forceinline__ void st_stream(C *p, C v) {
+    typedef decltype(C::x) V2 __attribute__((ext_vector_type(2)));
+    V2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<V2 *>(p));
+}
 // complex value converted between precisions
 template <typename D, typename S> __host__ __device__ __forceinline__ D ccast(S v) {
     return mk<D>((decltype(D::x))v.x, (decltype(D::x))v.y);

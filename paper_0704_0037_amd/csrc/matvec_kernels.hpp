@@ -41,6 +41,21 @@ __device__ __forceinline__ bool row_run(const int2 *__restrict__ rows, int row, 
     return x0 != 0xFFFF;
 }
 
+// Workgroups go to the eight XCDs round-robin by index.  The x and y passes renumber them so that
+// each XCD runs one contiguous range of the logical block order: the neighbouring tiles that read
+// or write neighbouring segments of the same rows then share an L2 (0: hardware order).
+#ifndef DDA_XCD_REMAP
+#define DDA_XCD_REMAP 1
+#endif
+__device__ __forceinline__ int xcd_block() {
+#if DDA_XCD_REMAP
+    const int G = gridDim.x, b = blockIdx.x, q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+#else
+    return blockIdx.x;
+#endif
+}
+
 template <typename R, int LC, typename RX = R>
 __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restrict__ gmap, const int2 *__restrict__ rows,
                                                 const cplx<RX> *__restrict__ x,
@@ -56,7 +71,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
     const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
     const int ytiles = (ny + NL - 1) >> lnl;
-    int b = blockIdx.x;
+    int b = xcd_block();
     const int y0 = (b % ytiles) * NL;
     b /= ytiles;
     const int z = b % nz;
@@ -100,7 +115,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
             C a[kMaxRadix];
             const C *ln = lds + line * S;
             load_rt<-1, kMaxRadix>(a, Rp, j, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            if (y < ny) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) { dstc[(size_t)i * ny + y] = v; });
+            if (y < ny) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) { st_stream(&dstc[(size_t)i * ny + y], v); });
         }
     } else {
         for (int e = t; e < NL * L; e += blockDim.x) {
@@ -127,7 +142,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
     const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
     const int ztiles = (nz + NL - 1) >> lnl;
-    int b = blockIdx.x;
+    int b = xcd_block();
     const int z0 = (b % ztiles) * NL;
     b /= ztiles;
     const int kx = b % Lx;
@@ -141,7 +156,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
             const C *src = B1 + (((size_t)c * nz + (zok ? z : 0)) * Lx + kx) * ny;
             C a[kMaxRadix];
             load_rt<-1, kMaxRadix, true>(a, R0, j, L, 1, tw,
-                                   [&](int i) -> C { return (zok && i < ny) ? src[i] : czero<C>(); });
+                                   [&](int i) -> C { return (zok && i < ny) ? ld_stream(&src[i]) : czero<C>(); });
             C *ln = lds + line * S;
             store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
@@ -164,7 +179,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
             C a[kMaxRadix];
             const C *ln = lds + line * S;
             load_rt<-1, kMaxRadix>(a, Rp, j, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            if (z < nz) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) { dst[(size_t)i * kystride + z] = v; });
+            if (z < nz) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) { st_stream(&dst[(size_t)i * kystride + z], v); });
         }
     } else {
         for (int e = t; e < NL * L; e += blockDim.x) {
@@ -254,7 +269,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             if (j < q0) {
                 C a[kMaxRadixZ];
                 load_rt<-1, kMaxRadixZ, true>(a, R0, j, L, 1, tw,
-                                        [&](int i) -> C { return (ok && i < nz) ? line[i] : czero<C>(); });
+                                        [&](int i) -> C { return (ok && i < nz) ? ld_stream(&line[i]) : czero<C>(); });
                 store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
             }
             lds_sync<W>();
@@ -324,14 +339,14 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             }
             __syncthreads();  // every thread has read the three transformed lines
             if (np == 1) {
-                if (act && ok) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { if (i < nz) line[i] = v; });
+                if (act && ok) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { if (i < nz) st_stream(&line[i], v); });
             } else {
                 if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
                 lds_sync<W>();
                 lds_passes<+1, kMaxRadixZ, LC, true>(ln, pi_rt, 1, np - 1, j, tw);
                 if (j < L / RQ) {
                     load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, tw, [&](int i) { return ln[pidx(i)]; });
-                    if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) line[i] = v; });
+                    if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) st_stream(&line[i], v); });
                 }
             }
             lds_sync<W>();  // the slot's lines are rewritten by the next round
@@ -361,7 +376,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
     const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
     const int ztiles = (nz + NL - 1) >> lnl;
-    int b = blockIdx.x;
+    int b = xcd_block();
     const int z0 = (b % ztiles) * NL;
     b /= ztiles;
     const int kx = b % Lx;
@@ -381,7 +396,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
             const bool zok = z < nz;
             C a[kMaxRadix];
             load_rt<+1, kMaxRadix>(a, R0, j, L, 1, tw,
-                                   [&](int i) -> C { return zok ? src[(size_t)i * kystride + z] : czero<C>(); });
+                                   [&](int i) -> C { return zok ? ld_stream(&src[(size_t)i * kystride + z]) : czero<C>(); });
             C *ln = lds + line * S;
             store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
@@ -397,7 +412,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
             const C *ln = lds + line * S;
             load_rt<+1, kMaxRadix>(a, Rp, j, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
             if (z < nz) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) {
-                if (i < ny) dst[i] = v;
+                if (i < ny) st_stream(&dst[i], v);
             });
         }
     } else if (z < nz) {
@@ -408,7 +423,8 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
 // ----------------------------------------------- K5: inverse x pass, unpad, y = x - s * conv
 // Block: component c, plane z, NL consecutive lines y.  Reads B1 along kx, inverse transform,
 // keeps x < nx at non-void cells: y = x - scale[rhs] * v with scale = alpha / (Lx Ly Lz).
-// Optionally accumulates the bilinear dot sum x_i y_i of the block into dots[blockIdx.x].
+// Optionally accumulates the bilinear dot sum x_i y_i of the block into dots[b], b the logical block
+// index (right-hand side major, so that each right-hand side owns one contiguous range).
 template <typename R>
 __device__ __forceinline__ cplx<R> block_sum(cplx<R> v, cplx<R> *scratch) {
     // deterministic tree over LDS; works for any block size (blocks need not be whole waves)
@@ -446,7 +462,8 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     const C *tw = twall + pl_rt.tw_off;
     const int L = pl.L, TPL = pl.tpl, S = lds_line_stride(L);
     const int ytiles = (ny + NL - 1) >> lnl;
-    int b = blockIdx.x;
+    const int blk = xcd_block();  // logical block: dot partials are grouped by right-hand side in this order
+    int b = blk;
     const int y0 = (b % ytiles) * NL;
     b /= ytiles;
     const int z = b % nz;
@@ -460,7 +477,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
             const bool yok = y < ny;
             C a[kMaxRadix];
             load_rt<+1, kMaxRadix>(a, R0, j, L, 1, tw,
-                                   [&](int i) -> C { return yok ? src[(size_t)i * ny + y] : czero<C>(); });
+                                   [&](int i) -> C { return yok ? ld_stream(&src[(size_t)i * ny + y]) : czero<C>(); });
             C *ln = lds + line * S;
             store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
@@ -481,7 +498,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
             if (id >= 0) {
                 const CX xv = xc[id];
                 const CX out = csub(xv, cmul(sc, ccast<CX>(v)));
-                yc[id] = out;
+                st_stream(&yc[id], out);
                 acc = cadd(acc, cmul(xv, out));
             }
         }
@@ -499,7 +516,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     }
     if (dots) {
         CX s = block_sum<RX>(acc, reinterpret_cast<CX *>(lds));  // LDS reused as scratch: all FFT reads are done
-        if (t == 0) dots[blockIdx.x] = s;
+        if (t == 0) dots[blk] = s;
     }
 }
 
