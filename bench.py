@@ -264,6 +264,20 @@ def main():
                         "frac": ab32[k] / kms32[i] / 1e6 / HBM_PEAK_GBS} for i, k in enumerate(KERNELS)}
     del x32, y32
     traffic = recorded_traffic(dom, "sphere256_fp64_2rhs")
+    # reference point for the HBM-bound kernels: a plain 1 GiB device-to-device copy (bytes read
+    # plus bytes written over its duration, HIP events, median of 5)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    cms = []
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        cms.append(e0.elapsed_time(e1))
+    copy_gbps = 2 * src.numel() * 8 / float(np.median(cms[1:])) / 1e6
+    del src, dst
     log(f"product timed: {tot_ms:.2f} ms per fp64 batch of {nb}, {tot32:.2f} ms fp32")
 
     # ---- steps: the whole hot path
@@ -320,6 +334,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_kernel[dom]["GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": per_kernel[dom]["frac"],
                      "traffic": traffic, "alg_bytes": ab[dom], "launch": f"{nb} right-hand sides, fp64"},
+        "hbm_copy_reference": {"GBps": copy_gbps, "frac": copy_gbps / HBM_PEAK_GBS,
+                               "what": "1 GiB device-to-device copy, read + write bytes per second"},
         "fp32_matvec": {"ms_per_batch": tot32, "matvec_only_per_s": nb * 1e3 / tot32,
                         "frac": sum(ab32.values()) / tot32 / 1e6 / HBM_PEAK_GBS, "kernels": per_kernel32},
     }

@@ -1326,6 +1326,10 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)
         for (int r = 0; r < n_rhs; ++r) info[r].t_solve_s = dt;
+    if (st == DDA_ENOTCONV)
+        set_error("dda_solve: a right-hand side did not reach tol within maxit (per-RHS status in info)");
+    if (st == DDA_EBREAKDOWN)
+        set_error("dda_solve: QMR breakdown for a right-hand side (per-RHS status in info)");
     return st;
 }
 
@@ -1452,5 +1456,9 @@ extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const 
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info)
         for (int i = 0; i < n_ctx; ++i) info[i].t_solve_s = dt;
+    if (ret == DDA_ENOTCONV)
+        set_error("dda_solve_many: a particle did not reach tol within maxit (per-particle status in info)");
+    if (ret == DDA_EBREAKDOWN)
+        set_error("dda_solve_many: QMR breakdown for a particle (per-particle status in info)");
     return ret;
 }

@@ -152,8 +152,10 @@ def test_breakdown_maxit_and_exact_guess():
         x, info, st = ctx.solve([circ], tol=1e-8, raise_on_fail=False)
         assert st == dda.EBREAKDOWN and info[0]["iters"] == 0
         assert torch.isfinite(torch.view_as_real(x)).all()
+        assert b"breakdown" in dda.lib().dda_last_error()
         x, info, st = ctx.solve([inputs.X_POL], tol=1e-14, maxit=3, raise_on_fail=False)
         assert st == dda.ENOTCONV and info[0]["iters"] == 3
+        assert b"maxit" in dda.lib().dda_last_error()
         xs, _, _ = ctx.solve([inputs.X_POL], tol=1e-12)
         x, info, st = ctx.solve([inputs.X_POL], tol=1e-8, x0=xs)
         assert st == 0 and info[0]["iters"] == 0
