@@ -209,6 +209,28 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def deep_m2(dda, inputs, torch):
+    """The strongly scattering sphere (m = 2, x = 20, 160^3) solved to 1e-5 in double precision and
+    with single-precision transforms; minutes per solve, so the solver prints progress lines."""
+    os.environ.setdefault("DDA_PROGRESS", "30")
+    w = inputs.c3_sphere160()
+    out = {"workload": w.name + ", x-pol, tol 1e-5"}
+    with dda.Context(w.mask, w.m, w.kd, fp32=True) as ctx:
+        ctx.tune(dda.FP64)
+        ctx.tune(dda.FP32_REFINE)
+        out["n_dipoles"] = ctx.n
+        for name, prec in (("fp64", dda.FP64), ("fp32_products", dda.FP32_PRODUCT)):
+            (x, info, st), dt = _timed(torch, lambda: ctx.solve(w.beams, tol=1e-5, precision=prec, maxit=400000,
+                                                                 raise_on_fail=False))
+            c = ctx.cross_sections(w.beams[0], x[0].contiguous())
+            out[name] = {"s": dt, "status": st, "iterations": info[0]["iters"], "fp64_finish": info[0]["outer"],
+                         "res_true": info[0]["res_true"], "Cext": c[0]}
+            log(f"deep m=2 {name}: {json.dumps(out[name])}")
+            del x
+    out["speedup_fp32_products"] = out["fp64"]["s"] / out["fp32_products"]["s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +241,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the extension forms")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for byte-counter runs)")
+    ap.add_argument("--deep-m2", action="store_true",
+                    help="only: the m = 2 sphere to 1e-5, fp64 vs single-precision transforms (~10 min)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -226,6 +250,10 @@ def main():
 
     import torch
     from paper_0704_0037_amd import dda, inputs
+
+    if args.deep_m2:
+        print(json.dumps(deep_m2(dda, inputs, torch)), flush=True)
+        return
 
     if args.calibration_copy:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")

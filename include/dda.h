@@ -183,6 +183,8 @@ dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
  *   info    host [n_rhs] or NULL
  * Returns DDA_OK if every right-hand side converged, else the first failing status
  * (DDA_ENOTCONV / DDA_EBREAKDOWN); per-RHS statuses are in info.
+ * With the environment variable DDA_PROGRESS set to a number of seconds, a running solve prints
+ * the iteration count and residual of every unconverged right-hand side to stderr that often.
  */
 dda_status dda_solve(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, double tol,
                      const dda_solve_opts *opts, void *x_out, dda_solve_info *info);

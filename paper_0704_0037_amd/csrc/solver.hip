@@ -13,6 +13,8 @@
 // are bitwise reproducible run to run.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -734,7 +736,16 @@ template <typename R> struct Run {
     bool fin = false;
     bool pending = false;
     bool mixed = false;  // double-precision Krylov vectors, single-precision transforms (R = double)
+    double progress = 0;  // seconds between progress lines on stderr (0: none)
+    std::chrono::steady_clock::time_point last_report{};
 };
+
+// Progress lines for long solves: the environment variable DDA_PROGRESS gives the seconds between
+// lines (unset or 0: silent).
+static double progress_interval() {
+    const char *e = std::getenv("DDA_PROGRESS");
+    return e ? std::atof(e) : 0.0;
+}
 
 // the product a run applies: plain precision R, or double vectors through single-precision
 // transforms
@@ -807,6 +818,8 @@ template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
     Work<R> &w = work_of<R>(c);
     dda_status st;
     DDA_HIP_CHECK(hipEventCreateWithFlags(&k.ev, hipEventDisableTiming));
+    k.progress = progress_interval();
+    k.last_report = std::chrono::steady_clock::now();
     if (have_x0) {
         if ((st = run_matvec(k, k.x, v.pt, nullptr, nullptr)) != DDA_OK) return st;
     }
@@ -848,6 +861,8 @@ template <typename R> static dda_status run_issue(Run<R> &k) {
     return post_check(k);
 }
 
+static dda_status fetch_states(Ctx &c, Bufs &B, std::vector<SolveState> &h);
+
 template <typename R> static dda_status run_poll(Run<R> &k) {
     if (!k.pending) return DDA_OK;
     DDA_HIP_CHECK(hipEventSynchronize(k.ev));
@@ -856,6 +871,21 @@ template <typename R> static dda_status run_poll(Run<R> &k) {
     bool all = true;
     for (int r = 0; r < k.B.nrhs; ++r) all = all && hd[r];
     k.fin = all;
+    if (k.progress > 0 && !k.fin) {
+        const auto now = std::chrono::steady_clock::now();
+        if (std::chrono::duration<double>(now - k.last_report).count() >= k.progress) {
+            k.last_report = now;
+            std::vector<int> d(hd, hd + k.B.nrhs);
+            std::vector<SolveState> h;
+            dda_status st = fetch_states(*k.c, k.B, h);  // the stream is idle here
+            if (st != DDA_OK) return st;
+            for (int r = 0; r < k.B.nrhs; ++r)
+                if (!d[r])
+                    std::fprintf(stderr, "dda_solve: right-hand side %d: iteration %d, relative residual %.3e\n", r,
+                                 h[r].iter, h[r].res);
+            std::fflush(stderr);
+        }
+    }
     return DDA_OK;
 }
 

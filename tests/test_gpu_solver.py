@@ -192,6 +192,18 @@ def test_breakdown_recovery_reaches_the_dense_solution(precision):
         assert st == dda.EBREAKDOWN and info[0]["iters"] == 0
 
 
+def test_progress_lines_on_request(sphere16, capfd, monkeypatch):
+    w, ctx = sphere16
+    monkeypatch.setenv("DDA_PROGRESS", "1e-9")
+    x, info, st = ctx.solve([inputs.X_POL], tol=1e-8, check_every=4, graph=-1)
+    err = capfd.readouterr().err
+    lines = [l for l in err.splitlines() if l.startswith("dda_solve: right-hand side 0: iteration")]
+    assert st == 0 and 2 <= len(lines) <= info[0]["iters"]
+    monkeypatch.delenv("DDA_PROGRESS")
+    ctx.solve([inputs.X_POL], tol=1e-8)
+    assert "dda_solve:" not in capfd.readouterr().err
+
+
 def test_fp32_refinement_reaches_fp64_tolerance(sphere16):
     w, ctx = sphere16
     x64, i64, _ = ctx.solve([inputs.X_POL], tol=1e-8)
