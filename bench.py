@@ -263,7 +263,14 @@ def main():
 
     w = inputs.c2_sphere256()
     n = w.grid[0]
+    # setup of the particle: cell map and dipole list, row runs, the Fourier-transformed tensor
+    # octant in double and single precision (timed once, the first context is also warm-up)
+    dda.Context(w.mask, w.m, w.kd, fp32=True).close()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     ctx = dda.Context(w.mask, w.m, w.kd, fp32=True)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
     L = ctx.padded_grid()[0]
     N = ctx.n
     log(f"context ready: {N} dipoles, padded grid {L}^3")
@@ -353,6 +360,7 @@ def main():
         "iterations": iters,
         "res_true": res_true,
         "Cext": [c[0] for c in cs],
+        "setup_s": t_setup,
         "matvec_ms_per_batch": tot_ms,
         "matvec_batch": nb,
         "matvec_only_per_s": nb * 1e3 / tot_ms,

@@ -67,8 +67,10 @@ enum { DDA_QMR = 0, DDA_BICGSTAB = 1 };
  * (products, vectors, scalars) on the double-precision residual, double-precision residual and
  * update (iterative refinement).  DDA_FP32_PRODUCT: the double-precision solver whose products run
  * the FFTs and the tensor multiply in single precision (x, y and the epilogue in double), to
- * max(tol, 1e-6); a right-hand side whose true residual misses tol afterwards is finished in
- * DDA_FP64 from there (from zero if that iterate is no better than zero). */
+ * max(tol, 1e-6); when a residual stops halving (no halving within as many iterations as its best
+ * value took, at least 2000) the iteration continues with double-precision products; a right-hand
+ * side whose true residual misses tol afterwards is finished in DDA_FP64 from there (from zero if
+ * that iterate is no better than zero). */
 enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1, DDA_FP32_PRODUCT = 2 };
 
 /* Incident plane wave in the particle frame: unit propagation vector and complex unit
@@ -114,7 +116,8 @@ typedef struct {
     int32_t status;        /* dda_status of this right-hand side */
     int32_t iters;         /* solver iterations (summed over inner solves for DDA_FP32_REFINE) */
     int32_t matvecs;       /* interaction-matrix products */
-    int32_t outer;         /* refinement steps (DDA_FP32_REFINE); 1 if DDA_FP32_PRODUCT needed the
+    int32_t outer;         /* refinement steps (DDA_FP32_REFINE); 1 if DDA_FP32_PRODUCT switched to
+                              double-precision products after its residual stalled or needed the
                               double-precision finish; else 0 */
     double res_rec;        /* relative recursive residual at exit */
     double res_true;       /* relative true residual ||b - A x|| / ||b|| computed once at exit */

@@ -738,7 +738,21 @@ template <typename R> struct Run {
     bool mixed = false;  // double-precision Krylov vectors, single-precision transforms (R = double)
     double progress = 0;  // seconds between progress lines on stderr (0: none)
     std::chrono::steady_clock::time_point last_report{};
+    // stall guard of a mixed run: best relative residual of each right-hand side and the iteration
+    // that reached it; a stalled right-hand side is stopped (stalled[r])
+    std::vector<double> best;
+    std::vector<int> best_it;
+    std::vector<char> stalled;
+    std::chrono::steady_clock::time_point last_guard{};
 };
+
+// A mixed run (single-precision transforms) stalls where the transforms' rounding limits the
+// accuracy the Krylov process can reach.  A stalled right-hand side is stopped there and left to
+// the double-precision solver, restarted from its iterate (continuing the same recurrence with
+// double-precision products converged far more slowly than the restart).  Stall: no halving of
+// the residual within as many iterations as the best residual took, and at least kStallMin.
+constexpr int kStallMin = 2000;
+constexpr double kGuardSeconds = 0.5;  // host-side stall checks at most this often
 
 // Progress lines for long solves: the environment variable DDA_PROGRESS gives the seconds between
 // lines (unset or 0: silent).
@@ -820,6 +834,10 @@ template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
     DDA_HIP_CHECK(hipEventCreateWithFlags(&k.ev, hipEventDisableTiming));
     k.progress = progress_interval();
     k.last_report = std::chrono::steady_clock::now();
+    k.last_guard = k.last_report;
+    k.best.assign(B.nrhs, HUGE_VAL);
+    k.best_it.assign(B.nrhs, 0);
+    k.stalled.assign(B.nrhs, 0);
     if (have_x0) {
         if ((st = run_matvec(k, k.x, v.pt, nullptr, nullptr)) != DDA_OK) return st;
     }
@@ -871,6 +889,34 @@ template <typename R> static dda_status run_poll(Run<R> &k) {
     bool all = true;
     for (int r = 0; r < k.B.nrhs; ++r) all = all && hd[r];
     k.fin = all;
+    if (k.mixed && !k.fin) {
+        const auto now = std::chrono::steady_clock::now();
+        if (std::chrono::duration<double>(now - k.last_guard).count() >= kGuardSeconds) {
+            k.last_guard = now;
+            std::vector<int> d(hd, hd + k.B.nrhs);
+            std::vector<SolveState> h;
+            dda_status st = fetch_states(*k.c, k.B, h);  // the stream is idle here
+            if (st != DDA_OK) return st;
+            bool all = true;
+            for (int r = 0; r < k.B.nrhs; ++r) {
+                if (d[r]) continue;
+                if (h[r].res < 0.5 * k.best[r]) {
+                    k.best[r] = h[r].res;
+                    k.best_it[r] = h[r].iter;
+                } else if (h[r].iter - k.best_it[r] > std::max(kStallMin, k.best_it[r])) {
+                    // stop it: its done flag makes every later iteration skip it
+                    static const int one = 1;
+                    DDA_HIP_CHECK(hipMemcpyAsync(k.B.done + r, &one, sizeof(int), hipMemcpyHostToDevice,
+                                                 k.c->stream));
+                    DDA_HIP_CHECK(hipStreamSynchronize(k.c->stream));
+                    k.stalled[r] = 1;
+                    continue;
+                }
+                all = false;
+            }
+            k.fin = all;
+        }
+    }
     if (k.progress > 0 && !k.fin) {
         const auto now = std::chrono::steady_clock::now();
         if (std::chrono::duration<double>(now - k.last_report).count() >= k.progress) {
@@ -1017,7 +1063,7 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
         info[r].iters = h[r].iter;
         const bool bi = o.solver == DDA_BICGSTAB;
         info[r].matvecs = (bi ? 2 * h[r].iter - (h[r].half ? 1 : 0) : h[r].iter) + (o.x0 ? 1 + (o.x0_check ? 1 : 0) : 0);
-        info[r].outer = 0;
+        info[r].outer = k.stalled.size() > (size_t)r && k.stalled[r] ? 1 : 0;
         info[r].res_rec = h[r].res;
         info[r].res_true = rt[r];
         if (info[r].res_hist && info[r].res_hist_cap > 0) {
@@ -1090,7 +1136,7 @@ static dda_status solve_products32(Ctx &c, const dda_beam *beams, int nrhs, doub
         info[r].status = f.status;
         info[r].iters = first[r].iters + (again ? second[r].iters : 0);
         info[r].matvecs = first[r].matvecs + (again ? second[r].matvecs : 0);
-        info[r].outer = again ? 1 : 0;
+        info[r].outer = again || first[r].outer ? 1 : 0;
         info[r].res_rec = f.res_rec;
         info[r].res_true = f.res_true;
         info[r].res_hist_len = first[r].res_hist_len;

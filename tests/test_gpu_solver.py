@@ -192,6 +192,21 @@ def test_breakdown_recovery_reaches_the_dense_solution(precision):
         assert st == dda.EBREAKDOWN and info[0]["iters"] == 0
 
 
+def test_fp32_products_on_a_strongly_scattering_sphere_reach_tol():
+    # m = 3: single-precision products make the residual creep; the stalled right-hand side is
+    # stopped and finished by the double-precision solver from its iterate
+    dda = _dda()
+    mask = inputs.sphere_mask(32)
+    with dda.Context(mask, 3.0, 0.3, fp32=True) as ctx:
+        x64, i64, st64 = ctx.solve([inputs.X_POL], tol=1e-8)
+        x32, i32, st32 = ctx.solve([inputs.X_POL], tol=1e-8, precision=dda.FP32_PRODUCT, maxit=200000)
+        assert st64 == 0 and st32 == 0, (i64, i32)
+        assert i32[0]["outer"] == 1 and i32[0]["res_true"] < 1e-8
+        c64 = ctx.cross_sections(inputs.X_POL, x64[0].contiguous())[0]
+        c32 = ctx.cross_sections(inputs.X_POL, x32[0].contiguous())[0]
+        assert abs(c32 - c64) < 1e-6 * abs(c64)
+
+
 def test_progress_lines_on_request(sphere16, capfd, monkeypatch):
     w, ctx = sphere16
     monkeypatch.setenv("DDA_PROGRESS", "1e-9")
