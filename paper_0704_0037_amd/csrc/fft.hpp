@@ -252,6 +252,32 @@ template <int DIR, int RADIX, typename C> __device__ __forceinline__ void dftR(C
 // a[r] *= w^(r k) (conjugated for the inverse), w = exp(-2 pi i step / L), from the table tw.
 // With DDA_TW_DERIVED, radix 8 loads w, w^2, w^4 and forms the other four by products (fewer
 // cached loads per butterfly, ~2 ulps more rounding).
+// Twiddle source of a transform whose passes are all radix 8: the first L/8 entries of the
+// length-L table staged in LDS (lds), the full table in global memory (glob).  A radix-8 pass
+// reads w = lds[k step] (k step < L/8 there) and forms w^2, w^4 by squaring; other radices read
+// the global table.
+template <typename C> struct TwStaged {
+    const C *lds;
+    const C *glob;
+};
+
+template <int DIR, int RADIX, typename C>
+__device__ __forceinline__ void twiddle(C *a, int k, int step, TwStaged<C> tw) {
+    if constexpr (RADIX == 8) {
+        const C w1 = tw.lds[k * step], w2 = cmul(w1, w1), w4 = cmul(w2, w2);
+        const C w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+        const C w[8] = {w1, w1, w2, w3, w4, w5, w6, w7};
+#pragma unroll
+        for (int r = 1; r < 8; ++r) a[r] = cmul(a[r], DIR < 0 ? w[r] : cconj(w[r]));
+    } else {
+#pragma unroll
+        for (int r = 1; r < RADIX; ++r) {
+            C w = tw.glob[r * k * step];
+            a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
+        }
+    }
+}
+
 template <int DIR, int RADIX, typename C>
 __device__ __forceinline__ void twiddle(C *a, int k, int step, const C *__restrict__ tw) {
     if constexpr (DDA_TW_DERIVED && RADIX == 8) {
@@ -281,6 +307,15 @@ __device__ __forceinline__ void bfly_load(C *a, int j, int L, int Ns, const C *_
     dftR<DIR, RADIX>(a);
 }
 
+template <int DIR, int RADIX, typename C, class LD, bool UPPER_ZERO = false>
+__device__ __forceinline__ void bfly_load(C *a, int j, int L, int Ns, TwStaged<C> tw, LD ld) {
+    const int q = L / RADIX;
+#pragma unroll
+    for (int r = 0; r < RADIX; ++r) a[r] = (UPPER_ZERO && 2 * r >= RADIX) ? czero<C>() : ld(j + r * q);
+    if (Ns > 1) twiddle<DIR, RADIX>(a, j % Ns, q / Ns, tw);
+    dftR<DIR, RADIX>(a);
+}
+
 // Twiddle and transform values already in registers (for a pass whose inputs a thread holds).
 template <int DIR, int RADIX, typename C>
 __device__ __forceinline__ void bfly_regs(C *a, int j, int L, int Ns, const C *__restrict__ tw) {
@@ -299,6 +334,19 @@ __device__ __forceinline__ void bfly_store(const C *a, int j, int Ns, ST st) {
 // Runtime-radix dispatch.  MAXR bounds the radices a kernel supports (register array size).
 template <int DIR, int MAXR, bool UPPER_ZERO = false, typename C, class LD>
 __device__ __forceinline__ void load_rt(C *a, int R, int j, int L, int Ns, const C *__restrict__ tw, LD ld) {
+    switch (R) {
+        case 1: a[0] = ld(j); break;
+        case 2: bfly_load<DIR, 2, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 3: bfly_load<DIR, 3, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 4: bfly_load<DIR, 4, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 5: bfly_load<DIR, 5, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 8: if constexpr (MAXR >= 8) bfly_load<DIR, 8, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        default: if constexpr (MAXR >= 16) bfly_load<DIR, 16, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+    }
+}
+
+template <int DIR, int MAXR, bool UPPER_ZERO = false, typename C, class LD>
+__device__ __forceinline__ void load_rt(C *a, int R, int j, int L, int Ns, TwStaged<C> tw, LD ld) {
     switch (R) {
         case 1: a[0] = ld(j); break;
         case 2: bfly_load<DIR, 2, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
@@ -366,9 +414,8 @@ template <int LC, int MAXR> __host__ __device__ constexpr bool wave_lines() {
 // must call this (it may contain barriers).  LC > 0 selects the plan make_plan(LC, MAXR, REV)
 // known at compile time: passes are then unrolled with constant radices and strides, and when a
 // line fits in a wave the passes sync only that wave; LC = 0 runs the runtime plan `pl`.
-template <int DIR, int MAXR, int LC, bool REV, typename C>
-__device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
-                                           const C *__restrict__ tw) {
+template <int DIR, int MAXR, int LC, bool REV, typename C, class TW>
+__device__ __forceinline__ void lds_passes_tw(C *ln, const FftPlan &pl, int p0, int p1, int j, TW tw) {
     auto ld = [&](int i) { return ln[pidx(i)]; };
     auto st = [&](int i, C v) { ln[pidx(i)] = v; };
     if constexpr (LC > 0) {
@@ -397,6 +444,26 @@ __device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int
             __syncthreads();
         }
     }
+}
+
+template <int DIR, int MAXR, int LC, bool REV, typename C>
+__device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
+                                           const C *__restrict__ tw) {
+    lds_passes_tw<DIR, MAXR, LC, REV>(ln, pl, p0, p1, j, tw);
+}
+template <int DIR, int MAXR, int LC, bool REV, typename C>
+__device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j, TwStaged<C> tw) {
+    lds_passes_tw<DIR, MAXR, LC, REV>(ln, pl, p0, p1, j, tw);
+}
+
+// true when every pass of the compile-time plan of length L is radix 8 (its twiddle bases fit in
+// L/8 table entries)
+__host__ __device__ constexpr bool all_radix8(int L, int maxr) {
+    if (L <= 0) return false;
+    const FftPlan P = make_plan(L, maxr, false);
+    for (int p = 0; p < P.npass; ++p)
+        if (P.radix[p] != 8) return false;
+    return P.npass > 0;
 }
 
 // compile-time pass count of the specialized plan (0 for the runtime plan)

@@ -233,6 +233,18 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
         const C *gcol = Gh + (size_t)oct * 6 * hz1;
         for (int e = t; e < 6 * hz1; e += blockDim.x) gsh[e] = gcol[e];
     }
+    // all-radix-8 lengths: the twiddle bases of every pass staged after the lines (no global
+    // twiddle loads inside the rounds)
+    constexpr bool TWL = LC > 0 && all_radix8(LC, kMaxRadixZ);
+    C *tws = lds + 6 * hz1 + DDA_ZMUL_SLOTS * 3 * S;
+    if constexpr (TWL) {
+        for (int e = t; e < LC / 8; e += blockDim.x) tws[e] = tw[e];
+        __syncthreads();
+    }
+    const auto twp = [&] {
+        if constexpr (TWL) return TwStaged<C>{tws, tw};
+        else return tw;
+    }();
     C *ln = lcol + comp * S;
     constexpr bool W = wave_lines<LC, kMaxRadixZ>();
     constexpr int ngroups = 4 / DDA_ZMUL_SLOTS;
@@ -268,7 +280,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
 #endif
             if (j < q0) {
                 C a[kMaxRadixZ];
-                load_rt<-1, kMaxRadixZ, true>(a, R0, j, L, 1, tw,
+                load_rt<-1, kMaxRadixZ, true>(a, R0, j, L, 1, twp,
                                         [&](int i) -> C { return (ok && i < nz) ? ld_stream(&line[i]) : czero<C>(); });
                 store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
             }
@@ -280,9 +292,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             C a[kMaxRadixZ];
             if constexpr (OWN) {
                 if (np >= 2) {
-                    lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np - 1, j, tw);
+                    lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np - 1, j, twp);
                     const int NsL = L / Ri;  // Ns of the last forward pass
-                    if (act) load_rt<-1, kMaxRadixZ>(a, Ri, j, L, NsL, tw, [&](int i) { return ln[pidx(i)]; });
+                    if (act) load_rt<-1, kMaxRadixZ>(a, Ri, j, L, NsL, twp, [&](int i) { return ln[pidx(i)]; });
                     lds_sync<W>();
                     if (act) store_rt<kMaxRadixZ>(a, Ri, j, NsL, [&](int i, C v) { ln[pidx(i)] = v; });
                 } else if (act) {
@@ -291,7 +303,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                 }
                 __syncthreads();  // the multiply reads the other two lines and the staged tensor
             } else {
-                lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, tw);  // natural order in LDS afterwards
+                lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, twp);  // natural order in LDS afterwards
                 if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
             }
             if (act) {
@@ -343,9 +355,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             } else {
                 if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
                 lds_sync<W>();
-                lds_passes<+1, kMaxRadixZ, LC, true>(ln, pi_rt, 1, np - 1, j, tw);
+                lds_passes<+1, kMaxRadixZ, LC, true>(ln, pi_rt, 1, np - 1, j, twp);
                 if (j < L / RQ) {
-                    load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, tw, [&](int i) { return ln[pidx(i)]; });
+                    load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, twp, [&](int i) { return ln[pidx(i)]; });
                     if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) st_stream(&line[i], v); });
                 }
             }
@@ -356,7 +368,8 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
 
 // LDS elements of the z-pass block: the tensor column and DDA_ZMUL_SLOTS slots of three lines
 __host__ __device__ constexpr size_t zmul_lds_elems(int Lz) {
-    return (size_t)6 * (Lz / 2 + 1) + (size_t)DDA_ZMUL_SLOTS * 3 * lds_line_stride(Lz);
+    return (size_t)6 * (Lz / 2 + 1) + (size_t)DDA_ZMUL_SLOTS * 3 * lds_line_stride(Lz) +
+           (all_radix8(Lz, kMaxRadixZ) ? (size_t)Lz / 8 : 0);
 }
 
 // ---------------------------------------------------------------- K4: inverse y pass
