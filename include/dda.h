@@ -67,10 +67,9 @@ enum { DDA_QMR = 0, DDA_BICGSTAB = 1 };
  * (products, vectors, scalars) on the double-precision residual, double-precision residual and
  * update (iterative refinement).  DDA_FP32_PRODUCT: the double-precision solver whose products run
  * the FFTs and the tensor multiply in single precision (x, y and the epilogue in double), to
- * max(tol, 1e-6); when a residual stops halving (no halving within as many iterations as its best
- * value took, at least 2000) the iteration continues with double-precision products; a right-hand
- * side whose true residual misses tol afterwards is finished in DDA_FP64 from there (from zero if
- * that iterate is no better than zero). */
+ * max(tol, 1e-6), or until its residual stalls (no halving within as many iterations as its best
+ * value took, at least 5000); a right-hand side whose true residual misses tol afterwards is
+ * finished in DDA_FP64 from there (from zero if that iterate is no better than zero). */
 enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1, DDA_FP32_PRODUCT = 2 };
 
 /* Incident plane wave in the particle frame: unit propagation vector and complex unit

@@ -366,7 +366,8 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     }
 }
 
-// LDS elements of the z-pass block: the tensor column and DDA_ZMUL_SLOTS slots of three lines
+// LDS elements of the z-pass block: the tensor column, DDA_ZMUL_SLOTS slots of three lines and,
+// for all-radix-8 lengths, the staged twiddle bases
 __host__ __device__ constexpr size_t zmul_lds_elems(int Lz) {
     return (size_t)6 * (Lz / 2 + 1) + (size_t)DDA_ZMUL_SLOTS * 3 * lds_line_stride(Lz) +
            (all_radix8(Lz, kMaxRadixZ) ? (size_t)Lz / 8 : 0);

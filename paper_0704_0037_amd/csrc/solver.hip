@@ -751,7 +751,7 @@ template <typename R> struct Run {
 // the double-precision solver, restarted from its iterate (continuing the same recurrence with
 // double-precision products converged far more slowly than the restart).  Stall: no halving of
 // the residual within as many iterations as the best residual took, and at least kStallMin.
-constexpr int kStallMin = 2000;
+constexpr int kStallMin = 5000;
 constexpr double kGuardSeconds = 0.5;  // host-side stall checks at most this often
 
 // Progress lines for long solves: the environment variable DDA_PROGRESS gives the seconds between
