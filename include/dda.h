@@ -30,7 +30,8 @@
  * thread-safe; separate contexts are independent.
  *
  * Errors: every entry point returns a dda_status; nothing throws or aborts across the ABI.
- * dda_last_error() returns a message describing the most recent failure on the calling thread.
+ * dda_last_error() describes the failure of the calling thread's most recent call ("" after a
+ * call that succeeded).
  */
 #ifndef DDA_MI355X_H
 #define DDA_MI355X_H
@@ -321,7 +322,8 @@ dda_status dda_guess(dda_ctx *ctx, dda_net *net, const dda_beam *beams, int32_t 
 /* Human-readable name of a status code. */
 const char *dda_strerror(dda_status status);
 
-/* Message of the most recent failure on the calling thread ("" if none). */
+/* Message of the calling thread's most recent call: why it failed, "" if it succeeded (every other
+ * entry point clears it on entry). */
 const char *dda_last_error(void);
 
 #ifdef __cplusplus

@@ -73,6 +73,7 @@ extern "C" {
 
 dda_status dda_setup(dda_ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2], double kd,
                      int32_t polarizability, const dda_setup_opts *opts, void *stream) {
+    clear_error();
     Ctx *c = nullptr;
     dda_status st = setup(&c, grid, mask, m, kd, polarizability, opts, stream);
     if (out) *out = reinterpret_cast<dda_ctx *>(c);
@@ -80,6 +81,7 @@ dda_status dda_setup(dda_ctx **out, const int32_t grid[3], const uint8_t *mask, 
 }
 
 dda_status dda_free(dda_ctx *ctx) {
+    clear_error();
     destroy(cx(ctx));
     return DDA_OK;
 }
@@ -87,6 +89,7 @@ dda_status dda_free(dda_ctx *ctx) {
 int64_t dda_num_dipoles(const dda_ctx *ctx) { return ctx ? cx(ctx)->N : -1; }
 
 dda_status dda_padded_grid(const dda_ctx *ctx, int32_t out[3]) {
+    clear_error();
     if (!ctx || !out) {
         set_error("dda_padded_grid: NULL argument");
         return DDA_EINVAL;
@@ -98,6 +101,7 @@ dda_status dda_padded_grid(const dda_ctx *ctx, int32_t out[3]) {
 }
 
 dda_status dda_polarizability(const dda_ctx *ctx, const dda_beam *beam, double out[2]) {
+    clear_error();
     if (!ctx || !out || !beam_ok(beam)) {
         set_error("dda_polarizability: NULL context/output or beam without unit vectors");
         return DDA_EINVAL;
@@ -107,6 +111,7 @@ dda_status dda_polarizability(const dda_ctx *ctx, const dda_beam *beam, double o
 }
 
 dda_status dda_rhs(dda_ctx *ctx, const dda_beam *beam, void *b) {
+    clear_error();
     if (!ctx || !b || !beam_ok(beam)) {
         set_error("dda_rhs: NULL argument or beam without unit vectors");
         return DDA_EINVAL;
@@ -144,14 +149,17 @@ static dda_status matvec_common(dda_ctx *h, const dda_beam *beams, int32_t n, co
 }
 
 dda_status dda_matvec(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y) {
+    clear_error();
     return matvec_common(ctx, beam, 1, x, y, false);
 }
 
 dda_status dda_matvec_f32(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y) {
+    clear_error();
     return matvec_common(ctx, beam, 1, x, y, true);
 }
 
 dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, const void *x, void *y) {
+    clear_error();
     return matvec_common(ctx, beams, n_rhs, x, y, false);
 }
 
@@ -196,6 +204,7 @@ extern "C" {
 
 dda_status dda_matvec_timed(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, int32_t precision, const void *x,
                             void *y, int32_t reps, float kernel_ms[5], float *total_ms) {
+    clear_error();
     Ctx *ctx = cx(h);
     if (!ctx || !beams || n_rhs < 1 || !x || !y || reps < 1 || !kernel_ms || !total_ms || x == y) {
         set_error("dda_matvec_timed: bad argument");
@@ -283,6 +292,7 @@ template <typename R> static dda_status tune(Ctx &c, int nrhs, int reps, int32_t
 extern "C" {
 
 dda_status dda_tune(dda_ctx *h, int32_t precision, int32_t n_rhs, int32_t reps, int32_t tiles_out[2]) {
+    clear_error();
     Ctx *c = cx(h);
     if (!c || reps < 1 || n_rhs < 1 || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
         set_error("dda_tune: NULL context, reps < 1, n_rhs < 1 or unknown precision");
@@ -296,6 +306,7 @@ dda_status dda_tune(dda_ctx *h, int32_t precision, int32_t n_rhs, int32_t reps, 
 }
 
 dda_status dda_get_tiles(const dda_ctx *h, int32_t precision, int32_t tiles[2]) {
+    clear_error();
     const Ctx *c = cx(h);
     if (!c || !tiles || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
         set_error("dda_get_tiles: bad argument");
@@ -308,6 +319,7 @@ dda_status dda_get_tiles(const dda_ctx *h, int32_t precision, int32_t tiles[2]) 
 }
 
 dda_status dda_set_tiles(dda_ctx *h, int32_t precision, const int32_t tiles[2]) {
+    clear_error();
     Ctx *c = cx(h);
     if (!c || !tiles || (precision != DDA_FP64 && precision != DDA_FP32_REFINE)) {
         set_error("dda_set_tiles: bad argument");

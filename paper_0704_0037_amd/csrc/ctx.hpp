@@ -12,6 +12,9 @@
 
 namespace dda {
 
+// every exported call starts with it, so the thread's error message describes that call only
+void clear_error();
+
 // Work buffers of one precision, sized for `nrhs` right-hand sides.
 template <typename R> struct Work {
     int nrhs = 0;

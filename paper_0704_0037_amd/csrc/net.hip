@@ -691,6 +691,7 @@ int64_t dda_net_num_params(void) {
 }
 
 dda_status dda_net_create(dda_net **out, int32_t grid, int32_t max_batch, const float *params, void *stream) {
+    dda::clear_error();
     if (!out || !params || grid < 8 || grid % 8 || max_batch < 1 || grid > 256 ||
         (int64_t)max_batch * grid * grid * grid * 64 > (int64_t)1 << 31) {
         set_error("dda_net_create: NULL argument, grid not a multiple of 8 in [8, 256], or batch too large");
@@ -770,6 +771,7 @@ dda_status dda_net_create(dda_net **out, int32_t grid, int32_t max_batch, const 
 }
 
 dda_status dda_net_free(dda_net *h) {
+    dda::clear_error();
     Net *n = nx_(h);
     if (!n) return DDA_OK;
     (void)hipStreamSynchronize(n->stream);
@@ -778,6 +780,7 @@ dda_status dda_net_free(dda_net *h) {
 }
 
 dda_status dda_net_set_params(dda_net *h, const float *params) {
+    dda::clear_error();
     Net *n = nx_(h);
     if (!n || !params) {
         set_error("dda_net_set_params: NULL argument");
@@ -795,6 +798,7 @@ dda_status dda_net_set_params(dda_net *h, const float *params) {
 }
 
 dda_status dda_net_get_params(dda_net *h, float *params) {
+    dda::clear_error();
     Net *n = nx_(h);
     if (!n || !params) {
         set_error("dda_net_get_params: NULL argument");
@@ -820,6 +824,7 @@ static BeamArgs beam_args(const dda_beam &b, double br, double bi) {
 static bool fits(const Net &n, const dda::Ctx &c) { return c.nx <= n.G && c.ny <= n.G && c.nz <= n.G; }
 
 dda_status dda_net_features(dda_net *h, dda_ctx *ch, const dda_beam *beam, void *feat) {
+    dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
     if (!n || !c || !feat || !dda::beam_ok(beam) || !fits(*n, *c)) {
@@ -834,6 +839,7 @@ dda_status dda_net_features(dda_net *h, dda_ctx *ch, const dda_beam *beam, void 
 }
 
 dda_status dda_net_target(dda_net *h, dda_ctx *ch, const dda_beam *beam, const void *x, void *tgt) {
+    dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
     if (!n || !c || !x || !tgt || !dda::beam_ok(beam) || !fits(*n, *c)) {
@@ -852,6 +858,7 @@ dda_status dda_net_target(dda_net *h, dda_ctx *ch, const dda_beam *beam, const v
 }
 
 dda_status dda_net_forward(dda_net *h, const void *feat, int32_t batch, void *out) {
+    dda::clear_error();
     Net *n = nx_(h);
     if (!n || !feat || !out || batch < 1 || batch > n->maxb) {
         set_error("dda_net_forward: NULL argument or batch outside [1, max_batch]");
@@ -874,6 +881,7 @@ static dda_status loss_grad(Net &n, const void *feat, const void *tgt, int batch
 }
 
 dda_status dda_net_grad(dda_net *h, const void *feat, const void *tgt, int32_t batch, double *loss, float *grad) {
+    dda::clear_error();
     Net *n = nx_(h);
     if (!n || !feat || !tgt || batch < 1 || batch > n->maxb) {
         set_error("dda_net_grad: NULL argument or batch outside [1, max_batch]");
@@ -889,6 +897,7 @@ dda_status dda_net_grad(dda_net *h, const void *feat, const void *tgt, int32_t b
 }
 
 dda_status dda_net_train_step(dda_net *h, const void *feat, const void *tgt, int32_t batch, double lr, double *loss) {
+    dda::clear_error();
     Net *n = nx_(h);
     if (!n || !feat || !tgt || batch < 1 || batch > n->maxb || !(lr > 0)) {
         set_error("dda_net_train_step: NULL argument, batch outside [1, max_batch] or lr <= 0");
@@ -907,6 +916,7 @@ dda_status dda_net_train_step(dda_net *h, const void *feat, const void *tgt, int
 }
 
 dda_status dda_guess(dda_ctx *ch, dda_net *h, const dda_beam *beams, int32_t n_rhs, const void *feat, void *x0) {
+    dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
     if (!n || !c || !beams || !feat || !x0 || n_rhs < 1 || n_rhs > n->maxb || !fits(*n, *c)) {

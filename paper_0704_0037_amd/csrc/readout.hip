@@ -245,6 +245,7 @@ using namespace dda;
 extern "C" {
 
 dda_status dda_cross_sections(dda_ctx *h, const dda_beam *beam, const void *x, double out[3]) {
+    clear_error();
     Ctx *c = cx(h);
     if (!c || !x || !out || !beam_ok(beam)) {
         set_error("dda_cross_sections: NULL argument or beam without unit vectors");
@@ -285,6 +286,7 @@ dda_status dda_cross_sections(dda_ctx *h, const dda_beam *beam, const void *x, d
 
 dda_status dda_farfield(dda_ctx *h, const dda_beam *beam, const void *x, int32_t n_dir, const double *dirs,
                         double *F) {
+    clear_error();
     Ctx *c = cx(h);
     if (!c || !x || !dirs || !F || n_dir < 1 || !beam_ok(beam)) {
         set_error("dda_farfield: NULL argument, n_dir < 1 or beam without unit vectors");
@@ -299,6 +301,7 @@ dda_status dda_farfield(dda_ctx *h, const dda_beam *beam, const void *x, int32_t
 
 dda_status dda_mueller(dda_ctx *h, const dda_beam *beam, const void *x1, const void *x2, double phi,
                        const double *theta, int32_t n_theta, double *M) {
+    clear_error();
     Ctx *c = cx(h);
     if (!c || !x1 || !theta || !M || n_theta < 1 || !beam_ok(beam)) {
         set_error("dda_mueller: NULL argument, n_theta < 1 or beam without unit vectors");

@@ -16,6 +16,7 @@ namespace dda {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
 const char *last_error() { return g_last_error.c_str(); }
 
 dda_status device_alloc(void **p, size_t bytes) {

@@ -1362,6 +1362,7 @@ static dda_status recover_breakdowns(Ctx &c, const dda_beam *beams, int nrhs, do
 
 extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, double tol,
                                 const dda_solve_opts *opts, void *x_out, dda_solve_info *info) {
+    clear_error();
     Ctx *c = cx(h);
     if (!c || !beams || !x_out || n_rhs < 1 || !(tol > 0)) {
         set_error("dda_solve: NULL argument, n_rhs < 1 or tol <= 0");
@@ -1411,6 +1412,7 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
 
 extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const dda_beam *beams, double tol,
                                      const dda_solve_opts *opts, void *const *x_out, dda_solve_info *info) {
+    clear_error();
     if (!ctxs || !beams || !x_out || n_ctx < 1 || !(tol > 0)) {
         set_error("dda_solve_many: NULL argument, n_ctx < 1 or tol <= 0");
         return DDA_EINVAL;

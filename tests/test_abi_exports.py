@@ -81,3 +81,17 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_last_error_describes_the_latest_call_only():
+    # no GPU work: a NULL context fails argument checking, and dda_free(NULL) succeeds
+    _ensure_built()
+    lib = ctypes.CDLL(LIB)
+    lib.dda_last_error.restype = ctypes.c_char_p
+    lib.dda_padded_grid.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.dda_free.argtypes = [ctypes.c_void_p]
+    out = (ctypes.c_int32 * 3)()
+    assert lib.dda_padded_grid(None, out) == -1
+    assert b"dda_padded_grid" in lib.dda_last_error()
+    assert lib.dda_free(None) == 0
+    assert lib.dda_last_error() == b""
