@@ -245,7 +245,7 @@ def main():
                     help="only: the m = 2 sphere to 1e-5, fp64 vs single-precision transforms (~10 min)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch

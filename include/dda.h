@@ -52,7 +52,7 @@ typedef enum {
     DDA_ENOTCONV = -4,     /* maxit reached before tol; x_out holds the last iterate */
     DDA_EBREAKDOWN = -5,   /* Krylov breakdown (e.g. b^T b = 0 for QMR); x_out holds the last iterate */
     DDA_ESYMMETRY = -6,    /* one-polarization read-out asked for a particle without 90-degree symmetry */
-    DDA_ENOTSUP = -7       /* option not supported by this build */
+    DDA_ENOTSUP = -7       /* option or combination of options not supported */
 } dda_status;
 
 /* Polarizability prescriptions (Sec. 2 lists four; LDR is the one used in Sec. 3). */
