@@ -55,8 +55,12 @@ typedef enum {
     DDA_ENOTSUP = -7       /* option or combination of options not supported */
 } dda_status;
 
-/* Polarizability prescriptions (Sec. 2 lists four; LDR is the one used in Sec. 3). */
-enum { DDA_POL_LDR = 0, DDA_POL_CM = 1 };
+/* Polarizability prescriptions (Sec. 2 lists four; LDR is the one used in Sec. 3).  For a unit
+ * cube and wavenumber k: DDA_POL_CM  alpha_CM = (3/4pi)(m^2-1)/(m^2+2) (Clausius-Mossotti);
+ * DDA_POL_RR  1/alpha = 1/alpha_CM - (2/3) i k^3 (radiative-reaction correction);
+ * DDA_POL_LDR 1/alpha = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 S) k^2 - (2/3) i k^3 (lattice
+ * dispersion relation, S from the beam).  The corrected LDR, a diagonal tensor, is not provided. */
+enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
 
 /* Iterative solvers (Sec. 2). */
 enum { DDA_QMR = 0, DDA_BICGSTAB = 1 };
@@ -135,7 +139,7 @@ typedef struct {
  *   mask   host uint8 [nz][ny][nx]; at least one nonzero cell
  *   m      {Re m, Im m}, refractive index of the (homogeneous) material
  *   kd     wavenumber times dipole size, > 0
- *   polarizability  DDA_POL_LDR or DDA_POL_CM
+ *   polarizability  DDA_POL_LDR, DDA_POL_CM or DDA_POL_RR
  *   opts   NULL or settings above
  *   stream hipStream_t the context runs on (NULL = default stream)
  * Errors: DDA_EINVAL for bad arguments or an unsupported padded size, DDA_ENOMEM, DDA_EHIP.

@@ -54,6 +54,16 @@ def alpha_cm(m):
     return 3.0 / (4.0 * math.pi) * (m2 - 1.0) / (m2 + 2.0)
 
 
+def alpha_rr(m, k):
+    """Clausius-Mossotti with the radiative-reaction correction (Draine 1988; one of the four
+    prescriptions the paper lists, Sec. 2): 1/alpha = 1/alpha_CM - (2/3) i k^3.
+
+    pinned by: the CM limit as k -> 0; a single dipole of real m conserves energy (its extinction
+    equals its scattering, computed by the independent double-sum scattering cross section).
+    """
+    return 1.0 / (1.0 / alpha_cm(m) - (2.0 / 3.0) * 1j * k ** 3)
+
+
 def ldr_s(prop, pol):
     """S = sum_mu (a_mu |e_mu|)^2 for unit propagation a and unit polarization e.
 

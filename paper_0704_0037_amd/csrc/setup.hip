@@ -201,6 +201,16 @@ void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
         im = cmi;
         return;
     }
+    if (c.polarizability == DDA_POL_RR) {
+        // radiative-reaction correction (Draine 1988): 1/alpha = 1/alpha_CM - (2/3) i k^3
+        const double k = c.kd;
+        const double cm2 = cmr * cmr + cmi * cmi;
+        const double ir = cmr / cm2, ii = -cmi / cm2 - (2.0 / 3.0) * k * k * k;
+        const double n2 = ir * ir + ii * ii;
+        re = ir / n2;
+        im = -ii / n2;
+        return;
+    }
     // LDR (Draine & Goodman 1993): 1/alpha = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 S) k^2 - (2/3) i k^3
     const double b1 = -1.8915316, b2 = 0.1648469, b3 = -1.7700004;
     double S = 0;
@@ -356,7 +366,7 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
         set_error("dda_setup: kd must be > 0 and m finite");
         return DDA_EINVAL;
     }
-    if (pol != DDA_POL_LDR && pol != DDA_POL_CM) {
+    if (pol != DDA_POL_LDR && pol != DDA_POL_CM && pol != DDA_POL_RR) {
         set_error("dda_setup: unknown polarizability");
         return DDA_EINVAL;
     }

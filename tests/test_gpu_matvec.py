@@ -99,6 +99,30 @@ def test_cm_polarizability():
         assert abs(ctx.polarizability(inputs.X_POL) - odda.alpha_cm(1.5 + 0.1j)) < 1e-15
 
 
+def test_rr_polarizability_solve_matches_dense():
+    # radiative-reaction prescription: alpha, the solution and the cross sections against the
+    # oracle's dense solve; real m, so Cabs vanishes
+    dda = _dda()
+    mask = inputs.sphere_mask(6)
+    m, kd = 1.7, 0.5
+    with dda.Context(mask, m, kd, polarizability=dda.POL_RR) as ctx:
+        a = ctx.polarizability(inputs.X_POL)
+        a_ref = odda.alpha_rr(m, kd)
+        assert abs(a - a_ref) <= 1e-14 * abs(a_ref)
+        x, info, st = ctx.solve([inputs.X_POL], tol=1e-11)
+        assert st == 0
+        pos, _ = odda.dipoles(mask)
+        beta = odda.beta_of_alpha(a_ref)
+        A = odda.interaction_matrix(pos, kd, beta)
+        b = odda.rhs(pos, kd, beta, (0, 0, 1), (1, 0, 0))
+        xs = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+        xg = x[0].cpu().numpy().T
+        assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) < 1e-9
+        cext, cabs, csca = ctx.cross_sections(inputs.X_POL, x[0].contiguous())
+        ref = odda.cross_sections(pos, kd, a_ref, beta * xs, (0, 0, 1), (1, 0, 0))
+        assert abs(cext - ref[0]) <= 1e-9 * abs(ref[0]) and abs(cabs) <= 1e-12 * cext
+
+
 def test_batch_matvec_equals_single():
     dda = _dda()
     mask = inputs.ellipsoid_mask((12, 10, 8), (6, 4.2, 3))

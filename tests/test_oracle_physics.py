@@ -106,6 +106,29 @@ def test_ldr_radiative_reaction_term():
                 assert abs((1 / a).imag + 2 / 3 * k ** 3) < 1e-12
 
 
+def test_rr_reduces_to_cm_for_small_k():
+    for m in (1.05, 1.5, 2.0 + 0.3j):
+        assert abs(dda.alpha_rr(m, 1e-6) / dda.alpha_cm(m) - 1) < 1e-12
+        assert abs(dda.alpha_rr(m, 0.5) / dda.alpha_cm(m) - 1) > 1e-4  # it does differ at finite k
+
+
+def test_rr_single_dipole_conserves_energy():
+    # one dipole has no interactions, so P = alpha E_inc; for real m the radiative-reaction
+    # correction makes its extinction equal its scattering (the CM value alone does not)
+    pos = np.zeros((1, 3))
+    prop, pol = (0.0, 0.0, 1.0), (1.0, 0.0, 0.0)
+    for m in (1.2, 1.5, 2.5):
+        for k in (0.2, 0.6, 1.0):
+            for alpha in (dda.alpha_rr(m, k), dda.alpha_cm(m)):
+                P = alpha * dda.incident_field(pos, k, prop, pol)
+                cext, cabs = dda.cross_sections(pos, k, alpha, P, prop, pol)[:2]
+                csca = dda.csca_exact(pos, k, P)
+                if alpha == dda.alpha_rr(m, k):
+                    assert abs(cabs) < 1e-12 * csca and abs(cext - csca) < 1e-12 * csca
+                else:
+                    assert abs(cext) < 1e-12 * csca  # CM: no extinction, yet it scatters
+
+
 # ------------------------------------------------------------------ interaction matrix
 def _small_particle(seed=3, shape=(5, 4, 6), fill=0.7):
     rng = np.random.default_rng(seed)
