@@ -342,6 +342,64 @@ def bicgstab(apply_A, b, tol, maxit=100000, x0=None):
     return x, info
 
 
+def bicg(apply_A, b, tol, maxit=100000, x0=None):
+    """Bi-CG for a complex-symmetric matrix (the paper's Bi-CG, Sec. 2 and its ref. [16]): with
+    A^T = A the shadow sequence of Bi-CG equals the conjugate of the primary one, so the method
+    needs one product per iteration and runs on the bilinear form u^T v (no conjugation):
+
+        r = b - A x;  p = r;  rho = r^T r
+        q = A p;  alpha = rho / p^T q;  x += alpha p;  r -= alpha q
+        rho_new = r^T r;  p = r + (rho_new / rho) p
+
+    Same stopping rule as `qmr`; rho = 0 or p^T q = 0 is a breakdown.
+    pinned by: dense LU; for a real symmetric positive definite matrix it is conjugate gradients
+    (iterates equal scipy's CG step by step); its residuals are conjugate-orthogonal (r_i^T r_j = 0).
+    """
+    bn = np.linalg.norm(_flat(b))
+    x = np.zeros(b.shape, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    nmv = 0
+    if x0 is None:
+        r = b.astype(np.complex128).copy()
+    else:
+        r = b - apply_A(x)
+        nmv += 1
+    hist = [np.linalg.norm(_flat(r)) / bn]
+    info = {"iters": 0, "matvecs": nmv, "status": "maxit", "res_hist": hist, "residuals": [r.copy()]}
+    if hist[-1] < tol:
+        info["status"] = "converged"
+        info["res_rec"] = hist[-1]
+        return x, info
+    p = r.copy()
+    rho = np.dot(_flat(r), _flat(r))
+    for it in range(1, maxit + 1):
+        if rho == 0:
+            info["status"] = "breakdown"
+            break
+        q = apply_A(p)
+        nmv += 1
+        eps = np.dot(_flat(p), _flat(q))
+        if eps == 0:
+            info["status"] = "breakdown"
+            break
+        alpha = rho / eps
+        x = x + alpha * p
+        r = r - alpha * q
+        info["iters"] = it
+        res = np.linalg.norm(_flat(r)) / bn
+        hist.append(res)
+        if len(info["residuals"]) < 16:
+            info["residuals"].append(r.copy())
+        if res < tol:
+            info["status"] = "converged"
+            break
+        rho_new = np.dot(_flat(r), _flat(r))
+        p = r + (rho_new / rho) * p
+        rho = rho_new
+    info["matvecs"] = nmv
+    info["res_rec"] = hist[-1]
+    return x, info
+
+
 def solve_dense(pos, k, beta, b):
     """Exact solution of eq. (3) by dense LU (numpy.linalg.solve); for small systems only."""
     A = interaction_matrix(pos, k, beta)

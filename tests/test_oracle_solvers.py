@@ -106,3 +106,51 @@ def test_maxit_and_zero_iterations():
     x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
     x, info = dda.qmr(mv, b, 1e-8, x0=x_lu)
     assert info["status"] == "converged" and info["iters"] == 0 and info["matvecs"] == 1
+
+
+# ------------------------------------------------------------------ Bi-CG (complex symmetric)
+@pytest.mark.parametrize("m", [1.5, 1.33 + 0.1j])
+def test_bicg_reaches_lu_solution(m):
+    pos, alpha, beta, A, b, mv = _system(m=m)
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    x, info = dda.bicg(mv, b, 1e-11)
+    assert info["status"] == "converged" and info["matvecs"] == info["iters"]
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-8
+
+
+def test_bicg_is_conjugate_gradients_on_a_real_spd_matrix():
+    # a library routine as the reference: scipy's CG, compared iterate by iterate
+    from scipy.sparse.linalg import cg
+    rng = np.random.default_rng(4)
+    Q = rng.standard_normal((40, 40))
+    A = Q @ Q.T + 40 * np.eye(40)
+    b = rng.standard_normal(40)
+    ref = []
+    cg(A, b, rtol=1e-14, atol=0, maxiter=12, callback=lambda xk: ref.append(xk.copy()))
+    mine = []
+    for k in range(1, 13):
+        xk, info = dda.bicg(lambda v: A @ v, b.astype(np.complex128), 1e-30, maxit=k)
+        mine.append(xk.real)
+        assert np.abs(xk.imag).max() == 0
+    n = min(len(ref), len(mine))
+    assert n >= 10
+    for a, c in zip(mine[:n], ref[:n]):
+        assert np.linalg.norm(a - c) <= 1e-10 * np.linalg.norm(c)
+
+
+def test_bicg_residuals_are_conjugate_orthogonal():
+    pos, alpha, beta, A, b, mv = _system(m=1.5)
+    x, info = dda.bicg(mv, b, 1e-30, maxit=8)
+    R = [r.reshape(-1) for r in info["residuals"]]
+    scale = max(np.linalg.norm(r) ** 2 for r in R)
+    for i in range(len(R)):
+        for j in range(i):
+            assert abs(np.dot(R[i], R[j])) < 1e-9 * scale
+    # and not Hermitian-orthogonal: the bilinear form is what the method keeps
+    assert max(abs(np.vdot(R[i], R[j])) for i in range(len(R)) for j in range(i)) > 1e-3 * scale
+
+
+def test_bicg_breaks_down_for_circular_polarization():
+    pos, alpha, beta, A, b, mv = _system(pol=(1 / math.sqrt(2), 1j / math.sqrt(2), 0))
+    x, info = dda.bicg(mv, b, 1e-8)
+    assert info["status"] == "breakdown" and info["iters"] == 0
