@@ -231,6 +231,29 @@ def deep_m2(dda, inputs, torch):
     return out
 
 
+def solver_study(dda, inputs, torch, n=64, tol=1e-5):
+    """The three solvers on one strongly scattering sphere (x = 20, m = 1.8, the case of the paper's
+    residual-history figure, Sec. 4) on an n^3 grid: iterations, products, time and the relative
+    residual at log-spaced iterations."""
+    os.environ.setdefault("DDA_PROGRESS", "30")
+    mask = inputs.sphere_mask(n)
+    N = int(mask.sum())
+    kd = inputs.kd_for_size_parameter(20.0, N)
+    out = {"workload": f"sphere{n}, x = 20, m = 1.8, kd = {kd:.4f}, x-pol, tol {tol:g}", "n_dipoles": N}
+    with dda.Context(mask, 1.8, kd) as ctx:
+        ctx.tune(dda.FP64)
+        for name, solver in (("qmr", dda.QMR), ("bicg", dda.BICG), ("bicgstab", dda.BICGSTAB)):
+            (x, info, st), dt = _timed(torch, lambda: ctx.solve([inputs.X_POL], tol=tol, solver=solver, maxit=200000,
+                                                                 history=200001, raise_on_fail=False))
+            h = info[0]["res_hist"]
+            marks = sorted({min(len(h) - 1, int(round(v))) for v in np.geomspace(1, max(1, len(h) - 1), 12)})
+            out[name] = {"s": dt, "status": st, "iterations": info[0]["iters"], "matvecs": info[0]["matvecs"],
+                         "res_true": info[0]["res_true"], "Cext": ctx.cross_sections(inputs.X_POL, x[0].contiguous())[0],
+                         "res_hist": {str(i): h[i] for i in marks}}
+            log(f"solver study {name}: {out[name]['iterations']} iterations, {dt:.2f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +266,8 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for byte-counter runs)")
     ap.add_argument("--deep-m2", action="store_true",
                     help="only: the m = 2 sphere to 1e-5, fp64 vs single-precision transforms (~10 min)")
+    ap.add_argument("--solver-study", action="store_true",
+                    help="only: QMR, Bi-CG and Bi-CGSTAB on a 64^3 sphere with x = 20, m = 1.8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -253,6 +278,9 @@ def main():
 
     if args.deep_m2:
         print(json.dumps(deep_m2(dda, inputs, torch)), flush=True)
+        return
+    if args.solver_study:
+        print(json.dumps(solver_study(dda, inputs, torch)), flush=True)
         return
 
     if args.calibration_copy:

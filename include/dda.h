@@ -62,8 +62,10 @@ typedef enum {
  * dispersion relation, S from the beam).  The corrected LDR, a diagonal tensor, is not provided. */
 enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
 
-/* Iterative solvers (Sec. 2). */
-enum { DDA_QMR = 0, DDA_BICGSTAB = 1 };
+/* Iterative solvers (Sec. 2): QMR and Bi-CG use the complex symmetry of the interaction matrix
+ * (one product per iteration, bilinear form u^T v); Bi-CGSTAB takes two products per iteration
+ * with Hermitian inner products. */
+enum { DDA_QMR = 0, DDA_BICGSTAB = 1, DDA_BICG = 2 };
 
 /* Arithmetic of the solve: plain double precision everywhere (Sec. 2: all floats double), or
  * single-precision FFTs, tensor multiply and inner QMR with double-precision residuals, iterate
@@ -94,7 +96,7 @@ typedef struct {
 
 /* Options of dda_solve (pass NULL for defaults). */
 typedef struct {
-    int32_t solver;        /* DDA_QMR (default) or DDA_BICGSTAB */
+    int32_t solver;        /* DDA_QMR (default), DDA_BICGSTAB or DDA_BICG */
     int32_t precision;     /* DDA_FP64 (default), DDA_FP32_REFINE or DDA_FP32_PRODUCT */
     int32_t maxit;         /* iteration limit; 0 = 100000 */
     int32_t check_every;   /* iterations between host-side convergence checks; 0 = automatic */
@@ -106,13 +108,13 @@ typedef struct {
     int32_t on_breakdown;  /* DDA_BREAKDOWN_REPORT (default) or DDA_BREAKDOWN_RECOVER, below */
 } dda_solve_opts;
 
-/* What dda_solve does when QMR breaks down for a right-hand side (the paper does not say):
- * DDA_BREAKDOWN_REPORT stops that right-hand side with DDA_EBREAKDOWN and its last iterate.
- * DDA_BREAKDOWN_RECOVER solves it again from its current iterate: QMR restarted (a fresh Lanczos
- * sequence on the current residual) at most twice, then Bi-CGSTAB; a breakdown before the first
- * step (b^T b = 0, e.g. a circularly polarized beam, for which the bilinear form vanishes) goes
- * to Bi-CGSTAB at once.  The attempts share opts.maxit; iters, matvecs and the residual history
- * (concatenated) cover all of them.  Ignored by dda_solve_many. */
+/* What dda_solve does when QMR or Bi-CG breaks down for a right-hand side (the paper does not
+ * say): DDA_BREAKDOWN_REPORT stops that right-hand side with DDA_EBREAKDOWN and its last iterate.
+ * DDA_BREAKDOWN_RECOVER solves it again from its current iterate: the same method restarted (a
+ * fresh Lanczos sequence on the current residual) at most twice, then Bi-CGSTAB; a breakdown
+ * before the first step (b^T b = 0, e.g. a circularly polarized beam, for which the bilinear form
+ * vanishes) goes to Bi-CGSTAB at once.  The attempts share opts.maxit; iters, matvecs and the
+ * residual history (concatenated) cover all of them.  Ignored by dda_solve_many. */
 enum { DDA_BREAKDOWN_REPORT = 0, DDA_BREAKDOWN_RECOVER = 1 };
 
 /* Per-right-hand-side report of dda_solve. */

@@ -316,6 +316,130 @@ __global__ void k_qmr_scal_3(SolveState *st, int *done, const double2 *part, int
     }
 }
 
+// ====================================================================== Bi-CG (complex symmetric)
+// One product per iteration on the bilinear form u^T v (Sec. 2: Bi-CG uses the complex symmetry
+// of the interaction matrix).  Initialization reuses k_qmr_init with p as its copy of r:
+// partials (|b|^2, |r|^2) and r^T r.
+__global__ void k_bicg_scal_init(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;  // excluded from this solve by the caller
+    double2 s[2];
+    sum_partials<2>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.bnorm = sqrt(s[0].x);
+    S.res = S.bnorm > 0 ? sqrt(s[0].y) / S.bnorm : 0.0;
+    S.rho_b = s[1];  // r^T r
+    S.iter = 0;
+    S.pending = 0;
+    S.status = ST_RUN;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap] = S.res;
+    if (S.res < S.tol || S.bnorm == 0.0) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+        return;
+    }
+    if (dabs(S.rho_b) < kBreakdown * s[0].y || !dfinite(S.rho_b)) {  // r^T r = 0: no Bi-CG step
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+        return;
+    }
+    done[rhs] = 0;
+}
+
+// eps = p^T A p from the matvec epilogue partials; alpha = rho / eps
+template <typename R>
+__global__ void k_bicg_scal_alpha(SolveState *st, int *done, const cplx<R> *dots, int ndots) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 v[1] = {make_double2(0, 0)};
+    for (int b = threadIdx.x; b < ndots; b += blockDim.x) {
+        const double2 d = up<R>(dots[(size_t)rhs * ndots + b]);
+        v[0].x += d.x;
+        v[0].y += d.y;
+    }
+    block_reduce<1>(v, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.eps = v[0];
+    if ((S.eps.x == 0 && S.eps.y == 0) || !dfinite(S.eps)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+        return;
+    }
+    S.alpha = ddiv(S.rho_b, S.eps);
+}
+
+// x += alpha p;  r -= alpha q;  partials |r|^2, r^T r
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_bicg_update(const SolveState *st, const int *done,
+                                                             const cplx<R> *__restrict__ p, const cplx<R> *__restrict__ q,
+                                                             cplx<R> *__restrict__ x, cplx<R> *__restrict__ r, size_t n3,
+                                                             double2 *part) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const cplx<R> a = dn<R>(st[rhs].alpha);
+    double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        x[off + i] = cadd(x[off + i], cmul(a, p[off + i]));
+        const cplx<R> ri = csub(r[off + i], cmul(a, q[off + i]));
+        r[off + i] = ri;
+        const double2 d = up<R>(ri);
+        acc[0].x += d.x * d.x + d.y * d.y;
+        acc[1].x += d.x * d.x - d.y * d.y;
+        acc[1].y += 2 * d.x * d.y;
+    }
+    block_reduce<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        double2 *pp = part + ((size_t)rhs * gridDim.x + blockIdx.x) * 4;
+        pp[0] = acc[0];
+        pp[1] = acc[1];
+    }
+}
+
+// residual, stopping rule; beta = rho_new / rho
+__global__ void k_bicg_scal_2(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[2 * kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[2];
+    sum_partials<2>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.iter += 1;
+    S.res = sqrt(s[0].x) / S.bnorm;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap + (S.iter < hcap ? S.iter : hcap - 1)] = S.res;
+    if (S.res < S.tol) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+    } else if (!isfinite(S.res) || dabs(s[1]) < kBreakdown * s[0].x || !dfinite(s[1])) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+    } else if (S.iter >= S.maxit) {
+        S.status = ST_MAXIT;
+        done[rhs] = 1;
+    } else {
+        S.beta_b = ddiv(s[1], S.rho_b);
+        S.rho_b = s[1];
+    }
+}
+
+// p = r + beta p
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_bicg_p(const SolveState *st, const int *done,
+                                                        const cplx<R> *__restrict__ r, cplx<R> *__restrict__ p,
+                                                        size_t n3) {
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const cplx<R> b = dn<R>(st[rhs].beta_b);
+    VEC_LOOP(n3) p[off + i] = cadd(r[off + i], cmul(b, p[off + i]));
+}
+
 // ====================================================================== Bi-CGSTAB
 // r = b - Ax0 or b; rs = r; partials (|b|^2, |r|^2)
 template <typename R>
@@ -786,7 +910,13 @@ template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count)
     cplx<R> *x = k.x;
     dda_status st;
     for (int it = 0; it < count; ++it) {
-        if (k.solver == DDA_QMR) {
+        if (k.solver == DDA_BICG) {
+            if ((st = run_matvec(k, v.p, v.pt, w.dots, B.done)) != DDA_OK) return st;
+            hipLaunchKernelGGL(k_bicg_scal_alpha<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
+            hipLaunchKernelGGL(k_bicg_update<R>, vg, vb, 0, s, B.st, B.done, v.p, v.pt, x, v.r, n3, B.part);
+            hipLaunchKernelGGL(k_bicg_scal_2, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+            hipLaunchKernelGGL(k_bicg_p<R>, vg, vb, 0, s, B.st, B.done, v.r, v.p, n3);
+        } else if (k.solver == DDA_QMR) {
             if ((st = run_matvec(k, v.p, v.pt, w.dots, B.done)) != DDA_OK) return st;
             hipLaunchKernelGGL(k_qmr_scal_eps<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
             hipLaunchKernelGGL(k_qmr_vt<R>, vg, vb, 0, s, B.st, B.done, v.pt, v.vt, n3, B.part);
@@ -841,7 +971,11 @@ template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
     if (have_x0) {
         if ((st = run_matvec(k, k.x, v.pt, nullptr, nullptr)) != DDA_OK) return st;
     }
-    if (k.solver == DDA_QMR) {
+    if (k.solver == DDA_BICG) {
+        hipLaunchKernelGGL(k_qmr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, k.x, v.r, v.p, n3, B.part,
+                           have_x0 ? 0 : 1);
+        hipLaunchKernelGGL(k_bicg_scal_init, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+    } else if (k.solver == DDA_QMR) {
         hipLaunchKernelGGL(k_qmr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, k.x, v.r, v.vt, n3, B.part,
                            have_x0 ? 0 : 1);
         hipLaunchKernelGGL(k_qmr_scal_init, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
@@ -1278,7 +1412,7 @@ static dda_status check_opts(const dda_solve_opts *opts, dda_solve_opts &o) {
     o = dda_solve_opts{};
     if (opts) o = *opts;
     if (o.maxit <= 0) o.maxit = 100000;
-    if (o.solver != DDA_QMR && o.solver != DDA_BICGSTAB) {
+    if (o.solver != DDA_QMR && o.solver != DDA_BICGSTAB && o.solver != DDA_BICG) {
         set_error("dda_solve: unknown solver");
         return DDA_EINVAL;
     }
@@ -1314,9 +1448,9 @@ static dda_status solve_with(Ctx &c, const dda_beam *beams, int nrhs, double tol
     return solve_products32(c, beams, nrhs, tol, o, x, info, check, graph);
 }
 
-// Breakdown recovery (DDA_BREAKDOWN_RECOVER): every right-hand side that stopped on a QMR
-// breakdown is solved again, alone, from its current iterate: QMR restarted on the current
-// residual (new Lanczos vectors) at most twice, Bi-CGSTAB after that or at once when the
+// Breakdown recovery (DDA_BREAKDOWN_RECOVER): every right-hand side that stopped on a QMR or Bi-CG
+// breakdown is solved again, alone, from its current iterate: the same method restarted on the
+// current residual (new Lanczos vectors) at most twice, Bi-CGSTAB after that or at once when the
 // breakdown came before the first step (the bilinear form b^T b of the start vector vanishes, and
 // so it would again).  The refined single-precision form recovers in double precision.
 static dda_status recover_breakdowns(Ctx &c, const dda_beam *beams, int nrhs, double tol,
@@ -1325,11 +1459,11 @@ static dda_status recover_breakdowns(Ctx &c, const dda_beam *beams, int nrhs, do
     const size_t n3 = (size_t)3 * c.N;
     for (int r = 0; r < nrhs; ++r) {
         int restarts = 0, last_iters = inf[r].iters;
-        bool bicg = o.solver == DDA_BICGSTAB;
-        while (inf[r].status == DDA_EBREAKDOWN && !bicg) {
-            bicg = last_iters == 0 || restarts >= 2;
+        bool stab = o.solver == DDA_BICGSTAB;
+        while (inf[r].status == DDA_EBREAKDOWN && !stab) {
+            stab = last_iters == 0 || restarts >= 2;
             dda_solve_opts s = o;
-            s.solver = bicg ? DDA_BICGSTAB : DDA_QMR;
+            s.solver = stab ? DDA_BICGSTAB : o.solver;
             s.precision = o.precision == DDA_FP32_REFINE ? DDA_FP64 : o.precision;
             s.x0 = x + r * n3;  // the solve starts from, and overwrites, the current iterate
             s.x0_check = 0;
@@ -1353,7 +1487,7 @@ static dda_status recover_breakdowns(Ctx &c, const dda_beam *beams, int nrhs, do
             inf[r].res_true = si.res_true;
             inf[r].res_hist_len += si.res_hist_len;
             last_iters = si.iters;
-            if (!bicg) ++restarts;
+            if (!stab) ++restarts;
         }
     }
     return DDA_OK;

@@ -161,6 +161,48 @@ def test_breakdown_maxit_and_exact_guess():
         assert st == 0 and info[0]["iters"] == 0
 
 
+def test_bicg_matches_oracle_history_and_dense_solution():
+    # Bi-CG (complex symmetric): the residual history follows the oracle's Bi-CG step by step, the
+    # solution is the dense one; a batch of orientations gives the single results
+    dda = _dda()
+    mask = inputs.sphere_mask(8)
+    beam = inputs.X_POL
+    pos, alpha, beta, A, b = _oracle_system(mask, 1.6, 0.45, beam)
+    xo, io = odda.bicg(lambda v: (A @ v.reshape(-1)).reshape(v.shape), b, 1e-9)
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    with dda.Context(mask, 1.6, 0.45, fp32=True) as ctx:
+        x, info, st = ctx.solve([beam], tol=1e-9, solver=dda.BICG, history=2000)
+        assert st == 0 and info[0]["matvecs"] == info[0]["iters"]
+        assert abs(info[0]["iters"] - io["iters"]) <= 2
+        h, ho = np.array(info[0]["res_hist"]), np.array(io["res_hist"])
+        assert np.abs(h[:6] / ho[:6] - 1).max() < 1e-10
+        xg = x[0].cpu().numpy().T
+        assert np.linalg.norm(xg - x_lu) / np.linalg.norm(x_lu) < 1e-7
+        assert info[0]["res_true"] < 2e-9
+        beams = inputs.beams_for_orientations(2, seed=21)
+        xb, ib, st = ctx.solve(beams, tol=1e-8, solver=dda.BICG)
+        assert st == 0
+        for r, bm in enumerate(beams):
+            x1, i1, _ = ctx.solve([bm], tol=1e-8, solver=dda.BICG)
+            assert i1[0]["iters"] == ib[r]["iters"] and torch.equal(x1[0], xb[r])
+        xp, ip, st = ctx.solve([beam], tol=1e-8, solver=dda.BICG, precision=dda.FP32_PRODUCT)
+        assert st == 0 and ip[0]["res_true"] < 1e-8
+
+
+def test_bicg_breakdown_recovers():
+    dda = _dda()
+    mask = inputs.sphere_mask(6)
+    circ = inputs.Beam((0.0, 0.0, 1.0), (1 / math.sqrt(2), 1j / math.sqrt(2), 0j))
+    with dda.Context(mask, 1.5, 0.5) as ctx:
+        x, info, st = ctx.solve([circ], tol=1e-8, solver=dda.BICG, raise_on_fail=False)
+        assert st == dda.EBREAKDOWN and info[0]["iters"] == 0
+        x, info, st = ctx.solve([circ], tol=1e-10, solver=dda.BICG, on_breakdown=dda.BREAKDOWN_RECOVER)
+        *_, A, b = _oracle_system(mask, 1.5, 0.5, circ)
+        x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+        assert st == 0
+        assert np.linalg.norm(x[0].cpu().numpy().T - x_lu) / np.linalg.norm(x_lu) < 1e-8
+
+
 @pytest.mark.parametrize("precision", ["FP64", "FP32_PRODUCT", "FP32_REFINE"])
 def test_breakdown_recovery_reaches_the_dense_solution(precision):
     # a circularly polarized beam along z: b^T b = 0, so QMR breaks down before its first step and
