@@ -400,6 +400,69 @@ def bicg(apply_A, b, tol, maxit=100000, x0=None):
     return x, info
 
 
+def cgnr(apply_A, b, tol, maxit=100000, x0=None):
+    """CGNR (the paper's first solver, Sec. 2): conjugate gradients on the normal equations
+    A^H A x = A^H b, which minimizes ||b - A x|| over its Krylov space.  A is complex symmetric, so
+    A^H v = conj(A conj(v)): two products with A per iteration.
+
+        r = b - A x;  z = A^H r;  p = z;  g = ||z||^2
+        w = A p;  alpha = g / ||w||^2;  x += alpha p;  r -= alpha w
+        z = A^H r;  g_new = ||z||^2;  p = z + (g_new / g) p
+
+    Same stopping rule as `qmr` on ||r||; g = 0 or w = 0 is a breakdown.
+    pinned by: dense LU; its iterates equal scipy's conjugate gradients on A^H A x = A^H b step by
+    step; its residual norm never increases.
+    """
+    def apply_AH(v):
+        return np.conj(apply_A(np.conj(v)))
+
+    bn = np.linalg.norm(_flat(b))
+    x = np.zeros(b.shape, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    nmv = 0
+    if x0 is None:
+        r = b.astype(np.complex128).copy()
+    else:
+        r = b - apply_A(x)
+        nmv += 1
+    hist = [np.linalg.norm(_flat(r)) / bn]
+    info = {"iters": 0, "matvecs": nmv, "status": "maxit", "res_hist": hist}
+    if hist[-1] < tol:
+        info["status"] = "converged"
+        info["res_rec"] = hist[-1]
+        return x, info
+    z = apply_AH(r)
+    nmv += 1
+    p = z.copy()
+    g = np.vdot(_flat(z), _flat(z)).real
+    for it in range(1, maxit + 1):
+        if g == 0:
+            info["status"] = "breakdown"
+            break
+        w = apply_A(p)
+        nmv += 1
+        ww = np.vdot(_flat(w), _flat(w)).real
+        if ww == 0:
+            info["status"] = "breakdown"
+            break
+        alpha = g / ww
+        x = x + alpha * p
+        r = r - alpha * w
+        info["iters"] = it
+        res = np.linalg.norm(_flat(r)) / bn
+        hist.append(res)
+        if res < tol:
+            info["status"] = "converged"
+            break
+        z = apply_AH(r)
+        nmv += 1
+        g_new = np.vdot(_flat(z), _flat(z)).real
+        p = z + (g_new / g) * p
+        g = g_new
+    info["matvecs"] = nmv
+    info["res_rec"] = hist[-1]
+    return x, info
+
+
 def solve_dense(pos, k, beta, b):
     """Exact solution of eq. (3) by dense LU (numpy.linalg.solve); for small systems only."""
     A = interaction_matrix(pos, k, beta)

@@ -154,3 +154,29 @@ def test_bicg_breaks_down_for_circular_polarization():
     pos, alpha, beta, A, b, mv = _system(pol=(1 / math.sqrt(2), 1j / math.sqrt(2), 0))
     x, info = dda.bicg(mv, b, 1e-8)
     assert info["status"] == "breakdown" and info["iters"] == 0
+
+
+# ------------------------------------------------------------------ CGNR
+def test_cgnr_reaches_lu_solution_with_monotone_residual():
+    pos, alpha, beta, A, b, mv = _system(m=1.33 + 0.1j, n=5)
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    x, info = dda.cgnr(mv, b, 1e-10, maxit=5000)
+    assert info["status"] == "converged"
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-7
+    h = np.array(info["res_hist"])
+    assert np.all(h[1:] <= h[:-1] * (1 + 1e-12))  # minimal residual over a growing space
+    assert info["matvecs"] == 2 * info["iters"]  # the converged step needs no A^H r
+
+
+def test_cgnr_is_cg_on_the_normal_equations():
+    from scipy.sparse.linalg import cg
+    pos, alpha, beta, A, b, mv = _system(m=1.5, n=4)
+    AH = A.conj().T
+    M = AH @ A
+    rhs = AH @ b.reshape(-1)
+    ref = []
+    cg(M, rhs, rtol=1e-14, atol=0, maxiter=10, callback=lambda xk: ref.append(xk.copy()))
+    for k in range(1, 11):
+        xk, info = dda.cgnr(mv, b, 1e-30, maxit=k)
+        c = ref[k - 1]
+        assert np.linalg.norm(xk.reshape(-1) - c) <= 1e-9 * np.linalg.norm(c)
