@@ -232,7 +232,7 @@ def deep_m2(dda, inputs, torch):
 
 
 def solver_study(dda, inputs, torch, n=64, tol=1e-5):
-    """The three solvers on one strongly scattering sphere (x = 20, m = 1.8, the case of the paper's
+    """The four solvers on one strongly scattering sphere (x = 20, m = 1.8, the case of the paper's
     residual-history figure, Sec. 4) on an n^3 grid: iterations, products, time and the relative
     residual at log-spaced iterations."""
     os.environ.setdefault("DDA_PROGRESS", "30")
@@ -242,7 +242,7 @@ def solver_study(dda, inputs, torch, n=64, tol=1e-5):
     out = {"workload": f"sphere{n}, x = 20, m = 1.8, kd = {kd:.4f}, x-pol, tol {tol:g}", "n_dipoles": N}
     with dda.Context(mask, 1.8, kd) as ctx:
         ctx.tune(dda.FP64)
-        for name, solver in (("qmr", dda.QMR), ("bicg", dda.BICG), ("bicgstab", dda.BICGSTAB)):
+        for name, solver in (("qmr", dda.QMR), ("bicg", dda.BICG), ("bicgstab", dda.BICGSTAB), ("cgnr", dda.CGNR)):
             (x, info, st), dt = _timed(torch, lambda: ctx.solve([inputs.X_POL], tol=tol, solver=solver, maxit=200000,
                                                                  history=200001, raise_on_fail=False))
             h = info[0]["res_hist"]
@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--deep-m2", action="store_true",
                     help="only: the m = 2 sphere to 1e-5, fp64 vs single-precision transforms (~10 min)")
     ap.add_argument("--solver-study", action="store_true",
-                    help="only: QMR, Bi-CG and Bi-CGSTAB on a 64^3 sphere with x = 20, m = 1.8")
+                    help="only: QMR, Bi-CG, Bi-CGSTAB and CGNR on a 64^3 sphere with x = 20, m = 1.8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)

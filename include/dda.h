@@ -64,8 +64,9 @@ enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
 
 /* Iterative solvers (Sec. 2): QMR and Bi-CG use the complex symmetry of the interaction matrix
  * (one product per iteration, bilinear form u^T v); Bi-CGSTAB takes two products per iteration
- * with Hermitian inner products. */
-enum { DDA_QMR = 0, DDA_BICGSTAB = 1, DDA_BICG = 2 };
+ * with Hermitian inner products; CGNR is conjugate gradients on A^H A x = A^H b (minimal residual
+ * over its Krylov space; two products per iteration, A^H v formed as conj(A conj(v))). */
+enum { DDA_QMR = 0, DDA_BICGSTAB = 1, DDA_BICG = 2, DDA_CGNR = 3 };
 
 /* Arithmetic of the solve: plain double precision everywhere (Sec. 2: all floats double), or
  * single-precision FFTs, tensor multiply and inner QMR with double-precision residuals, iterate
@@ -96,7 +97,7 @@ typedef struct {
 
 /* Options of dda_solve (pass NULL for defaults). */
 typedef struct {
-    int32_t solver;        /* DDA_QMR (default), DDA_BICGSTAB or DDA_BICG */
+    int32_t solver;        /* DDA_QMR (default), DDA_BICGSTAB, DDA_BICG or DDA_CGNR */
     int32_t precision;     /* DDA_FP64 (default), DDA_FP32_REFINE or DDA_FP32_PRODUCT */
     int32_t maxit;         /* iteration limit; 0 = 100000 */
     int32_t check_every;   /* iterations between host-side convergence checks; 0 = automatic */

@@ -440,6 +440,163 @@ __global__ void __launch_bounds__(kVecThreads) k_bicg_p(const SolveState *st, co
     VEC_LOOP(n3) p[off + i] = cadd(r[off + i], cmul(b, p[off + i]));
 }
 
+// ====================================================================== CGNR
+// Conjugate gradients on the normal equations A^H A x = A^H b (Sec. 2's CGNR); A is complex
+// symmetric, so A^H v = conj(A conj(v)): the product runs on t = conj(r) and its result d is
+// conjugated where it is read.  Two products per iteration; g = ||A^H r||^2.
+
+// r = b - Ax0 (Ax0 given) or b; t = conj(r); x zeroed without a guess; partials (|b|^2, |r|^2)
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_cgnr_init(const cplx<R> *__restrict__ b, const cplx<R> *__restrict__ ax,
+                                                           cplx<R> *__restrict__ x, cplx<R> *__restrict__ r,
+                                                           cplx<R> *__restrict__ t, size_t n3, double2 *part,
+                                                           int zero_x) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.y;
+    const size_t off = (size_t)rhs * n3;
+    double2 acc[1] = {make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const cplx<R> bi = b[off + i];
+        const cplx<R> ri = ax ? csub(bi, ax[off + i]) : bi;
+        if (zero_x) x[off + i] = czero<cplx<R>>();
+        r[off + i] = ri;
+        t[off + i] = cconj(ri);
+        const double2 bd = up<R>(bi), rd = up<R>(ri);
+        acc[0].x += bd.x * bd.x + bd.y * bd.y;
+        acc[0].y += rd.x * rd.x + rd.y * rd.y;
+    }
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)rhs * gridDim.x + blockIdx.x) * 4] = acc[0];
+}
+
+__global__ void k_cgnr_scal_init(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;  // excluded from this solve by the caller
+    double2 s[1];
+    sum_partials<1>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.bnorm = sqrt(s[0].x);
+    S.res = S.bnorm > 0 ? sqrt(s[0].y) / S.bnorm : 0.0;
+    S.iter = 0;
+    S.pending = 0;
+    S.status = ST_RUN;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap] = S.res;
+    if (S.res < S.tol || S.bnorm == 0.0) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+        return;
+    }
+    done[rhs] = 0;
+}
+
+// sum of |v|^2 over a vector into part slot 0 (v = A p, or d = A conj(r) whose conjugate has the
+// same norm)
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_cgnr_norm(const int *done, const cplx<R> *__restrict__ v, size_t n3,
+                                                           double2 *part) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    double2 acc[1] = {make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        const double2 d = up<R>(v[off + i]);
+        acc[0].x += d.x * d.x + d.y * d.y;
+    }
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)rhs * gridDim.x + blockIdx.x) * 4] = acc[0];
+}
+
+// which = 0: g = ||z||^2 of the first direction;  1: alpha = g / ||w||^2;  2: beta = g_new / g
+__global__ void k_cgnr_scal(SolveState *st, int *done, const double2 *part, int nb, int which) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[1];
+    sum_partials<1>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    const double v = s[0].x;
+    if (!(v > 0) || !isfinite(v)) {  // A^H r = 0 or A p = 0 with r != 0
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+        return;
+    }
+    if (which == 0) {
+        S.rho = v;
+    } else if (which == 1) {
+        S.alpha = make_double2(S.rho / v, 0);
+    } else {
+        S.beta_b = make_double2(v / S.rho, 0);
+        S.rho = v;
+    }
+}
+
+// p = conj(d) (first direction);  or p = conj(d) + beta p
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_cgnr_p(const SolveState *st, const int *done,
+                                                        const cplx<R> *__restrict__ d, cplx<R> *__restrict__ p,
+                                                        size_t n3, int first) {
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const R b = first ? (R)0 : (R)st[rhs].beta_b.x;
+    VEC_LOOP(n3) {
+        const cplx<R> z = cconj(d[off + i]);
+        p[off + i] = first ? z : cadd(z, cscale(p[off + i], b));
+    }
+}
+
+// x += alpha p;  r -= alpha w;  t = conj(r);  partials |r|^2
+template <typename R>
+__global__ void __launch_bounds__(kVecThreads) k_cgnr_update(const SolveState *st, const int *done,
+                                                             const cplx<R> *__restrict__ p, const cplx<R> *__restrict__ w,
+                                                             cplx<R> *__restrict__ x, cplx<R> *__restrict__ r,
+                                                             cplx<R> *__restrict__ t, size_t n3, double2 *part) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.y;
+    if (done[rhs]) return;
+    const size_t off = (size_t)rhs * n3;
+    const R a = (R)st[rhs].alpha.x;
+    double2 acc[1] = {make_double2(0, 0)};
+    VEC_LOOP(n3) {
+        x[off + i] = cadd(x[off + i], cscale(p[off + i], a));
+        const cplx<R> ri = csub(r[off + i], cscale(w[off + i], a));
+        r[off + i] = ri;
+        t[off + i] = cconj(ri);
+        const double2 d = up<R>(ri);
+        acc[0].x += d.x * d.x + d.y * d.y;
+    }
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)rhs * gridDim.x + blockIdx.x) * 4] = acc[0];
+}
+
+// residual and stopping rule after an update
+__global__ void k_cgnr_scal_res(SolveState *st, int *done, const double2 *part, int nb, double *hist, int hcap) {
+    __shared__ double2 sh[kVecThreads];
+    const int rhs = blockIdx.x;
+    if (done[rhs]) return;
+    double2 s[1];
+    sum_partials<1>(part + (size_t)rhs * nb * 4, nb, s, sh);
+    if (threadIdx.x != 0) return;
+    SolveState &S = st[rhs];
+    S.iter += 1;
+    S.res = sqrt(s[0].x) / S.bnorm;
+    if (hist && hcap > 0) hist[(size_t)rhs * hcap + (S.iter < hcap ? S.iter : hcap - 1)] = S.res;
+    if (S.res < S.tol) {
+        S.status = ST_CONV;
+        done[rhs] = 1;
+    } else if (!isfinite(S.res)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+    } else if (S.iter >= S.maxit) {
+        S.status = ST_MAXIT;
+        done[rhs] = 1;
+    }
+}
+
 // ====================================================================== Bi-CGSTAB
 // r = b - Ax0 or b; rs = r; partials (|b|^2, |r|^2)
 template <typename R>
@@ -910,7 +1067,17 @@ template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count)
     cplx<R> *x = k.x;
     dda_status st;
     for (int it = 0; it < count; ++it) {
-        if (k.solver == DDA_BICG) {
+        if (k.solver == DDA_CGNR) {
+            if ((st = run_matvec(k, v.p, v.pt, nullptr, B.done)) != DDA_OK) return st;  // w = A p
+            hipLaunchKernelGGL(k_cgnr_norm<R>, vg, vb, 0, s, B.done, v.pt, n3, B.part);
+            hipLaunchKernelGGL(k_cgnr_scal, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, 1);
+            hipLaunchKernelGGL(k_cgnr_update<R>, vg, vb, 0, s, B.st, B.done, v.p, v.pt, x, v.r, v.vt, n3, B.part);
+            hipLaunchKernelGGL(k_cgnr_scal_res, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+            if ((st = run_matvec(k, v.vt, v.d, nullptr, B.done)) != DDA_OK) return st;  // d = A conj(r)
+            hipLaunchKernelGGL(k_cgnr_norm<R>, vg, vb, 0, s, B.done, v.d, n3, B.part);
+            hipLaunchKernelGGL(k_cgnr_scal, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, 2);
+            hipLaunchKernelGGL(k_cgnr_p<R>, vg, vb, 0, s, B.st, B.done, v.d, v.p, n3, 0);
+        } else if (k.solver == DDA_BICG) {
             if ((st = run_matvec(k, v.p, v.pt, w.dots, B.done)) != DDA_OK) return st;
             hipLaunchKernelGGL(k_bicg_scal_alpha<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
             hipLaunchKernelGGL(k_bicg_update<R>, vg, vb, 0, s, B.st, B.done, v.p, v.pt, x, v.r, n3, B.part);
@@ -971,7 +1138,15 @@ template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
     if (have_x0) {
         if ((st = run_matvec(k, k.x, v.pt, nullptr, nullptr)) != DDA_OK) return st;
     }
-    if (k.solver == DDA_BICG) {
+    if (k.solver == DDA_CGNR) {  // r, t = conj(r); d = A t; p = conj(d) = A^H r; g = ||p||^2
+        hipLaunchKernelGGL(k_cgnr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, k.x, v.r, v.vt, n3, B.part,
+                           have_x0 ? 0 : 1);
+        hipLaunchKernelGGL(k_cgnr_scal_init, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
+        if ((st = run_matvec(k, v.vt, v.d, nullptr, B.done)) != DDA_OK) return st;
+        hipLaunchKernelGGL(k_cgnr_norm<R>, vg, vb, 0, s, B.done, v.d, n3, B.part);
+        hipLaunchKernelGGL(k_cgnr_scal, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, 0);
+        hipLaunchKernelGGL(k_cgnr_p<R>, vg, vb, 0, s, B.st, B.done, v.d, v.p, n3, 1);
+    } else if (k.solver == DDA_BICG) {
         hipLaunchKernelGGL(k_qmr_init<R>, vg, vb, 0, s, v.b, have_x0 ? v.pt : nullptr, k.x, v.r, v.p, n3, B.part,
                            have_x0 ? 0 : 1);
         hipLaunchKernelGGL(k_bicg_scal_init, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
@@ -1195,8 +1370,10 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
         if (!info) continue;
         info[r].status = sr;
         info[r].iters = h[r].iter;
-        const bool bi = o.solver == DDA_BICGSTAB;
-        info[r].matvecs = (bi ? 2 * h[r].iter - (h[r].half ? 1 : 0) : h[r].iter) + (o.x0 ? 1 + (o.x0_check ? 1 : 0) : 0);
+        const int per_run = o.solver == DDA_BICGSTAB ? 2 * h[r].iter - (h[r].half ? 1 : 0)
+                            : o.solver == DDA_CGNR   ? 2 * h[r].iter  // the converged step skips A^H r
+                                                     : h[r].iter;
+        info[r].matvecs = per_run + (o.x0 ? 1 + (o.x0_check ? 1 : 0) : 0);
         info[r].outer = k.stalled.size() > (size_t)r && k.stalled[r] ? 1 : 0;
         info[r].res_rec = h[r].res;
         info[r].res_true = rt[r];
@@ -1412,7 +1589,7 @@ static dda_status check_opts(const dda_solve_opts *opts, dda_solve_opts &o) {
     o = dda_solve_opts{};
     if (opts) o = *opts;
     if (o.maxit <= 0) o.maxit = 100000;
-    if (o.solver != DDA_QMR && o.solver != DDA_BICGSTAB && o.solver != DDA_BICG) {
+    if (o.solver != DDA_QMR && o.solver != DDA_BICGSTAB && o.solver != DDA_BICG && o.solver != DDA_CGNR) {
         set_error("dda_solve: unknown solver");
         return DDA_EINVAL;
     }

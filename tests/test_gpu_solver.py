@@ -189,6 +189,32 @@ def test_bicg_matches_oracle_history_and_dense_solution():
         assert st == 0 and ip[0]["res_true"] < 1e-8
 
 
+def test_cgnr_matches_oracle_history_and_dense_solution():
+    # CGNR: two products per iteration, a residual that never increases, the oracle's history
+    dda = _dda()
+    mask = inputs.sphere_mask(6)
+    beam = inputs.X_POL
+    pos, alpha, beta, A, b = _oracle_system(mask, 1.33 + 0.05j, 0.5, beam)
+    xo, io = odda.cgnr(lambda v: (A @ v.reshape(-1)).reshape(v.shape), b, 1e-9)
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    with dda.Context(mask, 1.33 + 0.05j, 0.5) as ctx:
+        x, info, st = ctx.solve([beam], tol=1e-9, solver=dda.CGNR, history=5000)
+        assert st == 0 and info[0]["matvecs"] == 2 * info[0]["iters"]
+        assert abs(info[0]["iters"] - io["iters"]) <= 2
+        h, ho = np.array(info[0]["res_hist"]), np.array(io["res_hist"])
+        assert np.abs(h[:6] / ho[:6] - 1).max() < 1e-10
+        assert np.all(h[1:] <= h[:-1] * (1 + 1e-9))
+        xg = x[0].cpu().numpy().T
+        assert np.linalg.norm(xg - x_lu) / np.linalg.norm(x_lu) < 1e-6
+        assert info[0]["res_true"] < 2e-9
+        beams = inputs.beams_for_orientations(1, seed=22)
+        xb, ib, st = ctx.solve(beams, tol=1e-8, solver=dda.CGNR)
+        assert st == 0
+        for r, bm in enumerate(beams):
+            x1, i1, _ = ctx.solve([bm], tol=1e-8, solver=dda.CGNR)
+            assert i1[0]["iters"] == ib[r]["iters"] and torch.equal(x1[0], xb[r])
+
+
 def test_bicg_breakdown_recovers():
     dda = _dda()
     mask = inputs.sphere_mask(6)
