@@ -534,6 +534,38 @@ def farfield(pos, k, P, n):
     return -1j * k ** 3 * s
 
 
+def sphere_quadrature(prop, n_theta, n_phi):
+    """Directions and weights integrating over the unit sphere: Gauss-Legendre in mu = cos(theta)
+    about the propagation direction, uniform in phi.  Returns (n (M, 3), w (M,), mu (M,))."""
+    a = np.asarray(prop, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    t = np.array([1.0, 0.0, 0.0]) if abs(a[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(a, t)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(a, e1)
+    mu, wmu = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2.0 * math.pi * np.arange(n_phi) / n_phi
+    M, PH = np.meshgrid(mu, phi, indexing="ij")
+    W = np.outer(wmu, np.full(n_phi, 2.0 * math.pi / n_phi))
+    st = np.sqrt(1.0 - M ** 2)
+    n = (M[..., None] * a + st[..., None] * (np.cos(PH)[..., None] * e1 + np.sin(PH)[..., None] * e2))
+    return n.reshape(-1, 3), W.reshape(-1), M.reshape(-1)
+
+
+def asymmetry(pos, k, P, prop, n_theta, n_phi):
+    """Scattering cross section and asymmetry parameter g = <cos theta> by integrating the far field
+    over the sphere: dCsca/dOmega = |F|^2 / k^2 (the scattered field is exp(ikr)/(-ikr) F).
+    ADDA reports g (its paper's Fig. 5 axis; not defined there).
+    pinned by: Csca equals the exact double sum `csca_exact`; a single dipole scatters with g = 0;
+    a sphere's g approaches Mie theory's.
+    """
+    n, w, mu = sphere_quadrature(prop, n_theta, n_phi)
+    F = farfield(pos, k, P, n)
+    dc = np.sum(np.abs(F) ** 2, axis=1) / k ** 2
+    csca = float(np.sum(w * dc))
+    return csca, float(np.sum(w * mu * dc) / csca)
+
+
 def beam_frame(prop, pol):
     """(e1, e2, e3): e3 = propagation, e1 = (real) polarization, e2 = e3 x e1."""
     e3 = np.asarray(prop, dtype=np.float64)

@@ -211,3 +211,41 @@ def test_ghat_parity_of_components():
                 odd = (a == comp) != (b == comp)
                 sgn = -1.0 if odd else 1.0
                 np.testing.assert_allclose(flip(Gh[..., a, b], axis), sgn * Gh[..., a, b], atol=1e-10)
+
+
+# ------------------------------------------------------------------ asymmetry parameter
+def test_asymmetry_quadrature_reproduces_the_exact_scattering_cross_section():
+    mask = _small_particle(seed=5, shape=(4, 5, 3))
+    pos, _ = dda.dipoles(mask)
+    k = 0.8
+    prop, pol = (0.6, 0.0, 0.8), (0.8, 0.0, -0.6)
+    alpha = dda.alpha_ldr(1.4 + 0.05j, k, prop, pol)
+    P = alpha * dda.incident_field(pos, k, prop, pol)  # any polarization field will do
+    csca, g = dda.asymmetry(pos, k, P, prop, 24, 48)
+    ref = dda.csca_exact(pos, k, P)
+    assert abs(csca - ref) < 1e-10 * ref
+    assert -1 < g < 1
+
+
+def test_single_dipole_scatters_symmetrically():
+    pos = np.zeros((1, 3))
+    P = np.array([[0.3 + 0.1j, 0.0, 0.0]])
+    csca, g = dda.asymmetry(pos, 0.7, P, (0, 0, 1), 16, 32)
+    assert abs(g) < 1e-14
+    assert abs(csca - 8 * math.pi / 3 * 0.7 ** 4 * np.sum(np.abs(P) ** 2)) < 1e-12 * csca
+
+
+def test_sphere_asymmetry_near_mie():
+    from oracle import mie
+    n, m, kd = 10, 1.3 + 0j, 0.35
+    mask = inputs.sphere_mask(n)
+    pos, _ = dda.dipoles(mask)
+    alpha = dda.alpha_ldr(m, kd, (0, 0, 1), (1, 0, 0))
+    beta = dda.beta_of_alpha(alpha)
+    A = dda.interaction_matrix(pos, kd, beta)
+    b = dda.rhs(pos, kd, beta, (0, 0, 1), (1, 0, 0))
+    x = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    csca, g = dda.asymmetry(pos, kd, beta * x, (0, 0, 1), 32, 64)
+    xeq = dda.size_parameter(kd, len(pos))
+    g_mie = mie.asymmetry(xeq, m)
+    assert abs(g - g_mie) < 0.03 * abs(g_mie)
