@@ -230,6 +230,18 @@ dda_status dda_farfield(dda_ctx *ctx, const dda_beam *beam, const void *x, int32
                         const double *dirs, double *F);
 
 /*
+ * dda_asymmetry — out = {Csca, g}: the scattering cross section (units of d^2) and the asymmetry
+ * parameter g = <cos theta> from the far field of the solution x (device complex128 [3][N]) of
+ * beam, integrated over the sphere of directions: n_theta Gauss-Legendre nodes in cos theta about
+ * the propagation direction times n_phi equally spaced azimuths (dCsca/dOmega = |F|^2 / k^2).
+ * The paper computes g for every sphere (Sec. 3.1) and compares it with Mie theory (Sec. 3.2,
+ * Fig. 5) without defining it; this is the usual definition.
+ * Errors: DDA_EINVAL for NULL pointers, n_theta or n_phi < 1, more than 2^22 directions.
+ */
+dda_status dda_asymmetry(dda_ctx *ctx, const dda_beam *beam, const void *x, int32_t n_theta, int32_t n_phi,
+                         double out[2]);
+
+/*
  * dda_mueller — 4x4 Mueller matrix (Bohren & Huffman eq. 3.16, unnormalized) at n_theta
  * scattering angles in the scattering plane at azimuth phi (Sec. 3.1: all elements in one
  * scattering plane).  The beam frame is e3 = beam->prop, e1 = Re(beam->pol), e2 = e3 x e1;

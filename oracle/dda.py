@@ -555,7 +555,8 @@ def sphere_quadrature(prop, n_theta, n_phi):
 def asymmetry(pos, k, P, prop, n_theta, n_phi):
     """Scattering cross section and asymmetry parameter g = <cos theta> by integrating the far field
     over the sphere: dCsca/dOmega = |F|^2 / k^2 (the scattered field is exp(ikr)/(-ikr) F).
-    ADDA reports g (its paper's Fig. 5 axis; not defined there).
+    The paper computes g for every sphere (Sec. 3.1) and compares it with Mie theory (Sec. 3.2,
+    Fig. 5) without defining it.
     pinned by: Csca equals the exact double sum `csca_exact`; a single dipole scatters with g = 0;
     a sphere's g approaches Mie theory's.
     """

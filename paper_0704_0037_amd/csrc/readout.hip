@@ -224,6 +224,38 @@ static void finish_farfield(const Ctx &c, const dda_beam &bm, int ndir, const do
     }
 }
 
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_n, evaluated by the
+// three-term recurrence, from the usual cosine first guesses
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;  // P_0, P_1
+            for (int j = 1; j < n; ++j) {
+                const double p2 = ((2.0 * j + 1.0) * z * p1 - j * p0) / (j + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);  // P_n'(z)
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) <= 1e-16 * std::max(1.0, std::fabs(z))) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int j = 1; j < n; ++j) {
+            const double p2 = ((2.0 * j + 1.0) * z * p1 - j * p0) / (j + 1.0);
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
 // mask invariant under the +90 degree rotation about z: cell (i, j) -> (n-1-j, i)
 static bool rot90_symmetric(const Ctx &c) {
     if (c.nx != c.ny) return false;
@@ -296,6 +328,52 @@ dda_status dda_farfield(dda_ctx *h, const dda_beam *beam, const void *x, int32_t
     dda_status st = farfield_sums(*c, (const double2 *)x, n_dir, dirs, S);
     if (st != DDA_OK) return st;
     finish_farfield(*c, *beam, n_dir, dirs, S, F);
+    return DDA_OK;
+}
+
+dda_status dda_asymmetry(dda_ctx *h, const dda_beam *beam, const void *x, int32_t n_theta, int32_t n_phi,
+                         double out[2]) {
+    clear_error();
+    Ctx *c = cx(h);
+    if (!c || !x || !out || n_theta < 1 || n_phi < 1 || (int64_t)n_theta * n_phi > (1 << 22) || !beam_ok(beam)) {
+        set_error("dda_asymmetry: NULL argument, grid sizes outside 1..2^22 directions or beam without unit vectors");
+        return DDA_EINVAL;
+    }
+    // directions n = mu a + sqrt(1 - mu^2) (cos phi e1 + sin phi e2) about the propagation a
+    const double *a = beam->prop;
+    const double t[3] = {std::fabs(a[0]) < 0.9 ? 1.0 : 0.0, std::fabs(a[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+    double e1[3] = {a[1] * t[2] - a[2] * t[1], a[2] * t[0] - a[0] * t[2], a[0] * t[1] - a[1] * t[0]};
+    const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (double &v : e1) v /= l1;
+    const double e2[3] = {a[1] * e1[2] - a[2] * e1[1], a[2] * e1[0] - a[0] * e1[2], a[0] * e1[1] - a[1] * e1[0]};
+    std::vector<double> mu, wmu;
+    gauss_legendre(n_theta, mu, wmu);
+    const int ndir = n_theta * n_phi;
+    std::vector<double> dirs((size_t)ndir * 3), wt(ndir), cs(ndir);
+    for (int i = 0; i < n_theta; ++i)
+        for (int j = 0; j < n_phi; ++j) {
+            const double ph = 2.0 * M_PI * j / n_phi, st = std::sqrt(std::max(0.0, 1.0 - mu[i] * mu[i]));
+            const int d = i * n_phi + j;
+            for (int q = 0; q < 3; ++q)
+                dirs[3 * d + q] = mu[i] * a[q] + st * (std::cos(ph) * e1[q] + std::sin(ph) * e2[q]);
+            wt[d] = wmu[i] * 2.0 * M_PI / n_phi;
+            cs[d] = mu[i];
+        }
+    std::vector<double2> S;
+    dda_status st = farfield_sums(*c, (const double2 *)x, ndir, dirs.data(), S);
+    if (st != DDA_OK) return st;
+    std::vector<double> F((size_t)ndir * 6);
+    finish_farfield(*c, *beam, ndir, dirs.data(), S, F.data());
+    double csca = 0, gs = 0;
+    const double k2 = c->kd * c->kd;
+    for (int d = 0; d < ndir; ++d) {
+        double f2 = 0;
+        for (int q = 0; q < 6; ++q) f2 += F[6 * d + q] * F[6 * d + q];
+        csca += wt[d] * f2 / k2;
+        gs += wt[d] * cs[d] * f2 / k2;
+    }
+    out[0] = csca;
+    out[1] = csca > 0 ? gs / csca : 0.0;
     return DDA_OK;
 }
 

@@ -59,6 +59,8 @@ _SIGS = {
     "dda_num_dipoles": (ct.c_int64, [ct.c_void_p]),
     "dda_padded_grid": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int32)]),
     "dda_polarizability": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.POINTER(ct.c_double)]),
+    "dda_asymmetry": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_int32, ct.c_int32,
+                                 ct.POINTER(ct.c_double)]),
     "dda_rhs": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
     "dda_matvec": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
     "dda_matvec_f32": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
@@ -327,6 +329,13 @@ class Context:
                                   len(dirs), dirs.ctypes.data_as(ct.POINTER(ct.c_double)),
                                   F.ctypes.data_as(ct.POINTER(ct.c_double))), "dda_farfield")
         return F
+
+    def asymmetry(self, beam, x, n_theta=32, n_phi=64):
+        """(Csca, g) by integrating the far field over the sphere (dda_asymmetry)."""
+        out = (ct.c_double * 2)()
+        _check(lib().dda_asymmetry(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
+                                   int(n_theta), int(n_phi), out), "dda_asymmetry")
+        return out[0], out[1]
 
     def mueller(self, beam, x1, x2, phi, theta):
         theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))

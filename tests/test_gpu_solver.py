@@ -298,6 +298,24 @@ def test_fp32_refinement_reaches_fp64_tolerance(sphere16):
     assert abs(c32 - c64) < 1e-7 * c64
 
 
+def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((10, 8, 6), (5, 4, 3))
+    m, kd = 1.4 + 0.02j, 0.5
+    beam = inputs.beams_for_orientations(1, seed=31)[0]
+    with dda.Context(mask, m, kd) as ctx:
+        x, info, st = ctx.solve([beam], tol=1e-11)
+        csca, g = ctx.asymmetry(beam, x[0].contiguous(), 24, 48)
+        cext, cabs, _ = ctx.cross_sections(beam, x[0].contiguous())
+    pos, _ = odda.dipoles(mask)
+    beta = odda.beta_of_alpha(odda.alpha_ldr(m, kd, beam.prop, beam.pol))
+    P = beta * x[0].cpu().numpy().T
+    cref, gref = odda.asymmetry(pos, kd, P, beam.prop, 24, 48)
+    assert abs(csca - cref) < 1e-11 * cref and abs(g - gref) < 1e-11
+    assert abs(csca - odda.csca_exact(pos, kd, P)) < 1e-9 * csca
+    assert abs(cext - (csca + cabs)) < 1e-8 * cext  # optical theorem through the integrated Csca
+
+
 def test_mueller_two_polarizations_equal_symmetry_route():
     dda = _dda()
     mask = inputs.sphere_mask(8)
