@@ -567,6 +567,74 @@ def asymmetry(pos, k, P, prop, n_theta, n_phi):
     return csca, float(np.sum(w * mu * dc) / csca)
 
 
+def romberg(fvals, a, b):
+    """Romberg integration of samples f(a + i h), i = 0..2^n, h = (b - a) / 2^n: trapezoid sums on
+    the nested grids, then Richardson extrapolation.  Returns (integral, |R(n,n) - R(n,n-1)|).
+    pinned by: polynomials up to degree 2n + 1 integrate exactly."""
+    f = np.asarray(fvals, dtype=np.float64)
+    n = int(round(math.log2(len(f) - 1)))
+    assert len(f) == 2 ** n + 1
+    T = []
+    for kk in range(n + 1):
+        step = 2 ** (n - kk)
+        sub = f[::step]
+        h = (b - a) / 2 ** kk
+        T.append(h * (np.sum(sub) - 0.5 * (sub[0] + sub[-1])))
+    R = [T]
+    for j in range(1, n + 1):
+        prev = R[-1]
+        R.append([prev[i] + (prev[i] - prev[i - 1]) / (4 ** j - 1) for i in range(1, len(prev))])
+    best = R[-1][-1]
+    err = abs(best - R[-2][-1]) if n >= 1 else float("nan")
+    return best, err
+
+
+def orientation_average(mask, m, k, n_beta, n_gamma, tol=1e-10, polarizability="ldr"):
+    """Cross sections averaged over particle orientations (the paper's program averages over the
+    Euler angles, Sec. 2).  Orientation R = Rz(alpha) Ry(beta) Rz(gamma); alpha only turns the
+    scattering plane, so the cross sections need beta and gamma.  Romberg in cos(beta) on
+    2^n_beta + 1 points, the periodic trapezoid rule on 2^n_gamma points in gamma; unpolarized:
+    the mean of the x- and y-polarized incident beams, each brought into the particle frame by R^T.
+    Returns ({"Cext", "Cabs", "Csca"} averages, Romberg error estimate of <Cext>).
+    pinned by: the Romberg rule on polynomials; a CM single dipole (isotropic) gives its fixed
+    value; invariance of the average under a 90-degree lattice rotation of the particle."""
+    pos, _ = dipoles(mask)
+    nb, ng = 2 ** n_beta + 1, 2 ** n_gamma
+    vals = np.zeros((nb, ng, 3))
+    for i in range(nb):
+        mu = -1.0 + 2.0 * i / (nb - 1)
+        beta_e = math.acos(max(-1.0, min(1.0, mu)))
+        for j in range(ng):
+            gam = 2.0 * math.pi * j / ng
+            c, s = math.cos(beta_e), math.sin(beta_e)
+            cg, sg = math.cos(gam), math.sin(gam)
+            Ry = np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
+            Rz = np.array([[cg, -sg, 0.0], [sg, cg, 0.0], [0.0, 0.0, 1.0]])
+            R = Ry @ Rz
+            prop = R.T @ np.array([0.0, 0.0, 1.0])
+            acc = np.zeros(3)
+            for e in (np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])):
+                pol = R.T @ e
+                if polarizability == "cm":
+                    alpha = alpha_cm(m)
+                else:
+                    alpha = alpha_ldr(m, k, prop, pol)
+                bt = beta_of_alpha(alpha)
+                A = interaction_matrix(pos, k, bt)
+                b = rhs(pos, k, bt, prop, pol)
+                x = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+                cext, cabs = cross_sections(pos, k, alpha, bt * x, prop, pol)[:2]
+                acc += np.array([cext, cabs, cext - cabs])
+            vals[i, j] = acc / 2.0
+    over_gamma = vals.mean(axis=1)  # (nb, 3)
+    out, errs = {}, []
+    for q, name in enumerate(("Cext", "Cabs", "Csca")):
+        v, e = romberg(over_gamma[:, q], -1.0, 1.0)
+        out[name] = v / 2.0
+        errs.append(e / 2.0)
+    return out, errs[0]
+
+
 def beam_frame(prop, pol):
     """(e1, e2, e3): e3 = propagation, e1 = (real) polarization, e2 = e3 x e1."""
     e3 = np.asarray(prop, dtype=np.float64)

@@ -249,3 +249,39 @@ def test_sphere_asymmetry_near_mie():
     xeq = dda.size_parameter(kd, len(pos))
     g_mie = mie.asymmetry(xeq, m)
     assert abs(g - g_mie) < 0.03 * abs(g_mie)
+
+
+# ------------------------------------------------------------------ orientation averaging
+def test_romberg_is_exact_on_polynomials():
+    for n in (1, 2, 3, 4):
+        x = np.linspace(-1.0, 1.0, 2 ** n + 1)
+        for deg in range(0, 2 * n + 2):
+            v, _ = dda.romberg(x ** deg, -1.0, 1.0)
+            exact = 0.0 if deg % 2 else 2.0 / (deg + 1)
+            assert abs(v - exact) < 1e-12, (n, deg)
+    v, _ = dda.romberg(np.cos(np.linspace(0, 1, 17)), 0.0, 1.0)
+    assert abs(v - math.sin(1.0)) < 1e-12
+
+
+def test_orientation_average_of_an_isotropic_dipole():
+    mask = np.ones((1, 1, 1), np.uint8)
+    avg, err = dda.orientation_average(mask, 1.5, 0.6, 2, 2, polarizability="cm")
+    pos = np.zeros((1, 3))
+    alpha = dda.alpha_cm(1.5)
+    P = alpha * dda.incident_field(pos, 0.6, (0, 0, 1), (1, 0, 0))
+    cext = dda.cross_sections(pos, 0.6, alpha, P, (0, 0, 1), (1, 0, 0))[0]
+    assert abs(avg["Cext"] - cext) < 1e-12 * abs(cext) + 1e-15
+
+
+def test_orientation_average_invariant_under_a_lattice_rotation():
+    # the average over all orientations does not depend on how the particle was placed: the same
+    # particle turned by 90 degrees about x (an exact lattice rotation) gives the same average
+    mask = np.zeros((3, 2, 2), np.uint8)
+    mask[:, 0, 0] = 1
+    mask[0, 1, 0] = 1
+    mask[2, 0, 1] = 1
+    turned = np.ascontiguousarray(np.rot90(mask, 1, axes=(0, 1)))
+    a1, e1 = dda.orientation_average(mask, 1.5, 0.5, 4, 4)
+    a2, e2 = dda.orientation_average(turned, 1.5, 0.5, 4, 4)
+    assert abs(a1["Cext"] - a2["Cext"]) < 1e-4 * a1["Cext"]
+    assert e1 < 1e-3 * a1["Cext"]
