@@ -170,6 +170,13 @@ def forms(ctx, w, beams, theta, dda, inputs, torch):
             "sequential_fp64_s": tseq, "batched_fp64_s": tb64, "batched_refine_s": tb32,
             "speedup_batched_fp64": tseq / tb64, "speedup_batched_refine": tseq / tb32,
             "iterations_fp64": [min(i["iters"] for i in ib64), max(i["iters"] for i in ib64)]}
+        # orientation-averaged cross sections: Romberg over cos(beta) (9 points) x 8 gammas x 2 pols
+        oa, toa = _timed(torch, lambda: c4.orientation_average(3, 3, tol=w4.tol))
+        oa5, _ = _timed(torch, lambda: c4.orientation_average(3, 3, tol=w4.tol, precision=dda.FP32_REFINE))
+        res["orientation_average"] = {
+            "workload": "the same ellipsoid, 9 x 8 orientations x 2 pols (144 RHS), tol 1e-5",
+            "s": toa, "Cext": oa["Cext"], "Cabs": oa["Cabs"], "Csca": oa["Csca"], "romberg_err_Cext": oa["err"],
+            "Cext_fp32_refine": oa5["Cext"]}
     log("form batched_orientations done")
     # (2b) 32 spheres of 24..96 cells, solved concurrently
     ws = inputs.c4b_sphere_batch()

@@ -230,6 +230,21 @@ dda_status dda_farfield(dda_ctx *ctx, const dda_beam *beam, const void *x, int32
                         const double *dirs, double *F);
 
 /*
+ * dda_orientation_average — cross sections averaged over particle orientations (the paper's
+ * program averages over the Euler angles, Sec. 2).  Orientation R = Rz(alpha) Ry(beta) Rz(gamma);
+ * alpha only turns the scattering plane, so the cross sections need beta and gamma: Romberg
+ * integration in cos(beta) on 2^n_beta + 1 points, the periodic trapezoid rule on 2^n_gamma points
+ * in gamma.  Each orientation is solved for the x and y polarizations of a beam along the
+ * laboratory z axis (rotated into the particle frame), as batched right-hand sides of dda_solve.
+ *   n_beta 1..10, n_gamma 0..10;  tol, opts as for dda_solve (opts->x0 must be NULL)
+ *   out    host {<Cext>, <Cabs>, <Csca>, err}: unpolarized averages (units of d^2) and the Romberg
+ *          error estimate of <Cext> (difference of the last two extrapolation columns)
+ * Errors: DDA_EINVAL; solver failures are passed on from dda_solve.
+ */
+dda_status dda_orientation_average(dda_ctx *ctx, int32_t n_beta, int32_t n_gamma, double tol,
+                                   const dda_solve_opts *opts, double out[4]);
+
+/*
  * dda_asymmetry — out = {Csca, g}: the scattering cross section (units of d^2) and the asymmetry
  * parameter g = <cos theta> from the far field of the solution x (device complex128 [3][N]) of
  * beam, integrated over the sphere of directions: n_theta Gauss-Legendre nodes in cos theta about

@@ -61,6 +61,8 @@ _SIGS = {
     "dda_polarizability": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.POINTER(ct.c_double)]),
     "dda_asymmetry": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_int32, ct.c_int32,
                                  ct.POINTER(ct.c_double)]),
+    "dda_orientation_average": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_double, ct.c_void_p,
+                                           ct.POINTER(ct.c_double)]),
     "dda_rhs": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
     "dda_matvec": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
     "dda_matvec_f32": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
@@ -329,6 +331,15 @@ class Context:
                                   len(dirs), dirs.ctypes.data_as(ct.POINTER(ct.c_double)),
                                   F.ctypes.data_as(ct.POINTER(ct.c_double))), "dda_farfield")
         return F
+
+    def orientation_average(self, n_beta=3, n_gamma=3, tol=1e-5, solver=QMR, precision=FP64, maxit=0):
+        """Orientation-averaged (Cext, Cabs, Csca) and the Romberg error of <Cext>
+        (dda_orientation_average)."""
+        opts = SolveOpts(solver, precision, maxit, 0, 0.0, None, 0, 0, BREAKDOWN_REPORT)
+        out = (ct.c_double * 4)()
+        _check(lib().dda_orientation_average(self._h, int(n_beta), int(n_gamma), float(tol), ct.byref(opts), out),
+               "dda_orientation_average")
+        return {"Cext": out[0], "Cabs": out[1], "Csca": out[2], "err": out[3]}
 
     def asymmetry(self, beam, x, n_theta=32, n_phi=64):
         """(Csca, g) by integrating the far field over the sphere (dda_asymmetry)."""

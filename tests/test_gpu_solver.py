@@ -298,6 +298,20 @@ def test_fp32_refinement_reaches_fp64_tolerance(sphere16):
     assert abs(c32 - c64) < 1e-7 * c64
 
 
+def test_orientation_average_matches_oracle():
+    dda = _dda()
+    mask = np.zeros((3, 2, 2), np.uint8)
+    mask[:, 0, 0] = 1
+    mask[0, 1, 0] = 1
+    mask[2, 0, 1] = 1
+    ref, err = odda.orientation_average(mask, 1.5 + 0.02j, 0.5, 2, 2)
+    with dda.Context(mask, 1.5 + 0.02j, 0.5) as ctx:
+        got = ctx.orientation_average(2, 2, tol=1e-12)
+    for q in ("Cext", "Cabs", "Csca"):
+        assert abs(got[q] - ref[q]) < 1e-9 * abs(ref["Cext"]), (q, got, ref)
+    assert abs(got["err"] - err) < 1e-9 * abs(ref["Cext"])
+
+
 def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
     dda = _dda()
     mask = inputs.ellipsoid_mask((10, 8, 6), (5, 4, 3))
