@@ -375,7 +375,7 @@ def main():
     res_true = max(i["res_true"] for i in info)
     # after the timed steps: scattering cross section and asymmetry parameter of the x-polarized
     # solution by integration over the sphere of directions
-    csca_int, g_asym = ctx.asymmetry(beams[0], xs[0].contiguous(), 32, 64)
+    csca_int, g_asym = ctx.asymmetry(beams[0], xs[0].contiguous())
 
     out = {
         "metric": "matvecs/s + time-to-1e-5-residual per solve (plain FP64 vs chosen form), 1 GPU",
@@ -399,7 +399,7 @@ def main():
         "res_true": res_true,
         "Cext": [c[0] for c in cs],
         "asymmetry": {"g": g_asym, "Csca_integrated": csca_int, "Csca_from_Cext_minus_Cabs": cs[0][2],
-                      "grid": "32 Gauss-Legendre x 64 azimuths"},
+                      "grid": "automatic: ceil(k R) + 4 Gauss-Legendre nodes x 2 ceil(k R) + 8 azimuths"},
         "setup_s": t_setup,
         "matvec_ms_per_batch": tot_ms,
         "matvec_batch": nb,

@@ -249,9 +249,11 @@ dda_status dda_orientation_average(dda_ctx *ctx, int32_t n_beta, int32_t n_gamma
  * parameter g = <cos theta> from the far field of the solution x (device complex128 [3][N]) of
  * beam, integrated over the sphere of directions: n_theta Gauss-Legendre nodes in cos theta about
  * the propagation direction times n_phi equally spaced azimuths (dCsca/dOmega = |F|^2 / k^2).
+ * n_theta or n_phi <= 0: chosen from the band limit of |F|^2 (Legendre degree 2 k R, R the radius
+ * of the grid's circumscribing sphere): n_theta = ceil(k R) + 4, n_phi = 2 ceil(k R) + 8.
  * The paper computes g for every sphere (Sec. 3.1) and compares it with Mie theory (Sec. 3.2,
  * Fig. 5) without defining it; this is the usual definition.
- * Errors: DDA_EINVAL for NULL pointers, n_theta or n_phi < 1, more than 2^22 directions.
+ * Errors: DDA_EINVAL for NULL pointers or more than 2^22 directions.
  */
 dda_status dda_asymmetry(dda_ctx *ctx, const dda_beam *beam, const void *x, int32_t n_theta, int32_t n_phi,
                          double out[2]);

@@ -335,6 +335,15 @@ dda_status dda_asymmetry(dda_ctx *h, const dda_beam *beam, const void *x, int32_
                          double out[2]) {
     clear_error();
     Ctx *c = cx(h);
+    if (c && (n_theta <= 0 || n_phi <= 0)) {
+        // automatic: |F(n)|^2 is band-limited to Legendre degree 2 k R (R the radius of the grid's
+        // circumscribing sphere), so n_theta >= k R + 2 Gauss nodes and n_phi > 2 k R azimuths
+        // integrate it (times cos theta) exactly
+        const double R = 0.5 * std::sqrt((double)c->nx * c->nx + (double)c->ny * c->ny + (double)c->nz * c->nz);
+        const int kr = (int)std::ceil(c->kd * R);
+        if (n_theta <= 0) n_theta = kr + 4;
+        if (n_phi <= 0) n_phi = 2 * kr + 8;
+    }
     if (!c || !x || !out || n_theta < 1 || n_phi < 1 || (int64_t)n_theta * n_phi > (1 << 22) || !beam_ok(beam)) {
         set_error("dda_asymmetry: NULL argument, grid sizes outside 1..2^22 directions or beam without unit vectors");
         return DDA_EINVAL;

@@ -341,8 +341,9 @@ class Context:
                "dda_orientation_average")
         return {"Cext": out[0], "Cabs": out[1], "Csca": out[2], "err": out[3]}
 
-    def asymmetry(self, beam, x, n_theta=32, n_phi=64):
-        """(Csca, g) by integrating the far field over the sphere (dda_asymmetry)."""
+    def asymmetry(self, beam, x, n_theta=0, n_phi=0):
+        """(Csca, g) by integrating the far field over the sphere (dda_asymmetry; grid sizes 0:
+        chosen from the particle's size)."""
         out = (ct.c_double * 2)()
         _check(lib().dda_asymmetry(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
                                    int(n_theta), int(n_phi), out), "dda_asymmetry")

@@ -328,6 +328,13 @@ def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
     assert abs(csca - cref) < 1e-11 * cref and abs(g - gref) < 1e-11
     assert abs(csca - odda.csca_exact(pos, kd, P)) < 1e-9 * csca
     assert abs(cext - (csca + cabs)) < 1e-8 * cext  # optical theorem through the integrated Csca
+    # the automatic grid resolves a larger particle too (x ~ 10): optical theorem again
+    mask2 = inputs.sphere_mask(24)
+    with dda.Context(mask2, 1.2, 0.8) as ctx2:
+        x2, _, _ = ctx2.solve([inputs.X_POL], tol=1e-10)
+        c2, g2 = ctx2.asymmetry(inputs.X_POL, x2[0].contiguous())
+        e2, a2, _ = ctx2.cross_sections(inputs.X_POL, x2[0].contiguous())
+    assert abs(e2 - (c2 + a2)) < 1e-7 * e2 and 0 < g2 < 1
 
 
 def test_mueller_two_polarizations_equal_symmetry_route():
