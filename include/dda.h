@@ -107,6 +107,12 @@ typedef struct {
     int32_t graph;         /* iterations replayed as a captured hipGraph: 0 = automatic, 1 = on, -1 = off */
     int32_t x0_check;      /* 1: keep x0 for a right-hand side only if |b - A x0| < |b|, else start from 0 */
     int32_t on_breakdown;  /* DDA_BREAKDOWN_REPORT (default) or DDA_BREAKDOWN_RECOVER, below */
+    int32_t resume;        /* 1: continue this context's last double-precision solve, which stopped at
+                              its iteration limit (same beams, batch size and solver; x_out holding its
+                              iterate, or a checkpoint loaded by dda_checkpoint_load): right-hand sides
+                              at their limit get maxit more iterations toward tol, exactly as if the
+                              solve had not stopped; iters and matvecs count from its start; no
+                              residual history */
 } dda_solve_opts;
 
 /* What dda_solve does when QMR or Bi-CG breaks down for a right-hand side (the paper does not
@@ -198,6 +204,17 @@ dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
  */
 dda_status dda_solve(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, double tol,
                      const dda_solve_opts *opts, void *x_out, dda_solve_info *info);
+
+/*
+ * dda_checkpoint_save / dda_checkpoint_load — the state of the context's last double-precision
+ * solve that stopped at its iteration limit (per right-hand side scalars, iterate, Krylov vectors)
+ * to and from a file, to continue it later with opts.resume (the paper's program checkpoints long
+ * runs, Sec. 2).  x: device complex128 [n_rhs][3][N], the iterate (read by save, written by load).
+ * The file belongs to this library build and a particle with the same number of dipoles.
+ * Errors: DDA_EINVAL (nothing to save, unreadable or mismatched file), DDA_EHIP.
+ */
+dda_status dda_checkpoint_save(dda_ctx *ctx, const void *x, const char *path);
+dda_status dda_checkpoint_load(dda_ctx *ctx, void *x, const char *path);
 
 /*
  * dda_solve_many — one right-hand side on each of n_ctx particles (contexts), solved concurrently:

@@ -68,6 +68,12 @@ struct Ctx {
     size_t hbuf_bytes = 0;
     double2 *red = nullptr;     // read-out partials
     size_t red_elems = 0;
+
+    // a double-precision solve that stopped at its iteration limit leaves its complete state in
+    // vecs / sbuf and can be continued (dda_solve with opts.resume): its batch size and method
+    // (resume_nrhs = 0: nothing to continue)
+    int resume_nrhs = 0;
+    int resume_solver = -1;
 };
 
 // the work buffers of precision R

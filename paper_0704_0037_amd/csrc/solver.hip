@@ -39,7 +39,7 @@ struct SolveState {
     double2 eps, delta, beta, eta, cp;
     // Bi-CGSTAB
     double2 rho_b, rho_old, alpha, omega, beta_b;
-    int iter, status, maxit, pending, half, first, pad0, pad1;
+    int iter, status, maxit, pending, half, first, stop_after, pad1;  // stop_after: at the limit, end this iteration
 };
 
 // ------------------------------------------------------------------ small helpers
@@ -419,12 +419,24 @@ __global__ void k_bicg_scal_2(SolveState *st, int *done, const double2 *part, in
     } else if (!isfinite(S.res) || dabs(s[1]) < kBreakdown * s[0].x || !dfinite(s[1])) {
         S.status = ST_BREAK;
         done[rhs] = 1;
-    } else if (S.iter >= S.maxit) {
-        S.status = ST_MAXIT;
-        done[rhs] = 1;
     } else {
         S.beta_b = ddiv(s[1], S.rho_b);
         S.rho_b = s[1];
+        // at the limit the iteration still forms p, so that a continued solve starts from a whole
+        // iteration (k_stop_after ends it)
+        if (S.iter >= S.maxit) S.stop_after = 1;
+    }
+}
+
+// end of an iteration: a right-hand side that reached its limit stops here
+__global__ void k_stop_after(SolveState *st, int *done, int nrhs) {
+    const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rhs >= nrhs || done[rhs]) return;
+    SolveState &S = st[rhs];
+    if (S.stop_after) {
+        S.stop_after = 0;
+        S.status = ST_MAXIT;
+        done[rhs] = 1;
     }
 }
 
@@ -592,8 +604,7 @@ __global__ void k_cgnr_scal_res(SolveState *st, int *done, const double2 *part, 
         S.status = ST_BREAK;
         done[rhs] = 1;
     } else if (S.iter >= S.maxit) {
-        S.status = ST_MAXIT;
-        done[rhs] = 1;
+        S.stop_after = 1;  // the iteration still forms the next direction (k_stop_after ends it)
     }
 }
 
@@ -1077,12 +1088,14 @@ template <typename R> static dda_status enqueue_iterations(Run<R> &k, int count)
             hipLaunchKernelGGL(k_cgnr_norm<R>, vg, vb, 0, s, B.done, v.d, n3, B.part);
             hipLaunchKernelGGL(k_cgnr_scal, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, 2);
             hipLaunchKernelGGL(k_cgnr_p<R>, vg, vb, 0, s, B.st, B.done, v.d, v.p, n3, 0);
+            hipLaunchKernelGGL(k_stop_after, dim3((nrhs + 63) / 64), dim3(64), 0, s, B.st, B.done, nrhs);
         } else if (k.solver == DDA_BICG) {
             if ((st = run_matvec(k, v.p, v.pt, w.dots, B.done)) != DDA_OK) return st;
             hipLaunchKernelGGL(k_bicg_scal_alpha<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
             hipLaunchKernelGGL(k_bicg_update<R>, vg, vb, 0, s, B.st, B.done, v.p, v.pt, x, v.r, n3, B.part);
             hipLaunchKernelGGL(k_bicg_scal_2, dim3(nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
             hipLaunchKernelGGL(k_bicg_p<R>, vg, vb, 0, s, B.st, B.done, v.r, v.p, n3);
+            hipLaunchKernelGGL(k_stop_after, dim3((nrhs + 63) / 64), dim3(64), 0, s, B.st, B.done, nrhs);
         } else if (k.solver == DDA_QMR) {
             if ((st = run_matvec(k, v.p, v.pt, w.dots, B.done)) != DDA_OK) return st;
             hipLaunchKernelGGL(k_qmr_scal_eps<R>, dim3(nrhs), vb, 0, s, B.st, B.done, w.dots, ndots);
@@ -1161,6 +1174,18 @@ template <typename R> static dda_status run_begin(Run<R> &k, bool have_x0) {
         hipLaunchKernelGGL(k_bi_scal_init, dim3(B.nrhs), vb, 0, s, B.st, B.done, B.part, B.nb, B.hist, B.hcap);
     }
     DDA_HIP_CHECK(hipGetLastError());
+    return post_check(k);
+}
+
+// continue a run whose vectors and states are already in place (no initialization kernels)
+template <typename R> static dda_status run_resume(Run<R> &k) {
+    DDA_HIP_CHECK(hipEventCreateWithFlags(&k.ev, hipEventDisableTiming));
+    k.progress = progress_interval();
+    k.last_report = std::chrono::steady_clock::now();
+    k.last_guard = k.last_report;
+    k.best.assign(k.B.nrhs, HUGE_VAL);
+    k.best_it.assign(k.B.nrhs, 0);
+    k.stalled.assign(k.B.nrhs, 0);
     return post_check(k);
 }
 
@@ -1355,7 +1380,12 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
     std::vector<SolveState> h;
     if ((st = fetch_states(c, k.B, h)) != DDA_OK) return st;
     std::vector<double> rt;
-    if ((st = true_residual(c, k.B, k.v, k.x, nullptr, rt)) != DDA_OK) return st;
+    // A x goes to a slot the iteration recomputes before reading it, so that a solve stopped at
+    // its limit keeps its state (Bi-CGSTAB carries v = A p in pt into the next iteration; t is
+    // recomputed)
+    Vecs<double> tv = k.v;
+    if (k.solver == DDA_BICGSTAB) tv.pt = k.v.t;
+    if ((st = true_residual(c, k.B, tv, k.x, nullptr, rt)) != DDA_OK) return st;
     std::vector<double> hist;
     if (hcap > 0) {
         hist.resize((size_t)nrhs * hcap);
@@ -1364,6 +1394,12 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
         DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
     }
     dda_status ret = DDA_OK;
+    c.resume_nrhs = 0;  // continuable: a double-precision run with a right-hand side at its limit
+    for (int r = 0; r < nrhs; ++r)
+        if (!k.mixed && h[r].status == ST_MAXIT) {
+            c.resume_nrhs = nrhs;
+            c.resume_solver = o.solver;
+        }
     for (int r = 0; r < nrhs; ++r) {
         const dda_status sr = status_of(h[r].status);
         if (ret == DDA_OK && sr != DDA_OK) ret = sr;
@@ -1371,13 +1407,13 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
         info[r].status = sr;
         info[r].iters = h[r].iter;
         const int per_run = o.solver == DDA_BICGSTAB ? 2 * h[r].iter - (h[r].half ? 1 : 0)
-                            : o.solver == DDA_CGNR   ? 2 * h[r].iter  // the converged step skips A^H r
+                            : o.solver == DDA_CGNR   ? 2 * h[r].iter + (h[r].status == ST_MAXIT ? 1 : 0)  // a limit stop ends with A^H r
                                                      : h[r].iter;
         info[r].matvecs = per_run + (o.x0 ? 1 + (o.x0_check ? 1 : 0) : 0);
         info[r].outer = k.stalled.size() > (size_t)r && k.stalled[r] ? 1 : 0;
         info[r].res_rec = h[r].res;
         info[r].res_true = rt[r];
-        if (info[r].res_hist && info[r].res_hist_cap > 0) {
+        if (hcap > 0 && info[r].res_hist && info[r].res_hist_cap > 0) {
             const int n = std::min(info[r].res_hist_cap, h[r].iter + 1);
             for (int q = 0; q < n; ++q) info[r].res_hist[q] = hist[(size_t)r * hcap + q];
             info[r].res_hist_len = n;
@@ -1388,13 +1424,52 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
     return ret;
 }
 
+// continue the context's stopped solve (opts.resume): right-hand sides that hit the iteration
+// limit get opts.maxit more iterations and the new tol; the others stay as they ended
+static dda_status prepare_resume(Ctx &c, Run<double> &k, const dda_beam *beams, int nrhs, double tol,
+                                 const dda_solve_opts &o, double2 *x) {
+    if (c.resume_nrhs != nrhs || c.resume_solver != o.solver || o.precision != DDA_FP64 || o.x0) {
+        set_error("dda_solve: nothing to resume for this batch size, method and precision (double precision, "
+                  "no initial guess)");
+        return DDA_EINVAL;
+    }
+    dda_status st;
+    if ((st = ensure_vecs<double>(c, nrhs)) != DDA_OK) return st;
+    if ((st = ensure_bufs(c, k.B, nrhs, 0)) != DDA_OK) return st;  // the states stay where they are
+    std::vector<double> ar(nrhs), ai(nrhs);
+    for (int r = 0; r < nrhs; ++r) polarizability(c, beams[r], ar[r], ai[r]);
+    if ((st = upload_scales<double>(c, ar, ai)) != DDA_OK) return st;
+    k.c = &c;
+    k.v = vecs_of<double>(c, nrhs);
+    k.x = x;
+    k.solver = o.solver;
+    k.mixed = false;
+    std::vector<SolveState> h;
+    if ((st = fetch_states(c, k.B, h)) != DDA_OK) return st;
+    std::vector<int> d(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        d[r] = 1;
+        if (h[r].status == ST_MAXIT) {
+            h[r].status = ST_RUN;
+            h[r].maxit = h[r].iter + o.maxit;
+            h[r].tol = tol;
+            d[r] = 0;
+        }
+    }
+    DDA_HIP_CHECK(hipMemcpyAsync(k.B.st, h.data(), nrhs * sizeof(SolveState), hipMemcpyHostToDevice, c.stream));
+    DDA_HIP_CHECK(hipMemcpyAsync(k.B.done, d.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    return run_resume(k);
+}
+
 static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
                              double2 *x, dda_solve_info *info, int check_every, bool graph) {
-    const int hcap = hist_cap(info, nrhs);
+    const int hcap = o.resume ? 0 : hist_cap(info, nrhs);  // a continued solve keeps no history
     Run<double> k;
     k.check_every = check_every;
     k.graph = graph;
-    dda_status st = prepare_fp64(c, k, beams, nrhs, tol, o, x, hcap);
+    dda_status st = o.resume ? prepare_resume(c, k, beams, nrhs, tol, o, x)
+                             : prepare_fp64(c, k, beams, nrhs, tol, o, x, hcap);
     if (st == DDA_OK) st = run_poll(k);
     while (st == DDA_OK && !k.fin) {
         if ((st = run_issue(k)) != DDA_OK) break;
@@ -1601,6 +1676,10 @@ static dda_status check_opts(const dda_solve_opts *opts, dda_solve_opts &o) {
         set_error("dda_solve: the refined single-precision solve uses QMR only");
         return DDA_ENOTSUP;
     }
+    if (o.resume && (o.precision != DDA_FP64 || o.x0)) {
+        set_error("dda_solve: resume continues a double-precision solve without an initial guess");
+        return DDA_EINVAL;
+    }
     if (o.on_breakdown != DDA_BREAKDOWN_REPORT && o.on_breakdown != DDA_BREAKDOWN_RECOVER) {
         set_error("dda_solve: unknown breakdown policy");
         return DDA_EINVAL;
@@ -1671,6 +1750,115 @@ static dda_status recover_breakdowns(Ctx &c, const dda_beam *beams, int nrhs, do
 }
 }  // namespace dda
 
+namespace dda {
+// Checkpoint file: header, the per-RHS solver states, the iterate x, the Krylov vectors.  Written
+// and read by the same library build (the header carries the state size as a check).
+struct CkptHeader {
+    char magic[8];
+    int32_t version, nrhs, solver, state_bytes;
+    int64_t N, vec_elems;
+};
+static const char kCkptMagic[8] = {'D', 'D', 'A', 'C', 'K', 'P', 'T', '1'};
+
+static dda_status ckpt_io(FILE *f, void *dev, size_t bytes, bool write, hipStream_t s) {
+    std::vector<char> buf(std::min<size_t>(bytes, (size_t)64 << 20));
+    for (size_t off = 0; off < bytes; off += buf.size()) {
+        const size_t n = std::min(buf.size(), bytes - off);
+        if (write) {
+            DDA_HIP_CHECK(hipMemcpyAsync(buf.data(), (char *)dev + off, n, hipMemcpyDeviceToHost, s));
+            DDA_HIP_CHECK(hipStreamSynchronize(s));
+            if (std::fwrite(buf.data(), 1, n, f) != n) {
+                set_error("dda_checkpoint_save: write failed");
+                return DDA_EINVAL;
+            }
+        } else {
+            if (std::fread(buf.data(), 1, n, f) != n) {
+                set_error("dda_checkpoint_load: file too short");
+                return DDA_EINVAL;
+            }
+            DDA_HIP_CHECK(hipMemcpyAsync((char *)dev + off, buf.data(), n, hipMemcpyHostToDevice, s));
+            DDA_HIP_CHECK(hipStreamSynchronize(s));
+        }
+    }
+    return DDA_OK;
+}
+}  // namespace dda
+
+extern "C" dda_status dda_checkpoint_save(dda_ctx *h, const void *x, const char *path) {
+    clear_error();
+    Ctx *c = cx(h);
+    if (!c || !x || !path) {
+        set_error("dda_checkpoint_save: NULL argument");
+        return DDA_EINVAL;
+    }
+    if (c->resume_nrhs <= 0) {
+        set_error("dda_checkpoint_save: the context holds no double-precision solve stopped at its limit");
+        return DDA_EINVAL;
+    }
+    const int nrhs = c->resume_nrhs;
+    Bufs B;
+    dda_status st = ensure_bufs(*c, B, nrhs, 0);  // the layout of the stopped solve's states
+    if (st != DDA_OK) return st;
+    CkptHeader hd{};
+    std::memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 1;
+    hd.nrhs = nrhs;
+    hd.solver = c->resume_solver;
+    hd.state_bytes = (int32_t)(nrhs * sizeof(SolveState));
+    hd.N = c->N;
+    hd.vec_elems = (int64_t)kNumVecs * nrhs * 3 * c->N;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) {
+        set_error(std::string("dda_checkpoint_save: cannot open ") + path);
+        return DDA_EINVAL;
+    }
+    if (std::fwrite(&hd, sizeof hd, 1, f) != 1) {
+        set_error("dda_checkpoint_save: write failed");
+        st = DDA_EINVAL;
+    }
+    if (st == DDA_OK) st = ckpt_io(f, B.st, hd.state_bytes, true, c->stream);
+    if (st == DDA_OK) st = ckpt_io(f, const_cast<void *>(x), (size_t)nrhs * 3 * c->N * sizeof(double2), true, c->stream);
+    if (st == DDA_OK) st = ckpt_io(f, c->vecs, (size_t)hd.vec_elems * sizeof(double2), true, c->stream);
+    if (std::fclose(f) != 0 && st == DDA_OK) {
+        set_error("dda_checkpoint_save: closing the file failed");
+        st = DDA_EINVAL;
+    }
+    return st;
+}
+
+extern "C" dda_status dda_checkpoint_load(dda_ctx *h, void *x, const char *path) {
+    clear_error();
+    Ctx *c = cx(h);
+    if (!c || !x || !path) {
+        set_error("dda_checkpoint_load: NULL argument");
+        return DDA_EINVAL;
+    }
+    FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        set_error(std::string("dda_checkpoint_load: cannot open ") + path);
+        return DDA_EINVAL;
+    }
+    CkptHeader hd{};
+    dda_status st = DDA_OK;
+    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1 ||
+        hd.nrhs < 1 || hd.N != c->N || hd.state_bytes != (int32_t)(hd.nrhs * sizeof(SolveState)) ||
+        hd.vec_elems != (int64_t)kNumVecs * hd.nrhs * 3 * c->N ||
+        (hd.solver != DDA_QMR && hd.solver != DDA_BICGSTAB && hd.solver != DDA_BICG && hd.solver != DDA_CGNR)) {
+        set_error("dda_checkpoint_load: not a checkpoint of this library for a particle of this size");
+        st = DDA_EINVAL;
+    }
+    Bufs B;
+    if (st == DDA_OK) st = ensure_vecs<double>(*c, hd.nrhs);
+    if (st == DDA_OK) st = ensure_bufs(*c, B, hd.nrhs, 0);
+    if (st == DDA_OK) st = ckpt_io(f, B.st, hd.state_bytes, false, c->stream);
+    if (st == DDA_OK) st = ckpt_io(f, x, (size_t)hd.nrhs * 3 * c->N * sizeof(double2), false, c->stream);
+    if (st == DDA_OK) st = ckpt_io(f, c->vecs, (size_t)hd.vec_elems * sizeof(double2), false, c->stream);
+    std::fclose(f);
+    c->resume_nrhs = st == DDA_OK ? hd.nrhs : 0;
+    c->resume_solver = hd.solver;
+    return st;
+}
+
 extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs, double tol,
                                 const dda_solve_opts *opts, void *x_out, dda_solve_info *info) {
     clear_error();
@@ -1704,6 +1892,7 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
             own.assign(n_rhs, dda_solve_info{});
             inf = own.data();
         }
+        if (!o.resume) c->resume_nrhs = 0;  // any other solve overwrites the stopped state
         st = solve_with(*c, beams, n_rhs, tol, o, (double2 *)x_out, inf, check, graph);
         if ((st == DDA_EBREAKDOWN || st == DDA_ENOTCONV) && o.on_breakdown == DDA_BREAKDOWN_RECOVER) {
             st = recover_breakdowns(*c, beams, n_rhs, tol, o, (double2 *)x_out, inf, check, graph);

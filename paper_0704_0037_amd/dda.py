@@ -33,7 +33,8 @@ class SetupOpts(ct.Structure):
 class SolveOpts(ct.Structure):
     _fields_ = [("solver", ct.c_int32), ("precision", ct.c_int32), ("maxit", ct.c_int32),
                 ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p),
-                ("graph", ct.c_int32), ("x0_check", ct.c_int32), ("on_breakdown", ct.c_int32)]
+                ("graph", ct.c_int32), ("x0_check", ct.c_int32), ("on_breakdown", ct.c_int32),
+                ("resume", ct.c_int32)]
 
 
 class SolveInfo(ct.Structure):
@@ -61,6 +62,8 @@ _SIGS = {
     "dda_polarizability": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.POINTER(ct.c_double)]),
     "dda_asymmetry": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_int32, ct.c_int32,
                                  ct.POINTER(ct.c_double)]),
+    "dda_checkpoint_save": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_char_p]),
+    "dda_checkpoint_load": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_char_p]),
     "dda_orientation_average": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_double, ct.c_void_p,
                                            ct.POINTER(ct.c_double)]),
     "dda_rhs": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
@@ -292,12 +295,13 @@ class Context:
         return res
 
     def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
-              x_out=None, history=0, raise_on_fail=True, graph=0, x0_check=False, on_breakdown=BREAKDOWN_REPORT):
+              x_out=None, history=0, raise_on_fail=True, graph=0, x0_check=False, on_breakdown=BREAKDOWN_REPORT,
+              resume=False):
         n = len(beams)
         x_out = self.vector(n) if x_out is None else x_out
         opts = SolveOpts(solver, precision, maxit, check_every, inner_tol,
                          None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value, graph,
-                         1 if x0_check else 0, on_breakdown)
+                         1 if x0_check else 0, on_breakdown, 1 if resume else 0)
         infos = (SolveInfo * n)()
         hists = []
         for i in range(n):
@@ -331,6 +335,19 @@ class Context:
                                   len(dirs), dirs.ctypes.data_as(ct.POINTER(ct.c_double)),
                                   F.ctypes.data_as(ct.POINTER(ct.c_double))), "dda_farfield")
         return F
+
+    def checkpoint_save(self, path, x):
+        """Write the last stopped double-precision solve (iterate x [n][3][N]) to `path`."""
+        _check(lib().dda_checkpoint_save(self._h, ct.c_void_p(x.data_ptr()) if x.is_cuda else None,
+                                         os.fsencode(path)), "dda_checkpoint_save")
+
+    def checkpoint_load(self, path, x):
+        """Read a checkpoint into the context and the iterate buffer x [n][3][N] (then solve with
+        resume=True)."""
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()):
+            raise TypeError("x must be a contiguous complex128 CUDA/HIP tensor")
+        _check(lib().dda_checkpoint_load(self._h, ct.c_void_p(x.data_ptr()), os.fsencode(path)),
+               "dda_checkpoint_load")
 
     def orientation_average(self, n_beta=3, n_gamma=3, tol=1e-5, solver=QMR, precision=FP64, maxit=0):
         """Orientation-averaged (Cext, Cabs, Csca) and the Romberg error of <Cext>

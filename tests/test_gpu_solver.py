@@ -298,6 +298,37 @@ def test_fp32_refinement_reaches_fp64_tolerance(sphere16):
     assert abs(c32 - c64) < 1e-7 * c64
 
 
+@pytest.mark.parametrize("solver", ["QMR", "BICG", "BICGSTAB", "CGNR"])
+def test_resume_and_checkpoint_continue_exactly(solver, tmp_path):
+    # a solve stopped at its iteration limit and continued (in place, or through a checkpoint file
+    # into a fresh context) gives bitwise the uninterrupted solve
+    dda = _dda()
+    sv = getattr(dda, solver)
+    mask = inputs.ellipsoid_mask((10, 8, 7), (5, 4, 3.5))
+    beams = inputs.beams_for_orientations(1, seed=41)
+    kw = dict(tol=1e-9, solver=sv, check_every=3, graph=-1)
+    with dda.Context(mask, 1.4 + 0.01j, 0.5) as ctx:
+        xf, inf, st = ctx.solve(beams, **kw)
+        assert st == 0
+        x, i1, st = ctx.solve(beams, maxit=5, raise_on_fail=False, **kw)
+        assert st == dda.ENOTCONV and all(i["iters"] == 5 for i in i1)
+        x2, i2, st = ctx.solve(beams, x_out=x, resume=True, **kw)
+        assert st == 0 and torch.equal(x2, xf)
+        assert [i["iters"] for i in i2] == [i["iters"] for i in inf]
+        # nothing left to continue once it converged
+        _, _, st = ctx.solve(beams, x_out=x, resume=True, raise_on_fail=False, **kw)
+        assert st == dda.EINVAL
+        x, _, st = ctx.solve(beams, maxit=4, raise_on_fail=False, **kw)
+        path = str(tmp_path / "solve.ckpt")
+        ctx.checkpoint_save(path, x)
+    with dda.Context(mask, 1.4 + 0.01j, 0.5) as ctx2:
+        y = ctx2.vector(len(beams))
+        ctx2.checkpoint_load(path, y)
+        y2, i3, st = ctx2.solve(beams, x_out=y, resume=True, **kw)
+        assert st == 0 and torch.equal(y2, xf)
+        assert [i["iters"] for i in i3] == [i["iters"] for i in inf]
+
+
 def test_orientation_average_matches_oracle():
     dda = _dda()
     mask = np.zeros((3, 2, 2), np.uint8)
