@@ -589,30 +589,49 @@ def romberg(fvals, a, b):
     return best, err
 
 
-def orientation_average(mask, m, k, n_beta, n_gamma, tol=1e-10, polarizability="ldr"):
-    """Cross sections averaged over particle orientations (the paper's program averages over the
-    Euler angles, Sec. 2).  Orientation R = Rz(alpha) Ry(beta) Rz(gamma); alpha only turns the
-    scattering plane, so the cross sections need beta and gamma.  Romberg in cos(beta) on
-    2^n_beta + 1 points, the periodic trapezoid rule on 2^n_gamma points in gamma; unpolarized:
-    the mean of the x- and y-polarized incident beams, each brought into the particle frame by R^T.
-    Returns ({"Cext", "Cabs", "Csca"} averages, Romberg error estimate of <Cext>).
-    pinned by: the Romberg rule on polynomials; a CM single dipole (isotropic) gives its fixed
-    value; invariance of the average under a 90-degree lattice rotation of the particle."""
-    pos, _ = dipoles(mask)
-    nb, ng = 2 ** n_beta + 1, 2 ** n_gamma
-    vals = np.zeros((nb, ng, 3))
-    for i in range(nb):
-        mu = -1.0 + 2.0 * i / (nb - 1)
+def romberg_adaptive(f, a, b, eps, n_min=2, n_max=10):
+    """Romberg integration with doubling: f is sampled at a + i h, i = 0..2^n, for n = n_min,
+    n_min + 1, ... (a new level evaluates only the new midpoints), until every column's error
+    estimate |R(n,n) - R(n,n-1)| is at most eps |R(n,n)| of column 0, or n = n_max.  f maps an
+    array of abscissae to an array of rows (one per abscissa).  Returns (integrals per column,
+    error estimates per column, n).
+    pinned by: closed-form integrals, the level at which polynomials become exact, one evaluation
+    per abscissa, the fixed-level rule at the level it stops on."""
+    assert 1 <= n_min <= n_max
+    n = n_min
+    pts = a + (b - a) * np.arange(2 ** n + 1) / 2 ** n
+    vals = np.atleast_2d(np.asarray(f(pts), dtype=np.float64).reshape(len(pts), -1))
+    while True:
+        cols = [romberg(vals[:, q], a, b) for q in range(vals.shape[1])]
+        v = np.array([c[0] for c in cols])
+        e = np.array([c[1] for c in cols])
+        if np.all(e <= eps * abs(v[0])) or n == n_max:
+            return v, e, n
+        n += 1
+        new_idx = np.arange(1, 2 ** n, 2)
+        new_vals = np.asarray(f(a + (b - a) * new_idx / 2 ** n), dtype=np.float64).reshape(len(new_idx), -1)
+        merged = np.empty((2 ** n + 1, vals.shape[1]))
+        merged[0::2] = vals
+        merged[1::2] = new_vals
+        vals = merged
+
+
+def _orientation_rows(pos, m, k, mus, n_gamma, polarizability):
+    """Mean (Cext, Cabs, Csca) over the 2^n_gamma equispaced gamma and the x and y incident
+    polarizations, at each cos(beta) in mus.  Orientation R = Ry(beta) Rz(gamma) (alpha = 0); the
+    particle-frame beam is R^T applied to the laboratory vectors."""
+    ng = 2 ** n_gamma
+    rows = np.zeros((len(mus), 3))
+    for i, mu in enumerate(mus):
         beta_e = math.acos(max(-1.0, min(1.0, mu)))
+        c, s = math.cos(beta_e), math.sin(beta_e)
         for j in range(ng):
             gam = 2.0 * math.pi * j / ng
-            c, s = math.cos(beta_e), math.sin(beta_e)
             cg, sg = math.cos(gam), math.sin(gam)
             Ry = np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
             Rz = np.array([[cg, -sg, 0.0], [sg, cg, 0.0], [0.0, 0.0, 1.0]])
             R = Ry @ Rz
             prop = R.T @ np.array([0.0, 0.0, 1.0])
-            acc = np.zeros(3)
             for e in (np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])):
                 pol = R.T @ e
                 if polarizability == "cm":
@@ -624,15 +643,48 @@ def orientation_average(mask, m, k, n_beta, n_gamma, tol=1e-10, polarizability="
                 b = rhs(pos, k, bt, prop, pol)
                 x = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
                 cext, cabs = cross_sections(pos, k, alpha, bt * x, prop, pol)[:2]
-                acc += np.array([cext, cabs, cext - cabs])
-            vals[i, j] = acc / 2.0
-    over_gamma = vals.mean(axis=1)  # (nb, 3)
+                rows[i] += np.array([cext, cabs, cext - cabs])
+    return rows / (2.0 * ng)
+
+
+def orientation_average(mask, m, k, n_beta, n_gamma, tol=1e-10, polarizability="ldr"):
+    """Cross sections averaged over particle orientations (the paper's program averages over the
+    Euler angles, Sec. 2).  Orientation R = Rz(alpha) Ry(beta) Rz(gamma); alpha only turns the
+    scattering plane, so the cross sections need beta and gamma.  Romberg in cos(beta) on
+    2^n_beta + 1 points, the periodic trapezoid rule on 2^n_gamma points in gamma; unpolarized:
+    the mean of the x- and y-polarized incident beams, each brought into the particle frame by R^T.
+    Returns ({"Cext", "Cabs", "Csca"} averages, Romberg error estimate of <Cext>).
+    pinned by: the Romberg rule on polynomials; a CM single dipole (isotropic) gives its fixed
+    value; invariance of the average under a 90-degree lattice rotation of the particle."""
+    pos, _ = dipoles(mask)
+    nb = 2 ** n_beta + 1
+    mus = [-1.0 + 2.0 * i / (nb - 1) for i in range(nb)]
+    over_gamma = _orientation_rows(pos, m, k, mus, n_gamma, polarizability)
     out, errs = {}, []
     for q, name in enumerate(("Cext", "Cabs", "Csca")):
         v, e = romberg(over_gamma[:, q], -1.0, 1.0)
         out[name] = v / 2.0
         errs.append(e / 2.0)
     return out, errs[0]
+
+
+def orientation_average_adaptive(mask, m, k, eps, n_beta_min, n_beta_max, n_gamma, polarizability="ldr"):
+    """Orientation average with the number of beta values chosen adaptively (the paper's program
+    integrates over the Euler angles by Romberg's method with 2^n + 1 points, adaptively, Sec. 2):
+    the cos(beta) grid doubles from 2^n_beta_min + 1 points until the Romberg error estimates of
+    <Cext> and <Cabs> are at most eps <Cext>, or n_beta_max is reached; gamma keeps 2^n_gamma
+    points (the periodic trapezoid rule).  Returns ({"Cext", "Cabs", "Csca"}, {"Cext", "Cabs"}
+    error estimates, n_beta used).
+    pinned by: romberg_adaptive's pins and equality with the fixed-level average at the level
+    it stops on."""
+    pos, _ = dipoles(mask)
+
+    def f(mus):
+        return _orientation_rows(pos, m, k, list(mus), n_gamma, polarizability)[:, :2]
+
+    v, e, n = romberg_adaptive(f, -1.0, 1.0, eps, n_beta_min, n_beta_max)
+    out = {"Cext": v[0] / 2.0, "Cabs": v[1] / 2.0, "Csca": (v[0] - v[1]) / 2.0}
+    return out, {"Cext": e[0] / 2.0, "Cabs": e[1] / 2.0}, n
 
 
 def beam_frame(prop, pol):

@@ -285,3 +285,41 @@ def test_orientation_average_invariant_under_a_lattice_rotation():
     a2, e2 = dda.orientation_average(turned, 1.5, 0.5, 4, 4)
     assert abs(a1["Cext"] - a2["Cext"]) < 1e-4 * a1["Cext"]
     assert e1 < 1e-3 * a1["Cext"]
+
+
+def test_adaptive_romberg_closed_form_and_one_evaluation_per_point():
+    seen = []
+
+    def f(x):
+        seen.extend(x.tolist())
+        return np.exp(x)
+
+    v, e, n = dda.romberg_adaptive(f, -1.0, 1.0, 1e-12)
+    assert abs(v[0] - (math.e - 1.0 / math.e)) < 1e-13
+    assert len(seen) == 2 ** n + 1 == len(set(seen))  # every abscissa evaluated once
+    assert e[0] <= 1e-12 * v[0]
+
+
+def test_adaptive_romberg_stops_where_polynomials_become_exact():
+    # R(n,n) is exact up to degree 2n + 1 and R(n,n-1) up to degree 2n - 1: a cubic stops at the
+    # first level (n = 2), a quintic needs one doubling
+    v, e, n = dda.romberg_adaptive(lambda x: x ** 3 + x ** 2 + 1.0, -1.0, 1.0, 1e-12, 2, 8)
+    assert n == 2 and abs(v[0] - 8.0 / 3.0) < 1e-14
+    v, e, n = dda.romberg_adaptive(lambda x: x ** 5 + x ** 4 + 1.0, -1.0, 1.0, 1e-12, 2, 8)
+    assert n == 3 and abs(v[0] - 2.4) < 1e-14
+    # a kink converges slowly: the level cap ends it, with the cap's error estimate
+    v, e, n = dda.romberg_adaptive(lambda x: np.abs(x - 0.3), -1.0, 1.0, 1e-14, 2, 5)
+    assert n == 5 and e[0] > 1e-14 * v[0] and abs(v[0] - 1.09) < 1e-2
+
+
+def test_adaptive_orientation_average_equals_the_fixed_rule_at_its_level():
+    mask = np.zeros((3, 2, 2), np.uint8)
+    mask[:, 0, 0] = 1
+    mask[0, 1, 0] = 1
+    mask[2, 0, 1] = 1
+    avg, err, n = dda.orientation_average_adaptive(mask, 1.5 + 0.02j, 0.5, 1e-5, 2, 6, 2)
+    assert n == 4  # level 3 misses 1e-5 (3.7e-5 of <Cext>), level 4 meets it
+    fixed, ferr = dda.orientation_average(mask, 1.5 + 0.02j, 0.5, n, 2)
+    for q in ("Cext", "Cabs", "Csca"):
+        assert abs(avg[q] - fixed[q]) < 1e-14 * fixed["Cext"]
+    assert abs(err["Cext"] - ferr) < 1e-14 * fixed["Cext"] and err["Cabs"] <= 1e-5 * avg["Cext"]
