@@ -262,6 +262,23 @@ dda_status dda_orientation_average(dda_ctx *ctx, int32_t n_beta, int32_t n_gamma
                                    const dda_solve_opts *opts, double out[4]);
 
 /*
+ * dda_orientation_average_adaptive — the same average with the number of beta values chosen
+ * adaptively (the paper's program integrates over the Euler angles by Romberg's method on 2^n + 1
+ * points, adaptively, Sec. 2): the cos(beta) grid starts at 2^n_beta_min + 1 points and doubles,
+ * solving only the new points, until the Romberg error estimates of <Cext> and <Cabs> are both at
+ * most eps <Cext>, or n_beta_max is reached (then the result carries its larger estimates).
+ * gamma keeps 2^n_gamma points.
+ *   eps > 0; 1 <= n_beta_min <= n_beta_max <= 10; n_gamma 0..10; tol, opts as for dda_solve
+ *   (opts->x0 must be NULL)
+ *   out          host {<Cext>, <Cabs>, <Csca>, err(<Cext>), err(<Cabs>)}
+ *   n_beta_used  host, may be NULL: the level n the result comes from (2^n + 1 beta values)
+ * Errors: DDA_EINVAL; solver failures are passed on from dda_solve.
+ */
+dda_status dda_orientation_average_adaptive(dda_ctx *ctx, double eps, int32_t n_beta_min, int32_t n_beta_max,
+                                            int32_t n_gamma, double tol, const dda_solve_opts *opts,
+                                            double out[5], int32_t *n_beta_used);
+
+/*
  * dda_asymmetry — out = {Csca, g}: the scattering cross section (units of d^2) and the asymmetry
  * parameter g = <cos theta> from the far field of the solution x (device complex128 [3][N]) of
  * beam, integrated over the sphere of directions: n_theta Gauss-Legendre nodes in cos theta about

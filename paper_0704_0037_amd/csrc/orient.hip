@@ -3,7 +3,9 @@
 // the scattering plane, so the cross sections need beta and gamma: Romberg integration in
 // cos(beta) on 2^n_beta + 1 points and the trapezoid rule on 2^n_gamma points in gamma (periodic).
 // Every orientation is solved for both incident polarizations (x and y in the laboratory frame,
-// brought into the particle frame by R^T), as batched right-hand sides of dda_solve.
+// brought into the particle frame by R^T), as batched right-hand sides of dda_solve.  The adaptive
+// form doubles the cos(beta) grid (solving only the new points) until Romberg's error estimates
+// meet a relative tolerance, as the paper's program integrates adaptively over the angles.
 #include <cmath>
 #include <string>
 #include <vector>
@@ -30,25 +32,15 @@ static void romberg(const std::vector<double> &f, double a, double b, double &va
     err = n >= 1 ? std::fabs(R[n][n] - R[n][n - 1]) : 0.0;
 }
 
-}  // namespace dda
-
-using namespace dda;
-
-extern "C" dda_status dda_orientation_average(dda_ctx *h, int32_t n_beta, int32_t n_gamma, double tol,
-                                              const dda_solve_opts *opts, double out[4]) {
-    clear_error();
-    Ctx *c = cx(h);
-    if (!c || !out || n_beta < 1 || n_beta > 10 || n_gamma < 0 || n_gamma > 10 || !(tol > 0) || (opts && opts->x0)) {
-        set_error("dda_orientation_average: NULL argument, n_beta outside 1..10, n_gamma outside 0..10, tol <= 0 "
-                  "or an initial guess");
-        return DDA_EINVAL;
-    }
-    const int nb = (1 << n_beta) + 1, ng = 1 << n_gamma;
+// Mean Cext and Cabs over the ng equispaced gamma and the two incident polarizations at each
+// cos(beta) in mus: every orientation solved for both polarizations as batched right-hand sides
+static dda_status beta_rows(dda_ctx *h, Ctx *c, const std::vector<double> &mus, int ng, double tol,
+                            const dda_solve_opts *opts, std::vector<double> &fe, std::vector<double> &fa) {
+    const int nb = (int)mus.size();
     std::vector<dda_beam> beams;
     beams.reserve((size_t)2 * nb * ng);
     for (int i = 0; i < nb; ++i) {
-        const double mu = -1.0 + 2.0 * i / (nb - 1);
-        const double be = std::acos(std::max(-1.0, std::min(1.0, mu)));
+        const double be = std::acos(std::max(-1.0, std::min(1.0, mus[i])));
         const double cb = std::cos(be), sb = std::sin(be);
         for (int j = 0; j < ng; ++j) {
             const double ga = 2.0 * M_PI * j / ng, cg = std::cos(ga), sg = std::sin(ga);
@@ -86,8 +78,9 @@ extern "C" dda_status dda_orientation_average(dda_ctx *h, int32_t n_beta, int32_
     }
     (void)hipFree(xbuf);
     if (st != DDA_OK) return st;  // the failing call's message stays
-    // unpolarized mean over the two polarizations and over gamma, then Romberg in cos(beta)
-    std::vector<double> fe(nb), fa(nb);
+    // unpolarized mean over the two polarizations and over gamma
+    fe.assign(nb, 0.0);
+    fa.assign(nb, 0.0);
     for (int i = 0; i < nb; ++i) {
         double se = 0, sa = 0;
         for (int j = 0; j < ng; ++j)
@@ -99,6 +92,32 @@ extern "C" dda_status dda_orientation_average(dda_ctx *h, int32_t n_beta, int32_
         fe[i] = se / (2.0 * ng);
         fa[i] = sa / (2.0 * ng);
     }
+    return DDA_OK;
+}
+
+// the 2^n + 1 equispaced cos(beta) on [-1, 1] (a point of level n is bitwise the same value at
+// every finer level)
+static double mu_at(int i, int n) { return -1.0 + 2.0 * i / (1 << n); }
+
+}  // namespace dda
+
+using namespace dda;
+
+extern "C" dda_status dda_orientation_average(dda_ctx *h, int32_t n_beta, int32_t n_gamma, double tol,
+                                              const dda_solve_opts *opts, double out[4]) {
+    clear_error();
+    Ctx *c = cx(h);
+    if (!c || !out || n_beta < 1 || n_beta > 10 || n_gamma < 0 || n_gamma > 10 || !(tol > 0) || (opts && opts->x0)) {
+        set_error("dda_orientation_average: NULL argument, n_beta outside 1..10, n_gamma outside 0..10, tol <= 0 "
+                  "or an initial guess");
+        return DDA_EINVAL;
+    }
+    const int nb = (1 << n_beta) + 1, ng = 1 << n_gamma;
+    std::vector<double> mus(nb), fe, fa;
+    for (int i = 0; i < nb; ++i) mus[i] = mu_at(i, n_beta);
+    const dda_status st = beta_rows(h, c, mus, ng, tol, opts, fe, fa);
+    if (st != DDA_OK) return st;
+    // Romberg in cos(beta)
     double ve, ee, va, ea;
     romberg(fe, -1.0, 1.0, ve, ee);
     romberg(fa, -1.0, 1.0, va, ea);
@@ -107,4 +126,50 @@ extern "C" dda_status dda_orientation_average(dda_ctx *h, int32_t n_beta, int32_
     out[2] = (ve - va) / 2.0;
     out[3] = ee / 2.0;
     return DDA_OK;
+}
+
+extern "C" dda_status dda_orientation_average_adaptive(dda_ctx *h, double eps, int32_t n_beta_min,
+                                                       int32_t n_beta_max, int32_t n_gamma, double tol,
+                                                       const dda_solve_opts *opts, double out[5],
+                                                       int32_t *n_beta_used) {
+    clear_error();
+    Ctx *c = cx(h);
+    if (!c || !out || !(eps > 0) || n_beta_min < 1 || n_beta_max < n_beta_min || n_beta_max > 10 || n_gamma < 0 ||
+        n_gamma > 10 || !(tol > 0) || (opts && opts->x0)) {
+        set_error("dda_orientation_average_adaptive: NULL argument, eps <= 0, not 1 <= n_beta_min <= n_beta_max <= "
+                  "10, n_gamma outside 0..10, tol <= 0 or an initial guess");
+        return DDA_EINVAL;
+    }
+    const int ng = 1 << n_gamma;
+    int n = n_beta_min;
+    std::vector<double> mus((1 << n) + 1), fe, fa;
+    for (int i = 0; i <= (1 << n); ++i) mus[i] = mu_at(i, n);
+    dda_status st = beta_rows(h, c, mus, ng, tol, opts, fe, fa);
+    if (st != DDA_OK) return st;
+    for (;;) {
+        double ve, ee, va, ea;
+        romberg(fe, -1.0, 1.0, ve, ee);
+        romberg(fa, -1.0, 1.0, va, ea);
+        if ((ee <= eps * std::fabs(ve) && ea <= eps * std::fabs(ve)) || n == n_beta_max) {
+            out[0] = ve / 2.0;
+            out[1] = va / 2.0;
+            out[2] = (ve - va) / 2.0;
+            out[3] = ee / 2.0;
+            out[4] = ea / 2.0;
+            if (n_beta_used) *n_beta_used = n;
+            return DDA_OK;
+        }
+        // next level: only the new midpoints are solved
+        ++n;
+        std::vector<double> nm, ne, na;
+        for (int i = 1; i < (1 << n); i += 2) nm.push_back(mu_at(i, n));
+        if ((st = beta_rows(h, c, nm, ng, tol, opts, ne, na)) != DDA_OK) return st;
+        std::vector<double> me((1 << n) + 1), ma((1 << n) + 1);
+        for (int i = 0; i <= (1 << n); ++i) {
+            me[i] = i % 2 ? ne[i / 2] : fe[i / 2];
+            ma[i] = i % 2 ? na[i / 2] : fa[i / 2];
+        }
+        fe.swap(me);
+        fa.swap(ma);
+    }
 }

@@ -66,6 +66,9 @@ _SIGS = {
     "dda_checkpoint_load": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_char_p]),
     "dda_orientation_average": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_double, ct.c_void_p,
                                            ct.POINTER(ct.c_double)]),
+    "dda_orientation_average_adaptive": (ct.c_int, [ct.c_void_p, ct.c_double, ct.c_int32, ct.c_int32, ct.c_int32,
+                                                    ct.c_double, ct.c_void_p, ct.POINTER(ct.c_double),
+                                                    ct.POINTER(ct.c_int32)]),
     "dda_rhs": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
     "dda_matvec": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
     "dda_matvec_f32": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
@@ -357,6 +360,19 @@ class Context:
         _check(lib().dda_orientation_average(self._h, int(n_beta), int(n_gamma), float(tol), ct.byref(opts), out),
                "dda_orientation_average")
         return {"Cext": out[0], "Cabs": out[1], "Csca": out[2], "err": out[3]}
+
+    def orientation_average_adaptive(self, eps=1e-3, n_beta_min=2, n_beta_max=8, n_gamma=3, tol=1e-5, solver=QMR,
+                                     precision=FP64, maxit=0):
+        """Orientation average with the cos(beta) grid doubled until Romberg's error estimates are
+        at most eps <Cext> (dda_orientation_average_adaptive): averages, error estimates and the
+        level n used (2^n + 1 beta values)."""
+        opts = SolveOpts(solver, precision, maxit, 0, 0.0, None, 0, 0, BREAKDOWN_REPORT)
+        out = (ct.c_double * 5)()
+        n = ct.c_int32(0)
+        _check(lib().dda_orientation_average_adaptive(self._h, float(eps), int(n_beta_min), int(n_beta_max),
+                                                      int(n_gamma), float(tol), ct.byref(opts), out, ct.byref(n)),
+               "dda_orientation_average_adaptive")
+        return {"Cext": out[0], "Cabs": out[1], "Csca": out[2], "err": out[3], "err_abs": out[4], "n_beta": n.value}
 
     def asymmetry(self, beam, x, n_theta=0, n_phi=0):
         """(Csca, g) by integrating the far field over the sphere (dda_asymmetry; grid sizes 0:

@@ -343,6 +343,30 @@ def test_orientation_average_matches_oracle():
     assert abs(got["err"] - err) < 1e-9 * abs(ref["Cext"])
 
 
+def test_orientation_average_adaptive_matches_oracle():
+    # the oracle stops at level 4 with wide margins on both sides of eps (level 3: 3.7e-5 of
+    # <Cext>, level 4: 2.2e-7), so the device run takes the same decisions
+    dda = _dda()
+    mask = np.zeros((3, 2, 2), np.uint8)
+    mask[:, 0, 0] = 1
+    mask[0, 1, 0] = 1
+    mask[2, 0, 1] = 1
+    ref, err, n = odda.orientation_average_adaptive(mask, 1.5 + 0.02j, 0.5, 1e-5, 2, 6, 2)
+    assert n == 4
+    with dda.Context(mask, 1.5 + 0.02j, 0.5) as ctx:
+        got = ctx.orientation_average_adaptive(1e-5, 2, 6, 2, tol=1e-12)
+        capped = ctx.orientation_average_adaptive(1e-5, 2, 3, 2, tol=1e-12)
+        with pytest.raises(dda.DDAError):
+            ctx.orientation_average_adaptive(1e-5, 4, 3, 2)
+    assert got["n_beta"] == 4 and capped["n_beta"] == 3
+    for q in ("Cext", "Cabs", "Csca"):
+        assert abs(got[q] - ref[q]) < 1e-9 * abs(ref["Cext"]), (q, got, ref)
+    assert abs(got["err"] - err["Cext"]) < 1e-9 * abs(ref["Cext"])
+    assert abs(got["err_abs"] - err["Cabs"]) < 1e-9 * abs(ref["Cext"])
+    fixed, ferr = odda.orientation_average(mask, 1.5 + 0.02j, 0.5, 3, 2)
+    assert abs(capped["Cext"] - fixed["Cext"]) < 1e-9 * abs(ref["Cext"]) and capped["err"] > 1e-5 * capped["Cext"]
+
+
 def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
     dda = _dda()
     mask = inputs.ellipsoid_mask((10, 8, 6), (5, 4, 3))
