@@ -687,6 +687,58 @@ def orientation_average_adaptive(mask, m, k, eps, n_beta_min, n_beta_max, n_gamm
     return out, {"Cext": e[0] / 2.0, "Cabs": e[1] / 2.0}, n
 
 
+def orientation_average_mueller(mask, m, k, n_beta, n_gamma, n_alpha, theta, polarizability="ldr"):
+    """Mueller matrix averaged over particle orientations (Sec. 2: the average over the Euler
+    angle alpha comes from several scattering planes, beta and gamma need separate solves).
+    Orientation R = Rz(alpha) Ry(beta) Rz(gamma): turning the particle by alpha about the incident
+    direction is the same as turning the scattering plane by -alpha, so for each (beta, gamma) the
+    matrix is averaged over the n_alpha equispaced planes phi = 2 pi j / n_alpha (the periodic
+    trapezoid rule, the sign of the turn does not matter), over the 2^n_gamma equispaced gamma,
+    and integrated by Romberg in cos(beta) on 2^n_beta + 1 points.  The solutions of the x and y
+    polarized beams of each orientation give the matrix in every plane.
+    Returns ((len(theta), 4, 4) averaged matrix, Romberg error estimate of S11 per angle).
+    pinned by: a CM single dipole gives the Rayleigh matrix in closed form; for a particle with a
+    mirror plane the eight off-block elements vanish and S21 = S12, S43 = -S34; invariance under a
+    lattice rotation of the particle; 2 pi times the integral of S11 sin(theta) / k^2 is <Csca>."""
+    pos, _ = dipoles(mask)
+    theta = np.asarray(theta, dtype=np.float64)
+    nb, ng = 2 ** n_beta + 1, 2 ** n_gamma
+    rows = np.zeros((nb, len(theta), 4, 4))
+    for i in range(nb):
+        mu = -1.0 + 2.0 * i / (nb - 1)
+        beta_e = math.acos(max(-1.0, min(1.0, mu)))
+        c, s = math.cos(beta_e), math.sin(beta_e)
+        for j in range(ng):
+            gam = 2.0 * math.pi * j / ng
+            cg, sg = math.cos(gam), math.sin(gam)
+            Ry = np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
+            Rz = np.array([[cg, -sg, 0.0], [sg, cg, 0.0], [0.0, 0.0, 1.0]])
+            R = Ry @ Rz
+            prop = R.T @ np.array([0.0, 0.0, 1.0])
+            P = []
+            for e in (np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])):
+                pol = R.T @ e
+                alpha = alpha_cm(m) if polarizability == "cm" else alpha_ldr(m, k, prop, pol)
+                bt = beta_of_alpha(alpha)
+                A = interaction_matrix(pos, k, bt)
+                b = rhs(pos, k, bt, prop, pol)
+                P.append(bt * np.linalg.solve(A, b.reshape(-1)).reshape(b.shape))
+            pol1 = R.T @ np.array([1.0, 0.0, 0.0])
+            for a in range(n_alpha):
+                rows[i] += mueller(pos, k, prop, pol1, P[0], P[1], theta, 2.0 * math.pi * a / n_alpha)
+    rows /= ng * n_alpha
+    out = np.zeros((len(theta), 4, 4))
+    err = np.zeros(len(theta))
+    for t in range(len(theta)):
+        for a in range(4):
+            for b in range(4):
+                v, e = romberg(rows[:, t, a, b], -1.0, 1.0)
+                out[t, a, b] = v / 2.0
+                if a == 0 and b == 0:
+                    err[t] = e / 2.0
+    return out, err
+
+
 def beam_frame(prop, pol):
     """(e1, e2, e3): e3 = propagation, e1 = (real) polarization, e2 = e3 x e1."""
     e3 = np.asarray(prop, dtype=np.float64)

@@ -323,3 +323,54 @@ def test_adaptive_orientation_average_equals_the_fixed_rule_at_its_level():
     for q in ("Cext", "Cabs", "Csca"):
         assert abs(avg[q] - fixed[q]) < 1e-14 * fixed["Cext"]
     assert abs(err["Cext"] - ferr) < 1e-14 * fixed["Cext"] and err["Cabs"] <= 1e-5 * avg["Cext"]
+
+
+def test_orientation_averaged_mueller_of_a_single_dipole_is_rayleigh():
+    # an isotropic (CM) dipole: S1 = -i k^3 alpha, S2 = -i k^3 alpha cos(theta), S3 = S4 = 0 in
+    # every orientation and plane
+    mask = np.ones((1, 1, 1), np.uint8)
+    k, m = 0.6, 1.5 + 0.1j
+    th = np.linspace(0.0, math.pi, 7)
+    M, err = dda.orientation_average_mueller(mask, m, k, 2, 1, 4, th, polarizability="cm")
+    a2 = k ** 6 * abs(dda.alpha_cm(m)) ** 2
+    c = np.cos(th)
+    ref = np.zeros((len(th), 4, 4))
+    ref[:, 0, 0] = ref[:, 1, 1] = a2 * (1 + c ** 2) / 2
+    ref[:, 0, 1] = ref[:, 1, 0] = a2 * (c ** 2 - 1) / 2
+    ref[:, 2, 2] = ref[:, 3, 3] = a2 * c
+    assert np.max(np.abs(M - ref)) < 1e-12 * a2 and np.max(err) < 1e-12 * a2
+
+
+def _l_particle():
+    mask = np.zeros((1, 2, 2), np.uint8)
+    mask[0, 0, 0] = mask[0, 0, 1] = mask[0, 1, 0] = 1
+    return mask
+
+
+def test_orientation_averaged_mueller_integrates_to_csca_and_has_mirror_structure():
+    mask = _l_particle()  # planar: its plane is a mirror plane
+    k = 0.5
+    x, w = np.polynomial.legendre.leggauss(24)
+    M, err = dda.orientation_average_mueller(mask, 1.5 + 0.02j, k, 4, 3, 8, np.arccos(x))
+    avg, _ = dda.orientation_average(mask, 1.5 + 0.02j, k, 4, 3)
+    csca = 2 * math.pi * np.sum(w * M[:, 0, 0]) / k ** 2  # the averaged matrix does not depend on phi
+    assert abs(csca - avg["Csca"]) < 1e-6 * avg["Csca"]
+    s11 = M[:, 0, 0]
+    for i, j in ((0, 2), (0, 3), (1, 2), (1, 3), (2, 0), (2, 1), (3, 0), (3, 1)):
+        assert np.max(np.abs(M[:, i, j]) / s11) < 1e-12
+    assert np.max(np.abs(M[:, 1, 0] - M[:, 0, 1]) / s11) < 1e-3
+    assert np.max(np.abs(M[:, 3, 2] + M[:, 2, 3]) / s11) < 1e-4
+
+
+def test_orientation_averaged_mueller_does_not_depend_on_the_particle_placement():
+    # the same particle turned by 90 degrees (an exact lattice rotation) has the same average;
+    # without the average over the scattering planes (alpha) it differs by several per cent
+    mask = _l_particle()
+    turned = np.ascontiguousarray(np.rot90(mask, 1, axes=(0, 1)))
+    th = np.linspace(0.0, math.pi, 9)
+    M1, _ = dda.orientation_average_mueller(mask, 1.5 + 0.02j, 0.5, 4, 4, 8, th)
+    M2, _ = dda.orientation_average_mueller(turned, 1.5 + 0.02j, 0.5, 4, 4, 8, th)
+    scale = np.max(M1[:, 0, 0])
+    assert np.max(np.abs(M1 - M2)) < 1e-3 * scale
+    N2, _ = dda.orientation_average_mueller(turned, 1.5 + 0.02j, 0.5, 4, 4, 1, th)
+    assert np.max(np.abs(M1 - N2)) > 1e-2 * scale
