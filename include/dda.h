@@ -279,6 +279,24 @@ dda_status dda_orientation_average_adaptive(dda_ctx *ctx, double eps, int32_t n_
                                             double out[5], int32_t *n_beta_used);
 
 /*
+ * dda_orientation_average_mueller — the Mueller matrix (as dda_mueller) averaged over particle
+ * orientations (Sec. 2: the Euler angle alpha is averaged through scattering planes, beta and
+ * gamma need separate solves).  Turning the particle by alpha about the incident direction turns
+ * the scattering plane by -alpha, so each orientation's matrix is averaged over the n_alpha
+ * planes phi = 2 pi j / n_alpha; then over the 2^n_gamma equispaced gamma, and Romberg in
+ * cos(beta) on 2^n_beta + 1 points, element by element.  Orientations and beams as for
+ * dda_orientation_average; the averaged matrix does not depend on the plane.
+ *   n_beta 1..10, n_gamma 0..10, n_alpha 1..1024;  tol, opts as for dda_solve (opts->x0 NULL)
+ *   theta  host [n_theta] radians, 1 <= n_theta <= 65536
+ *   M      host double [n_theta][4][4] row-major (unnormalized, units of d^2 as dda_mueller)
+ *   err    host [n_theta] or NULL: Romberg error estimate of the averaged S11 at each angle
+ * Errors: DDA_EINVAL; solver and read-out failures are passed on.
+ */
+dda_status dda_orientation_average_mueller(dda_ctx *ctx, int32_t n_beta, int32_t n_gamma, int32_t n_alpha,
+                                           double tol, const dda_solve_opts *opts, const double *theta,
+                                           int32_t n_theta, double *M, double *err);
+
+/*
  * dda_asymmetry — out = {Csca, g}: the scattering cross section (units of d^2) and the asymmetry
  * parameter g = <cos theta> from the far field of the solution x (device complex128 [3][N]) of
  * beam, integrated over the sphere of directions: n_theta Gauss-Legendre nodes in cos theta about

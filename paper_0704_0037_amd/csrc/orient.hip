@@ -5,7 +5,10 @@
 // Every orientation is solved for both incident polarizations (x and y in the laboratory frame,
 // brought into the particle frame by R^T), as batched right-hand sides of dda_solve.  The adaptive
 // form doubles the cos(beta) grid (solving only the new points) until Romberg's error estimates
-// meet a relative tolerance, as the paper's program integrates adaptively over the angles.
+// meet a relative tolerance, as the paper's program integrates adaptively over the angles.  The
+// averaged Mueller matrix takes alpha from the scattering planes: turning the particle by alpha
+// about the incident direction turns the scattering plane by -alpha, so each orientation's matrix
+// is averaged over equispaced planes.
 #include <cmath>
 #include <string>
 #include <vector>
@@ -32,15 +35,13 @@ static void romberg(const std::vector<double> &f, double a, double b, double &va
     err = n >= 1 ? std::fabs(R[n][n] - R[n][n - 1]) : 0.0;
 }
 
-// Mean Cext and Cabs over the ng equispaced gamma and the two incident polarizations at each
-// cos(beta) in mus: every orientation solved for both polarizations as batched right-hand sides
-static dda_status beta_rows(dda_ctx *h, Ctx *c, const std::vector<double> &mus, int ng, double tol,
-                            const dda_solve_opts *opts, std::vector<double> &fe, std::vector<double> &fa) {
-    const int nb = (int)mus.size();
+// The beams of the orientations (cos(beta) in mus) x (ng equispaced gamma), x and y polarized
+// in the laboratory frame, in that order (orientation-major, polarization fastest)
+static std::vector<dda_beam> orientation_beams(const std::vector<double> &mus, int ng) {
     std::vector<dda_beam> beams;
-    beams.reserve((size_t)2 * nb * ng);
-    for (int i = 0; i < nb; ++i) {
-        const double be = std::acos(std::max(-1.0, std::min(1.0, mus[i])));
+    beams.reserve((size_t)2 * mus.size() * ng);
+    for (const double mu : mus) {
+        const double be = std::acos(std::max(-1.0, std::min(1.0, mu)));
         const double cb = std::cos(be), sb = std::sin(be);
         for (int j = 0; j < ng; ++j) {
             const double ga = 2.0 * M_PI * j / ng, cg = std::cos(ga), sg = std::sin(ga);
@@ -58,26 +59,47 @@ static dda_status beta_rows(dda_ctx *h, Ctx *c, const std::vector<double> &mus, 
             }
         }
     }
-    // solve in batches that fit a modest device buffer
+    return beams;
+}
+
+// Solve the beams as batched right-hand sides, in chunks of whole polarization pairs that fit a
+// modest device buffer; use(s0, cnt, x, per) sees the solutions of beams s0 .. s0 + cnt - 1
+// (x: device [cnt][3][N], per bytes each)
+template <typename F>
+static dda_status solve_in_chunks(dda_ctx *h, Ctx *c, const std::vector<dda_beam> &beams, double tol,
+                                  const dda_solve_opts *opts, F &&use) {
     const size_t per = (size_t)3 * c->N * sizeof(double2);
     const int chunk = (int)std::max<size_t>(2, std::min<size_t>(64, ((size_t)1 << 30) / per)) / 2 * 2;
     void *xbuf = nullptr;
     dda_status st = device_alloc(&xbuf, per * chunk);
     if (st != DDA_OK) return st;
-    std::vector<double> cext(beams.size()), cabs(beams.size());
     for (size_t s0 = 0; s0 < beams.size() && st == DDA_OK; s0 += chunk) {
         const int cnt = (int)std::min<size_t>(chunk, beams.size() - s0);
         st = dda_solve(h, beams.data() + s0, cnt, tol, opts, xbuf, nullptr);
-        if (st != DDA_OK) break;
-        for (int r = 0; r < cnt && st == DDA_OK; ++r) {
+        if (st == DDA_OK) st = use(s0, cnt, (const char *)xbuf, per);
+    }
+    (void)hipFree(xbuf);
+    return st;  // a failing call's message stays
+}
+
+// Mean Cext and Cabs over the ng equispaced gamma and the two incident polarizations at each
+// cos(beta) in mus
+static dda_status beta_rows(dda_ctx *h, Ctx *c, const std::vector<double> &mus, int ng, double tol,
+                            const dda_solve_opts *opts, std::vector<double> &fe, std::vector<double> &fa) {
+    const int nb = (int)mus.size();
+    const std::vector<dda_beam> beams = orientation_beams(mus, ng);
+    std::vector<double> cext(beams.size()), cabs(beams.size());
+    dda_status st = solve_in_chunks(h, c, beams, tol, opts, [&](size_t s0, int cnt, const char *x, size_t per) {
+        for (int r = 0; r < cnt; ++r) {
             double cs[3];
-            st = dda_cross_sections(h, &beams[s0 + r], (const char *)xbuf + per * r, cs);
+            const dda_status e = dda_cross_sections(h, &beams[s0 + r], x + per * r, cs);
+            if (e != DDA_OK) return e;
             cext[s0 + r] = cs[0];
             cabs[s0 + r] = cs[1];
         }
-    }
-    (void)hipFree(xbuf);
-    if (st != DDA_OK) return st;  // the failing call's message stays
+        return DDA_OK;
+    });
+    if (st != DDA_OK) return st;
     // unpolarized mean over the two polarizations and over gamma
     fe.assign(nb, 0.0);
     fa.assign(nb, 0.0);
@@ -172,4 +194,48 @@ extern "C" dda_status dda_orientation_average_adaptive(dda_ctx *h, double eps, i
         fe.swap(me);
         fa.swap(ma);
     }
+}
+
+extern "C" dda_status dda_orientation_average_mueller(dda_ctx *h, int32_t n_beta, int32_t n_gamma, int32_t n_alpha,
+                                                      double tol, const dda_solve_opts *opts, const double *theta,
+                                                      int32_t n_theta, double *M, double *err) {
+    clear_error();
+    Ctx *c = cx(h);
+    if (!c || !theta || !M || n_theta < 1 || n_theta > (1 << 16) || n_beta < 1 || n_beta > 10 || n_gamma < 0 ||
+        n_gamma > 10 || n_alpha < 1 || n_alpha > 1024 || !(tol > 0) || (opts && opts->x0)) {
+        set_error("dda_orientation_average_mueller: NULL argument, n_theta outside 1..65536, n_beta outside 1..10, "
+                  "n_gamma outside 0..10, n_alpha outside 1..1024, tol <= 0 or an initial guess");
+        return DDA_EINVAL;
+    }
+    const int nb = (1 << n_beta) + 1, ng = 1 << n_gamma;
+    std::vector<double> mus(nb);
+    for (int i = 0; i < nb; ++i) mus[i] = mu_at(i, n_beta);
+    const std::vector<dda_beam> beams = orientation_beams(mus, ng);
+    const size_t per_row = (size_t)n_theta * 16;
+    std::vector<double> rows((size_t)nb * per_row, 0.0), m1(per_row);
+    // every chunk holds whole (x, y) pairs: the pair's solutions give the matrix in any plane
+    dda_status st = solve_in_chunks(h, c, beams, tol, opts, [&](size_t s0, int cnt, const char *x, size_t per) {
+        for (int r = 0; r < cnt; r += 2) {
+            const size_t q = s0 + r, i = q / (2 * (size_t)ng);
+            for (int a = 0; a < n_alpha; ++a) {
+                const double phi = 2.0 * M_PI * a / n_alpha;
+                const dda_status e = dda_mueller(h, &beams[q], x + per * r, x + per * (r + 1), phi, theta, n_theta,
+                                                 m1.data());
+                if (e != DDA_OK) return e;
+                for (size_t t = 0; t < per_row; ++t) rows[i * per_row + t] += m1[t];
+            }
+        }
+        return DDA_OK;
+    });
+    if (st != DDA_OK) return st;
+    // mean over gamma and alpha, then Romberg in cos(beta) element by element
+    std::vector<double> f(nb);
+    for (size_t t = 0; t < per_row; ++t) {
+        for (int i = 0; i < nb; ++i) f[i] = rows[i * per_row + t] / ((double)ng * n_alpha);
+        double v, e;
+        romberg(f, -1.0, 1.0, v, e);
+        M[t] = v / 2.0;
+        if (err && t % 16 == 0) err[t / 16] = e / 2.0;
+    }
+    return DDA_OK;
 }

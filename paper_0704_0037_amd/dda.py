@@ -66,6 +66,9 @@ _SIGS = {
     "dda_checkpoint_load": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_char_p]),
     "dda_orientation_average": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_double, ct.c_void_p,
                                            ct.POINTER(ct.c_double)]),
+    "dda_orientation_average_mueller": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double,
+                                                   ct.c_void_p, ct.POINTER(ct.c_double), ct.c_int32,
+                                                   ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]),
     "dda_orientation_average_adaptive": (ct.c_int, [ct.c_void_p, ct.c_double, ct.c_int32, ct.c_int32, ct.c_int32,
                                                     ct.c_double, ct.c_void_p, ct.POINTER(ct.c_double),
                                                     ct.POINTER(ct.c_int32)]),
@@ -373,6 +376,21 @@ class Context:
                                                       int(n_gamma), float(tol), ct.byref(opts), out, ct.byref(n)),
                "dda_orientation_average_adaptive")
         return {"Cext": out[0], "Cabs": out[1], "Csca": out[2], "err": out[3], "err_abs": out[4], "n_beta": n.value}
+
+    def orientation_average_mueller(self, theta, n_beta=3, n_gamma=3, n_alpha=8, tol=1e-5, solver=QMR,
+                                    precision=FP64, maxit=0):
+        """Orientation-averaged Mueller matrix [n_theta][4][4] (alpha through n_alpha scattering
+        planes) and the Romberg error estimate of S11 per angle (dda_orientation_average_mueller)."""
+        theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        M = np.zeros((len(theta), 4, 4), dtype=np.float64)
+        err = np.zeros(len(theta), dtype=np.float64)
+        opts = SolveOpts(solver, precision, maxit, 0, 0.0, None, 0, 0, BREAKDOWN_REPORT)
+        dp = ct.POINTER(ct.c_double)
+        _check(lib().dda_orientation_average_mueller(self._h, int(n_beta), int(n_gamma), int(n_alpha), float(tol),
+                                                     ct.byref(opts), theta.ctypes.data_as(dp), len(theta),
+                                                     M.ctypes.data_as(dp), err.ctypes.data_as(dp)),
+               "dda_orientation_average_mueller")
+        return M, err
 
     def asymmetry(self, beam, x, n_theta=0, n_phi=0):
         """(Csca, g) by integrating the far field over the sphere (dda_asymmetry; grid sizes 0:

@@ -367,6 +367,23 @@ def test_orientation_average_adaptive_matches_oracle():
     assert abs(capped["Cext"] - fixed["Cext"]) < 1e-9 * abs(ref["Cext"]) and capped["err"] > 1e-5 * capped["Cext"]
 
 
+def test_orientation_averaged_mueller_matches_oracle():
+    dda = _dda()
+    mask = np.zeros((3, 2, 2), np.uint8)
+    mask[:, 0, 0] = 1
+    mask[0, 1, 0] = 1
+    mask[2, 0, 1] = 1
+    th = np.linspace(0.0, math.pi, 13)
+    ref, rerr = odda.orientation_average_mueller(mask, 1.5 + 0.02j, 0.5, 2, 2, 4, th)
+    with dda.Context(mask, 1.5 + 0.02j, 0.5) as ctx:
+        M, err = ctx.orientation_average_mueller(th, 2, 2, 4, tol=1e-12)
+        with pytest.raises(dda.DDAError):
+            ctx.orientation_average_mueller(th, 2, 2, 0)
+    scale = np.max(ref[:, 0, 0])
+    assert np.max(np.abs(M - ref)) < 1e-9 * scale, np.max(np.abs(M - ref)) / scale
+    assert np.max(np.abs(err - rerr)) < 1e-9 * scale
+
+
 def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
     dda = _dda()
     mask = inputs.ellipsoid_mask((10, 8, 6), (5, 4, 3))
