@@ -374,3 +374,72 @@ def test_orientation_averaged_mueller_does_not_depend_on_the_particle_placement(
     assert np.max(np.abs(M1 - M2)) < 1e-3 * scale
     N2, _ = dda.orientation_average_mueller(turned, 1.5 + 0.02j, 0.5, 4, 4, 1, th)
     assert np.max(np.abs(M1 - N2)) > 1e-2 * scale
+
+
+# ------------------------------------------------------------------ focused (Gaussian) beam
+_CIRC = np.array([1.0, 1.0j, 0.0]) / math.sqrt(2.0)
+_AZ = np.array([0.0, 0.0, 1.0])
+
+
+@pytest.mark.parametrize("kw0", [2.0, 5.0, 50.0])
+def test_gaussian_beam_focal_value_closed_form(kw0):
+    # at the focus the phi integral of (e - (e.k^)k^) is pi (2 - sin^2) e, which leaves
+    # E(c) = e [(1 - exp(-A)) - (2 / (k w0)^2) (1 - exp(-A)(1 + A))], A = (k w0)^2 / 4
+    k = 0.7
+    w0 = kw0 / k
+    A = kw0 ** 2 / 4.0
+    ref = (1 - math.exp(-A)) - (2.0 / kw0 ** 2) * (1 - math.exp(-A) * (1 + A))
+    E = dda.gaussian_beam_field(np.array([[0.4, -0.1, 0.2]]), k, _AZ, _CIRC, w0, (0.4, -0.1, 0.2))[0]
+    assert np.max(np.abs(E - ref * _CIRC)) < 1e-14
+
+
+def test_gaussian_beam_is_transverse_and_solves_helmholtz():
+    k, w0, c = 1.0, 2.0, (0.3, -0.2, 0.5)
+    rng = np.random.default_rng(0)
+    pts = rng.uniform(-3.0, 3.0, (5, 3))
+    far = np.array([[10.0, 0.0, 0.0]])  # fixes the quadrature (it is sized by the farthest point)
+
+    def F(r):
+        return dda.gaussian_beam_field(np.vstack([r, far]), k, _AZ, _CIRC, w0, c)[:-1]
+
+    h = 1e-3
+    E0 = F(pts)
+    div = np.zeros(len(pts), complex)
+    lap = np.zeros_like(E0)
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = h
+        Ep, Em = F(pts + e), F(pts - e)
+        div += (Ep[:, d] - Em[:, d]) / (2 * h)
+        lap += (Ep - 2 * E0 + Em) / h ** 2
+    scale = np.max(np.abs(E0))
+    assert np.max(np.abs(div)) < 1e-7 * scale
+    assert np.max(np.abs(lap + k * k * E0)) < 1e-6 * scale
+
+
+def test_gaussian_beam_plane_wave_and_paraxial_limits():
+    k = 1.0
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(-5.0, 5.0, (6, 3))
+    E = dda.gaussian_beam_field(pts, k, _AZ, _CIRC, 1e4, (0.0, 0.0, 0.0))
+    assert np.max(np.abs(E - np.exp(1j * k * pts @ _AZ)[:, None] * _CIRC)) < 1e-6
+    # k w0 = 20: the paraxial Gaussian up to O(1 / (k w0)^2)
+    w0 = 20.0
+    pts = rng.uniform(-15.0, 15.0, (8, 3))
+    pts[:, 2] *= 3
+    E = dda.gaussian_beam_field(pts, k, _AZ, _CIRC, w0, (0.0, 0.0, 0.0))
+    q = 1 + 2j * pts[:, 2] / (k * w0 ** 2)
+    psi = np.exp(-(pts[:, 0] ** 2 + pts[:, 1] ** 2) / (w0 ** 2 * q)) / q * np.exp(1j * k * pts[:, 2])
+    err = np.max(np.abs(E[:, :2] - psi[:, None] * _CIRC[:2]))
+    assert err < 2.0 / (k * w0) ** 2 and np.max(np.abs(E[:, 2])) < 5.0 / (k * w0)
+
+
+def test_gaussian_beam_quadrature_is_converged():
+    k, w0 = 0.9, 3.0
+    rng = np.random.default_rng(2)
+    pts = rng.uniform(-6.0, 6.0, (20, 3))
+    E = dda.gaussian_beam_field(pts, k, (0.6, 0.0, 0.8), (0.8, 0.0, -0.6), w0, (0.5, 0.5, 0.0))
+    # the same field with twice the nodes: the rule sized by the farthest point is converged
+    big = np.vstack([pts, [[0.5 + 40.0, 0.5, 0.0]]])
+    E2 = dda.gaussian_beam_field(big, k, (0.6, 0.0, 0.8), (0.8, 0.0, -0.6), w0, (0.5, 0.5, 0.0))[:-1]
+    assert np.max(np.abs(E - E2)) < 1e-12
