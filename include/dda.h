@@ -80,12 +80,22 @@ enum { DDA_QMR = 0, DDA_BICGSTAB = 1, DDA_BICG = 2, DDA_CGNR = 3 };
  * finished in DDA_FP64 from there (from zero if that iterate is no better than zero). */
 enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1, DDA_FP32_PRODUCT = 2 };
 
-/* Incident plane wave in the particle frame: unit propagation vector and complex unit
- * polarization (E_inc(r) = pol * exp(i kd prop.r)). */
+/* Incident beam in the particle frame: unit propagation vector and complex unit polarization.
+ * w0 = 0: the plane wave E_inc(r) = pol * exp(i kd prop.r).
+ * w0 > 0: a focused beam of waist radius w0 (units of d) at center (the lattice frame: cell
+ * (i, j, l) at (i + 1/2 - nx/2, ...)), the paper's tightly focused Gaussian beams (Sec. 2): the
+ * angular spectrum of plane waves
+ *   E(r) = (w0^2 / 4 pi) int_{|q| < k} exp(-w0^2 |q|^2 / 4) (pol - (pol.k^) k^) exp(i k k^.(r - center)) d^2q
+ * (k^ = (q + sqrt(k^2 - |q|^2) prop) / k), an exact Maxwell solution whose paraxial limit is the
+ * Gaussian beam; pol must be orthogonal to prop.  It enters the right-hand side and Cext; the
+ * one-polarization Mueller shortcut and the learned guess take plane waves only.  Zero-initialize
+ * the struct to get a plane wave. */
 typedef struct {
     double prop[3];
     double pol_re[3];
     double pol_im[3];
+    double w0;
+    double center[3];
 } dda_beam;
 
 /* Optional settings of dda_setup (pass NULL for defaults). */

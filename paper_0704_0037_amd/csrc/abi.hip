@@ -41,9 +41,13 @@ void beta_of(const Ctx &c, const dda_beam &bm, double &br, double &bi) {
     bi = std::copysign(std::sqrt(0.5 * (mod - ar)), ai);
 }
 
+template <typename R> dda_status beam_field_launch(Ctx &c, const dda_beam &b, cplx<R> *out, double sr, double si,
+                                                   hipStream_t st);
+
 template <typename R> dda_status rhs_launch(Ctx &c, const dda_beam &bm, cplx<R> *b, hipStream_t s) {
     double br, bi;
     beta_of(c, bm, br, bi);
+    if (bm.w0 > 0) return beam_field_launch<R>(c, bm, b, br, bi, s);
     const int N = (int)c.N;
     hipLaunchKernelGGL(k_rhs<R>, dim3((N + 255) / 256), dim3(256), 0, s, c.lin, b, N, c.nx, c.ny, c.nz, c.kd,
                        bm.prop[0], bm.prop[1], bm.prop[2], bm.pol_re[0], bm.pol_im[0], bm.pol_re[1], bm.pol_im[1],
@@ -62,7 +66,17 @@ bool beam_ok(const dda_beam *b) {
         a2 += b->prop[i] * b->prop[i];
         e2 += b->pol_re[i] * b->pol_re[i] + b->pol_im[i] * b->pol_im[i];
     }
-    return std::fabs(a2 - 1) < 1e-6 && std::fabs(e2 - 1) < 1e-6;
+    if (!(std::fabs(a2 - 1) < 1e-6 && std::fabs(e2 - 1) < 1e-6)) return false;
+    if (b->w0 == 0) return true;
+    // a focused beam: finite waist and focus, polarization orthogonal to the propagation
+    if (!(std::isfinite(b->w0) && b->w0 > 0)) return false;
+    double dr = 0, di = 0;
+    for (int i = 0; i < 3; ++i) {
+        if (!std::isfinite(b->center[i])) return false;
+        dr += b->pol_re[i] * b->prop[i];
+        di += b->pol_im[i] * b->prop[i];
+    }
+    return std::fabs(dr) < 1e-6 && std::fabs(di) < 1e-6;
 }
 
 }  // namespace dda

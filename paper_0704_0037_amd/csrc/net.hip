@@ -827,8 +827,9 @@ dda_status dda_net_features(dda_net *h, dda_ctx *ch, const dda_beam *beam, void 
     dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
-    if (!n || !c || !feat || !dda::beam_ok(beam) || !fits(*n, *c)) {
-        set_error("dda_net_features: NULL argument, bad beam, or particle grid larger than the network's");
+    if (!n || !c || !feat || !dda::beam_ok(beam) || beam->w0 > 0 || !fits(*n, *c)) {
+        set_error("dda_net_features: NULL argument, bad or focused beam (plane waves only), or particle grid larger "
+                  "than the network's");
         return DDA_EINVAL;
     }
     const int G = n->G, nv = G * G * G;
@@ -842,8 +843,9 @@ dda_status dda_net_target(dda_net *h, dda_ctx *ch, const dda_beam *beam, const v
     dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
-    if (!n || !c || !x || !tgt || !dda::beam_ok(beam) || !fits(*n, *c)) {
-        set_error("dda_net_target: NULL argument, bad beam, or particle grid larger than the network's");
+    if (!n || !c || !x || !tgt || !dda::beam_ok(beam) || beam->w0 > 0 || !fits(*n, *c)) {
+        set_error("dda_net_target: NULL argument, bad or focused beam (plane waves only), or particle grid larger "
+                  "than the network's");
         return DDA_EINVAL;
     }
     double br, bi;
@@ -924,8 +926,8 @@ dda_status dda_guess(dda_ctx *ch, dda_net *h, const dda_beam *beams, int32_t n_r
         return DDA_EINVAL;
     }
     for (int r = 0; r < n_rhs; ++r)
-        if (!dda::beam_ok(&beams[r])) {
-            set_error("dda_guess: beam without unit vectors");
+        if (!dda::beam_ok(&beams[r]) || beams[r].w0 > 0) {
+            set_error("dda_guess: beam without unit vectors, or a focused beam (plane waves only)");
             return DDA_EINVAL;
         }
     dda_status st = forward(*n, (const bf16 *)feat, n_rhs);

@@ -16,6 +16,8 @@
 namespace dda {
 
 bool beam_ok(const dda_beam *b);
+template <typename R> dda_status beam_field_launch(Ctx &c, const dda_beam &b, cplx<R> *out, double sr, double si,
+                                                   hipStream_t st);
 void beta_of(const Ctx &c, const dda_beam &bm, double &br, double &bi);
 
 constexpr int kRoThreads = 256;
@@ -24,7 +26,8 @@ constexpr int kRoThreads = 256;
 __global__ void __launch_bounds__(kRoThreads) k_xsec(const double2 *__restrict__ x, const int *__restrict__ lin, int N,
                                                      int nx, int ny, int nz, double k, double a0, double a1, double a2,
                                                      double e0r, double e0i, double e1r, double e1i, double e2r,
-                                                     double e2i, double2 *part) {
+                                                     double e2i, const double2 *__restrict__ einc,
+                                                     double2 *part) {
     __shared__ double2 sh[2 * kRoThreads];
     double2 ex = make_double2(0, 0);  // sum conj(E).x  (complex)
     double xx = 0;
@@ -33,14 +36,21 @@ __global__ void __launch_bounds__(kRoThreads) k_xsec(const double2 *__restrict__
         const double px = (l % nx) + 0.5 - 0.5 * nx;
         const double py = ((l / nx) % ny) + 0.5 - 0.5 * ny;
         const double pz = (l / (nx * ny)) + 0.5 - 0.5 * nz;
-        double sn, cs;
-        sincos(k * (a0 * px + a1 * py + a2 * pz), &sn, &cs);
-        // conj(E_c) = conj(e_c) exp(-i phase)
+        double sn = 0, cs = 1;
+        if (!einc) sincos(k * (a0 * px + a1 * py + a2 * pz), &sn, &cs);
+        // conj(E_c) = conj(e_c) exp(-i phase), or conj(einc[c][i]) for a focused beam
         const double er[3] = {e0r, e1r, e2r}, ei[3] = {e0i, e1i, e2i};
         for (int c = 0; c < 3; ++c) {
             const double2 v = x[(size_t)c * N + i];
-            const double ur = er[c] * cs + ei[c] * sn;   // Re(conj(e) exp(-i ph))
-            const double ui = -er[c] * sn + ei[c] * cs;  // Im
+            double ur, ui;
+            if (einc) {
+                const double2 e = einc[(size_t)c * N + i];
+                ur = e.x;
+                ui = -e.y;
+            } else {
+                ur = er[c] * cs + ei[c] * sn;   // Re(conj(e) exp(-i ph))
+                ui = -er[c] * sn + ei[c] * cs;  // Im
+            }
             ex.x += ur * v.x - ui * v.y;
             ex.y += ur * v.y + ui * v.x;
             xx += v.x * v.x + v.y * v.y;
@@ -226,7 +236,7 @@ static void finish_farfield(const Ctx &c, const dda_beam &bm, int ndir, const do
 
 // Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_n, evaluated by the
 // three-term recurrence, from the usual cosine first guesses
-static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
     x.assign(n, 0.0);
     w.assign(n, 0.0);
     for (int i = 0; i < n; ++i) {
@@ -287,10 +297,23 @@ dda_status dda_cross_sections(dda_ctx *h, const dda_beam *beam, const void *x, d
     dda_status st;
     if ((st = ensure_red(*c, 2 * (size_t)nb)) != DDA_OK) return st;
     const dda_beam &b = *beam;
+    void *einc = nullptr;  // a focused beam's field at the dipoles
+    if (b.w0 > 0) {
+        if ((st = device_alloc(&einc, 3 * (size_t)c->N * sizeof(double2))) != DDA_OK) return st;
+        if ((st = beam_field_launch<double>(*c, b, (double2 *)einc, 1.0, 0.0, c->stream)) != DDA_OK) {
+            (void)hipFree(einc);
+            return st;
+        }
+    }
     hipLaunchKernelGGL(k_xsec, dim3(nb), dim3(kRoThreads), 0, c->stream, (const double2 *)x, c->lin, (int)c->N, c->nx,
                        c->ny, c->nz, c->kd, b.prop[0], b.prop[1], b.prop[2], b.pol_re[0], b.pol_im[0], b.pol_re[1],
-                       b.pol_im[1], b.pol_re[2], b.pol_im[2], c->red);
-    DDA_HIP_CHECK(hipGetLastError());
+                       b.pol_im[1], b.pol_re[2], b.pol_im[2], (const double2 *)einc, c->red);
+    const hipError_t le = hipGetLastError();
+    if (einc) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(einc);
+    }
+    DDA_HIP_CHECK(le);
     std::vector<double2> p(2 * (size_t)nb);
     DDA_HIP_CHECK(hipMemcpyAsync(p.data(), c->red, p.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
     DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -392,6 +415,10 @@ dda_status dda_mueller(dda_ctx *h, const dda_beam *beam, const void *x1, const v
     Ctx *c = cx(h);
     if (!c || !x1 || !theta || !M || n_theta < 1 || !beam_ok(beam)) {
         set_error("dda_mueller: NULL argument, n_theta < 1 or beam without unit vectors");
+        return DDA_EINVAL;
+    }
+    if (!x2 && beam->w0 > 0) {
+        set_error("dda_mueller: the one-polarization shortcut (x2 = NULL) takes plane waves only");
         return DDA_EINVAL;
     }
     const dda_beam &b = *beam;

@@ -23,7 +23,8 @@ BREAKDOWN_REPORT, BREAKDOWN_RECOVER = 0, 1
 
 
 class Beam(ct.Structure):
-    _fields_ = [("prop", ct.c_double * 3), ("pol_re", ct.c_double * 3), ("pol_im", ct.c_double * 3)]
+    _fields_ = [("prop", ct.c_double * 3), ("pol_re", ct.c_double * 3), ("pol_im", ct.c_double * 3),
+                ("w0", ct.c_double), ("center", ct.c_double * 3)]
 
 
 class SetupOpts(ct.Structure):
@@ -130,13 +131,16 @@ def _check(status, what):
         raise DDAError(status, f"{what}: {msg}")
 
 
-def make_beam(prop=(0.0, 0.0, 1.0), pol=(1.0, 0.0, 0.0)):
+def make_beam(prop=(0.0, 0.0, 1.0), pol=(1.0, 0.0, 0.0), w0=0.0, center=(0.0, 0.0, 0.0)):
+    """dda_beam: a plane wave (w0 = 0) or a focused beam of waist radius w0 at center."""
     b = Beam()
     pol = [complex(p) for p in pol]
     for i in range(3):
         b.prop[i] = float(prop[i])
         b.pol_re[i] = pol[i].real
         b.pol_im[i] = pol[i].imag
+        b.center[i] = float(center[i])
+    b.w0 = float(w0)
     return b
 
 
@@ -144,7 +148,7 @@ def _beam(obj):
     if isinstance(obj, Beam):
         return obj
     if hasattr(obj, "prop") and hasattr(obj, "pol"):
-        return make_beam(obj.prop, obj.pol)
+        return make_beam(obj.prop, obj.pol, getattr(obj, "w0", 0.0), getattr(obj, "center", (0.0, 0.0, 0.0)))
     prop, pol = obj
     return make_beam(prop, pol)
 

@@ -93,15 +93,18 @@ def zyz_matrix(alpha, beta, gamma):
 
 @dataclass
 class Beam:
-    """Plane wave in the particle frame: unit propagation vector and complex unit polarization."""
+    """Incident beam in the particle frame: unit propagation vector and complex unit polarization;
+    w0 > 0 makes it a focused beam of waist radius w0 (units of d) focused at center."""
     prop: tuple = (0.0, 0.0, 1.0)
     pol: tuple = (1.0 + 0j, 0j, 0j)
+    w0: float = 0.0
+    center: tuple = (0.0, 0.0, 0.0)
 
     def second(self):
         """The orthogonal polarization prop x pol (used for the second incident polarization)."""
         a = np.asarray(self.prop, dtype=np.float64)
         e = np.asarray(self.pol, dtype=np.complex128)
-        return Beam(tuple(a), tuple(np.cross(a, e)))
+        return Beam(tuple(a), tuple(np.cross(a, e)), self.w0, self.center)
 
 
 X_POL = Beam((0.0, 0.0, 1.0), (1.0 + 0j, 0j, 0j))

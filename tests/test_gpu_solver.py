@@ -384,6 +384,35 @@ def test_orientation_averaged_mueller_matches_oracle():
     assert np.max(np.abs(err - rerr)) < 1e-9 * scale
 
 
+@pytest.mark.parametrize("circular", [False, True])
+def test_focused_beam_rhs_solution_and_cext_match_oracle(circular):
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((8, 7, 6), (4, 3.5, 3))
+    m, kd = 1.3 + 0.05j, 0.6
+    prop = np.array([0.6, 0.0, 0.8])
+    pol = np.array([0.8, 0.0, -0.6], complex)
+    if circular:
+        pol = (pol + 1j * np.array([0.0, 1.0, 0.0])) / math.sqrt(2.0)
+    w0, center = 3.0 / kd, (1.0, -0.5, 0.5)  # k w0 = 3: a tightly focused beam, off the particle's centre
+    beam = inputs.Beam(tuple(prop), tuple(pol), w0, center)
+    pos, _ = odda.dipoles(mask)
+    alpha = odda.alpha_ldr(m, kd, prop, pol)
+    bt = odda.beta_of_alpha(alpha)
+    b_ref = odda.rhs(pos, kd, bt, prop, pol, w0, center)
+    x_ref = np.linalg.solve(odda.interaction_matrix(pos, kd, bt), b_ref.reshape(-1)).reshape(b_ref.shape)
+    cext, cabs = odda.cross_sections(pos, kd, alpha, bt * x_ref, prop, pol, w0, center)
+    with dda.Context(mask, m, kd) as ctx:
+        b = ctx.rhs(beam).cpu().numpy()  # [3][N]
+        assert np.max(np.abs(b.T - b_ref)) < 1e-12 * np.max(np.abs(b_ref))
+        x, info, st = ctx.solve([beam], tol=1e-11)
+        assert st == 0
+        got = ctx.cross_sections(beam, x[0].contiguous())
+        with pytest.raises(dda.DDAError):
+            ctx.mueller(beam, x[0].contiguous(), None, 0.0, [0.5])
+    assert abs(got[0] - cext) < 1e-8 * abs(cext) and abs(got[1] - cabs) < 1e-8 * abs(cext)
+    assert np.max(np.abs(x[0].cpu().numpy().T - x_ref)) < 1e-8 * np.max(np.abs(x_ref))
+
+
 def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
     dda = _dda()
     mask = inputs.ellipsoid_mask((10, 8, 6), (5, 4, 3))
