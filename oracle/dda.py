@@ -94,6 +94,26 @@ def beta_of_alpha(alpha):
     return np.sqrt(complex(alpha))
 
 
+def material_alphas(mask, ms, k, prop, pol, polarizability="ldr"):
+    """Polarizability of every dipole of an inhomogeneous particle: mask values 1..len(ms) name
+    the material of each non-void cell, ms their refractive indices (eq. 1 allows a different
+    alpha_i at every dipole; the symmetrized system of eqs. 2-3 then has beta_i = sqrt(alpha_i)).
+    Returns (N,) complex in the dipoles' order.
+    pinned by: eq. 1 solved directly agrees with the symmetrized system; equal indices give the
+    homogeneous particle; a material with m = 1 (alpha = 0 under CM) acts as void cells."""
+    _, lin = dipoles(mask)
+    mat = np.asarray(mask).reshape(-1)[lin].astype(int) - 1
+    per = []
+    for m in ms:
+        if polarizability == "cm":
+            per.append(alpha_cm(m))
+        elif polarizability == "rr":
+            per.append(alpha_rr(m, k))
+        else:
+            per.append(alpha_ldr(m, k, prop, pol))
+    return np.asarray(per, dtype=np.complex128)[mat]
+
+
 # ---------------------------------------------------------------------- Green's tensor
 def green(r, k):
     """Free-space Green's tensor G(r) of eq. (1): the field at r of a unit dipole at 0.

@@ -443,3 +443,56 @@ def test_gaussian_beam_quadrature_is_converged():
     big = np.vstack([pts, [[0.5 + 40.0, 0.5, 0.0]]])
     E2 = dda.gaussian_beam_field(big, k, (0.6, 0.0, 0.8), (0.8, 0.0, -0.6), w0, (0.5, 0.5, 0.0))[:-1]
     assert np.max(np.abs(E - E2)) < 1e-12
+
+
+# ------------------------------------------------------------------ inhomogeneous particles
+def _two_material_mask():
+    mask = np.zeros((3, 3, 4), np.uint8)
+    mask[:, :, :2] = 1
+    mask[:, :, 2:] = 2
+    mask[0, 0, 3] = 0
+    return mask
+
+
+def test_inhomogeneous_symmetrized_system_equals_equation_1():
+    # eq. 1 with a different alpha per dipole, solved directly for P, against the symmetrized
+    # eqs. 2-3 (A = I - beta G beta, b = beta E, P = beta x)
+    mask = _two_material_mask()
+    pos, _ = dda.dipoles(mask)
+    k, prop, pol = 0.7, np.array([0.0, 0.6, 0.8]), np.array([1.0, 0.0, 0.0])
+    alpha = dda.material_alphas(mask, [1.5 + 0.1j, 1.2 + 0.3j], k, prop, pol)
+    N = len(pos)
+    M = np.zeros((N, 3, N, 3), complex)
+    for i in range(N):
+        for j in range(N):
+            if i == j:
+                M[i, :, i, :] = np.eye(3) / alpha[i]
+            else:
+                M[i, :, j, :] = -dda.green(pos[i] - pos[j], k)
+    E = dda.incident_field(pos, k, prop, pol)
+    P1 = np.linalg.solve(M.reshape(3 * N, 3 * N), E.reshape(-1)).reshape(N, 3)
+    bt = np.sqrt(alpha)
+    A = dda.interaction_matrix(pos, k, bt)
+    assert np.max(np.abs(A - A.T)) == 0.0
+    x = np.linalg.solve(A, dda.rhs(pos, k, bt, prop, pol).reshape(-1)).reshape(N, 3)
+    assert np.max(np.abs(bt[:, None] * x - P1)) < 1e-12 * np.max(np.abs(P1))
+
+
+def test_inhomogeneous_reduces_to_homogeneous_and_to_void():
+    mask = _two_material_mask()
+    pos, lin = dda.dipoles(mask)
+    k, prop, pol = 0.7, np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0])
+    a2 = dda.material_alphas(mask, [1.4 + 0.05j, 1.4 + 0.05j], k, prop, pol)
+    assert np.all(a2 == dda.alpha_ldr(1.4 + 0.05j, k, prop, pol))
+    # CM with m = 1 for material 2: those dipoles have alpha = 0 and the particle is material 1 alone
+    a = dda.material_alphas(mask, [1.5 + 0.1j, 1.0], k, prop, pol, polarizability="cm")
+    bt = np.sqrt(a)
+    x = np.linalg.solve(dda.interaction_matrix(pos, k, bt), dda.rhs(pos, k, bt, prop, pol).reshape(-1))
+    cext, cabs = dda.cross_sections(pos, k, np.where(a == 0, 1.0, a), bt[:, None] * x.reshape(-1, 3), prop, pol)
+    only = np.where(mask == 1, 1, 0).astype(np.uint8)
+    p1, _ = dda.dipoles(only)
+    a1 = dda.alpha_cm(1.5 + 0.1j)
+    b1 = np.sqrt(a1)
+    x1 = np.linalg.solve(dda.interaction_matrix(p1, k, b1), dda.rhs(p1, k, b1, prop, pol).reshape(-1))
+    c1, d1 = dda.cross_sections(p1, k, a1, b1 * x1.reshape(-1, 3), prop, pol)
+    assert abs(cext - c1) < 1e-12 * abs(c1) and abs(cabs - d1) < 1e-12 * abs(c1)
