@@ -166,6 +166,21 @@ typedef struct {
 dda_status dda_setup(dda_ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2],
                      double kd, int32_t polarizability, const dda_setup_opts *opts, void *stream);
 
+/*
+ * dda_setup_materials — dda_setup for an inhomogeneous particle (eq. 1 takes a polarizability
+ * per dipole; the symmetrized system of eqs. 2-3 then has beta_i = sqrt(alpha_i) per dipole):
+ * mask values 1..n_mat name each cell's material, m holds {Re m, Im m} of each material
+ * ([n_mat][2]); every polarizability prescription applies per material.  n_mat = 1 is dda_setup.
+ * With n_mat > 1 the product runs the homogeneous kernels with unit polarizability between a
+ * scaling of the vector by each dipole's beta and back (five extra vector passes); solves run in
+ * DDA_FP64 only (opts->fp32 is refused with DDA_ENOTSUP), the read-out uses P = beta x and Cabs
+ * per material; dda_mueller needs both polarizations, and the learned guess refuses the context.
+ * Errors: as dda_setup; DDA_EINVAL for n_mat outside 1..255 or a mask value above n_mat.
+ */
+dda_status dda_setup_materials(dda_ctx **out, const int32_t grid[3], const uint8_t *mask, int32_t n_mat,
+                               const double *m, double kd, int32_t polarizability, const dda_setup_opts *opts,
+                               void *stream);
+
 /* Release the context and all device memory it owns.  NULL is accepted. */
 dda_status dda_free(dda_ctx *ctx);
 

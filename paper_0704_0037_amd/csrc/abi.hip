@@ -43,11 +43,29 @@ void beta_of(const Ctx &c, const dda_beam &bm, double &br, double &bi) {
 
 template <typename R> dda_status beam_field_launch(Ctx &c, const dda_beam &b, cplx<R> *out, double sr, double si,
                                                    hipStream_t st);
+template <typename R> static dda_status rhs_plane(Ctx &c, const dda_beam &bm, cplx<R> *b, double br, double bi,
+                                                  hipStream_t s);
 
 template <typename R> dda_status rhs_launch(Ctx &c, const dda_beam &bm, cplx<R> *b, hipStream_t s) {
     double br, bi;
     beta_of(c, bm, br, bi);
+    if (c.nmat > 1) {
+        // beta of each dipole's material (beta_of gives 1 for an inhomogeneous particle)
+        if constexpr (!std::is_same<R, double>::value) {
+            set_error("right-hand side: an inhomogeneous particle is solved in double precision only");
+            return DDA_ENOTSUP;
+        } else {
+            dda_status st = bm.w0 > 0 ? beam_field_launch<R>(c, bm, b, 1.0, 0.0, s) : rhs_plane<R>(c, bm, b, 1.0, 0.0, s);
+            if (st != DDA_OK) return st;
+            return material_scale(c, bm, b, b, s);
+        }
+    }
     if (bm.w0 > 0) return beam_field_launch<R>(c, bm, b, br, bi, s);
+    return rhs_plane<R>(c, bm, b, br, bi, s);
+}
+
+template <typename R> static dda_status rhs_plane(Ctx &c, const dda_beam &bm, cplx<R> *b, double br, double bi,
+                                                  hipStream_t s) {
     const int N = (int)c.N;
     hipLaunchKernelGGL(k_rhs<R>, dim3((N + 255) / 256), dim3(256), 0, s, c.lin, b, N, c.nx, c.ny, c.nz, c.kd,
                        bm.prop[0], bm.prop[1], bm.prop[2], bm.pol_re[0], bm.pol_im[0], bm.pol_re[1], bm.pol_im[1],
@@ -159,6 +177,8 @@ static dda_status matvec_common(dda_ctx *h, const dda_beam *beams, int32_t n, co
         return matvec_launch<float>(*ctx, (const float2 *)x, (float2 *)y, n, ar.data(), ai.data(), false,
                                     ctx->stream);
     }
+    dda_status st = material_prepare(*ctx, beams, n);
+    if (st != DDA_OK) return st;
     return matvec_launch<double>(*ctx, (const double2 *)x, (double2 *)y, n, ar.data(), ai.data(), false, ctx->stream);
 }
 
@@ -183,6 +203,10 @@ template <typename R>
 static dda_status matvec_timed(Ctx &c, int n, const std::vector<double> &ar, const std::vector<double> &ai,
                                const cplx<R> *x, cplx<R> *y, int reps, float kernel_ms[5], float *total_ms) {
     // first call uploads the scales and settles the work buffers
+    if (c.nmat > 1) {
+        set_error("dda_matvec_timed: homogeneous particles only");
+        return DDA_ENOTSUP;
+    }
     dda_status st = matvec_launch<R>(c, x, y, n, ar.data(), ai.data(), false, c.stream);
     if (st != DDA_OK) return st;
     Work<R> &w = work_of<R>(c);

@@ -74,7 +74,28 @@ struct Ctx {
     // (resume_nrhs = 0: nothing to continue)
     int resume_nrhs = 0;
     int resume_solver = -1;
+
+    // inhomogeneous particle (dda_setup_materials, nmat > 1): mask values name the material of
+    // each cell; the product runs with unit polarizability between a scaling by beta of each
+    // dipole's material and back (the solver's per-RHS scales and beta are then 1)
+    int nmat = 1;
+    std::vector<double> mat_re, mat_im;  // refractive index of each material
+    uint8_t *dmat = nullptr;             // device [N] material of each dipole (0-based)
+    double2 *mat_beta = nullptr;         // device [rows][nmat] beta per right-hand side and material
+    int mat_beta_rows = 0;
+    double2 *xtmp = nullptr;             // device [rows][3][N] scaled vectors
+    int xtmp_rows = 0;
 };
+
+// inhomogeneous particles: beta of every material for the beams (device table, rows = n), and the
+// scaled-vector buffer for at least max(n, 2) vectors; call before a solve's graphs are captured
+dda_status material_prepare(Ctx &c, const dda_beam *beams, int n);
+// P = beta x for one vector [3][N] of a beam (P may be c.xtmp rows)
+dda_status material_scale(Ctx &c, const dda_beam &b, const double2 *x, double2 *P, hipStream_t s);
+// Cabs of the dipole polarizations P [3][N] of a beam: per material (-Im(1/alpha) - 2k^3/3) |P|^2
+dda_status material_cabs(Ctx &c, const dda_beam &b, const double2 *P, double &cabs);
+// alpha of material m (refractive index m_re + i m_im) for a beam
+void polarizability_of(const Ctx &c, const dda_beam &b, double m_re, double m_im, double &re, double &im);
 
 // the work buffers of precision R
 template <typename R> inline Work<R> &work_of(Ctx &c) {
@@ -82,7 +103,8 @@ template <typename R> inline Work<R> &work_of(Ctx &c) {
     else return c.w32;
 }
 
-// alpha of the context's material for a beam (LDR depends on the beam)
+// alpha of the context's material for a beam (LDR depends on the beam); 1 for an inhomogeneous
+// particle, whose polarizabilities enter through material_prepare / material_scale
 void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im);
 
 // Matvec on nrhs vectors: y = A x; alphas [nrhs] host complex; optionally leaves per-block

@@ -297,6 +297,10 @@ dda_status dda_cross_sections(dda_ctx *h, const dda_beam *beam, const void *x, d
     dda_status st;
     if ((st = ensure_red(*c, 2 * (size_t)nb)) != DDA_OK) return st;
     const dda_beam &b = *beam;
+    if (c->nmat > 1) {  // the polarizations P = beta x of the materials take the place of x (beta_of gives 1)
+        if ((st = material_scale(*c, b, (const double2 *)x, c->xtmp, c->stream)) != DDA_OK) return st;
+        x = c->xtmp;
+    }
     void *einc = nullptr;  // a focused beam's field at the dipoles
     if (b.w0 > 0) {
         if ((st = device_alloc(&einc, 3 * (size_t)c->N * sizeof(double2))) != DDA_OK) return st;
@@ -332,7 +336,8 @@ dda_status dda_cross_sections(dda_ctx *h, const dda_beam *beam, const void *x, d
     const double cext = 4.0 * M_PI * k * im_ep;
     const double inv_im = -ai / (ar * ar + ai * ai);  // Im(1/alpha)
     const double w = -inv_im - (2.0 / 3.0) * k * k * k;
-    const double cabs = 4.0 * M_PI * k * w * (br * br + bi * bi) * xx;
+    double cabs = 4.0 * M_PI * k * w * (br * br + bi * bi) * xx;
+    if (c->nmat > 1 && (st = material_cabs(*c, b, (const double2 *)x, cabs)) != DDA_OK) return st;
     out[0] = cext;
     out[1] = cabs;
     out[2] = cext - cabs;
@@ -347,8 +352,13 @@ dda_status dda_farfield(dda_ctx *h, const dda_beam *beam, const void *x, int32_t
         set_error("dda_farfield: NULL argument, n_dir < 1 or beam without unit vectors");
         return DDA_EINVAL;
     }
+    dda_status st;
+    if (c->nmat > 1) {
+        if ((st = material_scale(*c, *beam, (const double2 *)x, c->xtmp, c->stream)) != DDA_OK) return st;
+        x = c->xtmp;
+    }
     std::vector<double2> S;
-    dda_status st = farfield_sums(*c, (const double2 *)x, n_dir, dirs, S);
+    st = farfield_sums(*c, (const double2 *)x, n_dir, dirs, S);
     if (st != DDA_OK) return st;
     finish_farfield(*c, *beam, n_dir, dirs, S, F);
     return DDA_OK;
@@ -370,6 +380,11 @@ dda_status dda_asymmetry(dda_ctx *h, const dda_beam *beam, const void *x, int32_
     if (!c || !x || !out || n_theta < 1 || n_phi < 1 || (int64_t)n_theta * n_phi > (1 << 22) || !beam_ok(beam)) {
         set_error("dda_asymmetry: NULL argument, grid sizes outside 1..2^22 directions or beam without unit vectors");
         return DDA_EINVAL;
+    }
+    if (c->nmat > 1) {
+        const dda_status sc = material_scale(*c, *beam, (const double2 *)x, c->xtmp, c->stream);
+        if (sc != DDA_OK) return sc;
+        x = c->xtmp;
     }
     // directions n = mu a + sqrt(1 - mu^2) (cos phi e1 + sin phi e2) about the propagation a
     const double *a = beam->prop;
@@ -417,8 +432,9 @@ dda_status dda_mueller(dda_ctx *h, const dda_beam *beam, const void *x1, const v
         set_error("dda_mueller: NULL argument, n_theta < 1 or beam without unit vectors");
         return DDA_EINVAL;
     }
-    if (!x2 && beam->w0 > 0) {
-        set_error("dda_mueller: the one-polarization shortcut (x2 = NULL) takes plane waves only");
+    if (!x2 && (beam->w0 > 0 || c->nmat > 1)) {
+        set_error("dda_mueller: the one-polarization shortcut (x2 = NULL) takes plane waves on homogeneous particles "
+                  "only");
         return DDA_EINVAL;
     }
     const dda_beam &b = *beam;
@@ -448,6 +464,15 @@ dda_status dda_mueller(dda_ctx *h, const dda_beam *beam, const void *x1, const v
     }
     std::vector<double> F1(6 * (size_t)n_theta), F2(6 * (size_t)n_theta);
     dda_status st;
+    if (c->nmat > 1) {  // P = beta x of each polarization (the second beam has polarization e2)
+        dda_beam bb = b;
+        for (int a = 0; a < 3; ++a) bb.pol_re[a] = e2[a];
+        double2 *P1 = c->xtmp, *P2 = c->xtmp + 3 * (size_t)c->N;
+        if ((st = material_scale(*c, b, (const double2 *)x1, P1, c->stream)) != DDA_OK) return st;
+        if ((st = material_scale(*c, bb, (const double2 *)x2, P2, c->stream)) != DDA_OK) return st;
+        x1 = P1;
+        x2 = P2;
+    }
     std::vector<double2> S;
     if ((st = farfield_sums(*c, (const double2 *)x1, n_theta, n.data(), S)) != DDA_OK) return st;
     finish_farfield(*c, b, n_theta, n.data(), S, F1.data());

@@ -189,8 +189,16 @@ void launch_to_f32(const double2 *a, float2 *b, size_t n, hipStream_t s) {
 }
 
 void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
+    if (c.nmat > 1) {
+        re = 1.0;
+        im = 0.0;
+        return;
+    }
+    polarizability_of(c, b, c.m_re, c.m_im, re, im);
+}
+
+void polarizability_of(const Ctx &c, const dda_beam &b, double mr, double mi, double &re, double &im) {
     // Clausius-Mossotti for a unit cube: (3/4pi)(m^2-1)/(m^2+2)
-    const double mr = c.m_re, mi = c.m_im;
     const double m2r = mr * mr - mi * mi, m2i = 2 * mr * mi;
     const double nr = m2r - 1, ni = m2i, dr = m2r + 2, di = m2i;
     const double den = dr * dr + di * di;
@@ -286,6 +294,9 @@ void destroy(Ctx *c) {
     else (void)hipDeviceSynchronize();
     free_work(c->w64);
     free_work(c->w32);
+    (void)hipFree(c->dmat);
+    (void)hipFree(c->mat_beta);
+    (void)hipFree(c->xtmp);
     (void)hipFree(c->gmap);
     (void)hipFree(c->rows);
     (void)hipFree(c->lin);

@@ -1358,6 +1358,7 @@ static dda_status prepare_fp64(Ctx &c, Run<double> &k, const dda_beam *beams, in
     std::vector<double> ar(nrhs), ai(nrhs);
     for (int r = 0; r < nrhs; ++r) polarizability(c, beams[r], ar[r], ai[r]);
     if ((st = upload_scales<double>(c, ar, ai)) != DDA_OK) return st;
+    if ((st = material_prepare(c, beams, nrhs)) != DDA_OK) return st;
     k.c = &c;
     k.v = vecs_of<double>(c, nrhs);
     k.x = x;
@@ -1439,6 +1440,7 @@ static dda_status prepare_resume(Ctx &c, Run<double> &k, const dda_beam *beams, 
     std::vector<double> ar(nrhs), ai(nrhs);
     for (int r = 0; r < nrhs; ++r) polarizability(c, beams[r], ar[r], ai[r]);
     if ((st = upload_scales<double>(c, ar, ai)) != DDA_OK) return st;
+    if ((st = material_prepare(c, beams, nrhs)) != DDA_OK) return st;
     k.c = &c;
     k.v = vecs_of<double>(c, nrhs);
     k.x = x;
@@ -1875,6 +1877,10 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
     dda_solve_opts o;
     dda_status st = check_opts(opts, o);
     if (st != DDA_OK) return st;
+    if (c->nmat > 1 && o.precision != DDA_FP64) {
+        set_error("dda_solve: an inhomogeneous particle is solved in DDA_FP64 only");
+        return DDA_ENOTSUP;
+    }
     int check;
     bool graph;
     cadence(*c, n_rhs, o, check, graph);

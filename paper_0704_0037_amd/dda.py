@@ -67,6 +67,9 @@ _SIGS = {
     "dda_checkpoint_load": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_char_p]),
     "dda_orientation_average": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_double, ct.c_void_p,
                                            ct.POINTER(ct.c_double)]),
+    "dda_setup_materials": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.POINTER(ct.c_int32), ct.c_void_p, ct.c_int32,
+                                       ct.POINTER(ct.c_double), ct.c_double, ct.c_int32, ct.POINTER(SetupOpts),
+                                       ct.c_void_p]),
     "dda_orientation_average_mueller": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double,
                                                    ct.c_void_p, ct.POINTER(ct.c_double), ct.c_int32,
                                                    ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]),
@@ -184,7 +187,8 @@ class Context:
         nz, ny, nx = mask.shape
         self.grid = (nx, ny, nz)
         grid = (ct.c_int32 * 3)(nx, ny, nz)
-        mm = (ct.c_double * 2)(complex(m).real, complex(m).imag)
+        ms = [complex(v) for v in m] if isinstance(m, (list, tuple, np.ndarray)) else [complex(m)]
+        mm = (ct.c_double * (2 * len(ms)))(*[p for v in ms for p in (v.real, v.imag)])
         opts = SetupOpts()
         if pad is not None:
             for i in range(3):
@@ -195,8 +199,13 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = ct.c_void_p()
-        _check(L.dda_setup(ct.byref(h), grid, mask.ctypes.data_as(ct.c_void_p), mm, float(kd), int(polarizability),
-                           ct.byref(opts), ct.c_void_p(stream.cuda_stream)), "dda_setup")
+        if len(ms) == 1:
+            _check(L.dda_setup(ct.byref(h), grid, mask.ctypes.data_as(ct.c_void_p), mm, float(kd),
+                               int(polarizability), ct.byref(opts), ct.c_void_p(stream.cuda_stream)), "dda_setup")
+        else:  # an inhomogeneous particle: mask values 1..len(m) name the materials
+            _check(L.dda_setup_materials(ct.byref(h), grid, mask.ctypes.data_as(ct.c_void_p), len(ms), mm, float(kd),
+                                         int(polarizability), ct.byref(opts), ct.c_void_p(stream.cuda_stream)),
+                   "dda_setup_materials")
         self._h = h
         self.n = int(L.dda_num_dipoles(h))
         self.device = torch.device("cuda", torch.cuda.current_device())

@@ -413,6 +413,55 @@ def test_focused_beam_rhs_solution_and_cext_match_oracle(circular):
     assert np.max(np.abs(x[0].cpu().numpy().T - x_ref)) < 1e-8 * np.max(np.abs(x_ref))
 
 
+def test_inhomogeneous_particle_matches_oracle():
+    # two materials: product, right-hand side, a batched solve of both polarizations, cross
+    # sections and the Mueller matrix against the oracle's per-dipole polarizabilities
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((8, 7, 6), (4, 3.5, 3)).astype(np.uint8)
+    mask[:, :, 4:] *= 2  # the half x >= 4 is material 2
+    ms, kd = [1.5 + 0.1j, 1.2 + 0.02j], 0.6
+    prop = np.array([0.0, 0.6, 0.8])
+    pol1 = np.array([1.0, 0.0, 0.0])
+    pol2 = np.cross(prop, pol1)
+    pos, _ = odda.dipoles(mask)
+    N = len(pos)
+    ref = []
+    for pol in (pol1, pol2):
+        alpha = odda.material_alphas(mask, ms, kd, prop, pol)
+        bt = np.sqrt(alpha)
+        A = odda.interaction_matrix(pos, kd, bt)
+        b = odda.rhs(pos, kd, bt, prop, pol)
+        x = np.linalg.solve(A, b.reshape(-1)).reshape(N, 3)
+        ref.append((A, b, x, bt[:, None] * x, odda.cross_sections(pos, kd, alpha, bt[:, None] * x, prop, pol)))
+    th = np.linspace(0.0, math.pi, 7)
+    M_ref = odda.mueller(pos, kd, prop, pol1, ref[0][3], ref[1][3], th, 0.4)
+    beams = [inputs.Beam(tuple(prop), tuple(pol1 + 0j)), inputs.Beam(tuple(prop), tuple(pol2 + 0j))]
+    rng = np.random.default_rng(3)
+    xr = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+    with dda.Context(mask, ms, kd) as ctx:
+        y = ctx.matvec(beams[0], torch.from_numpy(np.ascontiguousarray(xr.T)).cuda()).cpu().numpy().T
+        y_ref = (ref[0][0] @ xr.reshape(-1)).reshape(N, 3)
+        assert np.max(np.abs(y - y_ref)) < 1e-12 * np.max(np.abs(y_ref))
+        b = ctx.rhs(beams[0]).cpu().numpy().T
+        assert np.max(np.abs(b - ref[0][1])) < 1e-13 * np.max(np.abs(ref[0][1]))
+        x, info, st = ctx.solve(beams, tol=1e-11)
+        assert st == 0
+        for r in range(2):
+            xs = x[r].cpu().numpy().T
+            assert np.max(np.abs(xs - ref[r][2])) < 1e-8 * np.max(np.abs(ref[r][2]))
+            cext, cabs, _ = ctx.cross_sections(beams[r], x[r].contiguous())
+            assert abs(cext - ref[r][4][0]) < 1e-8 * abs(ref[r][4][0])
+            assert abs(cabs - ref[r][4][1]) < 1e-8 * abs(ref[r][4][0])
+        M = ctx.mueller(beams[0], x[0].contiguous(), x[1].contiguous(), 0.4, th)
+        assert np.max(np.abs(M - M_ref)) < 1e-8 * np.max(np.abs(M_ref))
+        with pytest.raises(dda.DDAError):
+            ctx.solve(beams, precision=dda.FP32_REFINE)
+        with pytest.raises(dda.DDAError):
+            ctx.mueller(beams[0], x[0].contiguous(), None, 0.0, th)
+    with pytest.raises(dda.DDAError):
+        dda.Context(mask, ms, kd, fp32=True)
+
+
 def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
     dda = _dda()
     mask = inputs.ellipsoid_mask((10, 8, 6), (5, 4, 3))
