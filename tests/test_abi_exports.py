@@ -95,3 +95,28 @@ def test_last_error_describes_the_latest_call_only():
     assert b"dda_padded_grid" in lib.dda_last_error()
     assert lib.dda_free(None) == 0
     assert lib.dda_last_error() == b""
+
+
+def test_newer_entry_points_check_arguments_without_a_gpu():
+    # every check below fails before any device call
+    _ensure_built()
+    from paper_0704_0037_amd import dda
+    L = dda.lib()
+    L.dda_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    grid = (ctypes.c_int32 * 3)(2, 2, 2)
+    m = (ctypes.c_double * 4)(1.5, 0.0, 1.2, 0.0)
+    mask = (ctypes.c_uint8 * 8)(1, 2, 3, 0, 1, 1, 2, 2)  # value 3 names no material
+    assert L.dda_setup_materials(ctypes.byref(h), grid, mask, 2, m, 0.4, 0, None, None) == dda.EINVAL
+    assert h.value is None and b"n_mat" in L.dda_last_error()
+    assert L.dda_setup_materials(ctypes.byref(h), grid, None, 2, m, 0.4, 0, None, None) == dda.EINVAL
+    assert L.dda_setup_materials(ctypes.byref(h), grid, mask, 0, m, 0.4, 0, None, None) == dda.EINVAL
+    out = (ctypes.c_double * 5)()
+    n = ctypes.c_int32()
+    assert L.dda_orientation_average_adaptive(None, 1e-3, 2, 4, 2, 1e-5, None, out, ctypes.byref(n)) == dda.EINVAL
+    th = (ctypes.c_double * 1)(0.5)
+    M = (ctypes.c_double * 16)()
+    assert L.dda_orientation_average_mueller(None, 2, 2, 4, 1e-5, None, th, 1, M, None) == dda.EINVAL
+    assert L.dda_checkpoint_save(None, None, b"/nonexistent/ckpt") == dda.EINVAL
+    assert L.dda_checkpoint_load(None, None, b"/nonexistent/ckpt") == dda.EINVAL
+    assert b"dda_checkpoint_load" in L.dda_last_error()
