@@ -462,6 +462,34 @@ def test_inhomogeneous_particle_matches_oracle():
         dda.Context(mask, ms, kd, fp32=True)
 
 
+def test_inhomogeneous_particle_with_a_focused_beam_and_resume():
+    # the extensions together: two materials, a focused beam, a solve stopped at its limit and
+    # continued bitwise, and the cross sections against the oracle
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((8, 7, 6), (4, 3.5, 3)).astype(np.uint8)
+    mask[3:, :, :] *= 2
+    ms, kd = [1.4 + 0.05j, 1.1 + 0.2j], 0.6
+    prop, pol = np.array([0.0, 0.0, 1.0]), np.array([0.0, 1.0, 0.0])
+    w0, center = 4.0 / kd, (0.5, 0.0, -1.0)
+    pos, _ = odda.dipoles(mask)
+    alpha = odda.material_alphas(mask, ms, kd, prop, pol)
+    bt = np.sqrt(alpha)
+    b = odda.rhs(pos, kd, bt, prop, pol, w0, center)
+    x_ref = np.linalg.solve(odda.interaction_matrix(pos, kd, bt), b.reshape(-1)).reshape(-1, 3)
+    cext, cabs = odda.cross_sections(pos, kd, alpha, bt[:, None] * x_ref, prop, pol, w0, center)
+    beam = inputs.Beam(tuple(prop), tuple(pol + 0j), w0, center)
+    kw = dict(tol=1e-11, check_every=3, graph=-1)
+    with dda.Context(mask, ms, kd) as ctx:
+        xf, inf, st = ctx.solve([beam], **kw)
+        assert st == 0
+        got = ctx.cross_sections(beam, xf[0].contiguous())
+        assert abs(got[0] - cext) < 1e-8 * abs(cext) and abs(got[1] - cabs) < 1e-8 * abs(cext)
+        x, _, st = ctx.solve([beam], maxit=5, raise_on_fail=False, **kw)
+        assert st == dda.ENOTCONV
+        x2, i2, st = ctx.solve([beam], x_out=x, resume=True, **kw)
+        assert st == 0 and torch.equal(x2, xf) and i2[0]["iters"] == inf[0]["iters"]
+
+
 def test_asymmetry_matches_oracle_quadrature_and_optical_theorem():
     dda = _dda()
     mask = inputs.ellipsoid_mask((10, 8, 6), (5, 4, 3))
