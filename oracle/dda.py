@@ -89,6 +89,20 @@ def alpha_ldr(m, k, prop, pol):
     return 1.0 / inv
 
 
+def alpha_cldr(m, k, prop):
+    """CLDR polarizability (Gutkowicz-Krusin & Draine 2004; one of the prescriptions the paper
+    lists, Sec. 2), a diagonal tensor that depends on the propagation direction a only:
+    1/alpha_jj = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 a_j^2) k^2 - (2/3) i k^3, j = x, y, z.
+    Returns the three diagonal elements.
+    pinned by: the CM limit as k -> 0; for a and the polarization e along lattice axes the
+    element along e equals LDR's (a_e = 0 and S = 0); Im(1/alpha_jj) = -(2/3) k^3 for real m.
+    The form and the b coefficients: parity unpinned (the paper names CLDR only)."""
+    m2 = complex(m) ** 2
+    a = np.asarray(prop, dtype=np.float64)
+    inv = 1.0 / alpha_cm(m) + (LDR_B1 + m2 * LDR_B2 + m2 * LDR_B3 * a * a) * k * k - (2.0 / 3.0) * 1j * k ** 3
+    return 1.0 / inv
+
+
 def beta_of_alpha(alpha):
     """beta with beta*beta = alpha (Sec. 2, text before eq. 2); principal square root."""
     return np.sqrt(complex(alpha))
@@ -98,7 +112,7 @@ def material_alphas(mask, ms, k, prop, pol, polarizability="ldr"):
     """Polarizability of every dipole of an inhomogeneous particle: mask values 1..len(ms) name
     the material of each non-void cell, ms their refractive indices (eq. 1 allows a different
     alpha_i at every dipole; the symmetrized system of eqs. 2-3 then has beta_i = sqrt(alpha_i)).
-    Returns (N,) complex in the dipoles' order.
+    Returns (N,) complex in the dipoles' order ((N, 3) diagonal elements for CLDR).
     pinned by: eq. 1 solved directly agrees with the symmetrized system; equal indices give the
     homogeneous particle; a material with m = 1 (alpha = 0 under CM) acts as void cells."""
     _, lin = dipoles(mask)
@@ -109,9 +123,11 @@ def material_alphas(mask, ms, k, prop, pol, polarizability="ldr"):
             per.append(alpha_cm(m))
         elif polarizability == "rr":
             per.append(alpha_rr(m, k))
+        elif polarizability == "cldr":
+            per.append(alpha_cldr(m, k, prop))
         else:
             per.append(alpha_ldr(m, k, prop, pol))
-    return np.asarray(per, dtype=np.complex128)[mat]
+    return np.asarray(per, dtype=np.complex128)[mat]  # (N,), or (N, 3) for the tensor CLDR
 
 
 # ---------------------------------------------------------------------- Green's tensor
@@ -142,14 +158,18 @@ def interaction_matrix(pos, k, beta):
     pinned by: A = A^T exactly; the direct sum below; numpy-FFT convolution on the lattice.
     """
     N = pos.shape[0]
-    b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
+    tensor = np.ndim(beta) == 2  # (N, 3): a diagonal polarizability tensor per dipole (CLDR)
+    b = np.asarray(beta, dtype=np.complex128) if tensor else np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
     A = np.zeros((N, 3, N, 3), dtype=np.complex128)
     for i in range(N):
         d = pos[i][None, :] - pos
         d[i] = 1.0  # placeholder, overwritten below
         G = green(d, k)
         G[i] = 0.0
-        A[i, :, :, :] = -(b[i] * b)[None, :, None] * G.transpose(1, 0, 2)
+        if tensor:  # A_ij = -diag(beta_i) G_ij diag(beta_j), the product of the betas taken first
+            A[i, :, :, :] = -(b[i][:, None, None] * b[None, :, :]) * G.transpose(1, 0, 2)
+        else:
+            A[i, :, :, :] = -(b[i] * b)[None, :, None] * G.transpose(1, 0, 2)
         A[i, :, i, :] = np.eye(3)
     return A.reshape(3 * N, 3 * N)
 
@@ -264,6 +284,8 @@ def gaussian_beam_field(pos, k, prop, pol, w0, center):
 def rhs(pos, k, beta, prop, pol, w0=0.0, center=(0.0, 0.0, 0.0)):
     """Right-hand side of eq. (3): b_i = beta_i E_inc,i."""
     N = pos.shape[0]
+    if np.ndim(beta) == 2:  # diagonal tensor per dipole
+        return np.asarray(beta, dtype=np.complex128) * incident_field(pos, k, prop, pol, w0, center)
     b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
     return b[:, None] * incident_field(pos, k, prop, pol, w0, center)
 
@@ -557,9 +579,12 @@ def cross_sections(pos, k, alpha, P, prop, pol, w0=0.0, center=(0.0, 0.0, 0.0)):
     """
     E = incident_field(pos, k, prop, pol, w0, center)
     cext = 4.0 * math.pi * k * float(np.sum(np.imag(np.conj(E) * P)))
-    inv = 1.0 / np.broadcast_to(np.asarray(alpha, dtype=np.complex128), (pos.shape[0],))
-    w = -np.imag(inv) - (2.0 / 3.0) * k ** 3
-    cabs = 4.0 * math.pi * k * float(np.sum(w[:, None] * np.abs(P) ** 2))
+    if np.ndim(alpha) == 2:  # diagonal tensor per dipole: a weight per component
+        w = -np.imag(1.0 / np.asarray(alpha, dtype=np.complex128)) - (2.0 / 3.0) * k ** 3
+    else:
+        inv = 1.0 / np.broadcast_to(np.asarray(alpha, dtype=np.complex128), (pos.shape[0],))
+        w = (-np.imag(inv) - (2.0 / 3.0) * k ** 3)[:, None]
+    cabs = 4.0 * math.pi * k * float(np.sum(w * np.abs(P) ** 2))
     return cext, cabs
 
 

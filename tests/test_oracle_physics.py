@@ -496,3 +496,39 @@ def test_inhomogeneous_reduces_to_homogeneous_and_to_void():
     x1 = np.linalg.solve(dda.interaction_matrix(p1, k, b1), dda.rhs(p1, k, b1, prop, pol).reshape(-1))
     c1, d1 = dda.cross_sections(p1, k, a1, b1 * x1.reshape(-1, 3), prop, pol)
     assert abs(cext - c1) < 1e-12 * abs(c1) and abs(cabs - d1) < 1e-12 * abs(c1)
+
+
+def test_cldr_limits_and_relation_to_ldr():
+    m = 1.5 + 0.02j
+    # k -> 0: CM
+    assert np.max(np.abs(dda.alpha_cldr(m, 1e-6, (0.0, 0.6, 0.8)) - dda.alpha_cm(m))) < 1e-10
+    # a along z, e along x: the element along e is LDR's (a_x = 0 and S = 0); the z element differs
+    a = dda.alpha_cldr(m, 0.7, (0.0, 0.0, 1.0))
+    assert abs(a[0] - dda.alpha_ldr(m, 0.7, (0, 0, 1), (1, 0, 0))) < 1e-15 and a[0] == a[1] and abs(a[2] - a[0]) > 1e-3
+    # radiative reaction for real m
+    ar = dda.alpha_cldr(1.5, 0.7, (0.6, 0.0, 0.8))
+    assert np.max(np.abs(np.imag(1.0 / ar) + (2.0 / 3.0) * 0.7 ** 3)) < 1e-12
+
+
+def test_tensor_polarizability_symmetrized_system_equals_equation_1():
+    mask = _two_material_mask()
+    pos, _ = dda.dipoles(mask)
+    k, prop, pol = 0.7, np.array([0.0, 0.6, 0.8]), np.array([1.0, 0.0, 0.0])
+    alpha = dda.material_alphas(mask, [1.5 + 0.1j, 1.2 + 0.3j], k, prop, pol, polarizability="cldr")
+    assert alpha.shape == (len(pos), 3)
+    N = len(pos)
+    M = np.zeros((N, 3, N, 3), complex)
+    for i in range(N):
+        for j in range(N):
+            M[i, :, j, :] = np.diag(1.0 / alpha[i]) if i == j else -dda.green(pos[i] - pos[j], k)
+    E = dda.incident_field(pos, k, prop, pol)
+    P1 = np.linalg.solve(M.reshape(3 * N, 3 * N), E.reshape(-1)).reshape(N, 3)
+    bt = np.sqrt(alpha)
+    A = dda.interaction_matrix(pos, k, bt)
+    assert np.max(np.abs(A - A.T)) < 1e-15 * np.max(np.abs(A))  # complex symmetric up to rounding
+    x = np.linalg.solve(A, dda.rhs(pos, k, bt, prop, pol).reshape(-1)).reshape(N, 3)
+    assert np.max(np.abs(bt * x - P1)) < 1e-12 * np.max(np.abs(P1))
+    # Cabs with a weight per component equals the sum over components of the scalar formula
+    cext, cabs = dda.cross_sections(pos, k, alpha, P1, prop, pol)
+    w = -np.imag(1.0 / alpha) - (2.0 / 3.0) * k ** 3
+    assert abs(cabs - 4 * math.pi * k * np.sum(w * np.abs(P1) ** 2)) < 1e-12 * abs(cext)
