@@ -57,10 +57,14 @@ typedef enum {
 
 /* Polarizability prescriptions (Sec. 2 lists four; LDR is the one used in Sec. 3).  For a unit
  * cube and wavenumber k: DDA_POL_CM  alpha_CM = (3/4pi)(m^2-1)/(m^2+2) (Clausius-Mossotti);
+ * DDA_POL_CLDR  a diagonal tensor (Gutkowicz-Krusin & Draine 2004), independent of the polarization:
+ *             1/alpha_jj = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 a_j^2) k^2 - (2/3) i k^3 with LDR's b;
+ *             it runs the product wrapped between per-component scalings (as dda_setup_materials),
+ *             in DDA_FP64 only;
  * DDA_POL_RR  1/alpha = 1/alpha_CM - (2/3) i k^3 (radiative-reaction correction);
  * DDA_POL_LDR 1/alpha = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 S) k^2 - (2/3) i k^3 (lattice
- * dispersion relation, S from the beam).  The corrected LDR, a diagonal tensor, is not provided. */
-enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
+ * dispersion relation, S from the beam). */
+enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2, DDA_POL_CLDR = 3 };
 
 /* Iterative solvers (Sec. 2): QMR and Bi-CG use the complex symmetry of the interaction matrix
  * (one product per iteration, bilinear form u^T v); Bi-CGSTAB takes two products per iteration
@@ -158,7 +162,7 @@ typedef struct {
  *   mask   host uint8 [nz][ny][nx]; at least one nonzero cell
  *   m      {Re m, Im m}, refractive index of the (homogeneous) material
  *   kd     wavenumber times dipole size, > 0
- *   polarizability  DDA_POL_LDR, DDA_POL_CM or DDA_POL_RR
+ *   polarizability  DDA_POL_LDR, DDA_POL_CM, DDA_POL_RR or DDA_POL_CLDR
  *   opts   NULL or settings above
  *   stream hipStream_t the context runs on (NULL = default stream)
  * Errors: DDA_EINVAL for bad arguments or an unsupported padded size, DDA_ENOMEM, DDA_EHIP.

@@ -49,7 +49,7 @@ template <typename R> static dda_status rhs_plane(Ctx &c, const dda_beam &bm, cp
 template <typename R> dda_status rhs_launch(Ctx &c, const dda_beam &bm, cplx<R> *b, hipStream_t s) {
     double br, bi;
     beta_of(c, bm, br, bi);
-    if (c.nmat > 1) {
+    if (wrapped(c)) {
         // beta of each dipole's material (beta_of gives 1 for an inhomogeneous particle)
         if constexpr (!std::is_same<R, double>::value) {
             set_error("right-hand side: an inhomogeneous particle is solved in double precision only");
@@ -106,8 +106,17 @@ extern "C" {
 dda_status dda_setup(dda_ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2], double kd,
                      int32_t polarizability, const dda_setup_opts *opts, void *stream) {
     clear_error();
+    if (polarizability == DDA_POL_CLDR && opts && opts->fp32) {
+        set_error("dda_setup: single-precision products are not available with CLDR");
+        if (out) *out = nullptr;
+        return DDA_ENOTSUP;
+    }
     Ctx *c = nullptr;
     dda_status st = setup(&c, grid, mask, m, kd, polarizability, opts, stream);
+    if (st == DDA_OK && (st = material_init(*c, 1, m)) != DDA_OK) {  // CLDR runs the wrapped product
+        destroy(c);
+        c = nullptr;
+    }
     if (out) *out = reinterpret_cast<dda_ctx *>(c);
     return st;
 }
@@ -137,6 +146,10 @@ dda_status dda_polarizability(const dda_ctx *ctx, const dda_beam *beam, double o
     if (!ctx || !out || !beam_ok(beam)) {
         set_error("dda_polarizability: NULL context/output or beam without unit vectors");
         return DDA_EINVAL;
+    }
+    if (wrapped(*cx(ctx))) {
+        set_error("dda_polarizability: the context has a polarizability per material or per component");
+        return DDA_ENOTSUP;
     }
     polarizability(*cx(ctx), *beam, out[0], out[1]);
     return DDA_OK;
@@ -203,7 +216,7 @@ template <typename R>
 static dda_status matvec_timed(Ctx &c, int n, const std::vector<double> &ar, const std::vector<double> &ai,
                                const cplx<R> *x, cplx<R> *y, int reps, float kernel_ms[5], float *total_ms) {
     // first call uploads the scales and settles the work buffers
-    if (c.nmat > 1) {
+    if (wrapped(c)) {
         set_error("dda_matvec_timed: homogeneous particles only");
         return DDA_ENOTSUP;
     }

@@ -75,17 +75,23 @@ struct Ctx {
     int resume_nrhs = 0;
     int resume_solver = -1;
 
-    // inhomogeneous particle (dda_setup_materials, nmat > 1): mask values name the material of
-    // each cell; the product runs with unit polarizability between a scaling by beta of each
-    // dipole's material and back (the solver's per-RHS scales and beta are then 1)
+    // inhomogeneous particle (dda_setup_materials, nmat > 1) or CLDR (a diagonal polarizability
+    // tensor): mask values name the material of each cell; the product runs with unit
+    // polarizability between a scaling by beta of each dipole's material and component and back
+    // (the solver's per-RHS scales and beta are then 1)
     int nmat = 1;
     std::vector<double> mat_re, mat_im;  // refractive index of each material
     uint8_t *dmat = nullptr;             // device [N] material of each dipole (0-based)
-    double2 *mat_beta = nullptr;         // device [rows][nmat] beta per right-hand side and material
+    double2 *mat_beta = nullptr;         // device [rows][nmat][3] beta per right-hand side, material, component
     int mat_beta_rows = 0;
     double2 *xtmp = nullptr;             // device [rows][3][N] scaled vectors
     int xtmp_rows = 0;
 };
+
+// whether the product runs wrapped between per-dipole scalings (several materials, or CLDR)
+inline bool wrapped(const Ctx &c) { return c.nmat > 1 || c.polarizability == DDA_POL_CLDR; }
+// set up the wrapping for a context made by setup(): n_mat refractive indices m [n_mat][2]
+dda_status material_init(Ctx &c, int n_mat, const double *m);
 
 // inhomogeneous particles: beta of every material for the beams (device table, rows = n), and the
 // scaled-vector buffer for at least max(n, 2) vectors; call before a solve's graphs are captured
@@ -96,6 +102,8 @@ dda_status material_scale(Ctx &c, const dda_beam &b, const double2 *x, double2 *
 dda_status material_cabs(Ctx &c, const dda_beam &b, const double2 *P, double &cabs);
 // alpha of material m (refractive index m_re + i m_im) for a beam
 void polarizability_of(const Ctx &c, const dda_beam &b, double m_re, double m_im, double &re, double &im);
+// component comp (0..2) of the diagonal polarizability (CLDR; the scalar alpha otherwise)
+void polarizability_comp(const Ctx &c, const dda_beam &b, double m_re, double m_im, int comp, double &re, double &im);
 
 // the work buffers of precision R
 template <typename R> inline Work<R> &work_of(Ctx &c) {

@@ -24,7 +24,7 @@ constexpr int kMatBlocks = 1024;
 
 __device__ inline double2 cm(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// xo[r] = beta[r][mat] x[r] over [3][N] per right-hand side (grid: blocks x nrhs)
+// xo[r][q][i] = beta[r][mat_i][q] x[r][q][i] per right-hand side (grid: blocks x nrhs)
 __global__ void __launch_bounds__(kMatThreads) k_mat_scale(const double2 *x, double2 *xo,  // may alias
                                                            const uint8_t *__restrict__ mat,
                                                            const double2 *__restrict__ beta, int nmat, int64_t N,
@@ -32,9 +32,9 @@ __global__ void __launch_bounds__(kMatThreads) k_mat_scale(const double2 *x, dou
     const int r = blockIdx.y;
     if (done && done[r]) return;
     const size_t n3 = 3 * (size_t)N, off = (size_t)r * n3;
-    const double2 *bt = beta + (size_t)r * nmat;
+    const double2 *bt = beta + (size_t)r * nmat * 3;
     for (size_t e = (size_t)blockIdx.x * kMatThreads + threadIdx.x; e < n3; e += (size_t)gridDim.x * kMatThreads)
-        xo[off + e] = cm(bt[mat[e % N]], x[off + e]);
+        xo[off + e] = cm(bt[3 * mat[e % N] + e / N], x[off + e]);
 }
 
 // y = x - beta (xs - y) in place of y, and per-block bilinear partials x^T y into dots[r][0..ndots)
@@ -48,11 +48,11 @@ __global__ void __launch_bounds__(kMatThreads) k_mat_post(const double2 *__restr
     const int r = blockIdx.y;
     if (done && done[r]) return;
     const size_t n3 = 3 * (size_t)N, off = (size_t)r * n3;
-    const double2 *bt = beta + (size_t)r * nmat;
+    const double2 *bt = beta + (size_t)r * nmat * 3;
     double2 acc = make_double2(0, 0);
     for (size_t e = (size_t)blockIdx.x * kMatThreads + threadIdx.x; e < n3; e += (size_t)gridDim.x * kMatThreads) {
         const double2 xv = x[off + e], d = xs[off + e], yv = y[off + e];
-        const double2 b = cm(bt[mat[e % N]], make_double2(d.x - yv.x, d.y - yv.y));
+        const double2 b = cm(bt[3 * mat[e % N] + e / N], make_double2(d.x - yv.x, d.y - yv.y));
         const double2 o = make_double2(xv.x - b.x, xv.y - b.y);
         y[off + e] = o;
         const double2 p = cm(xv, o);
@@ -76,18 +76,17 @@ __global__ void __launch_bounds__(kMatThreads) k_mat_post(const double2 *__restr
         dr[j] = make_double2(0, 0);
 }
 
-// per-block partial sum of |P|^2 over the dipoles of material m
+// per-block partial sum of |P_q|^2 over the dipoles of material m (component q)
 __global__ void __launch_bounds__(kMatThreads) k_mat_norm(const double2 *__restrict__ P,
-                                                          const uint8_t *__restrict__ mat, int m, int64_t N,
+                                                          const uint8_t *__restrict__ mat, int m, int q, int64_t N,
                                                           double *part) {
     __shared__ double sh[kMatThreads];
     double acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * kMatThreads + threadIdx.x; i < N; i += (int64_t)gridDim.x * kMatThreads)
-        if (mat[i] == m)
-            for (int q = 0; q < 3; ++q) {
-                const double2 v = P[(size_t)q * N + i];
-                acc += v.x * v.x + v.y * v.y;
-            }
+        if (mat[i] == m) {
+            const double2 v = P[(size_t)q * N + i];
+            acc += v.x * v.x + v.y * v.y;
+        }
     const int t = threadIdx.x;
     sh[t] = acc;
     __syncthreads();
@@ -100,14 +99,15 @@ __global__ void __launch_bounds__(kMatThreads) k_mat_norm(const double2 *__restr
 
 static int mat_blocks(int64_t N) { return (int)std::min<int64_t>(kMatBlocks, (3 * N + kMatThreads - 1) / kMatThreads); }
 
-// beta of every material for a beam (principal square roots)
+// beta of every material and component for a beam (principal square roots), [nmat][3]
 static void material_betas(const Ctx &c, const dda_beam &b, double2 *out) {
-    for (int m = 0; m < c.nmat; ++m) {
-        double ar, ai;
-        polarizability_of(c, b, c.mat_re[m], c.mat_im[m], ar, ai);
-        const double mod = std::hypot(ar, ai);
-        out[m] = make_double2(std::sqrt(0.5 * (mod + ar)), std::copysign(std::sqrt(0.5 * (mod - ar)), ai));
-    }
+    for (int m = 0; m < c.nmat; ++m)
+        for (int q = 0; q < 3; ++q) {
+            double ar, ai;
+            polarizability_comp(c, b, c.mat_re[m], c.mat_im[m], q, ar, ai);
+            const double mod = std::hypot(ar, ai);
+            out[3 * m + q] = make_double2(std::sqrt(0.5 * (mod + ar)), std::copysign(std::sqrt(0.5 * (mod - ar)), ai));
+        }
 }
 
 // table rows (the last row, index rows, serves single-beam scaling) and scaled-vector rows
@@ -116,7 +116,7 @@ static dda_status ensure_material_bufs(Ctx &c, int rows, int xrows) {
         (void)hipFree(c.mat_beta);
         c.mat_beta = nullptr;
         c.mat_beta_rows = 0;
-        dda_status st = device_alloc((void **)&c.mat_beta, (size_t)(rows + 1) * c.nmat * sizeof(double2));
+        dda_status st = device_alloc((void **)&c.mat_beta, (size_t)(rows + 1) * c.nmat * 3 * sizeof(double2));
         if (st != DDA_OK) return st;
         c.mat_beta_rows = rows;
     }
@@ -132,11 +132,11 @@ static dda_status ensure_material_bufs(Ctx &c, int rows, int xrows) {
 }
 
 dda_status material_prepare(Ctx &c, const dda_beam *beams, int n) {
-    if (c.nmat <= 1) return DDA_OK;
+    if (!wrapped(c)) return DDA_OK;
     dda_status st = ensure_material_bufs(c, n, std::max(n, 2));
     if (st != DDA_OK) return st;
-    std::vector<double2> t((size_t)n * c.nmat);
-    for (int r = 0; r < n; ++r) material_betas(c, beams[r], t.data() + (size_t)r * c.nmat);
+    std::vector<double2> t((size_t)n * c.nmat * 3);
+    for (int r = 0; r < n; ++r) material_betas(c, beams[r], t.data() + (size_t)r * c.nmat * 3);
     DDA_HIP_CHECK(hipMemcpyAsync(c.mat_beta, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, c.stream));
     DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
     return DDA_OK;
@@ -145,9 +145,9 @@ dda_status material_prepare(Ctx &c, const dda_beam *beams, int n) {
 dda_status material_scale(Ctx &c, const dda_beam &b, const double2 *x, double2 *P, hipStream_t s) {
     dda_status st = ensure_material_bufs(c, 1, 2);
     if (st != DDA_OK) return st;
-    std::vector<double2> t(c.nmat);
+    std::vector<double2> t((size_t)c.nmat * 3);
     material_betas(c, b, t.data());
-    double2 *row = c.mat_beta + (size_t)c.mat_beta_rows * c.nmat;
+    double2 *row = c.mat_beta + (size_t)c.mat_beta_rows * c.nmat * 3;
     DDA_HIP_CHECK(hipMemcpyAsync(row, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_mat_scale, dim3(mat_blocks(c.N), 1), dim3(kMatThreads), 0, s, x, P, c.dmat, row, c.nmat, c.N,
                        nullptr);
@@ -165,15 +165,16 @@ dda_status material_cabs(Ctx &c, const dda_beam &b, const double2 *P, double &ca
     const double k = c.kd;
     cabs = 0;
     hipError_t he = hipSuccess;
-    for (int m = 0; m < c.nmat && he == hipSuccess; ++m) {
-        hipLaunchKernelGGL(k_mat_norm, dim3(nb), dim3(kMatThreads), 0, c.stream, P, c.dmat, m, c.N, part);
+    for (int mq = 0; mq < 3 * c.nmat && he == hipSuccess; ++mq) {
+        const int m = mq / 3, q = mq % 3;
+        hipLaunchKernelGGL(k_mat_norm, dim3(nb), dim3(kMatThreads), 0, c.stream, P, c.dmat, m, q, c.N, part);
         he = hipGetLastError();
         if (he == hipSuccess) he = hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, c.stream);
         if (he == hipSuccess) he = hipStreamSynchronize(c.stream);
         double s = 0;
         for (int i = 0; i < nb; ++i) s += h[i];
         double ar, ai;
-        polarizability_of(c, b, c.mat_re[m], c.mat_im[m], ar, ai);
+        polarizability_comp(c, b, c.mat_re[m], c.mat_im[m], q, ar, ai);
         const double a2 = ar * ar + ai * ai;
         if (a2 > 0) cabs += 4.0 * M_PI * k * (ai / a2 - (2.0 / 3.0) * k * k * k) * s;  // -Im(1/alpha) = Im(alpha)/|alpha|^2
     }
@@ -183,6 +184,27 @@ dda_status material_cabs(Ctx &c, const dda_beam &b, const double2 *P, double &ca
         return DDA_EHIP;
     }
     return DDA_OK;
+}
+
+dda_status material_init(Ctx &c, int n_mat, const double *m) {
+    if (n_mat <= 1 && c.polarizability != DDA_POL_CLDR) return DDA_OK;
+    c.nmat = n_mat;
+    c.mat_re.resize(n_mat);
+    c.mat_im.resize(n_mat);
+    for (int i = 0; i < n_mat; ++i) {
+        c.mat_re[i] = m[2 * i];
+        c.mat_im[i] = m[2 * i + 1];
+    }
+    std::vector<uint8_t> mt(c.N);
+    for (int64_t i = 0; i < c.N; ++i) mt[i] = n_mat > 1 ? (uint8_t)(c.mask[c.lin_host[i]] - 1) : 0;
+    dda_status st = device_alloc((void **)&c.dmat, mt.size());
+    if (st != DDA_OK) return st;
+    const hipError_t he = hipMemcpy(c.dmat, mt.data(), mt.size(), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+        set_error(std::string("material set-up: ") + hipGetErrorString(he));
+        return DDA_EHIP;
+    }
+    return ensure_material_bufs(c, 1, 2);
 }
 
 dda_status matvec_materials(Ctx &c, const double2 *x, double2 *y, int nrhs, const double2 *scale, double2 *dots,
@@ -229,35 +251,17 @@ extern "C" dda_status dda_setup_materials(dda_ctx **out, const int32_t grid[3], 
             set_error("dda_setup_materials: non-finite refractive index");
             return DDA_EINVAL;
         }
-    if (n_mat > 1 && opts && opts->fp32) {
-        set_error("dda_setup_materials: single-precision products are not available for inhomogeneous particles");
+    if ((n_mat > 1 || polarizability == DDA_POL_CLDR) && opts && opts->fp32) {
+        set_error("dda_setup_materials: single-precision products are not available for inhomogeneous particles "
+                  "or CLDR");
         return DDA_ENOTSUP;
     }
     Ctx *c = nullptr;
     dda_status st = setup(&c, grid, mask, m, kd, polarizability, opts, stream);
     if (st != DDA_OK) return st;
-    if (n_mat > 1) {
-        c->nmat = n_mat;
-        c->mat_re.resize(n_mat);
-        c->mat_im.resize(n_mat);
-        for (int i = 0; i < n_mat; ++i) {
-            c->mat_re[i] = m[2 * i];
-            c->mat_im[i] = m[2 * i + 1];
-        }
-        std::vector<uint8_t> mt(c->N);
-        for (int64_t i = 0; i < c->N; ++i) mt[i] = (uint8_t)(c->mask[c->lin_host[i]] - 1);
-        st = device_alloc((void **)&c->dmat, mt.size());
-        hipError_t he = hipSuccess;
-        if (st == DDA_OK) he = hipMemcpy(c->dmat, mt.data(), mt.size(), hipMemcpyHostToDevice);
-        if (st == DDA_OK && he != hipSuccess) {
-            set_error(std::string("dda_setup_materials: ") + hipGetErrorString(he));
-            st = DDA_EHIP;
-        }
-        if (st == DDA_OK) st = ensure_material_bufs(*c, 1, 2);
-        if (st != DDA_OK) {
-            destroy(c);
-            return st;
-        }
+    if ((st = material_init(*c, n_mat, m)) != DDA_OK) {
+        destroy(c);
+        return st;
     }
     *out = reinterpret_cast<dda_ctx *>(c);
     return DDA_OK;

@@ -9,7 +9,7 @@ dda_status matvec_materials(Ctx &c, const double2 *x, double2 *y, int nrhs, cons
 template <>
 dda_status matvec_device<double>(Ctx &c, const double2 *x, double2 *y, int nrhs, const double2 *scale, double2 *dots,
                               hipStream_t s, const int *done, hipEvent_t *ev) {
-    if (c.nmat > 1) return matvec_materials(c, x, y, nrhs, scale, dots, s, done, ev);
+    if (wrapped(c)) return matvec_materials(c, x, y, nrhs, scale, dots, s, done, ev);
     return matvec_device_impl<double>(c, x, y, nrhs, scale, dots, s, done, ev);
 }
 

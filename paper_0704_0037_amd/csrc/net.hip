@@ -827,7 +827,7 @@ dda_status dda_net_features(dda_net *h, dda_ctx *ch, const dda_beam *beam, void 
     dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
-    if (!n || !c || !feat || !dda::beam_ok(beam) || beam->w0 > 0 || c->nmat > 1 || !fits(*n, *c)) {
+    if (!n || !c || !feat || !dda::beam_ok(beam) || beam->w0 > 0 || dda::wrapped(*c) || !fits(*n, *c)) {
         set_error("dda_net_features: NULL argument, bad or focused beam (plane waves only), inhomogeneous particle, "
                   "or particle grid larger than the network's");
         return DDA_EINVAL;
@@ -843,7 +843,7 @@ dda_status dda_net_target(dda_net *h, dda_ctx *ch, const dda_beam *beam, const v
     dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
-    if (!n || !c || !x || !tgt || !dda::beam_ok(beam) || beam->w0 > 0 || c->nmat > 1 || !fits(*n, *c)) {
+    if (!n || !c || !x || !tgt || !dda::beam_ok(beam) || beam->w0 > 0 || dda::wrapped(*c) || !fits(*n, *c)) {
         set_error("dda_net_target: NULL argument, bad or focused beam (plane waves only), inhomogeneous particle, "
                   "or particle grid larger than the network's");
         return DDA_EINVAL;
@@ -921,7 +921,7 @@ dda_status dda_guess(dda_ctx *ch, dda_net *h, const dda_beam *beams, int32_t n_r
     dda::clear_error();
     Net *n = nx_(h);
     dda::Ctx *c = dda::cx(ch);
-    if (!n || !c || !beams || !feat || !x0 || n_rhs < 1 || n_rhs > n->maxb || c->nmat > 1 || !fits(*n, *c)) {
+    if (!n || !c || !beams || !feat || !x0 || n_rhs < 1 || n_rhs > n->maxb || dda::wrapped(*c) || !fits(*n, *c)) {
         set_error("dda_guess: NULL argument, n_rhs outside [1, max_batch], inhomogeneous particle, or particle larger "
                   "than the network's grid");
         return DDA_EINVAL;

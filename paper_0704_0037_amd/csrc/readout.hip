@@ -297,7 +297,7 @@ dda_status dda_cross_sections(dda_ctx *h, const dda_beam *beam, const void *x, d
     dda_status st;
     if ((st = ensure_red(*c, 2 * (size_t)nb)) != DDA_OK) return st;
     const dda_beam &b = *beam;
-    if (c->nmat > 1) {  // the polarizations P = beta x of the materials take the place of x (beta_of gives 1)
+    if (wrapped(*c)) {  // the polarizations P = beta x of the materials take the place of x (beta_of gives 1)
         if ((st = material_scale(*c, b, (const double2 *)x, c->xtmp, c->stream)) != DDA_OK) return st;
         x = c->xtmp;
     }
@@ -337,7 +337,7 @@ dda_status dda_cross_sections(dda_ctx *h, const dda_beam *beam, const void *x, d
     const double inv_im = -ai / (ar * ar + ai * ai);  // Im(1/alpha)
     const double w = -inv_im - (2.0 / 3.0) * k * k * k;
     double cabs = 4.0 * M_PI * k * w * (br * br + bi * bi) * xx;
-    if (c->nmat > 1 && (st = material_cabs(*c, b, (const double2 *)x, cabs)) != DDA_OK) return st;
+    if (wrapped(*c) && (st = material_cabs(*c, b, (const double2 *)x, cabs)) != DDA_OK) return st;
     out[0] = cext;
     out[1] = cabs;
     out[2] = cext - cabs;
@@ -353,7 +353,7 @@ dda_status dda_farfield(dda_ctx *h, const dda_beam *beam, const void *x, int32_t
         return DDA_EINVAL;
     }
     dda_status st;
-    if (c->nmat > 1) {
+    if (wrapped(*c)) {
         if ((st = material_scale(*c, *beam, (const double2 *)x, c->xtmp, c->stream)) != DDA_OK) return st;
         x = c->xtmp;
     }
@@ -381,7 +381,7 @@ dda_status dda_asymmetry(dda_ctx *h, const dda_beam *beam, const void *x, int32_
         set_error("dda_asymmetry: NULL argument, grid sizes outside 1..2^22 directions or beam without unit vectors");
         return DDA_EINVAL;
     }
-    if (c->nmat > 1) {
+    if (wrapped(*c)) {
         const dda_status sc = material_scale(*c, *beam, (const double2 *)x, c->xtmp, c->stream);
         if (sc != DDA_OK) return sc;
         x = c->xtmp;
@@ -432,7 +432,7 @@ dda_status dda_mueller(dda_ctx *h, const dda_beam *beam, const void *x1, const v
         set_error("dda_mueller: NULL argument, n_theta < 1 or beam without unit vectors");
         return DDA_EINVAL;
     }
-    if (!x2 && (beam->w0 > 0 || c->nmat > 1)) {
+    if (!x2 && (beam->w0 > 0 || wrapped(*c))) {
         set_error("dda_mueller: the one-polarization shortcut (x2 = NULL) takes plane waves on homogeneous particles "
                   "only");
         return DDA_EINVAL;
@@ -464,7 +464,7 @@ dda_status dda_mueller(dda_ctx *h, const dda_beam *beam, const void *x1, const v
     }
     std::vector<double> F1(6 * (size_t)n_theta), F2(6 * (size_t)n_theta);
     dda_status st;
-    if (c->nmat > 1) {  // P = beta x of each polarization (the second beam has polarization e2)
+    if (wrapped(*c)) {  // P = beta x of each polarization (the second beam has polarization e2)
         dda_beam bb = b;
         for (int a = 0; a < 3; ++a) bb.pol_re[a] = e2[a];
         double2 *P1 = c->xtmp, *P2 = c->xtmp + 3 * (size_t)c->N;

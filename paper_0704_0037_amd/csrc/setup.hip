@@ -188,8 +188,10 @@ void launch_to_f32(const double2 *a, float2 *b, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
 }
 
+static void alpha_of(int pol, double kd, const dda_beam &b, double mr, double mi, double &re, double &im);
+
 void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
-    if (c.nmat > 1) {
+    if (wrapped(c)) {
         re = 1.0;
         im = 0.0;
         return;
@@ -197,21 +199,40 @@ void polarizability(const Ctx &c, const dda_beam &b, double &re, double &im) {
     polarizability_of(c, b, c.m_re, c.m_im, re, im);
 }
 
+void polarizability_comp(const Ctx &c, const dda_beam &b, double mr, double mi, int comp, double &re, double &im) {
+    if (c.polarizability != DDA_POL_CLDR) {
+        polarizability_of(c, b, mr, mi, re, im);
+        return;
+    }
+    // CLDR (Gutkowicz-Krusin & Draine 2004): LDR's S replaced by a_comp^2, polarization-free
+    dda_beam t = b;
+    for (int a = 0; a < 3; ++a) {
+        t.pol_re[a] = a == comp ? 1.0 : 0.0;
+        t.pol_im[a] = 0.0;
+    }
+    // LDR with e = the unit vector of the component gives S = a_comp^2
+    alpha_of(DDA_POL_LDR, c.kd, t, mr, mi, re, im);
+}
+
 void polarizability_of(const Ctx &c, const dda_beam &b, double mr, double mi, double &re, double &im) {
+    alpha_of(c.polarizability == DDA_POL_CLDR ? DDA_POL_LDR : c.polarizability, c.kd, b, mr, mi, re, im);
+}
+
+static void alpha_of(int pol, double kd, const dda_beam &b, double mr, double mi, double &re, double &im) {
     // Clausius-Mossotti for a unit cube: (3/4pi)(m^2-1)/(m^2+2)
     const double m2r = mr * mr - mi * mi, m2i = 2 * mr * mi;
     const double nr = m2r - 1, ni = m2i, dr = m2r + 2, di = m2i;
     const double den = dr * dr + di * di;
     const double f = 3.0 / (4.0 * M_PI);
     const double cmr = f * (nr * dr + ni * di) / den, cmi = f * (ni * dr - nr * di) / den;
-    if (c.polarizability == DDA_POL_CM) {
+    if (pol == DDA_POL_CM) {
         re = cmr;
         im = cmi;
         return;
     }
-    if (c.polarizability == DDA_POL_RR) {
+    if (pol == DDA_POL_RR) {
         // radiative-reaction correction (Draine 1988): 1/alpha = 1/alpha_CM - (2/3) i k^3
-        const double k = c.kd;
+        const double k = kd;
         const double cm2 = cmr * cmr + cmi * cmi;
         const double ir = cmr / cm2, ii = -cmi / cm2 - (2.0 / 3.0) * k * k * k;
         const double n2 = ir * ir + ii * ii;
@@ -223,7 +244,7 @@ void polarizability_of(const Ctx &c, const dda_beam &b, double mr, double mi, do
     const double b1 = -1.8915316, b2 = 0.1648469, b3 = -1.7700004;
     double S = 0;
     for (int a = 0; a < 3; ++a) S += b.prop[a] * b.prop[a] * (b.pol_re[a] * b.pol_re[a] + b.pol_im[a] * b.pol_im[a]);
-    const double k = c.kd;
+    const double k = kd;
     const double cm2 = cmr * cmr + cmi * cmi;
     double ir = cmr / cm2, ii = -cmi / cm2;  // 1/alpha_CM
     const double tr = b1 + m2r * b2 + m2r * b3 * S, ti = m2i * b2 + m2i * b3 * S;
@@ -377,7 +398,7 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
         set_error("dda_setup: kd must be > 0 and m finite");
         return DDA_EINVAL;
     }
-    if (pol != DDA_POL_LDR && pol != DDA_POL_CM && pol != DDA_POL_RR) {
+    if (pol != DDA_POL_LDR && pol != DDA_POL_CM && pol != DDA_POL_RR && pol != DDA_POL_CLDR) {
         set_error("dda_setup: unknown polarizability");
         return DDA_EINVAL;
     }

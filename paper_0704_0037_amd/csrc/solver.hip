@@ -1877,7 +1877,7 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
     dda_solve_opts o;
     dda_status st = check_opts(opts, o);
     if (st != DDA_OK) return st;
-    if (c->nmat > 1 && o.precision != DDA_FP64) {
+    if (wrapped(*c) && o.precision != DDA_FP64) {
         set_error("dda_solve: an inhomogeneous particle is solved in DDA_FP64 only");
         return DDA_ENOTSUP;
     }

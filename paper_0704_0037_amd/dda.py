@@ -16,7 +16,7 @@ import torch
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdda_mi355x.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESYMMETRY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
-POL_LDR, POL_CM, POL_RR = 0, 1, 2
+POL_LDR, POL_CM, POL_RR, POL_CLDR = 0, 1, 2, 3
 QMR, BICGSTAB, BICG, CGNR = 0, 1, 2, 3
 FP64, FP32_REFINE, FP32_PRODUCT = 0, 1, 2
 BREAKDOWN_REPORT, BREAKDOWN_RECOVER = 0, 1

@@ -462,6 +462,53 @@ def test_inhomogeneous_particle_matches_oracle():
         dda.Context(mask, ms, kd, fp32=True)
 
 
+@pytest.mark.parametrize("two_materials", [False, True])
+def test_cldr_matches_oracle(two_materials):
+    # the diagonal CLDR polarizability tensor: product, solve of both polarizations, cross
+    # sections and Mueller matrix against the oracle
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((8, 7, 6), (4, 3.5, 3)).astype(np.uint8)
+    ms = [1.5 + 0.1j]
+    if two_materials:
+        mask[:, 4:, :] *= 2
+        ms = [1.5 + 0.1j, 1.25 + 0.01j]
+    kd = 0.6
+    prop = np.array([0.48, 0.6, 0.64])
+    pol1 = np.array([0.8, 0.0, -0.6])
+    pol2 = np.cross(prop, pol1)
+    pos, _ = odda.dipoles(mask)
+    N = len(pos)
+    alpha = odda.material_alphas(mask, ms, kd, prop, pol1, polarizability="cldr")  # the same for pol2
+    bt = np.sqrt(alpha)
+    A = odda.interaction_matrix(pos, kd, bt)
+    P, xs_ref, cs_ref = [], [], []
+    for pol in (pol1, pol2):
+        x = np.linalg.solve(A, odda.rhs(pos, kd, bt, prop, pol).reshape(-1)).reshape(N, 3)
+        xs_ref.append(x)
+        P.append(bt * x)
+        cs_ref.append(odda.cross_sections(pos, kd, alpha, bt * x, prop, pol))
+    th = np.linspace(0.0, math.pi, 7)
+    M_ref = odda.mueller(pos, kd, prop, pol1, P[0], P[1], th, 1.1)
+    beams = [inputs.Beam(tuple(prop), tuple(pol1 + 0j)), inputs.Beam(tuple(prop), tuple(pol2 + 0j))]
+    rng = np.random.default_rng(5)
+    xr = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+    with dda.Context(mask, ms if two_materials else ms[0], kd, polarizability=dda.POL_CLDR) as ctx:
+        y = ctx.matvec(beams[0], torch.from_numpy(np.ascontiguousarray(xr.T)).cuda()).cpu().numpy().T
+        y_ref = (A @ xr.reshape(-1)).reshape(N, 3)
+        assert np.max(np.abs(y - y_ref)) < 1e-12 * np.max(np.abs(y_ref))
+        x, info, st = ctx.solve(beams, tol=1e-11)
+        assert st == 0
+        for r in range(2):
+            assert np.max(np.abs(x[r].cpu().numpy().T - xs_ref[r])) < 1e-8 * np.max(np.abs(xs_ref[r]))
+            cext, cabs, _ = ctx.cross_sections(beams[r], x[r].contiguous())
+            assert abs(cext - cs_ref[r][0]) < 1e-8 * abs(cs_ref[r][0])
+            assert abs(cabs - cs_ref[r][1]) < 1e-8 * abs(cs_ref[r][0])
+        M = ctx.mueller(beams[0], x[0].contiguous(), x[1].contiguous(), 1.1, th)
+        assert np.max(np.abs(M - M_ref)) < 1e-8 * np.max(np.abs(M_ref))
+    with pytest.raises(dda.DDAError):
+        dda.Context(mask, ms[0], kd, polarizability=dda.POL_CLDR, fp32=True)
+
+
 def test_inhomogeneous_particle_with_a_focused_beam_and_resume():
     # the extensions together: two materials, a focused beam, a solve stopped at its limit and
     # continued bitwise, and the cross sections against the oracle
