@@ -361,6 +361,8 @@ dda_status dda_mueller(dda_ctx *ctx, const dda_beam *beam, const void *x1, const
  * inverse y, inverse x) and of a whole product (total_ms).
  *   x, y   device [n_rhs][3][N], complex128 (DDA_FP64) or complex64 (DDA_FP32_REFINE; the context
  *          must have been set up with opts.fp32)
+ * Homogeneous contexts only (DDA_ENOTSUP for dda_setup_materials with several materials or
+ * CLDR, whose wrapped product runs these same kernels).
  */
 dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, int32_t precision,
                             const void *x, void *y, int32_t reps, float kernel_ms[5], float *total_ms);
@@ -373,6 +375,8 @@ dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
  * dda_get_tiles / dda_set_tiles read / impose a schedule (e.g. one cached from an earlier run;
  * DDA_EINVAL for an inadmissible one).  Results of products do not depend on the schedule except
  * through the order of the bilinear-dot partial sums.
+ * Homogeneous contexts only (DDA_ENOTSUP otherwise): a schedule tuned on a homogeneous context
+ * of the same grid applies unchanged to a wrapped one (dda_set_tiles).
  */
 dda_status dda_tune(dda_ctx *ctx, int32_t precision, int32_t n_rhs, int32_t reps, int32_t tiles_out[2]);
 dda_status dda_get_tiles(const dda_ctx *ctx, int32_t precision, int32_t tiles[2]);
