@@ -261,6 +261,44 @@ def solver_study(dda, inputs, torch, n=64, tol=1e-5):
     return out
 
 
+def materials_study(dda, inputs, torch, n=256, reps=10):
+    """Cost of the wrapped product (several materials, CLDR) and of focused-beam right-hand sides
+    on the n^3 sphere (x = 40): ms per single-vector product with HIP events over `reps` products,
+    for the homogeneous LDR particle, a core/shell particle of two materials and the homogeneous
+    particle under CLDR; seconds per focused-beam right-hand side for k w0 = 5 and 20."""
+    mask = inputs.sphere_mask(n)
+    N = int(np.count_nonzero(mask))
+    kd = inputs.kd_for_size_parameter(40.0, N)
+    zz, yy, xx = np.indices(mask.shape)
+    c = (n - 1) / 2.0
+    core = ((xx - c) ** 2 + (yy - c) ** 2 + (zz - c) ** 2) < (0.6 * n / 2) ** 2
+    shell = mask.copy()
+    shell[(shell > 0) & core] = 2
+    out = {"workload": f"sphere{n} ({N} dipoles), kd = {kd:.4f}, one right-hand side; core/shell: inner 0.6 of the "
+                       "radius is material 2 (m 1.2), the rest m 1.05"}
+    for name, mk, m, pol in (("homogeneous_ldr", mask, 1.05, dda.POL_LDR), ("core_shell_ldr", shell, [1.05, 1.2],
+                             dda.POL_LDR), ("homogeneous_cldr", mask, 1.05, dda.POL_CLDR)):
+        with dda.Context(mk, m, kd, polarizability=pol) as ctx:
+            x = torch.randn(3, ctx.n, dtype=torch.complex128, device="cuda")
+            y = ctx.matvec(inputs.X_POL, x)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ctx.matvec(inputs.X_POL, x, y)
+            e1.record()
+            torch.cuda.synchronize()
+            out[name + "_product_ms"] = e0.elapsed_time(e1) / reps
+            if name == "homogeneous_ldr":
+                for kw0 in (5.0, 20.0):
+                    fb = inputs.Beam((0.0, 0.0, 1.0), (1.0 + 0j, 0j, 0j), kw0 / kd, (0.0, 0.0, 0.0))
+                    _, dt = _timed(torch, lambda: ctx.rhs(fb))
+                    out[f"focused_rhs_s_kw0_{kw0:g}"] = dt
+        log(f"materials study {name}: {out[name + '_product_ms']:.3f} ms per product")
+    out["core_shell_overhead"] = out["core_shell_ldr_product_ms"] / out["homogeneous_ldr_product_ms"] - 1.0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +313,8 @@ def main():
                     help="only: the m = 2 sphere to 1e-5, fp64 vs single-precision transforms (~10 min)")
     ap.add_argument("--solver-study", action="store_true",
                     help="only: QMR, Bi-CG, Bi-CGSTAB and CGNR on a 64^3 sphere with x = 20, m = 1.8")
+    ap.add_argument("--materials-study", action="store_true",
+                    help="only: wrapped products (two materials, CLDR) and focused-beam right-hand sides, 256^3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -288,6 +328,9 @@ def main():
         return
     if args.solver_study:
         print(json.dumps(solver_study(dda, inputs, torch)), flush=True)
+        return
+    if args.materials_study:
+        print(json.dumps(materials_study(dda, inputs, torch)), flush=True)
         return
 
     if args.calibration_copy:
