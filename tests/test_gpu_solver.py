@@ -454,6 +454,9 @@ def test_inhomogeneous_particle_matches_oracle():
             assert abs(cabs - ref[r][4][1]) < 1e-8 * abs(ref[r][4][0])
         M = ctx.mueller(beams[0], x[0].contiguous(), x[1].contiguous(), 0.4, th)
         assert np.max(np.abs(M - M_ref)) < 1e-8 * np.max(np.abs(M_ref))
+        csca, g = ctx.asymmetry(beams[0], x[0].contiguous(), 24, 48)
+        cref, gref = odda.asymmetry(pos, kd, ref[0][3], prop, 24, 48)
+        assert abs(csca - cref) < 1e-8 * abs(cref) and abs(g - gref) < 1e-8
         with pytest.raises(dda.DDAError):
             ctx.solve(beams, precision=dda.FP32_REFINE)
         with pytest.raises(dda.DDAError):
