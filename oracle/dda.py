@@ -717,7 +717,7 @@ def romberg_adaptive(f, a, b, eps, n_min=2, n_max=10):
         vals = merged
 
 
-def _orientation_rows(pos, m, k, mus, n_gamma, polarizability):
+def _orientation_rows(pos, m, k, mus, n_gamma, polarizability, mask=None):
     """Mean (Cext, Cabs, Csca) over the 2^n_gamma equispaced gamma and the x and y incident
     polarizations, at each cos(beta) in mus.  Orientation R = Ry(beta) Rz(gamma) (alpha = 0); the
     particle-frame beam is R^T applied to the laboratory vectors."""
@@ -735,15 +735,20 @@ def _orientation_rows(pos, m, k, mus, n_gamma, polarizability):
             prop = R.T @ np.array([0.0, 0.0, 1.0])
             for e in (np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])):
                 pol = R.T @ e
-                if polarizability == "cm":
+                if isinstance(m, (list, tuple)):  # several materials: alpha per dipole
+                    alpha = material_alphas(mask, m, k, prop, pol, polarizability)
+                    bt = np.sqrt(alpha)
+                    bx = bt if np.ndim(bt) == 2 else bt[:, None]
+                elif polarizability == "cm":
                     alpha = alpha_cm(m)
+                    bt = bx = beta_of_alpha(alpha)
                 else:
                     alpha = alpha_ldr(m, k, prop, pol)
-                bt = beta_of_alpha(alpha)
+                    bt = bx = beta_of_alpha(alpha)
                 A = interaction_matrix(pos, k, bt)
                 b = rhs(pos, k, bt, prop, pol)
                 x = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
-                cext, cabs = cross_sections(pos, k, alpha, bt * x, prop, pol)[:2]
+                cext, cabs = cross_sections(pos, k, alpha, bx * x, prop, pol)[:2]
                 rows[i] += np.array([cext, cabs, cext - cabs])
     return rows / (2.0 * ng)
 
@@ -754,13 +759,14 @@ def orientation_average(mask, m, k, n_beta, n_gamma, tol=1e-10, polarizability="
     scattering plane, so the cross sections need beta and gamma.  Romberg in cos(beta) on
     2^n_beta + 1 points, the periodic trapezoid rule on 2^n_gamma points in gamma; unpolarized:
     the mean of the x- and y-polarized incident beams, each brought into the particle frame by R^T.
+    m may be a list of refractive indices (mask values name the materials).
     Returns ({"Cext", "Cabs", "Csca"} averages, Romberg error estimate of <Cext>).
     pinned by: the Romberg rule on polynomials; a CM single dipole (isotropic) gives its fixed
     value; invariance of the average under a 90-degree lattice rotation of the particle."""
     pos, _ = dipoles(mask)
     nb = 2 ** n_beta + 1
     mus = [-1.0 + 2.0 * i / (nb - 1) for i in range(nb)]
-    over_gamma = _orientation_rows(pos, m, k, mus, n_gamma, polarizability)
+    over_gamma = _orientation_rows(pos, m, k, mus, n_gamma, polarizability, mask)
     out, errs = {}, []
     for q, name in enumerate(("Cext", "Cabs", "Csca")):
         v, e = romberg(over_gamma[:, q], -1.0, 1.0)
@@ -781,7 +787,7 @@ def orientation_average_adaptive(mask, m, k, eps, n_beta_min, n_beta_max, n_gamm
     pos, _ = dipoles(mask)
 
     def f(mus):
-        return _orientation_rows(pos, m, k, list(mus), n_gamma, polarizability)[:, :2]
+        return _orientation_rows(pos, m, k, list(mus), n_gamma, polarizability, mask)[:, :2]
 
     v, e, n = romberg_adaptive(f, -1.0, 1.0, eps, n_beta_min, n_beta_max)
     out = {"Cext": v[0] / 2.0, "Cabs": v[1] / 2.0, "Csca": (v[0] - v[1]) / 2.0}

@@ -532,3 +532,12 @@ def test_tensor_polarizability_symmetrized_system_equals_equation_1():
     cext, cabs = dda.cross_sections(pos, k, alpha, P1, prop, pol)
     w = -np.imag(1.0 / alpha) - (2.0 / 3.0) * k ** 3
     assert abs(cabs - 4 * math.pi * k * np.sum(w * np.abs(P1) ** 2)) < 1e-12 * abs(cext)
+
+
+def test_orientation_average_of_two_equal_materials_is_the_homogeneous_one():
+    mask = _two_material_mask()
+    one = (mask > 0).astype(np.uint8)
+    a1, e1 = dda.orientation_average(one, 1.5 + 0.02j, 0.5, 2, 1)
+    a2, e2 = dda.orientation_average(mask, [1.5 + 0.02j, 1.5 + 0.02j], 0.5, 2, 1)
+    for q in ("Cext", "Cabs", "Csca"):
+        assert abs(a1[q] - a2[q]) < 1e-12 * a1["Cext"]
