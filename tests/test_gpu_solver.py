@@ -512,6 +512,21 @@ def test_cldr_matches_oracle(two_materials):
         dda.Context(mask, ms[0], kd, polarizability=dda.POL_CLDR, fp32=True)
 
 
+@pytest.mark.parametrize("pol", ["ldr", "cldr"])
+def test_orientation_average_of_an_inhomogeneous_particle_matches_oracle(pol):
+    dda = _dda()
+    mask = np.zeros((3, 2, 2), np.uint8)
+    mask[:, 0, 0] = 1
+    mask[0, 1, 0] = 2
+    mask[2, 0, 1] = 2
+    ms = [1.5 + 0.02j, 1.2 + 0.1j]
+    ref, err = odda.orientation_average(mask, ms, 0.5, 2, 2, polarizability=pol)
+    with dda.Context(mask, ms, 0.5, polarizability=dda.POL_LDR if pol == "ldr" else dda.POL_CLDR) as ctx:
+        got = ctx.orientation_average(2, 2, tol=1e-12)
+    for q in ("Cext", "Cabs", "Csca"):
+        assert abs(got[q] - ref[q]) < 1e-9 * abs(ref["Cext"]), (q, got, ref)
+
+
 def test_inhomogeneous_particle_with_a_focused_beam_and_resume():
     # the extensions together: two materials, a focused beam, a solve stopped at its limit and
     # continued bitwise, and the cross sections against the oracle
