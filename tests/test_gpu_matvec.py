@@ -191,6 +191,35 @@ def test_full_size_sampled_rows(name, make, nrhs, nrows):
         assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12, (name, r)
 
 
+@pytest.mark.slow
+def test_full_size_two_materials_sampled_rows():
+    """The wrapped product of an inhomogeneous particle at the 256^3 size: a core/shell sphere
+    (x = 40; inner 0.6 of the radius m = 1.2, the rest m = 1.05), two right-hand sides in one
+    batch, sampled rows against the oracle's direct sums with a beta per dipole."""
+    dda = _dda()
+    w = inputs.c2_sphere256()
+    n = w.mask.shape[0]
+    zz, yy, xx = np.indices(w.mask.shape)
+    c = (n - 1) / 2.0
+    core = ((xx - c) ** 2 + (yy - c) ** 2 + (zz - c) ** 2) < (0.6 * n / 2) ** 2
+    mask = w.mask.astype(np.uint8).copy()
+    mask[(mask > 0) & core] = 2
+    ms = [1.05, 1.2]
+    beams = w.beams[:2]
+    with dda.Context(mask, ms, w.kd) as ctx:
+        x = inputs.random_vector(ctx.n, seed=2025, n_rhs=2)
+        y = ctx.matvec_batch(beams, torch.from_numpy(x).cuda()).cpu().numpy()
+    pos, _ = odda.dipoles(mask)
+    rng = np.random.default_rng(6)
+    for r in range(2):
+        b = beams[r]
+        beta = np.sqrt(odda.material_alphas(mask, ms, w.kd, b.prop, b.pol))
+        rows = rng.choice(len(pos), 4, replace=False)
+        ref = odda.matvec_rows(pos, w.kd, beta, x[r].T, rows)
+        got = y[r][:, rows].T
+        assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12, r
+
+
 def test_matvec_timed_returns_the_product():
     """The measurement entry point computes the same product it times (fp64 batch and fp32)."""
     from paper_0704_0037_amd import dda
