@@ -239,7 +239,8 @@ dda_status dda_solve(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, double 
  * solve that stopped at its iteration limit (per right-hand side scalars, iterate, Krylov vectors)
  * to and from a file, to continue it later with opts.resume (the paper's program checkpoints long
  * runs, Sec. 2).  x: device complex128 [n_rhs][3][N], the iterate (read by save, written by load).
- * The file belongs to this library build and a particle with the same number of dipoles.
+ * The file belongs to this library build and the same particle: its header holds a hash of the
+ * grid, mask (materials), refractive indices, kd and polarizability prescription, checked on load.
  * Errors: DDA_EINVAL (nothing to save, unreadable or mismatched file), DDA_EHIP.
  */
 dda_status dda_checkpoint_save(dda_ctx *ctx, const void *x, const char *path);

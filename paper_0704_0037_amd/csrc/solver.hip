@@ -1759,8 +1759,30 @@ struct CkptHeader {
     char magic[8];
     int32_t version, nrhs, solver, state_bytes;
     int64_t N, vec_elems;
+    uint64_t particle;  // particle_hash of the context that wrote it
 };
-static const char kCkptMagic[8] = {'D', 'D', 'A', 'C', 'K', 'P', 'T', '1'};
+
+// FNV-1a over what defines the interaction matrix: grid, mask (materials), refractive indices, kd
+// and the polarizability prescription
+static uint64_t particle_hash(const Ctx &c) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    const int32_t g[5] = {c.nx, c.ny, c.nz, c.polarizability, c.nmat};
+    mix(g, sizeof g);
+    mix(c.mask.data(), c.mask.size());
+    mix(&c.kd, sizeof c.kd);
+    mix(&c.m_re, sizeof c.m_re);
+    mix(&c.m_im, sizeof c.m_im);
+    for (size_t i = 0; i < c.mat_re.size(); ++i) {
+        mix(&c.mat_re[i], sizeof(double));
+        mix(&c.mat_im[i], sizeof(double));
+    }
+    return h;
+}
+static const char kCkptMagic[8] = {'D', 'D', 'A', 'C', 'K', 'P', 'T', '2'};
 
 static dda_status ckpt_io(FILE *f, void *dev, size_t bytes, bool write, hipStream_t s) {
     std::vector<char> buf(std::min<size_t>(bytes, (size_t)64 << 20));
@@ -1803,7 +1825,8 @@ extern "C" dda_status dda_checkpoint_save(dda_ctx *h, const void *x, const char 
     if (st != DDA_OK) return st;
     CkptHeader hd{};
     std::memcpy(hd.magic, kCkptMagic, 8);
-    hd.version = 1;
+    hd.version = 2;
+    hd.particle = particle_hash(*c);
     hd.nrhs = nrhs;
     hd.solver = c->resume_solver;
     hd.state_bytes = (int32_t)(nrhs * sizeof(SolveState));
@@ -1842,11 +1865,12 @@ extern "C" dda_status dda_checkpoint_load(dda_ctx *h, void *x, const char *path)
     }
     CkptHeader hd{};
     dda_status st = DDA_OK;
-    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1 ||
+    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2 ||
+        hd.particle != particle_hash(*c) ||
         hd.nrhs < 1 || hd.N != c->N || hd.state_bytes != (int32_t)(hd.nrhs * sizeof(SolveState)) ||
         hd.vec_elems != (int64_t)kNumVecs * hd.nrhs * 3 * c->N ||
         (hd.solver != DDA_QMR && hd.solver != DDA_BICGSTAB && hd.solver != DDA_BICG && hd.solver != DDA_CGNR)) {
-        set_error("dda_checkpoint_load: not a checkpoint of this library for a particle of this size");
+        set_error("dda_checkpoint_load: not a checkpoint of this library for this particle");
         st = DDA_EINVAL;
     }
     Bufs B;

@@ -321,6 +321,9 @@ def test_resume_and_checkpoint_continue_exactly(solver, tmp_path):
         x, _, st = ctx.solve(beams, maxit=4, raise_on_fail=False, **kw)
         path = str(tmp_path / "solve.ckpt")
         ctx.checkpoint_save(path, x)
+    with dda.Context(mask, 1.4 + 0.02j, 0.5) as ctx3:  # another particle (m) with the same dipoles
+        with pytest.raises(dda.DDAError):
+            ctx3.checkpoint_load(path, ctx3.vector(len(beams)))
     with dda.Context(mask, 1.4 + 0.01j, 0.5) as ctx2:
         y = ctx2.vector(len(beams))
         ctx2.checkpoint_load(path, y)
