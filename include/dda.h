@@ -214,7 +214,8 @@ dda_status dda_matvec_f32(dda_ctx *ctx, const dda_beam *beam, const void *x, voi
 
 /*
  * dda_matvec_batch — y_r = A_r x_r for n_rhs vectors sharing the particle: one pass over the
- * Fourier-space tensor per batch.  beams[n_rhs]; x, y device complex128 [n_rhs][3][N].
+ * Fourier-space tensor per batch.  beams[n_rhs]; x, y device complex128 [n_rhs][3][N] (x and y
+ * must not overlap).
  */
 dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, const void *x, void *y);
 
@@ -227,7 +228,9 @@ dda_status dda_matvec_batch(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
  *   x_out   device complex128 [n_rhs][3][N]; receives x (P = beta x)
  *   info    host [n_rhs] or NULL
  * Returns DDA_OK if every right-hand side converged, else the first failing status
- * (DDA_ENOTCONV / DDA_EBREAKDOWN); per-RHS statuses are in info.
+ * (DDA_ENOTCONV / DDA_EBREAKDOWN); per-RHS statuses are in info.  DDA_EINVAL for bad arguments or
+ * options; DDA_ENOTSUP for single precision on a context of several materials or CLDR, or on one
+ * built without opts.fp32.
  * With the environment variable DDA_PROGRESS set to a number of seconds, a running solve prints
  * the iteration count and residual of every unconverged right-hand side to stderr that often.
  */
