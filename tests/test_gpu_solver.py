@@ -530,6 +530,32 @@ def test_orientation_average_of_an_inhomogeneous_particle_matches_oracle(pol):
         assert abs(got[q] - ref[q]) < 1e-9 * abs(ref["Cext"]), (q, got, ref)
 
 
+def test_extension_consistency_checks():
+    dda = _dda()
+    mask = inputs.ellipsoid_mask((8, 7, 6), (4, 3.5, 3))
+    m, kd = 1.3 + 0.05j, 0.6
+    beam = inputs.Beam((0.0, 0.6, 0.8), (1.0 + 0j, 0j, 0j))
+    x = torch.from_numpy(inputs.random_vector(int(np.count_nonzero(mask)), seed=9, n_rhs=1)[0]).cuda()
+    # one material through dda_setup_materials is dda_setup, bitwise
+    with dda.Context(mask, m, kd) as a, dda.Context(mask, [m], kd) as b:
+        assert torch.equal(a.matvec(beam, x), b.matvec(beam, x))
+        xa, _, st = a.solve([beam], tol=1e-10)
+        cext_plane = a.cross_sections(beam, xa[0].contiguous())[0]
+    # a focused beam much wider than the particle is the plane wave with its phase taken at the
+    # focus (here the origin): the same Cext
+    with dda.Context(mask, m, kd) as a:
+        wide = inputs.Beam(beam.prop, beam.pol, 2e4 / kd, (0.0, 0.0, 0.0))
+        xw, _, st = a.solve([wide], tol=1e-10)
+        assert st == 0
+        assert abs(a.cross_sections(wide, xw[0].contiguous())[0] - cext_plane) < 1e-6 * abs(cext_plane)
+    # the timing aid and the tuner take homogeneous contexts only
+    two = mask.astype(np.uint8).copy()
+    two[:, :, 4:] *= 2
+    with dda.Context(two, [m, 1.1], kd) as c:
+        with pytest.raises(dda.DDAError):
+            c.tune(dda.FP64)
+
+
 def test_inhomogeneous_particle_with_a_focused_beam_and_resume():
     # the extensions together: two materials, a focused beam, a solve stopped at its limit and
     # continued bitwise, and the cross sections against the oracle
