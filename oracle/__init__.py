@@ -8,8 +8,10 @@ CPU-baseline leg of the benchmark may import this package; the GPU library never
 does, and this package imports nothing from the GPU library.
 
 Modules
-  dda  — lattice, polarizability, Green's tensor, interaction matrix (dense and direct
-         sum), incident field, QMR and Bi-CGSTAB, cross sections, far field, Mueller.
+  dda  — lattice, polarizabilities (CM, RR, LDR, CLDR; per material), Green's tensor,
+         interaction matrix (dense and direct sum), incident field (plane wave, focused
+         beam), QMR, Bi-CG, Bi-CGSTAB and CGNR, cross sections, far field, Mueller,
+         asymmetry parameter, orientation averages (fixed and adaptive Romberg, Mueller).
   mie  — Mie theory for a homogeneous sphere (the exact reference the paper compares to).
   convnet — the learned-initial-guess network: forward, masked loss, exact gradient, and the
          features / target / guess maps between a DDA solution and the network's grid.
