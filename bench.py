@@ -299,6 +299,25 @@ def materials_study(dda, inputs, torch, n=256, reps=10):
     return out
 
 
+def product_only(dda, inputs, torch, reps):
+    """The 256^3 sphere's fp64 product on a batch of both polarizations: tile schedule tuned for that
+    batch, then `reps` products with HIP events around every kernel; ms per launch and the fraction
+    of the HBM peak from the algorithmic bytes."""
+    w = inputs.c2_sphere256()
+    n = w.grid[0]
+    beams = [inputs.X_POL, inputs.Y_POL]
+    with dda.Context(w.mask, w.m, w.kd) as ctx:
+        L, N = ctx.padded_grid()[0], ctx.n
+        tiles = ctx.tune(dda.FP64, n_rhs=len(beams))
+        x = torch.from_numpy(inputs.random_vector(N, seed=1, n_rhs=len(beams))).cuda()
+        y = torch.empty_like(x)
+        kms, tot = ctx.matvec_timed(beams, x, y, reps=reps)
+    ab = alg_bytes(n, N, L, 16, len(beams))
+    return {"workload": f"{w.name}, fp64, batch of {len(beams)}", "tiles": tiles, "reps": reps, "total_ms": tot,
+            "kernels": {k: {"ms": kms[i], "frac": ab[k] / kms[i] / 1e6 / HBM_PEAK_GBS} for i, k in enumerate(KERNELS)},
+            "product_frac": sum(ab.values()) / tot / 1e6 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +334,10 @@ def main():
                     help="only: QMR, Bi-CG, Bi-CGSTAB and CGNR on a 64^3 sphere with x = 20, m = 1.8")
     ap.add_argument("--materials-study", action="store_true",
                     help="only: wrapped products (two materials, CLDR) and focused-beam right-hand sides, 256^3")
+    ap.add_argument("--product-only", action="store_true",
+                    help="only: the 256^3 sphere's product on a batch of both polarizations, per-kernel HIP-event "
+                         "times over --reps products (a short run for counter profiles)")
+    ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -331,6 +354,9 @@ def main():
         return
     if args.materials_study:
         print(json.dumps(materials_study(dda, inputs, torch)), flush=True)
+        return
+    if args.product_only:
+        print(json.dumps(product_only(dda, inputs, torch, args.reps)), flush=True)
         return
 
     if args.calibration_copy:

@@ -122,8 +122,8 @@ typedef struct {
     int32_t x0_check;      /* 1: keep x0 for a right-hand side only if |b - A x0| < |b|, else start from 0 */
     int32_t on_breakdown;  /* DDA_BREAKDOWN_REPORT (default) or DDA_BREAKDOWN_RECOVER, below */
     int32_t resume;        /* 1: continue this context's last double-precision solve, which stopped at
-                              its iteration limit (same beams, batch size and solver; x_out holding its
-                              iterate, or a checkpoint loaded by dda_checkpoint_load): right-hand sides
+                              its iteration limit (same beams, batch size and solver, else DDA_EINVAL;
+                              x_out holding its iterate, or a checkpoint loaded by dda_checkpoint_load): right-hand sides
                               at their limit get maxit more iterations toward tol, exactly as if the
                               solve had not stopped; iters and matvecs count from its start; no
                               residual history */
@@ -243,7 +243,8 @@ dda_status dda_solve(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, double 
  * to and from a file, to continue it later with opts.resume (the paper's program checkpoints long
  * runs, Sec. 2).  x: device complex128 [n_rhs][3][N], the iterate (read by save, written by load).
  * The file belongs to this library build and the same particle: its header holds a hash of the
- * grid, mask (materials), refractive indices, kd and polarizability prescription, checked on load.
+ * grid, mask (materials), refractive indices, kd and polarizability prescription, checked on load,
+ * and a hash of the stopped solve's beams, which the continuing dda_solve must pass again.
  * Errors: DDA_EINVAL (nothing to save, unreadable or mismatched file), DDA_EHIP.
  */
 dda_status dda_checkpoint_save(dda_ctx *ctx, const void *x, const char *path);

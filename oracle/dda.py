@@ -20,7 +20,8 @@ import numpy as np
 
 # Lattice-dispersion-relation coefficients (Draine & Goodman 1993, the paper's ref. [13];
 # the paper names LDR as the polarizability used in all its runs, Sec. 3.1, but does not
-# print them).  parity unpinned against the paper itself.
+# print them).  Pinned by the dispersion relation itself: the k^2 coefficient of the Ewald-
+# summed Bloch lattice sum of an infinite cubic lattice (tests/test_oracle_ldr.py).
 LDR_B1 = -1.8915316
 LDR_B2 = 0.1648469
 LDR_B3 = -1.7700004
@@ -80,8 +81,9 @@ def alpha_ldr(m, k, prop, pol):
 
     1/alpha = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 S) k^2 - (2/3) i k^3.
     pinned by: the CM limit as k -> 0; Im(1/alpha) = -(2/3) k^3 for real m (radiative
-    reaction), which the optical-theorem test checks through the cross sections.
-    The three b coefficients: parity unpinned (not printed in the paper).
+    reaction), which the optical-theorem test checks through the cross sections; the k^2
+    coefficient (b1, b2, b3 and S) against the lattice dispersion relation of an infinite cubic
+    lattice, its Bloch-mode lattice sum evaluated by Ewald summation (tests/test_oracle_ldr.py).
     """
     m2 = complex(m) ** 2
     S = ldr_s(prop, pol)
@@ -95,8 +97,9 @@ def alpha_cldr(m, k, prop):
     1/alpha_jj = 1/alpha_CM + (b1 + m^2 b2 + m^2 b3 a_j^2) k^2 - (2/3) i k^3, j = x, y, z.
     Returns the three diagonal elements.
     pinned by: the CM limit as k -> 0; for a and the polarization e along lattice axes the
-    element along e equals LDR's (a_e = 0 and S = 0); Im(1/alpha_jj) = -(2/3) k^3 for real m.
-    The form and the b coefficients: parity unpinned (the paper names CLDR only)."""
+    element along e equals LDR's (a_e = 0 and S = 0); Im(1/alpha_jj) = -(2/3) k^3 for real m; the
+    quadratic form on every transverse polarization against the lattice dispersion relation (the
+    k^2 coefficient of the Ewald-summed lattice tensor) for a direction off the symmetry axes."""
     m2 = complex(m) ** 2
     a = np.asarray(prop, dtype=np.float64)
     inv = 1.0 / alpha_cm(m) + (LDR_B1 + m2 * LDR_B2 + m2 * LDR_B3 * a * a) * k * k - (2.0 / 3.0) * 1j * k ** 3

@@ -9,7 +9,9 @@ by upward recurrence.
 pinned by: Rayleigh limit (closed form), Qext = Qsca for real m, Qext from the series equal
 to (4/x^2) Re S(0) (forward-scattering theorem), the extinction-paradox limit Qext -> 2 at
 large x, and the worked example that Bohren & Huffman print for their BHMIE program
-(tests/golden/).
+(tests/golden/); the Mueller elements by the Rayleigh closed form, the identity
+S11^2 = S12^2 + S33^2 + S34^2 of a single amplitude pair, and the Stokes parameters of the
+scattered field computed from their definitions.
 """
 from __future__ import annotations
 
@@ -86,6 +88,21 @@ def s11(x, m, theta):
     """Unnormalized S11 = (|S1|^2 + |S2|^2) / 2."""
     S1, S2 = amplitudes(x, m, theta)
     return 0.5 * (np.abs(S1) ** 2 + np.abs(S2) ** 2)
+
+
+def mueller(x, m, theta):
+    """Nonzero elements of a sphere's Mueller matrix (Bohren & Huffman eq. 4.77, unnormalized):
+    S11 = (|S2|^2 + |S1|^2)/2, S12 = (|S2|^2 - |S1|^2)/2, S33 = Re(S2 S1^*), S34 = Im(S2 S1^*);
+    by the sphere's symmetry S22 = S11, S21 = S12, S44 = S33, S43 = -S34 and the rest vanish.
+    Returns (len(theta), 4, 4)."""
+    S1, S2 = amplitudes(x, m, theta)
+    M = np.zeros(S1.shape + (4, 4))
+    M[..., 0, 0] = M[..., 1, 1] = 0.5 * (np.abs(S2) ** 2 + np.abs(S1) ** 2)
+    M[..., 0, 1] = M[..., 1, 0] = 0.5 * (np.abs(S2) ** 2 - np.abs(S1) ** 2)
+    M[..., 2, 2] = M[..., 3, 3] = np.real(S2 * np.conj(S1))
+    M[..., 2, 3] = np.imag(S2 * np.conj(S1))
+    M[..., 3, 2] = -M[..., 2, 3]
+    return M
 
 
 def asymmetry(x, m):

@@ -74,6 +74,7 @@ struct Ctx {
     // (resume_nrhs = 0: nothing to continue)
     int resume_nrhs = 0;
     int resume_solver = -1;
+    uint64_t resume_beams = 0;  // hash of the beams of that solve (a continuation needs the same ones)
 
     // inhomogeneous particle (dda_setup_materials, nmat > 1) or CLDR (a diagonal polarizability
     // tensor): mask values name the material of each cell; the product runs with unit

@@ -241,9 +241,11 @@ __global__ void k_qmr_scal_2(SolveState *st, int *done, const double2 *part, int
     S.gamma_prev = gamma;
     S.rho = rho_new;
     if (rho_new == 0.0 || !isfinite(rho_new)) {
-        // the Krylov space is exhausted: this update is the last one
+        // rho_new = 0: the Krylov space is exhausted; not finite: the Lanczos recurrence has
+        // overflowed.  Either way this update is the last one, and the right-hand side stops as
+        // converged only if its residual meets tol (else breakdown)
         S.cp = make_double2(0, 0);
-        S.pending = 1;
+        S.pending = rho_new == 0.0 ? 1 : 2;
         return;
     }
     const double r2 = rho_new * rho_new;
@@ -304,10 +306,13 @@ __global__ void k_qmr_scal_3(SolveState *st, int *done, const double2 *part, int
     S.iter += 1;
     S.res = sqrt(s[0].x) / S.bnorm;
     if (hist && hcap > 0) hist[(size_t)rhs * hcap + (S.iter < hcap ? S.iter : hcap - 1)] = S.res;
-    if (S.res < S.tol || S.pending == 1) {
+    if (!isfinite(S.res)) {
+        S.status = ST_BREAK;
+        done[rhs] = 1;
+    } else if (S.res < S.tol) {
         S.status = ST_CONV;
         done[rhs] = 1;
-    } else if (S.pending == 2 || !isfinite(S.res)) {
+    } else if (S.pending != 0) {  // exhausted Krylov space, vanished v^T v or overflow, tol not met
         S.status = ST_BREAK;
         done[rhs] = 1;
     } else if (S.iter >= S.maxit) {
@@ -1013,6 +1018,15 @@ static dda_status init_states(Ctx &c, Bufs &B, double tol, int maxit, const int 
 // launches between convergence checks, and (optionally) that chunk captured once as a hipGraph
 // and replayed.  A right-hand side that is done turns every later kernel into a no-op, so
 // launching whole chunks past convergence never changes its iterate.
+// FNV-1a over the beams of a batch (propagation, polarization, waist, focus): with LDR or CLDR the
+// polarizability, and with it the matrix, depends on them, and the right-hand side always does
+static uint64_t beams_hash(const dda_beam *beams, int nrhs) {
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(beams);
+    for (size_t i = 0; i < (size_t)nrhs * sizeof(dda_beam); ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
 template <typename R> struct Run {
     Ctx *c = nullptr;
     Bufs B;
@@ -1028,6 +1042,7 @@ template <typename R> struct Run {
     bool fin = false;
     bool pending = false;
     bool mixed = false;  // double-precision Krylov vectors, single-precision transforms (R = double)
+    uint64_t beams_h = 0;  // beams_hash of the batch
     double progress = 0;  // seconds between progress lines on stderr (0: none)
     std::chrono::steady_clock::time_point last_report{};
     // stall guard of a mixed run: best relative residual of each right-hand side and the iteration
@@ -1364,6 +1379,7 @@ static dda_status prepare_fp64(Ctx &c, Run<double> &k, const dda_beam *beams, in
     k.x = x;
     k.solver = o.solver;
     k.mixed = o.precision == DDA_FP32_PRODUCT;
+    k.beams_h = beams_hash(beams, nrhs);
     for (int r = 0; r < nrhs; ++r)
         if ((st = rhs_launch<double>(c, beams[r], k.v.b + (size_t)r * k.B.n3, c.stream)) != DDA_OK) return st;
     if (o.x0 && o.x0 != x)
@@ -1400,6 +1416,7 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
         if (!k.mixed && h[r].status == ST_MAXIT) {
             c.resume_nrhs = nrhs;
             c.resume_solver = o.solver;
+            c.resume_beams = k.beams_h;
         }
     for (int r = 0; r < nrhs; ++r) {
         const dda_status sr = status_of(h[r].status);
@@ -1434,6 +1451,11 @@ static dda_status prepare_resume(Ctx &c, Run<double> &k, const dda_beam *beams, 
                   "no initial guess)");
         return DDA_EINVAL;
     }
+    if (c.resume_beams != beams_hash(beams, nrhs)) {
+        set_error("dda_solve: resume needs the beams of the stopped solve (they define its right-hand sides and, "
+                  "for LDR and CLDR, its matrix)");
+        return DDA_EINVAL;
+    }
     dda_status st;
     if ((st = ensure_vecs<double>(c, nrhs)) != DDA_OK) return st;
     if ((st = ensure_bufs(c, k.B, nrhs, 0)) != DDA_OK) return st;  // the states stay where they are
@@ -1446,6 +1468,7 @@ static dda_status prepare_resume(Ctx &c, Run<double> &k, const dda_beam *beams, 
     k.x = x;
     k.solver = o.solver;
     k.mixed = false;
+    k.beams_h = c.resume_beams;
     std::vector<SolveState> h;
     if ((st = fetch_states(c, k.B, h)) != DDA_OK) return st;
     std::vector<int> d(nrhs);
@@ -1760,6 +1783,7 @@ struct CkptHeader {
     int32_t version, nrhs, solver, state_bytes;
     int64_t N, vec_elems;
     uint64_t particle;  // particle_hash of the context that wrote it
+    uint64_t beams;     // beams_hash of the stopped solve
 };
 
 // FNV-1a over what defines the interaction matrix: grid, mask (materials), refractive indices, kd
@@ -1782,7 +1806,7 @@ static uint64_t particle_hash(const Ctx &c) {
     }
     return h;
 }
-static const char kCkptMagic[8] = {'D', 'D', 'A', 'C', 'K', 'P', 'T', '2'};
+static const char kCkptMagic[8] = {'D', 'D', 'A', 'C', 'K', 'P', 'T', '3'};
 
 static dda_status ckpt_io(FILE *f, void *dev, size_t bytes, bool write, hipStream_t s) {
     std::vector<char> buf(std::min<size_t>(bytes, (size_t)64 << 20));
@@ -1825,8 +1849,9 @@ extern "C" dda_status dda_checkpoint_save(dda_ctx *h, const void *x, const char 
     if (st != DDA_OK) return st;
     CkptHeader hd{};
     std::memcpy(hd.magic, kCkptMagic, 8);
-    hd.version = 2;
+    hd.version = 3;
     hd.particle = particle_hash(*c);
+    hd.beams = c->resume_beams;
     hd.nrhs = nrhs;
     hd.solver = c->resume_solver;
     hd.state_bytes = (int32_t)(nrhs * sizeof(SolveState));
@@ -1865,7 +1890,7 @@ extern "C" dda_status dda_checkpoint_load(dda_ctx *h, void *x, const char *path)
     }
     CkptHeader hd{};
     dda_status st = DDA_OK;
-    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2 ||
+    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 3 ||
         hd.particle != particle_hash(*c) ||
         hd.nrhs < 1 || hd.N != c->N || hd.state_bytes != (int32_t)(hd.nrhs * sizeof(SolveState)) ||
         hd.vec_elems != (int64_t)kNumVecs * hd.nrhs * 3 * c->N ||
@@ -1882,6 +1907,7 @@ extern "C" dda_status dda_checkpoint_load(dda_ctx *h, void *x, const char *path)
     std::fclose(f);
     c->resume_nrhs = st == DDA_OK ? hd.nrhs : 0;
     c->resume_solver = hd.solver;
+    c->resume_beams = hd.beams;
     return st;
 }
 

@@ -319,6 +319,11 @@ def test_resume_and_checkpoint_continue_exactly(solver, tmp_path):
         _, _, st = ctx.solve(beams, x_out=x, resume=True, raise_on_fail=False, **kw)
         assert st == dda.EINVAL
         x, _, st = ctx.solve(beams, maxit=4, raise_on_fail=False, **kw)
+        # another beam (another right-hand side and, under LDR, another matrix) is refused, and
+        # the refusal leaves the stopped state to continue
+        other = inputs.beams_for_orientations(1, seed=42)
+        _, _, st = ctx.solve(other, x_out=x.clone(), resume=True, raise_on_fail=False, **kw)
+        assert st == dda.EINVAL
         path = str(tmp_path / "solve.ckpt")
         ctx.checkpoint_save(path, x)
     with dda.Context(mask, 1.4 + 0.02j, 0.5) as ctx3:  # another particle (m) with the same dipoles
@@ -327,6 +332,8 @@ def test_resume_and_checkpoint_continue_exactly(solver, tmp_path):
     with dda.Context(mask, 1.4 + 0.01j, 0.5) as ctx2:
         y = ctx2.vector(len(beams))
         ctx2.checkpoint_load(path, y)
+        _, _, st = ctx2.solve(other, x_out=y.clone(), resume=True, raise_on_fail=False, **kw)
+        assert st == dda.EINVAL  # the file carries the beams of the stopped solve
         y2, i3, st = ctx2.solve(beams, x_out=y, resume=True, **kw)
         assert st == 0 and torch.equal(y2, xf)
         assert [i["iters"] for i in i3] == [i["iters"] for i in inf]

@@ -60,6 +60,36 @@ def test_single_dipole_is_rayleigh_scatterer():
     np.testing.assert_allclose(M[:, 0, 0], a2 * (1 + c * c) / 2, rtol=1e-13)
     np.testing.assert_allclose(M[:, 0, 1], a2 * (c * c - 1) / 2, rtol=0, atol=1e-13 * a2)
     np.testing.assert_allclose(M[:, 2, 2], a2 * c, rtol=0, atol=1e-13 * a2)
+    # S44 = S33 and S34 = S43 = 0: the dipole's S1 and S2 are in phase
+    np.testing.assert_allclose(M[:, 3, 3], a2 * c, rtol=0, atol=1e-13 * a2)
+    np.testing.assert_allclose(M[:, 2, 3], 0.0, rtol=0, atol=1e-13 * a2)
+    np.testing.assert_allclose(M[:, 3, 2], 0.0, rtol=0, atol=1e-13 * a2)
+
+
+def _stokes(Epar, Eperp):
+    """Stokes vector of a field from its components parallel and perpendicular to the scattering
+    plane, by the definitions of Bohren & Huffman (eq. 2.84): I = |E_par|^2 + |E_perp|^2,
+    Q = |E_par|^2 - |E_perp|^2, U = E_par E_perp^* + E_perp E_par^*, V = i (E_par E_perp^* - E_perp E_par^*)."""
+    a = Epar * np.conj(Eperp)
+    return np.array([abs(Epar) ** 2 + abs(Eperp) ** 2, abs(Epar) ** 2 - abs(Eperp) ** 2,
+                     (a + np.conj(a)).real, (1j * (a - np.conj(a))).real])
+
+
+def test_mueller_formula_equals_the_stokes_transfer_of_the_amplitude_matrix():
+    """Every element of the Mueller matrix formula, checked against its meaning: the scattered
+    field is (E_par, E_perp)_s = [[S2, S3], [S4, S1]] (E_par, E_perp)_i (Bohren & Huffman eq. 3.12,
+    common factor dropped), and the Mueller matrix maps the incident Stokes vector to the scattered
+    one.  Four incident states (parallel, perpendicular, +45 degrees, circular) give its four
+    columns; generic amplitudes leave no element zero."""
+    rng = np.random.default_rng(11)
+    S1, S2, S3, S4 = (rng.standard_normal(6) + 1j * rng.standard_normal(6) for _ in range(4))
+    M = dda.mueller_from_amplitudes(S1, S2, S3, S4)
+    states = [(1.0, 0.0), (0.0, 1.0), (1 / math.sqrt(2), 1 / math.sqrt(2)), (1 / math.sqrt(2), 1j / math.sqrt(2))]
+    for q in range(6):
+        Si = np.array([_stokes(complex(a), complex(b)) for a, b in states]).T          # columns: incident
+        Ss = np.array([_stokes(S2[q] * a + S3[q] * b, S4[q] * a + S1[q] * b) for a, b in states]).T
+        ref = Ss @ np.linalg.inv(Si)
+        assert np.abs(M[q] - ref).max() < 1e-12 * np.abs(ref).max()
 
 
 def test_s11_one_polarization_equals_two():
@@ -120,6 +150,28 @@ def test_mie_energy_and_forward_theorem():
             assert qabs > 0
 
 
+def test_mie_mueller_rayleigh_limit_and_single_amplitude_pair_identity():
+    th = np.radians(np.arange(0.0, 181.0, 5.0))
+    c = np.cos(th)
+    M = mie.mueller(1e-3, 1.5, th)  # corrections to the dipole are O(x^2)
+    s11 = M[:, 0, 0]
+    np.testing.assert_allclose(M[:, 0, 1] / s11, -(1 - c * c) / (1 + c * c), rtol=0, atol=1e-6)
+    np.testing.assert_allclose(M[:, 2, 2] / s11, 2 * c / (1 + c * c), rtol=0, atol=1e-6)
+    np.testing.assert_allclose(M[:, 3, 3], M[:, 2, 2], rtol=0, atol=0)
+    assert np.abs(M[:, 2, 3] / s11).max() < 1e-6
+    # one amplitude pair: a pure Mueller matrix, S11^2 = S12^2 + S33^2 + S34^2 at every angle
+    for x, m in [(3.368, 1.5), (6.0, 1.33 + 0.1j)]:
+        M = mie.mueller(x, m, th)
+        lhs = M[:, 0, 0] ** 2
+        rhs = M[:, 0, 1] ** 2 + M[:, 2, 2] ** 2 + M[:, 2, 3] ** 2
+        assert np.abs(lhs - rhs).max() < 1e-12 * lhs.max()
+        assert np.abs(M[:, 2, 3] / M[:, 0, 0]).max() > 0.2  # S34 is far from zero here
+        # the general amplitude-matrix formula with S3 = S4 = 0 gives the same matrix
+        S1, S2 = mie.amplitudes(x, m, th)
+        G = dda.mueller_from_amplitudes(S1, S2, np.zeros_like(S1), np.zeros_like(S1))
+        assert np.abs(G - M).max() < 1e-12 * M[:, 0, 0].max()
+
+
 def test_mie_extinction_paradox():
     # geometric-optics limit Qext -> 2, approached like x^(-2/3) (edge term)
     q400 = mie.efficiencies(400.0, 1.33)[0]
@@ -154,3 +206,15 @@ def test_sphere16_against_mie_and_paper_accuracy():
     assert np.abs(rel).max() < acc["small_particles_s11_max_rel_error"]["value"]
     assert math.sqrt(np.mean(rel ** 2)) < acc["s11_rms_rel_error_range"]["max"]
     assert abs(cabs) < 1e-12 * cext
+    # the other elements of the matrix (Sec. 3.1: all Mueller elements in one plane are compared
+    # with Mie theory): each within the paper's S11 bound relative to S11 (every element is at most
+    # S11 in size), and of Mie's sign wherever Mie's element is a quarter of S11 or more.  A sign
+    # slip in S34 or S44 would miss by up to 0.9 and 2 S11 here.
+    Mm = mie.mueller(xe, w.m, th)
+    s11 = Mm[:, 0, 0]
+    for i in range(4):
+        for j in range(4):
+            d = np.abs(M[:, i, j] - Mm[:, i, j]) / s11
+            assert d.max() < acc["small_particles_s11_max_rel_error"]["value"], (i, j, d.max())
+            big = np.abs(Mm[:, i, j]) > 0.25 * s11
+            assert np.all(np.sign(M[big, i, j]) == np.sign(Mm[big, i, j])), (i, j)

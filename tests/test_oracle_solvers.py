@@ -99,6 +99,23 @@ def test_circular_polarization_is_a_breakdown_not_a_nan():
     assert np.all(np.isfinite(x))
 
 
+def test_exhausted_krylov_space_converges_only_when_tol_is_met():
+    # A = 2I: the first Lanczos step leaves vt = A v - beta v = 0 exactly (rho = 0), and the QMR
+    # update gives x = b / 2 up to one rounding.  The exit counts as converged when the residual
+    # meets tol and as a breakdown when it does not (tol below the rounding of that update): the
+    # rule the device solver follows too, so a vanished or non-finite Lanczos norm never reports
+    # convergence with a residual above tol.
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((5, 3)) + 1j * rng.standard_normal((5, 3))
+    mv = lambda v: 2.0 * v
+    x, info = dda.qmr(mv, b, 1e-8)
+    assert info["status"] == "converged" and info["iters"] == 1
+    assert np.allclose(x, b / 2, rtol=0, atol=1e-15 * np.abs(b).max())
+    x, info = dda.qmr(mv, b, 1e-300)
+    assert info["status"] == "breakdown" and info["iters"] == 1
+    assert info["res_rec"] >= 1e-300
+
+
 def test_maxit_and_zero_iterations():
     pos, alpha, beta, A, b, mv = _system()
     x, info = dda.qmr(mv, b, 1e-12, maxit=3)
