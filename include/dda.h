@@ -213,6 +213,22 @@ dda_status dda_matvec(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y
 dda_status dda_matvec_f32(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y);
 
 /*
+ * dda_matvec_noalloc — dda_matvec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same result bit for bit, with the intermediates of the transforms (and the polarizability scale)
+ * in a fixed 128 MiB device array of the library instead of buffers of the context, so the call
+ * allocates nothing and makes no allocating library call.  The first call on a device resolves
+ * that array's address (hipGetSymbolAddress; make it outside graph capture).  Every call on one
+ * device shares the array: calls that overlap on one device (other streams, other threads, other
+ * contexts) race and must be ordered by the caller.  Homogeneous contexts only.
+ *   x, y   device complex128 [3][N]; must not overlap
+ * Errors: DDA_EINVAL (null pointers, overlap, or a particle whose intermediates exceed 128 MiB:
+ * 48 (nz Lx ny + nz Lx Ly) bytes plus alignment), DDA_ENOTSUP (several materials or CLDR),
+ * DDA_EHIP.
+ */
+dda_status dda_matvec_noalloc(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y);
+
+/*
  * dda_matvec_batch — y_r = A_r x_r for n_rhs vectors sharing the particle: one pass over the
  * Fourier-space tensor per batch.  beams[n_rhs]; x, y device complex128 [n_rhs][3][N] (x and y
  * must not overlap).

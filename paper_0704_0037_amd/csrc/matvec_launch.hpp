@@ -57,12 +57,14 @@ template <class K> inline void allow_lds(K kernel, size_t bytes) {
 #define DDA_CASE_k_inv_y(L) case L: allow_lds(&k_inv_y<R, L>, DDA_BYTES); hipLaunchKernelGGL((k_inv_y<R, L>), DDA_ARGS); break;
 #define DDA_CASE_k_inv_x(L) case L: allow_lds(&k_inv_x<R, L, RX>, DDA_BYTES); hipLaunchKernelGGL((k_inv_x<R, L, RX>), DDA_ARGS); break;
 
-// Transforms in precision R on the work buffers of precision R; x, y, scale and dots in RX.
+// Transforms in precision R on the work buffers of precision R (the context's, or the
+// intermediates B1 / B2 of `wk` when given); x, y, scale and dots in RX.
 template <typename R, typename RX = R>
 dda_status matvec_device_impl(Ctx &c, const cplx<RX> *x, cplx<RX> *y, int nrhs, const cplx<RX> *scale,
-                              cplx<RX> *dots, hipStream_t s, const int *done, hipEvent_t *ev) {
+                              cplx<RX> *dots, hipStream_t s, const int *done, hipEvent_t *ev,
+                              const Work<R> *wk = nullptr) {
     using C = cplx<R>;
-    Work<R> &w = work_of<R>(c);
+    const Work<R> &w = wk ? *wk : work_of<R>(c);
     const C *tw = tw_of<R>(c);
     const C *gh = ghat_of<R>(c);
     const int ncomp = 3 * nrhs;

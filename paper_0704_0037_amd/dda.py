@@ -78,6 +78,7 @@ _SIGS = {
                                                     ct.POINTER(ct.c_int32)]),
     "dda_rhs": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
     "dda_matvec": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
+    "dda_matvec_noalloc": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
     "dda_matvec_f32": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
     "dda_matvec_batch": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_void_p, ct.c_void_p]),
     "dda_solve": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_double, ct.POINTER(SolveOpts),
@@ -252,6 +253,12 @@ class Context:
         y = self.vector() if y is None else y
         _check(lib().dda_matvec(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
                                 _ptr(y, torch.complex128, (3, self.n), "y")), "dda_matvec")
+        return y
+
+    def matvec_noalloc(self, beam, x, y):
+        """dda_matvec_noalloc: the product with the library's fixed work array (y given by the caller)."""
+        _check(lib().dda_matvec_noalloc(self._h, ct.byref(_beam(beam)), _ptr(x, torch.complex128, (3, self.n), "x"),
+                                        _ptr(y, torch.complex128, (3, self.n), "y")), "dda_matvec_noalloc")
         return y
 
     def matvec_f32(self, beam, x, y=None):
