@@ -81,8 +81,14 @@ enum { DDA_QMR = 0, DDA_BICGSTAB = 1, DDA_BICG = 2, DDA_CGNR = 3 };
  * the FFTs and the tensor multiply in single precision (x, y and the epilogue in double), to
  * max(tol, 1e-6), or until its residual stalls (no halving within as many iterations as its best
  * value took, at least 5000); a right-hand side whose true residual misses tol afterwards is
- * finished in DDA_FP64 from there (from zero if that iterate is no better than zero). */
-enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1, DDA_FP32_PRODUCT = 2 };
+ * finished in DDA_FP64 from there (from zero if that iterate is no better than zero).
+ * DDA_FP32_RELAXED: DDA_FP32_PRODUCT whose products start in double precision and switch to single
+ * precision once the recursive residual of every right-hand side of the batch is below relax_at
+ * (default 100 tol): the accuracy a product needs falls as the residual falls (inexact Krylov
+ * methods), so the rounding of single-precision transforms, which stalls a strongly scattering
+ * particle's solve when it enters at the first iteration, enters here scaled by the residual
+ * reached.  Stall guard and double-precision finish as DDA_FP32_PRODUCT. */
+enum { DDA_FP64 = 0, DDA_FP32_REFINE = 1, DDA_FP32_PRODUCT = 2, DDA_FP32_RELAXED = 3 };
 
 /* Incident beam in the particle frame: unit propagation vector and complex unit polarization.
  * w0 = 0: the plane wave E_inc(r) = pol * exp(i kd prop.r).
@@ -127,6 +133,8 @@ typedef struct {
                               at their limit get maxit more iterations toward tol, exactly as if the
                               solve had not stopped; iters and matvecs count from its start; no
                               residual history */
+    double relax_at;       /* DDA_FP32_RELAXED: relative residual below which the products switch to
+                              single precision; 0 = 100 tol */
 } dda_solve_opts;
 
 /* What dda_solve does when QMR or Bi-CG breaks down for a right-hand side (the paper does not

@@ -1042,6 +1042,8 @@ template <typename R> struct Run {
     bool fin = false;
     bool pending = false;
     bool mixed = false;  // double-precision Krylov vectors, single-precision transforms (R = double)
+    double relax_at = 0;  // > 0: double-precision products until every residual is below it, then mixed
+    int switch_it = 0;    // iteration of the switch to single-precision products (0: from the start)
     uint64_t beams_h = 0;  // beams_hash of the batch
     double progress = 0;  // seconds between progress lines on stderr (0: none)
     std::chrono::steady_clock::time_point last_report{};
@@ -1060,6 +1062,7 @@ template <typename R> struct Run {
 // the residual within as many iterations as the best residual took, and at least kStallMin.
 constexpr int kStallMin = 5000;
 constexpr double kGuardSeconds = 0.5;  // host-side stall checks at most this often
+constexpr double kRelaxSeconds = 0.05;  // host-side checks of the switch to single-precision products
 
 // Progress lines for long solves: the environment variable DDA_PROGRESS gives the seconds between
 // lines (unset or 0: silent).
@@ -1238,6 +1241,37 @@ template <typename R> static dda_status run_poll(Run<R> &k) {
     bool all = true;
     for (int r = 0; r < k.B.nrhs; ++r) all = all && hd[r];
     k.fin = all;
+    if (k.relax_at > 0 && !k.mixed && !k.fin) {
+        const auto now = std::chrono::steady_clock::now();
+        if (std::chrono::duration<double>(now - k.last_guard).count() >= kRelaxSeconds) {
+            k.last_guard = now;
+            std::vector<int> d(hd, hd + k.B.nrhs);
+            std::vector<SolveState> h;
+            dda_status st = fetch_states(*k.c, k.B, h);  // the stream is idle here
+            if (st != DDA_OK) return st;
+            double worst = 0;
+            for (int r = 0; r < k.B.nrhs; ++r)
+                if (!d[r]) worst = std::max(worst, h[r].res);
+            if (worst < k.relax_at) {
+                // every active right-hand side is below the threshold: the later iterations run the
+                // single-precision transforms (a captured chunk is captured again with them)
+                k.mixed = true;
+                if (k.ge) (void)hipGraphExecDestroy(k.ge);
+                if (k.g) (void)hipGraphDestroy(k.g);
+                k.ge = nullptr;
+                k.g = nullptr;
+                k.chunks = 0;
+                int it = 0;
+                for (int r = 0; r < k.B.nrhs; ++r) {
+                    k.best[r] = h[r].res;
+                    k.best_it[r] = h[r].iter;
+                    it = std::max(it, h[r].iter);
+                }
+                k.switch_it = it;
+                k.last_guard = now;
+            }
+        }
+    }
     if (k.mixed && !k.fin) {
         const auto now = std::chrono::steady_clock::now();
         if (std::chrono::duration<double>(now - k.last_guard).count() >= kGuardSeconds) {
@@ -1252,7 +1286,7 @@ template <typename R> static dda_status run_poll(Run<R> &k) {
                 if (h[r].res < 0.5 * k.best[r]) {
                     k.best[r] = h[r].res;
                     k.best_it[r] = h[r].iter;
-                } else if (h[r].iter - k.best_it[r] > std::max(kStallMin, k.best_it[r])) {
+                } else if (h[r].iter - k.best_it[r] > std::max(kStallMin, k.best_it[r] - k.switch_it)) {
                     // stop it: its done flag makes every later iteration skip it
                     static const int one = 1;
                     DDA_HIP_CHECK(hipMemcpyAsync(k.B.done + r, &one, sizeof(int), hipMemcpyHostToDevice,
@@ -1379,7 +1413,10 @@ static dda_status prepare_fp64(Ctx &c, Run<double> &k, const dda_beam *beams, in
     k.x = x;
     k.solver = o.solver;
     k.mixed = o.precision == DDA_FP32_PRODUCT;
+    k.relax_at = o.precision == DDA_FP32_RELAXED ? (o.relax_at > 0 ? o.relax_at : 100.0 * tol) : 0.0;
+    k.switch_it = 0;
     k.beams_h = beams_hash(beams, nrhs);
+    if (k.relax_at > 0 && (st = ensure_work<float>(c, nrhs)) != DDA_OK) return st;  // before any capture
     for (int r = 0; r < nrhs; ++r)
         if ((st = rhs_launch<double>(c, beams[r], k.v.b + (size_t)r * k.B.n3, c.stream)) != DDA_OK) return st;
     if (o.x0 && o.x0 != x)
@@ -1513,7 +1550,7 @@ static dda_status solve_fp64(Ctx &c, const dda_beam *beams, int nrhs, double tol
 static dda_status solve_products32(Ctx &c, const dda_beam *beams, int nrhs, double tol, const dda_solve_opts &o,
                                    double2 *x, dda_solve_info *info, int check_every, bool graph) {
     if (!c.ghat32) {
-        set_error("dda_solve: DDA_FP32_PRODUCT needs a context set up with opts.fp32");
+        set_error("dda_solve: DDA_FP32_PRODUCT and DDA_FP32_RELAXED need a context set up with opts.fp32");
         return DDA_ENOTSUP;
     }
     std::vector<dda_solve_info> first(nrhs);
@@ -1693,7 +1730,8 @@ static dda_status check_opts(const dda_solve_opts *opts, dda_solve_opts &o) {
         set_error("dda_solve: unknown solver");
         return DDA_EINVAL;
     }
-    if (o.precision != DDA_FP64 && o.precision != DDA_FP32_REFINE && o.precision != DDA_FP32_PRODUCT) {
+    if (o.precision != DDA_FP64 && o.precision != DDA_FP32_REFINE && o.precision != DDA_FP32_PRODUCT &&
+        o.precision != DDA_FP32_RELAXED) {
         set_error("dda_solve: unknown precision");
         return DDA_EINVAL;
     }

@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdda_mi3
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESYMMETRY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 POL_LDR, POL_CM, POL_RR, POL_CLDR = 0, 1, 2, 3
 QMR, BICGSTAB, BICG, CGNR = 0, 1, 2, 3
-FP64, FP32_REFINE, FP32_PRODUCT = 0, 1, 2
+FP64, FP32_REFINE, FP32_PRODUCT, FP32_RELAXED = 0, 1, 2, 3
 BREAKDOWN_REPORT, BREAKDOWN_RECOVER = 0, 1
 
 
@@ -35,7 +35,7 @@ class SolveOpts(ct.Structure):
     _fields_ = [("solver", ct.c_int32), ("precision", ct.c_int32), ("maxit", ct.c_int32),
                 ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p),
                 ("graph", ct.c_int32), ("x0_check", ct.c_int32), ("on_breakdown", ct.c_int32),
-                ("resume", ct.c_int32)]
+                ("resume", ct.c_int32), ("relax_at", ct.c_double)]
 
 
 class SolveInfo(ct.Structure):
@@ -322,12 +322,12 @@ class Context:
 
     def solve(self, beams, tol=1e-5, solver=QMR, precision=FP64, maxit=0, check_every=0, inner_tol=0.0, x0=None,
               x_out=None, history=0, raise_on_fail=True, graph=0, x0_check=False, on_breakdown=BREAKDOWN_REPORT,
-              resume=False):
+              resume=False, relax_at=0.0):
         n = len(beams)
         x_out = self.vector(n) if x_out is None else x_out
         opts = SolveOpts(solver, precision, maxit, check_every, inner_tol,
                          None if x0 is None else _ptr(x0, torch.complex128, (n, 3, self.n), "x0").value, graph,
-                         1 if x0_check else 0, on_breakdown, 1 if resume else 0)
+                         1 if x0_check else 0, on_breakdown, 1 if resume else 0, float(relax_at))
         infos = (SolveInfo * n)()
         hists = []
         for i in range(n):

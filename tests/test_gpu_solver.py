@@ -33,6 +33,13 @@ def _oracle_system(mask, m, kd, beam):
     return pos, alpha, beta, A, b
 
 
+def _oracle_qmr(A, b, tol):
+    """The oracle's QMR on the dense matrix A (b (N, 3)); x (N, 3) at relative residual tol."""
+    x, info = odda.qmr(lambda v: (A @ v.reshape(-1)).reshape(v.shape), b, tol)
+    assert info["status"] == "converged", info["status"]
+    return x
+
+
 @pytest.fixture(scope="module")
 def sphere16():
     dda = _dda()
@@ -125,9 +132,10 @@ def test_qmr_iterates_track_oracle():
     assert info[0]["iters"] == io["iters"]
     h = np.array(info[0]["res_hist"])
     ho = np.array(io["res_hist"])
-    # rounding differences grow along a Krylov run: tight early, looser as the residual falls
+    # the same recurrences in the same order: the histories (residuals relative to |b|) differ by
+    # rounding only, which stays near 1e-13 |b| however far the residual falls
     assert np.abs(h[:6] / ho[:6] - 1).max() < 1e-10
-    assert np.abs(h / ho - 1).max() < 1e-3
+    assert np.abs(h - ho).max() < 1e-11, np.abs(h - ho).max()
     assert np.linalg.norm(x[0].cpu().numpy().T - xo) / np.linalg.norm(xo) < 1e-9
 
 
@@ -275,6 +283,33 @@ def test_fp32_products_on_a_strongly_scattering_sphere_reach_tol():
         assert abs(c32 - c64) < 1e-6 * abs(c64)
 
 
+def test_fp32_relaxed_products_reach_tol_on_strongly_scattering_spheres():
+    """Double-precision products until the residual is small, single-precision ones after: the
+    solution of a 16^3 sphere with m = 2.5 against the oracle's dense LU, and a 32^3 sphere with
+    m = 3 (where single-precision products from the start stall) against the double-precision
+    solve, with the switch forced early (1e-3) and at its default (100 tol)."""
+    dda = _dda()
+    mask = inputs.sphere_mask(16)
+    beam = inputs.X_POL
+    pos, alpha, beta, A, b = _oracle_system(mask, 2.5, 0.3, beam)
+    x_lu = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    c_lu = odda.cross_sections(pos, 0.3, alpha, beta * x_lu, beam.prop, beam.pol)[0]
+    with dda.Context(mask, 2.5, 0.3, fp32=True) as ctx:
+        x, info, st = ctx.solve([beam], tol=1e-9, precision=dda.FP32_RELAXED, relax_at=1e-3)
+        assert st == 0 and info[0]["res_true"] < 1e-9
+        assert np.linalg.norm(x[0].cpu().numpy().T - x_lu) / np.linalg.norm(x_lu) < 1e-6
+        assert abs(ctx.cross_sections(beam, x[0].contiguous())[0] - c_lu) < 1e-8 * abs(c_lu)
+    mask = inputs.sphere_mask(32)
+    with dda.Context(mask, 3.0, 0.3, fp32=True) as ctx:
+        x64, i64, st64 = ctx.solve([beam], tol=1e-8)
+        c64 = ctx.cross_sections(beam, x64[0].contiguous())[0]
+        for relax in (1e-3, 0.0):
+            xr, ir, st = ctx.solve([beam], tol=1e-8, precision=dda.FP32_RELAXED, relax_at=relax, maxit=200000)
+            assert st == 0 and ir[0]["res_true"] < 1e-8, (relax, ir)
+            cr = ctx.cross_sections(beam, xr[0].contiguous())[0]
+            assert abs(cr - c64) < 1e-7 * abs(c64), (relax, cr, c64)
+
+
 def test_progress_lines_on_request(sphere16, capfd, monkeypatch):
     w, ctx = sphere16
     monkeypatch.setenv("DDA_PROGRESS", "1e-9")
@@ -409,8 +444,11 @@ def test_focused_beam_rhs_solution_and_cext_match_oracle(circular):
     alpha = odda.alpha_ldr(m, kd, prop, pol)
     bt = odda.beta_of_alpha(alpha)
     b_ref = odda.rhs(pos, kd, bt, prop, pol, w0, center)
-    x_ref = np.linalg.solve(odda.interaction_matrix(pos, kd, bt), b_ref.reshape(-1)).reshape(b_ref.shape)
-    cext, cabs = odda.cross_sections(pos, kd, alpha, bt * x_ref, prop, pol, w0, center)
+    A = odda.interaction_matrix(pos, kd, bt)
+    x_ref = np.linalg.solve(A, b_ref.reshape(-1)).reshape(b_ref.shape)
+    # parity protocol: the oracle's QMR to the same tolerance as the device's
+    x_q = _oracle_qmr(A, b_ref, 1e-11)
+    cext, cabs = odda.cross_sections(pos, kd, alpha, bt * x_q, prop, pol, w0, center)
     with dda.Context(mask, m, kd) as ctx:
         b = ctx.rhs(beam).cpu().numpy()  # [3][N]
         assert np.max(np.abs(b.T - b_ref)) < 1e-12 * np.max(np.abs(b_ref))
@@ -419,7 +457,7 @@ def test_focused_beam_rhs_solution_and_cext_match_oracle(circular):
         got = ctx.cross_sections(beam, x[0].contiguous())
         with pytest.raises(dda.DDAError):
             ctx.mueller(beam, x[0].contiguous(), None, 0.0, [0.5])
-    assert abs(got[0] - cext) < 1e-8 * abs(cext) and abs(got[1] - cabs) < 1e-8 * abs(cext)
+    assert abs(got[0] - cext) < 1e-9 * abs(cext) and abs(got[1] - cabs) < 1e-9 * abs(cext)
     assert np.max(np.abs(x[0].cpu().numpy().T - x_ref)) < 1e-8 * np.max(np.abs(x_ref))
 
 
@@ -442,7 +480,8 @@ def test_inhomogeneous_particle_matches_oracle():
         A = odda.interaction_matrix(pos, kd, bt)
         b = odda.rhs(pos, kd, bt, prop, pol)
         x = np.linalg.solve(A, b.reshape(-1)).reshape(N, 3)
-        ref.append((A, b, x, bt[:, None] * x, odda.cross_sections(pos, kd, alpha, bt[:, None] * x, prop, pol)))
+        xq = _oracle_qmr(A, b, 1e-11)  # the device's method and tolerance
+        ref.append((A, b, x, bt[:, None] * xq, odda.cross_sections(pos, kd, alpha, bt[:, None] * xq, prop, pol)))
     th = np.linspace(0.0, math.pi, 7)
     M_ref = odda.mueller(pos, kd, prop, pol1, ref[0][3], ref[1][3], th, 0.4)
     beams = [inputs.Beam(tuple(prop), tuple(pol1 + 0j)), inputs.Beam(tuple(prop), tuple(pol2 + 0j))]
@@ -460,13 +499,13 @@ def test_inhomogeneous_particle_matches_oracle():
             xs = x[r].cpu().numpy().T
             assert np.max(np.abs(xs - ref[r][2])) < 1e-8 * np.max(np.abs(ref[r][2]))
             cext, cabs, _ = ctx.cross_sections(beams[r], x[r].contiguous())
-            assert abs(cext - ref[r][4][0]) < 1e-8 * abs(ref[r][4][0])
-            assert abs(cabs - ref[r][4][1]) < 1e-8 * abs(ref[r][4][0])
+            assert abs(cext - ref[r][4][0]) < 1e-9 * abs(ref[r][4][0])
+            assert abs(cabs - ref[r][4][1]) < 1e-9 * abs(ref[r][4][0])
         M = ctx.mueller(beams[0], x[0].contiguous(), x[1].contiguous(), 0.4, th)
-        assert np.max(np.abs(M - M_ref)) < 1e-8 * np.max(np.abs(M_ref))
+        assert np.max(np.abs(M - M_ref)) < 1e-9 * np.max(np.abs(M_ref))
         csca, g = ctx.asymmetry(beams[0], x[0].contiguous(), 24, 48)
         cref, gref = odda.asymmetry(pos, kd, ref[0][3], prop, 24, 48)
-        assert abs(csca - cref) < 1e-8 * abs(cref) and abs(g - gref) < 1e-8
+        assert abs(csca - cref) < 1e-9 * abs(cref) and abs(g - gref) < 1e-9
         with pytest.raises(dda.DDAError):
             ctx.solve(beams, precision=dda.FP32_REFINE)
         with pytest.raises(dda.DDAError):
@@ -496,10 +535,12 @@ def test_cldr_matches_oracle(two_materials):
     A = odda.interaction_matrix(pos, kd, bt)
     P, xs_ref, cs_ref = [], [], []
     for pol in (pol1, pol2):
-        x = np.linalg.solve(A, odda.rhs(pos, kd, bt, prop, pol).reshape(-1)).reshape(N, 3)
+        b = odda.rhs(pos, kd, bt, prop, pol)
+        x = np.linalg.solve(A, b.reshape(-1)).reshape(N, 3)
         xs_ref.append(x)
-        P.append(bt * x)
-        cs_ref.append(odda.cross_sections(pos, kd, alpha, bt * x, prop, pol))
+        xq = _oracle_qmr(A, b, 1e-11)  # the device's method and tolerance
+        P.append(bt * xq)
+        cs_ref.append(odda.cross_sections(pos, kd, alpha, bt * xq, prop, pol))
     th = np.linspace(0.0, math.pi, 7)
     M_ref = odda.mueller(pos, kd, prop, pol1, P[0], P[1], th, 1.1)
     beams = [inputs.Beam(tuple(prop), tuple(pol1 + 0j)), inputs.Beam(tuple(prop), tuple(pol2 + 0j))]
@@ -514,10 +555,10 @@ def test_cldr_matches_oracle(two_materials):
         for r in range(2):
             assert np.max(np.abs(x[r].cpu().numpy().T - xs_ref[r])) < 1e-8 * np.max(np.abs(xs_ref[r]))
             cext, cabs, _ = ctx.cross_sections(beams[r], x[r].contiguous())
-            assert abs(cext - cs_ref[r][0]) < 1e-8 * abs(cs_ref[r][0])
-            assert abs(cabs - cs_ref[r][1]) < 1e-8 * abs(cs_ref[r][0])
+            assert abs(cext - cs_ref[r][0]) < 1e-9 * abs(cs_ref[r][0])
+            assert abs(cabs - cs_ref[r][1]) < 1e-9 * abs(cs_ref[r][0])
         M = ctx.mueller(beams[0], x[0].contiguous(), x[1].contiguous(), 1.1, th)
-        assert np.max(np.abs(M - M_ref)) < 1e-8 * np.max(np.abs(M_ref))
+        assert np.max(np.abs(M - M_ref)) < 1e-9 * np.max(np.abs(M_ref))
     with pytest.raises(dda.DDAError):
         dda.Context(mask, ms[0], kd, polarizability=dda.POL_CLDR, fp32=True)
 
@@ -576,7 +617,7 @@ def test_inhomogeneous_particle_with_a_focused_beam_and_resume():
     alpha = odda.material_alphas(mask, ms, kd, prop, pol)
     bt = np.sqrt(alpha)
     b = odda.rhs(pos, kd, bt, prop, pol, w0, center)
-    x_ref = np.linalg.solve(odda.interaction_matrix(pos, kd, bt), b.reshape(-1)).reshape(-1, 3)
+    x_ref = _oracle_qmr(odda.interaction_matrix(pos, kd, bt), b, 1e-11)  # the device's method and tolerance
     cext, cabs = odda.cross_sections(pos, kd, alpha, bt[:, None] * x_ref, prop, pol, w0, center)
     beam = inputs.Beam(tuple(prop), tuple(pol + 0j), w0, center)
     kw = dict(tol=1e-11, check_every=3, graph=-1)
@@ -584,7 +625,7 @@ def test_inhomogeneous_particle_with_a_focused_beam_and_resume():
         xf, inf, st = ctx.solve([beam], **kw)
         assert st == 0
         got = ctx.cross_sections(beam, xf[0].contiguous())
-        assert abs(got[0] - cext) < 1e-8 * abs(cext) and abs(got[1] - cabs) < 1e-8 * abs(cext)
+        assert abs(got[0] - cext) < 1e-9 * abs(cext) and abs(got[1] - cabs) < 1e-9 * abs(cext)
         x, _, st = ctx.solve([beam], maxit=5, raise_on_fail=False, **kw)
         assert st == dda.ENOTCONV
         x2, i2, st = ctx.solve([beam], x_out=x, resume=True, **kw)
@@ -741,7 +782,7 @@ def test_bicgstab_iterates_track_oracle():
             ho = np.array(io["res_hist"])
             assert len(h) == len(ho)
             assert np.abs(h[:4] / ho[:4] - 1).max() < 1e-8
-            assert np.abs(h / ho - 1).max() < 1e-3
+            assert np.abs(h - ho).max() < 1e-10, np.abs(h - ho).max()  # relative to |b|
             assert np.linalg.norm(x[0].cpu().numpy().T - xo) / np.linalg.norm(xo) < 1e-8
 
 
