@@ -159,7 +159,7 @@ def up_adjoint(g):
 
 # ------------------------------------------------------------------------------ network
 def forward(params, feat, bf16_round=False):
-    """Activations of one sample (feat [G][G][G][10]) as a dict; 'out' is the prediction."""
+    """Activations of one sample (feat [G][G][G][16], the 16 input channels) as a dict; 'out' is the prediction."""
     r = bf16 if bf16_round else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(r(W), np.asarray(b, dtype=np.float64)) for W, b in unflatten(params)]
     a = {"f": r(feat)}
@@ -186,7 +186,7 @@ def forward(params, feat, bf16_round=False):
 def loss_and_grad(params, feats, targets, masks, bf16_round=False):
     """Masked mean-square loss over a batch and its gradient w.r.t. the flat parameters.
 
-    feats [B][G][G][G][10], targets [B][G][G][G][6], masks [B][G][G][G] (0/1).
+    feats [B][G][G][G][16], targets [B][G][G][G][6], masks [B][G][G][G] (0/1).
     """
     r = bf16 if bf16_round else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(r(W), b) for W, b in unflatten(params)]

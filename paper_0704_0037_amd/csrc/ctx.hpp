@@ -68,6 +68,8 @@ struct Ctx {
     size_t hbuf_bytes = 0;
     double2 *red = nullptr;     // read-out partials
     size_t red_elems = 0;
+    void *snap = nullptr;       // state of a relaxed-precision solve at its switch (rolled back on stall)
+    size_t snap_bytes = 0;
 
     // a double-precision solve that stopped at its iteration limit leaves its complete state in
     // vecs / sbuf and can be continued (dda_solve with opts.resume): its batch size and method

@@ -315,6 +315,7 @@ void destroy(Ctx *c) {
     else (void)hipDeviceSynchronize();
     free_work(c->w64);
     free_work(c->w32);
+    (void)hipFree(c->snap);
     (void)hipFree(c->dmat);
     (void)hipFree(c->mat_beta);
     (void)hipFree(c->xtmp);

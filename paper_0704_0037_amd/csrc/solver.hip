@@ -1044,6 +1044,8 @@ template <typename R> struct Run {
     bool mixed = false;  // double-precision Krylov vectors, single-precision transforms (R = double)
     double relax_at = 0;  // > 0: double-precision products until every residual is below it, then mixed
     int switch_it = 0;    // iteration of the switch to single-precision products (0: from the start)
+    bool snapped = false; // the double-precision state at the switch is saved (c.snap)
+    bool rolled = false;  // the single-precision phase stalled and the saved state was restored
     uint64_t beams_h = 0;  // beams_hash of the batch
     double progress = 0;  // seconds between progress lines on stderr (0: none)
     std::chrono::steady_clock::time_point last_report{};
@@ -1063,6 +1065,50 @@ template <typename R> struct Run {
 constexpr int kStallMin = 5000;
 constexpr double kGuardSeconds = 0.5;  // host-side stall checks at most this often
 constexpr double kRelaxSeconds = 0.05;  // host-side checks of the switch to single-precision products
+// A relaxed run whose single-precision phase does not halve a residual within this many iterations
+// (or a tenth of the iterations before the switch, if more) goes back to the saved state.
+constexpr int kRelaxStallMin = 500;
+
+// Save (save = true) or restore the state a solve carries between iterations: the Krylov vectors,
+// the iterate, the per-RHS scalar states and done flags.
+static dda_status snapshot(Ctx &c, Bufs &B, double2 *vecs, double2 *x, bool save) {
+    const size_t L = (size_t)B.nrhs * B.n3;
+    const size_t vb = (size_t)7 * L * sizeof(double2), xb = L * sizeof(double2);  // the 7 slots of vecs_of
+    const size_t sb = (size_t)B.nrhs * sizeof(SolveState), db = (size_t)B.nrhs * sizeof(int);
+    const size_t need = vb + xb + sb + db + 256;
+    if (save && c.snap_bytes < need) {
+        DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+        (void)hipFree(c.snap);
+        c.snap = nullptr;
+        c.snap_bytes = 0;
+        dda_status st = device_alloc(&c.snap, need);
+        if (st != DDA_OK) return st;
+        c.snap_bytes = need;
+    }
+    char *p = static_cast<char *>(c.snap);
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    if (save) {
+        DDA_HIP_CHECK(hipMemcpyAsync(p, vecs, vb, k, c.stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(p + vb, x, xb, k, c.stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(p + vb + xb, B.st, sb, k, c.stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(p + vb + xb + sb, B.done, db, k, c.stream));
+    } else {
+        DDA_HIP_CHECK(hipMemcpyAsync(vecs, p, vb, k, c.stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(x, p + vb, xb, k, c.stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(B.st, p + vb + xb, sb, k, c.stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(B.done, p + vb + xb + sb, db, k, c.stream));
+    }
+    DDA_HIP_CHECK(hipStreamSynchronize(c.stream));
+    return DDA_OK;
+}
+
+template <typename R> static void drop_graph(Run<R> &k) {
+    if (k.ge) (void)hipGraphExecDestroy(k.ge);
+    if (k.g) (void)hipGraphDestroy(k.g);
+    k.ge = nullptr;
+    k.g = nullptr;
+    k.chunks = 0;
+}
 
 // Progress lines for long solves: the environment variable DDA_PROGRESS gives the seconds between
 // lines (unset or 0: silent).
@@ -1254,13 +1300,14 @@ template <typename R> static dda_status run_poll(Run<R> &k) {
                 if (!d[r]) worst = std::max(worst, h[r].res);
             if (worst < k.relax_at) {
                 // every active right-hand side is below the threshold: the later iterations run the
-                // single-precision transforms (a captured chunk is captured again with them)
+                // single-precision transforms (a captured chunk is captured again with them); the
+                // double-precision state is saved first, to go back to if that phase stalls
+                if constexpr (std::is_same<R, double>::value) {
+                    if ((st = snapshot(*k.c, k.B, k.c->vecs, k.x, true)) != DDA_OK) return st;
+                    k.snapped = true;
+                }
                 k.mixed = true;
-                if (k.ge) (void)hipGraphExecDestroy(k.ge);
-                if (k.g) (void)hipGraphDestroy(k.g);
-                k.ge = nullptr;
-                k.g = nullptr;
-                k.chunks = 0;
+                drop_graph(k);
                 int it = 0;
                 for (int r = 0; r < k.B.nrhs; ++r) {
                     k.best[r] = h[r].res;
@@ -1281,23 +1328,49 @@ template <typename R> static dda_status run_poll(Run<R> &k) {
             dda_status st = fetch_states(*k.c, k.B, h);  // the stream is idle here
             if (st != DDA_OK) return st;
             bool all = true;
-            for (int r = 0; r < k.B.nrhs; ++r) {
-                if (d[r]) continue;
-                if (h[r].res < 0.5 * k.best[r]) {
-                    k.best[r] = h[r].res;
-                    k.best_it[r] = h[r].iter;
-                } else if (h[r].iter - k.best_it[r] > std::max(kStallMin, k.best_it[r] - k.switch_it)) {
-                    // stop it: its done flag makes every later iteration skip it
-                    static const int one = 1;
-                    DDA_HIP_CHECK(hipMemcpyAsync(k.B.done + r, &one, sizeof(int), hipMemcpyHostToDevice,
-                                                 k.c->stream));
-                    DDA_HIP_CHECK(hipStreamSynchronize(k.c->stream));
-                    k.stalled[r] = 1;
-                    continue;
+            if (k.snapped) {
+                // relaxed run: a right-hand side that has not halved its residual within the window
+                // sends the whole batch back to the saved double-precision state, for good
+                const int window = std::max(kRelaxStallMin, k.switch_it / 10);
+                bool stall = false;
+                for (int r = 0; r < k.B.nrhs; ++r) {
+                    if (d[r]) continue;
+                    if (h[r].res < 0.5 * k.best[r]) {
+                        k.best[r] = h[r].res;
+                        k.best_it[r] = h[r].iter;
+                    } else if (h[r].iter - k.best_it[r] > window) {
+                        stall = true;
+                    }
                 }
-                all = false;
+                if (stall) {
+                    if constexpr (std::is_same<R, double>::value)
+                        if ((st = snapshot(*k.c, k.B, k.c->vecs, k.x, false)) != DDA_OK) return st;
+                    k.mixed = false;
+                    k.relax_at = 0;
+                    k.snapped = false;
+                    k.rolled = true;
+                    drop_graph(k);
+                    k.fin = false;
+                }
+            } else {
+                for (int r = 0; r < k.B.nrhs; ++r) {
+                    if (d[r]) continue;
+                    if (h[r].res < 0.5 * k.best[r]) {
+                        k.best[r] = h[r].res;
+                        k.best_it[r] = h[r].iter;
+                    } else if (h[r].iter - k.best_it[r] > std::max(kStallMin, k.best_it[r] - k.switch_it)) {
+                        // stop it: its done flag makes every later iteration skip it
+                        static const int one = 1;
+                        DDA_HIP_CHECK(hipMemcpyAsync(k.B.done + r, &one, sizeof(int), hipMemcpyHostToDevice,
+                                                     k.c->stream));
+                        DDA_HIP_CHECK(hipStreamSynchronize(k.c->stream));
+                        k.stalled[r] = 1;
+                        continue;
+                    }
+                    all = false;
+                }
+                k.fin = all;
             }
-            k.fin = all;
         }
     }
     if (k.progress > 0 && !k.fin) {
@@ -1465,7 +1538,7 @@ static dda_status finish_fp64(Ctx &c, Run<double> &k, int nrhs, const dda_solve_
                             : o.solver == DDA_CGNR   ? 2 * h[r].iter + (h[r].status == ST_MAXIT ? 1 : 0)  // a limit stop ends with A^H r
                                                      : h[r].iter;
         info[r].matvecs = per_run + (o.x0 ? 1 + (o.x0_check ? 1 : 0) : 0);
-        info[r].outer = k.stalled.size() > (size_t)r && k.stalled[r] ? 1 : 0;
+        info[r].outer = (k.stalled.size() > (size_t)r && k.stalled[r]) || k.rolled ? 1 : 0;
         info[r].res_rec = h[r].res;
         info[r].res_true = rt[r];
         if (hcap > 0 && info[r].res_hist && info[r].res_hist_cap > 0) {
