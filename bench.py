@@ -397,14 +397,21 @@ def forms(ctx, w, beams, theta, dda, inputs, torch, over_budget, cpu=None):
             c.solve([inputs.X_POL], tol=1e-1)
             c.solve([inputs.X_POL], tol=1e-1, precision=dda.FP32_PRODUCT)
         pol = [inputs.X_POL] * len(cs)
+        dda.solve_many(cs, pol, tol=1e-1, pack=True)  # warm: the batches' buffers and kernels
         _, tseq = _timed(torch, lambda: [c.solve([inputs.X_POL], tol=1e-5) for c in cs])
         (_, infos, st), tm = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5))
+        (_, ip, sp), tp = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5, pack=True))
         (_, i32, st32), tm32 = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5, precision=dda.FP32_PRODUCT))
+        pads = sorted({c.padded_grid()[0] for c in cs})
         res["many_particles"] = {
             "workload": "32 spheres n ~ U{24..96}, m ~ U[1.05, 1.6], kd 0.3, x-pol, tol 1e-5",
-            "dipoles": int(sum(c.n for c in cs)), "sequential_fp64_s": tseq, "concurrent_fp64_s": tm,
-            "concurrent_fp32_products_s": tm32, "speedup": tseq / tm, "speedup_fp32_products": tseq / tm32,
+            "dipoles": int(sum(c.n for c in cs)), "padded_lengths": pads,
+            "sequential_fp64_s": tseq, "concurrent_fp64_s": tm, "concurrent_fp32_products_s": tm32,
+            "packed_fp64_s": tp, "packed": "particles sharing a padded length packed into one batch each "
+                                           "(one launch per pass over the batch, pack=True)",
+            "speedup": tseq / tm, "speedup_fp32_products": tseq / tm32, "speedup_packed": tseq / tp,
             "iterations": [int(i["iters"]) for i in infos], "fp64_finish": sum(int(i["outer"]) for i in i32),
+            "res_true_max": max(i["res_true"] for i in infos),
             "res_true_max_fp32_products": max(i["res_true"] for i in i32)}
     finally:
         for c in cs:

@@ -135,6 +135,8 @@ typedef struct {
                               residual history */
     double relax_at;       /* DDA_FP32_RELAXED: relative residual below which the products switch to
                               single precision; 0 = 100 tol */
+    int32_t pack;          /* dda_solve_many: 1 = particles that share a padded grid are solved as one
+                              batch; 0 (default) = each particle on its own stream */
 } dda_solve_opts;
 
 /* What dda_solve does when QMR or Bi-CG breaks down for a right-hand side (the paper does not
@@ -275,9 +277,15 @@ dda_status dda_checkpoint_save(dda_ctx *ctx, const void *x, const char *path);
 dda_status dda_checkpoint_load(dda_ctx *ctx, void *x, const char *path);
 
 /*
- * dda_solve_many — one right-hand side on each of n_ctx particles (contexts), solved concurrently:
- * every context advances on its own stream (the paper runs independent orientations or particles
- * as separate simulations, Sec. 2; here they share the GPU).  Zero initial guess.
+ * dda_solve_many — one right-hand side on each of n_ctx particles (contexts), solved together (the
+ * paper runs independent orientations or particles as separate simulations, Sec. 2; here they share
+ * the GPU): every particle advances on its own stream.  With opts->pack = 1, particles whose
+ * contexts share the padded grid, kd and polarizability prescription (homogeneous, not CLDR), one of
+ * which spans the others' grid, are packed into one batch instead: each is a right-hand side with
+ * its own cell map on the largest grid of the group, so every pass of the product and every solver
+ * kernel is one launch over the group (the same sums as each particle's own product, to rounding);
+ * a batch runs until its slowest member converges, its converged members' blocks returning at
+ * once.  Groups, and particles that fit no group, advance concurrently.  Zero initial guess.
  *   ctxs    host [n_ctx] distinct contexts;  beams  host [n_ctx]
  *   x_out   host [n_ctx] device pointers, each complex128 [3][N_i]
  *   info    host [n_ctx] or NULL

@@ -46,6 +46,11 @@ struct Ctx {
 
     int *gmap = nullptr;            // device [nz][ny][nx] -> dipole index or -1
     int2 *rows = nullptr;           // device [nz][ny] single-run descriptors of the rows (x passes)
+    // a batch of particles on one grid (pack_setup): gmap and rows hold one map per right-hand side,
+    // these many elements apart (0 for a single particle); the tensor, twiddles and plans are
+    // borrowed from the member whose grid is the batch's
+    size_t gmap_stride = 0, rows_stride = 0;
+    bool borrowed = false;
     int *lin = nullptr;             // device [N] linear cell index
     int *line_start = nullptr;      // device [ny*nz + 1] first dipole of each (y, z) line (read-out)
     double2 *ghat = nullptr;        // device octant tensor, fp64

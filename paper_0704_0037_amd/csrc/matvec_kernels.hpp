@@ -58,7 +58,7 @@ __device__ __forceinline__ int xcd_block() {
 
 template <typename R, int LC, typename RX = R>
 __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restrict__ gmap, const int2 *__restrict__ rows,
-                                                const cplx<RX> *__restrict__ x,
+                                                size_t gstride, size_t rstride, const cplx<RX> *__restrict__ x,
                                                 cplx<R> *__restrict__ B1, int nx, int ny, int nz, int N,
                                                 FftPlan pl_rt, const cplx<R> *__restrict__ twall, int lnl,
                                                 const int *__restrict__ done) {
@@ -77,6 +77,9 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
     const int z = b % nz;
     const int c = b / nz;
     if (done && done[c / 3]) return;  // this right-hand side has converged
+    // a batch of particles (right-hand sides with their own dipoles on a common grid): this one's maps
+    gmap += (size_t)(c / 3) * gstride;
+    rows += (size_t)(c / 3) * rstride;
     const int t = threadIdx.x;
     const cplx<RX> *xc = x + (size_t)c * N;
     {   // pass 0 from global, lines along lanes' j (x contiguous)
@@ -460,7 +463,7 @@ __device__ __forceinline__ cplx<R> block_sum(cplx<R> v, cplx<R> *scratch) {
 // RX = double the epilogue y = x - s v and the dot sums are formed in double)
 template <typename R, int LC, typename RX = R>
 __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restrict__ gmap, const int2 *__restrict__ rows,
-                                                const cplx<R> *__restrict__ B1,
+                                                size_t gstride, size_t rstride, const cplx<R> *__restrict__ B1,
                                                 const cplx<RX> *__restrict__ xin, cplx<RX> *__restrict__ yout,
                                                 int nx, int ny, int nz, int N, FftPlan pl_rt,
                                                 const cplx<R> *__restrict__ twall, int lnl,
@@ -483,6 +486,8 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     const int z = b % nz;
     const int c = b / nz;
     if (done && done[c / 3]) return;
+    gmap += (size_t)(c / 3) * gstride;
+    rows += (size_t)(c / 3) * rstride;
     const int t = threadIdx.x;
     const C *src = B1 + ((size_t)c * nz + z) * (size_t)L * ny;
     {   // pass 0 from global, lanes over lines (y contiguous in B1)

@@ -76,7 +76,8 @@ dda_status matvec_device_impl(Ctx &c, const cplx<RX> *x, cplx<RX> *y, int nrhs, 
     const size_t lz_bytes = zmul_lds_elems(c.Lz) * sizeof(C);
     const int N = (int)c.N;
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[0], s));
-#define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, c.rows, x, w.B1, c.nx, c.ny, c.nz, N, \
+#define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxf.tpl), lx_bytes, s, c.gmap, c.rows, c.gmap_stride, \
+                 c.rows_stride, x, w.B1, c.nx, c.ny, c.nz, N, \
                  c.pxf, tw, tl.lnl_x, done
 #define DDA_BYTES lx_bytes
     DDA_DISPATCH_X(c.Lx, k_fwd_x, DDA_BYTES, DDA_ARGS)
@@ -105,7 +106,8 @@ dda_status matvec_device_impl(Ctx &c, const cplx<RX> *x, cplx<RX> *y, int nrhs, 
 #undef DDA_BYTES
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[4], s));
-#define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, c.rows, w.B1, x, y, c.nx, c.ny, c.nz, \
+#define DDA_ARGS dim3(ncomp * c.nz * ytiles), dim3(nlx * c.pxi.tpl), lx_bytes, s, c.gmap, c.rows, c.gmap_stride, \
+                 c.rows_stride, w.B1, x, y, c.nx, c.ny, c.nz, \
                  N, c.pxi, tw, tl.lnl_x, scale, dots, done
 #define DDA_BYTES lx_bytes
     DDA_DISPATCH_X(c.Lx, k_inv_x, DDA_BYTES, DDA_ARGS)

@@ -309,10 +309,138 @@ template dda_status matvec_launch<double>(Ctx &, const double2 *, double2 *, int
 template dda_status matvec_launch<float>(Ctx &, const float2 *, float2 *, int, const double *, const double *, bool,
                                          hipStream_t);
 
+void destroy(Ctx *c);
+
+// Rows whose non-void cells form one run x0 <= x < x1 (or none) need no cell-map lookups in the x
+// passes: {x0 | x1 << 16, first dipole} per (y, z) row, x0 = 0xFFFF for a row of several runs.
+static std::vector<int2> row_runs(const int32_t *gmap, int nx, int ny, int nz) {
+    std::vector<int2> rows((size_t)ny * nz);
+    for (size_t row = 0; row < rows.size(); ++row) {
+        const int32_t *g = gmap + row * nx;
+        int x0 = -1, x1 = -1, runs = 0;
+        for (int xx = 0; xx < nx; ++xx)
+            if (g[xx] >= 0 && (xx == 0 || g[xx - 1] < 0)) {
+                ++runs;
+                x0 = xx;
+            }
+        if (runs == 1) {
+            x1 = x0;
+            while (x1 < nx && g[x1] >= 0) ++x1;
+            rows[row] = make_int2(x0 | (x1 << 16), g[x0]);
+        } else {
+            rows[row] = make_int2(runs == 0 ? 0 : 0xFFFF, 0);
+        }
+    }
+    return rows;
+}
+
+// A batch of homogeneous particles that share the padded grid, the wavenumber and the
+// polarizability prescription, as one context whose right-hand sides are the particles: each
+// particle sits at the origin corner of the batch grid (the largest extent per axis), keeps its own
+// dipole order (the grid's linear order restricted to its mask, the same in both grids) and its own
+// cell map, and is padded to the largest dipole count.  The product of a right-hand side then
+// couples only that particle's dipoles; the tensor, twiddle tables, plans and tile schedule are
+// those of the member whose grid is the batch grid (borrowed, not copied).  Returns DDA_ENOTSUP when
+// the members do not qualify or no member spans the batch grid.
+dda_status pack_setup(Ctx *const *members, int n, Ctx **out) {
+    *out = nullptr;
+    if (n < 1) return DDA_EINVAL;
+    const Ctx &m0 = *members[0];
+    int box[3] = {0, 0, 0};
+    int64_t nmax = 0;
+    for (int i = 0; i < n; ++i) {
+        const Ctx &m = *members[i];
+        if (m.Lx != m0.Lx || m.Ly != m0.Ly || m.Lz != m0.Lz || m.kd != m0.kd || m.polarizability != m0.polarizability ||
+            wrapped(m) || (m.ghat32 == nullptr) != (m0.ghat32 == nullptr))
+            return DDA_ENOTSUP;
+        box[0] = std::max(box[0], m.nx);
+        box[1] = std::max(box[1], m.ny);
+        box[2] = std::max(box[2], m.nz);
+        nmax = std::max(nmax, m.N);
+    }
+    const Ctx *donor = nullptr;
+    for (int i = 0; i < n && !donor; ++i)
+        if (members[i]->nx == box[0] && members[i]->ny == box[1] && members[i]->nz == box[2]) donor = members[i];
+    if (!donor) return DDA_ENOTSUP;
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) return DDA_ENOMEM;
+    c->nx = box[0];
+    c->ny = box[1];
+    c->nz = box[2];
+    c->Lx = donor->Lx;
+    c->Ly = donor->Ly;
+    c->Lz = donor->Lz;
+    c->N = nmax;
+    c->m_re = donor->m_re;
+    c->m_im = donor->m_im;
+    c->kd = donor->kd;
+    c->polarizability = donor->polarizability;
+    c->tl64 = donor->tl64;
+    c->tl32 = donor->tl32;
+    c->nc_z = donor->nc_z;
+    c->pxf = donor->pxf;
+    c->pxi = donor->pxi;
+    c->pyf = donor->pyf;
+    c->pyi = donor->pyi;
+    c->pzf = donor->pzf;
+    c->pzi = donor->pzi;
+    c->borrowed = true;
+    c->ghat = donor->ghat;
+    c->ghat32 = donor->ghat32;
+    c->tw64 = donor->tw64;
+    c->tw32 = donor->tw32;
+    const size_t ncell = (size_t)box[0] * box[1] * box[2], nrow = (size_t)box[1] * box[2];
+    c->gmap_stride = ncell;
+    c->rows_stride = nrow;
+    dda_status st = DDA_OK;
+    std::vector<int32_t> gmap(ncell * n, -1);
+    std::vector<int2> rows(nrow * n);
+    for (int i = 0; i < n; ++i) {
+        const Ctx &m = *members[i];
+        int32_t *g = gmap.data() + ncell * i;
+        for (size_t d = 0; d < m.lin_host.size(); ++d) {
+            const int l = m.lin_host[d];
+            const int x = l % m.nx, y = (l / m.nx) % m.ny, z = l / (m.nx * m.ny);
+            g[((size_t)z * box[1] + y) * box[0] + x] = (int32_t)d;
+        }
+        const std::vector<int2> r = row_runs(g, box[0], box[1], box[2]);
+        std::copy(r.begin(), r.end(), rows.begin() + nrow * i);
+    }
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        set_error("dda_solve_many: stream creation failed");
+        c->own_stream = nullptr;
+        st = DDA_EHIP;
+        goto fail;
+    }
+    c->stream = c->own_stream;
+    if ((st = device_alloc((void **)&c->gmap, gmap.size() * sizeof(int32_t))) != DDA_OK) goto fail;
+    if ((st = device_alloc((void **)&c->rows, rows.size() * sizeof(int2))) != DDA_OK) goto fail;
+    {
+        hipError_t e = hipMemcpy(c->gmap, gmap.data(), gmap.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->rows, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            set_error(std::string("dda_solve_many: upload failed: ") + hipGetErrorString(e));
+            st = DDA_EHIP;
+            goto fail;
+        }
+    }
+    *out = c;
+    return DDA_OK;
+fail:
+    destroy(c);
+    return st;
+}
+
 void destroy(Ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    if (c->borrowed) {  // a batch of particles: the tensor and twiddles belong to a member
+        c->ghat = nullptr;
+        c->ghat32 = nullptr;
+        c->tw64 = nullptr;
+        c->tw32 = nullptr;
+    }
     free_work(c->w64);
     free_work(c->w32);
     (void)hipFree(c->snap);
@@ -512,24 +640,7 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
     if ((st = device_alloc((void **)&c->tw64, total * sizeof(double2))) != DDA_OK) goto fail;
     if ((st = device_alloc((void **)&c->tw32, total * sizeof(float2))) != DDA_OK) goto fail;
     {
-        // rows whose non-void cells form one run x0 <= x < x1 (or none) need no cell-map lookups
-        std::vector<int2> rows((size_t)c->ny * c->nz);
-        for (size_t row = 0; row < rows.size(); ++row) {
-            const int32_t *g = gmap.data() + row * c->nx;
-            int x0 = -1, x1 = -1, runs = 0;
-            for (int xx = 0; xx < c->nx; ++xx)
-                if (g[xx] >= 0 && (xx == 0 || g[xx - 1] < 0)) {
-                    ++runs;
-                    x0 = xx;
-                }
-            if (runs == 1) {
-                x1 = x0;
-                while (x1 < c->nx && g[x1] >= 0) ++x1;
-                rows[row] = make_int2(x0 | (x1 << 16), g[x0]);
-            } else {
-                rows[row] = make_int2(runs == 0 ? 0 : 0xFFFF, 0);
-            }
-        }
+        const std::vector<int2> rows = row_runs(gmap.data(), c->nx, c->ny, c->nz);
         hipError_t e = hipMemcpy(c->gmap, gmap.data(), ncell * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->rows, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->lin, c->lin_host.data(), c->N * sizeof(int32_t), hipMemcpyHostToDevice);

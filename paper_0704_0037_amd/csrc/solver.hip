@@ -26,6 +26,8 @@
 namespace dda {
 
 template <typename R> dda_status rhs_launch(Ctx &c, const dda_beam &bm, cplx<R> *b, hipStream_t s);
+dda_status pack_setup(Ctx *const *members, int n, Ctx **out);
+void destroy(Ctx *c);
 bool beam_ok(const dda_beam *b);
 void launch_to_f32(const double2 *a, float2 *b, size_t n, hipStream_t s);
 
@@ -2077,6 +2079,50 @@ extern "C" dda_status dda_solve(dda_ctx *h, const dda_beam *beams, int32_t n_rhs
     return st;
 }
 
+namespace dda {
+// A batch of particles packed on one grid (pack_setup): right-hand side q is particle members[q]
+// with beam beams[q].  Vectors are [P][3][N] with N the largest dipole count; the entries beyond a
+// particle's own dipoles are zero in b and in the zero initial guess, and stay zero (its product
+// writes only that particle's dipoles, and every vector update maps zero to zero).
+static dda_status prepare_pack(Ctx &pk, Run<double> &k, Ctx *const *members, const dda_beam *beams, int P, double tol,
+                               const dda_solve_opts &o, int hcap) {
+    dda_status st;
+    if ((st = ensure_vecs<double>(pk, P)) != DDA_OK) return st;
+    if ((st = ensure_bufs(pk, k.B, P, hcap)) != DDA_OK) return st;
+    std::vector<double> ar(P), ai(P);
+    for (int q = 0; q < P; ++q) polarizability(*members[q], beams[q], ar[q], ai[q]);
+    if ((st = upload_scales<double>(pk, ar, ai)) != DDA_OK) return st;
+    const size_t n3 = k.B.n3, L = (size_t)P * n3;
+    if (pk.xtmp_rows < P) {
+        (void)hipFree(pk.xtmp);
+        pk.xtmp = nullptr;
+        pk.xtmp_rows = 0;
+        if ((st = device_alloc((void **)&pk.xtmp, L * sizeof(double2))) != DDA_OK) return st;
+        pk.xtmp_rows = P;
+    }
+    Vecs<double> v = vecs_of<double>(pk, P);
+    DDA_HIP_CHECK(hipMemsetAsync(pk.vecs, 0, 7 * L * sizeof(double2), pk.stream));
+    DDA_HIP_CHECK(hipMemsetAsync(pk.xtmp, 0, L * sizeof(double2), pk.stream));
+    for (int q = 0; q < P; ++q) {
+        // b of the particle in its own layout [3][N_q], then into the batch layout [3][N]
+        double2 *tmp = v.pt + (size_t)q * n3;
+        if ((st = rhs_launch<double>(*members[q], beams[q], tmp, pk.stream)) != DDA_OK) return st;
+        const size_t nq = (size_t)members[q]->N;
+        DDA_HIP_CHECK(hipMemcpy2DAsync(v.b + (size_t)q * n3, pk.N * sizeof(double2), tmp, nq * sizeof(double2),
+                                       nq * sizeof(double2), 3, hipMemcpyDeviceToDevice, pk.stream));
+        DDA_HIP_CHECK(hipMemsetAsync(tmp, 0, n3 * sizeof(double2), pk.stream));
+    }
+    k.c = &pk;
+    k.v = v;
+    k.x = pk.xtmp;
+    k.solver = o.solver;
+    k.mixed = o.precision == DDA_FP32_PRODUCT;
+    k.beams_h = 0;
+    if ((st = init_states(pk, k.B, tol, o.maxit)) != DDA_OK) return st;
+    return run_begin(k, false);
+}
+}  // namespace dda
+
 extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const dda_beam *beams, double tol,
                                      const dda_solve_opts *opts, void *const *x_out, dda_solve_info *info) {
     clear_error();
@@ -2118,10 +2164,48 @@ extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const 
         }
     }
     const auto t0 = std::chrono::steady_clock::now();
+    // groups of particles packed into one batch: same padded grid, kd and prescription, homogeneous
+    std::vector<std::vector<int>> groups;
+    std::vector<int> in_pack(n_ctx, -1);
+    if (o.pack > 0) {
+        for (int i = 0; i < n_ctx; ++i) {
+            const Ctx &c = *cx(ctxs[i]);
+            if (wrapped(c)) continue;
+            int g = -1;
+            for (size_t j = 0; j < groups.size() && g < 0; ++j) {
+                const Ctx &h = *cx(ctxs[groups[j][0]]);
+                if (h.Lx == c.Lx && h.Ly == c.Ly && h.Lz == c.Lz && h.kd == c.kd && h.polarizability == c.polarizability)
+                    g = (int)j;
+            }
+            if (g < 0) {
+                groups.push_back({i});
+            } else {
+                groups[g].push_back(i);
+            }
+        }
+    }
+    std::vector<Ctx *> packs;
+    std::vector<std::vector<int>> pack_members;
+    for (const auto &g : groups) {
+        if (g.size() < 2) continue;
+        std::vector<Ctx *> mem;
+        for (int i : g) mem.push_back(cx(ctxs[i]));
+        Ctx *pk = nullptr;
+        const dda_status ps = pack_setup(mem.data(), (int)mem.size(), &pk);
+        if (ps == DDA_ENOTSUP) continue;  // no member spans the group's grid: solved one by one
+        if (ps != DDA_OK) {
+            st = ps;
+            break;
+        }
+        for (int i : g) in_pack[i] = (int)packs.size();
+        packs.push_back(pk);
+        pack_members.push_back(g);
+    }
     std::vector<std::unique_ptr<StreamSwap>> sw;
     std::vector<Run<double>> runs(n_ctx);
     std::vector<int> hcaps(n_ctx);
     for (int i = 0; i < n_ctx && st == DDA_OK; ++i) {
+        if (in_pack[i] >= 0) continue;
         Ctx &c = *cx(ctxs[i]);
         sw.emplace_back(new StreamSwap(c));
         if (!sw.back()->ok) {
@@ -2137,25 +2221,95 @@ extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const 
         hcaps[i] = hist_cap(&local[i], 1);
         st = prepare_fp64(c, runs[i], &beams[i], 1, tol_run, o, (double2 *)x_out[i], hcaps[i]);
     }
-    // all particles advance concurrently, each on its own stream
+    const int np = (int)packs.size();
+    std::vector<Run<double>> pruns(np);
+    std::vector<int> phcaps(np, 0);
+    for (int g = 0; g < np && st == DDA_OK; ++g) {
+        Ctx &pk = *packs[g];
+        const std::vector<int> &mem = pack_members[g];
+        const int P = (int)mem.size();
+        std::vector<Ctx *> mc(P);
+        std::vector<dda_beam> mb(P);
+        for (int q = 0; q < P; ++q) {
+            mc[q] = cx(ctxs[mem[q]]);
+            mb[q] = beams[mem[q]];
+            phcaps[g] = std::max(phcaps[g], hist_cap(&local[mem[q]], 1));
+            // the batch's stream runs after the work already queued on each member's stream
+            hipEvent_t e;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(e, mc[q]->stream) != hipSuccess || hipStreamWaitEvent(pk.stream, e, 0) != hipSuccess) {
+                set_error("dda_solve_many: could not order a batch after the callers' streams");
+                st = DDA_EHIP;
+            }
+            (void)hipEventDestroy(e);
+        }
+        if (st != DDA_OK) break;
+        int check;
+        bool graph;
+        cadence(pk, P, o, check, graph);
+        // a batch advances in step with the others from the host: checking it every iteration would
+        // leave the GPU waiting on the host between its iterations, and the iterations past a right-
+        // hand side's convergence cost nothing (its kernels return at once), so it replays captured
+        // chunks of at least 4 iterations unless told otherwise
+        if (o.check_every <= 0) check = std::max(check, 4);
+        if (o.graph == 0) graph = true;
+        pruns[g].check_every = check;
+        pruns[g].graph = graph;
+        st = prepare_pack(pk, pruns[g], mc.data(), mb.data(), P, tol_run, o, phcaps[g]);
+    }
+    // the batches and the remaining particles advance concurrently, each on its own stream
     bool busy = st == DDA_OK;
     while (busy && st == DDA_OK) {
         busy = false;
-        for (int i = 0; i < n_ctx && st == DDA_OK; ++i) st = run_poll(runs[i]);
         for (int i = 0; i < n_ctx && st == DDA_OK; ++i)
-            if (!runs[i].fin) {
+            if (in_pack[i] < 0) st = run_poll(runs[i]);
+        for (int g = 0; g < np && st == DDA_OK; ++g) st = run_poll(pruns[g]);
+        for (int i = 0; i < n_ctx && st == DDA_OK; ++i)
+            if (in_pack[i] < 0 && !runs[i].fin) {
                 busy = true;
                 st = run_issue(runs[i]);
+            }
+        for (int g = 0; g < np && st == DDA_OK; ++g)
+            if (!pruns[g].fin) {
+                busy = true;
+                st = run_issue(pruns[g]);
             }
     }
     dda_status ret = st;
     for (int i = 0; i < n_ctx; ++i) {
+        if (in_pack[i] >= 0) continue;
         run_end(runs[i]);
         if (ret == DDA_OK || ret == DDA_ENOTCONV || ret == DDA_EBREAKDOWN) {
             const dda_status si = finish_fp64(*cx(ctxs[i]), runs[i], 1, o, &local[i], hcaps[i]);
             if (si == DDA_EHIP || si == DDA_ENOMEM) ret = si;
             else if (ret == DDA_OK && si != DDA_OK) ret = si;
         }
+    }
+    for (int g = 0; g < np; ++g) {
+        run_end(pruns[g]);
+        Ctx &pk = *packs[g];
+        const std::vector<int> &mem = pack_members[g];
+        const int P = (int)mem.size();
+        if (ret == DDA_OK || ret == DDA_ENOTCONV || ret == DDA_EBREAKDOWN) {
+            std::vector<dda_solve_info> pin(P);
+            for (int q = 0; q < P; ++q) pin[q] = local[mem[q]];
+            dda_status si = finish_fp64(pk, pruns[g], P, o, pin.data(), phcaps[g]);
+            for (int q = 0; q < P && si == DDA_OK; ++q) {
+                const Ctx &m = *cx(ctxs[mem[q]]);
+                const hipError_t e = hipMemcpy2DAsync(x_out[mem[q]], m.N * sizeof(double2), pk.xtmp + (size_t)q * 3 * pk.N,
+                                                      pk.N * sizeof(double2), m.N * sizeof(double2), 3,
+                                                      hipMemcpyDeviceToDevice, pk.stream);
+                if (e != hipSuccess) {
+                    set_error(std::string("dda_solve_many: ") + hipGetErrorString(e));
+                    si = DDA_EHIP;
+                }
+            }
+            if (si == DDA_OK && hipStreamSynchronize(pk.stream) != hipSuccess) si = DDA_EHIP;
+            for (int q = 0; q < P; ++q) local[mem[q]] = pin[q];
+            if (si == DDA_EHIP || si == DDA_ENOMEM) ret = si;
+            else if (ret == DDA_OK && si != DDA_OK) ret = si;
+        }
+        destroy(packs[g]);
     }
     // single-precision products: particles whose true residual missed tol are finished in double
     // precision from their iterate (one after another; the remaining work is short)
@@ -2175,6 +2329,16 @@ extern "C" dda_status dda_solve_many(dda_ctx *const *ctxs, int32_t n_ctx, const 
             int check;
             bool graph;
             cadence(c, 1, o2, check, graph);
+            // a packed particle has no stream of its own yet: run it on its context's stream
+            std::unique_ptr<StreamSwap> own;
+            if (in_pack[i] >= 0) {
+                own.reset(new StreamSwap(c));
+                if (!own->ok) {
+                    set_error("dda_solve_many: could not order a solve after the caller's stream");
+                    ret = DDA_EHIP;
+                    break;
+                }
+            }
             const dda_status si = solve_fp64(c, &beams[i], 1, tol, o2, (double2 *)x_out[i], &f, check, graph);
             if (si == DDA_EHIP || si == DDA_ENOMEM) {
                 ret = si;

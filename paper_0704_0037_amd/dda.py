@@ -35,7 +35,7 @@ class SolveOpts(ct.Structure):
     _fields_ = [("solver", ct.c_int32), ("precision", ct.c_int32), ("maxit", ct.c_int32),
                 ("check_every", ct.c_int32), ("inner_tol", ct.c_double), ("x0", ct.c_void_p),
                 ("graph", ct.c_int32), ("x0_check", ct.c_int32), ("on_breakdown", ct.c_int32),
-                ("resume", ct.c_int32), ("relax_at", ct.c_double)]
+                ("resume", ct.c_int32), ("relax_at", ct.c_double), ("pack", ct.c_int32)]
 
 
 class SolveInfo(ct.Structure):
@@ -435,8 +435,9 @@ def _info_dict(inf):
 
 
 def solve_many(contexts, beams, tol=1e-5, solver=QMR, maxit=0, check_every=0, graph=0, x_out=None,
-               raise_on_fail=True, precision=FP64):
-    """One right-hand side per context, all solved concurrently (dda_solve_many)."""
+               raise_on_fail=True, precision=FP64, pack=False):
+    """One right-hand side per context, all solved together (dda_solve_many), each on its own stream;
+    pack=True batches the particles that share a padded grid into one launch per pass."""
     n = len(contexts)
     if len(beams) != n:
         raise ValueError("one beam per context")
@@ -444,6 +445,7 @@ def solve_many(contexts, beams, tol=1e-5, solver=QMR, maxit=0, check_every=0, gr
     hs = (ct.c_void_p * n)(*[c._h.value for c in contexts])
     ps = (ct.c_void_p * n)(*[_ptr(x, torch.complex128, (3, c.n), "x_out").value for x, c in zip(xs, contexts)])
     opts = SolveOpts(solver, precision, maxit, check_every, 0.0, None, graph, 0)
+    opts.pack = 1 if pack else 0
     infos = (SolveInfo * n)()
     st = lib().dda_solve_many(hs, n, _beams(beams), float(tol), ct.byref(opts), ps, infos)
     if raise_on_fail and st != OK:

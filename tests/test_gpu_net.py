@@ -139,12 +139,15 @@ def test_initial_guess_check_falls_back_to_zero():
         assert st == 0 and ig[0]["iters"] == 0
 
 
-def test_trained_guess_against_zero_guess():
-    """Trained on solver output for small random particles, the network's guess has a lower initial
-    residual on held-out particles than the untrained network's (x0 = b), and QMR from it needs no
-    more iterations than from zero (plain QMR stays the fallback and the convergence judge)."""
+def test_trained_guess_lowers_the_initial_residual_but_not_the_iterations():
+    """What the trained network gains, measured: trained on solver output for small random particles,
+    its guess starts held-out solves from a residual at least a quarter below the untrained network's
+    (x0 = b), yet QMR from it needs within 10 % of the iterations from a zero guess.  This is the
+    negative result of the full-size runs (2,000 training and 200 held-out particles: initial residual
+    0.63 against 1.02, iterations x 0.99), asserted so that a change in either direction is seen; plain
+    QMR stays the fallback and the judge of convergence (every solve converges)."""
     from paper_0704_0037_amd import learned_guess as lg
     ev, _ = lg.run(grid=48, n_train=600, n_eval=16, epochs=30, batch=8, lr=1e-3, seed=5000, quiet=True)
     assert all(r["status"] == [0, 0, 0] for r in ev["rows"])
-    assert ev["mean_res0_guess"] < 0.85 * ev["mean_res0_b"], ev
-    assert ev["mean_iters_guess"] <= ev["mean_iters_zero"] + 0.5, ev
+    assert ev["mean_res0_guess"] < 0.75 * ev["mean_res0_b"], ev
+    assert 0.9 < ev["iteration_ratio"] < 1.1, ev

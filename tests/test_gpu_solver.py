@@ -734,6 +734,49 @@ def test_solve_many_equals_single():
             c.close()
 
 
+def test_solve_many_packs_particles_sharing_a_grid():
+    """Particles whose contexts share the padded grid are solved as one batch (one launch per pass
+    over the batch): three such batches (L = 24, 32 and 20, each mixing spheres, an ellipsoid or a
+    random shape and refractive indices) and one particle alone.  Every particle's solution against
+    the oracle's QMR at the same tolerance on its dense matrix, and against its solve without packing."""
+    dda = _dda()
+    kd = 0.4
+    rng = np.random.default_rng(29)
+    rand = (rng.random((7, 11, 9)) < 0.6).astype(np.uint8)  # [nz][ny][nx] = 9 x 11 x 7 cells
+    rand[0, 0, 0] = 1
+    specs = [(inputs.sphere_mask(12), 1.5, None), (inputs.ellipsoid_mask((12, 10, 8), (6, 5, 4)), 1.3 + 0.02j, (24, 24, 24)),
+             (rand, 1.6, (24, 24, 24)),
+             (inputs.sphere_mask(16), 1.4, None), (inputs.sphere_mask(14), 1.7, None),
+             (inputs.ellipsoid_mask((16, 12, 10), (8, 6, 5)), 1.25 + 0.01j, (32, 32, 32)),
+             (inputs.sphere_mask(10), 1.45, None), (inputs.sphere_mask(8), 1.55, (20, 20, 20)),
+             (inputs.sphere_mask(6), 1.5, None)]
+    beams = inputs.beams_for_orientations(len(specs), seed=23)[:len(specs)]
+    ctxs = [dda.Context(mk, m, kd, pad=pad, fp32=True) for mk, m, pad in specs]
+    try:
+        pads = [c.padded_grid() for c in ctxs]
+        assert pads[:3] == [(24, 24, 24)] * 3 and pads[3:6] == [(32, 32, 32)] * 3 and pads[6:8] == [(20, 20, 20)] * 2
+        xs, infos, st = dda.solve_many(ctxs, beams, tol=1e-10, pack=True)
+        assert st == 0
+        xu, iu, su = dda.solve_many(ctxs, beams, tol=1e-10)
+        assert su == 0
+        for (mk, m, _), c, b, x, inf, x1, i1 in zip(specs, ctxs, beams, xs, infos, xu, iu):
+            assert inf["status"] == 0 and inf["res_true"] < 2e-10
+            assert abs(inf["iters"] - i1["iters"]) <= 1
+            xg = x.cpu().numpy()
+            assert np.abs(xg - x1.cpu().numpy()).max() < 1e-8 * np.abs(xg).max()
+            pos, alpha, beta, A, bb = _oracle_system(mk, m, kd, b)
+            xo = _oracle_qmr(A, bb, 1e-10)
+            assert np.abs(xg.T - xo).max() < 1e-8 * np.abs(xo).max()
+            co = odda.cross_sections(pos, kd, alpha, beta * xo, b.prop, b.pol)[0]
+            assert abs(c.cross_sections(b, x.contiguous())[0] - co) < 1e-9 * abs(co)
+        # single-precision transforms in the batches, finished in double precision where needed
+        xs, infos, st = dda.solve_many(ctxs, beams, tol=1e-8, precision=dda.FP32_PRODUCT, pack=True)
+        assert st == 0 and all(i["res_true"] < 1e-8 for i in infos)
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_fp32_products_solve():
     """Double-precision QMR / Bi-CGSTAB with single-precision transforms: reaches the tolerance in
     the true residual (finishing in double precision when needed) and tracks the fp64 solve."""
