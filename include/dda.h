@@ -417,6 +417,22 @@ dda_status dda_matvec_timed(dda_ctx *ctx, const dda_beam *beams, int32_t n_rhs, 
  */
 dda_status dda_tune(dda_ctx *ctx, int32_t precision, int32_t n_rhs, int32_t reps, int32_t tiles_out[2]);
 dda_status dda_get_tiles(const dda_ctx *ctx, int32_t precision, int32_t tiles[2]);
+
+/*
+ * dda_tune_padding — autotuner of the padded grid (any L >= 2n - 1 per axis gives the same product
+ * up to rounding, Sec. 2's zero padding): for each candidate, the default choice of dda_setup and
+ * the k-th length with compile-time specialized kernels at or above 2n - 1 on every axis
+ * (k = 0 .. n_cand - 1), it sets the particle up, tunes its tile schedule for n_rhs vectors
+ * (dda_tune), times `reps` double-precision products and keeps the fastest.  Pass pad_out as
+ * dda_setup_opts.pad.  Arguments as dda_setup (homogeneous particles); n_cand 1..8; ms_out
+ * (optional) receives the winner's product time in milliseconds.  Runs on the default stream;
+ * the radix schedule of each length is its compile-time plan.
+ * Errors: DDA_EINVAL (bad arguments, or no candidate could be set up), DDA_ENOTSUP, DDA_ENOMEM,
+ * DDA_EHIP.
+ */
+dda_status dda_tune_padding(const int32_t grid[3], const uint8_t *mask, const double m[2], double kd,
+                            int32_t polarizability, int32_t n_rhs, int32_t reps, int32_t n_cand, int32_t pad_out[3],
+                            float *ms_out);
 dda_status dda_set_tiles(dda_ctx *ctx, int32_t precision, const int32_t tiles[2]);
 
 /* ------------------------------------------------------------------ learned initial guess

@@ -1,6 +1,8 @@
 // The C-ABI entry points (include/dda.h) that set up contexts, build right-hand sides and apply
 // the interaction matrix.  The solver and the read-out entry points live in solver.hip and
 // readout.hip.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -8,6 +10,7 @@
 #include "ctx.hpp"
 
 namespace dda {
+int default_pad(int n);
 dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const double m[2], double kd, int32_t pol,
                  const dda_setup_opts *opts, void *stream);
 void destroy(Ctx *c);
@@ -354,6 +357,83 @@ dda_status dda_tune(dda_ctx *h, int32_t precision, int32_t n_rhs, int32_t reps, 
         return DDA_ENOTSUP;
     }
     return precision == DDA_FP64 ? tune<double>(*c, n_rhs, reps, tiles_out) : tune<float>(*c, n_rhs, reps, tiles_out);
+}
+
+dda_status dda_tune_padding(const int32_t grid[3], const uint8_t *mask, const double m[2], double kd,
+                            int32_t polarizability, int32_t n_rhs, int32_t reps, int32_t n_cand, int32_t pad_out[3],
+                            float *ms_out) {
+    clear_error();
+    if (!grid || !mask || !m || !pad_out || n_rhs < 1 || reps < 1 || n_cand < 1 || n_cand > 8) {
+        set_error("dda_tune_padding: NULL argument, n_rhs < 1, reps < 1 or n_cand outside 1..8");
+        return DDA_EINVAL;
+    }
+#define DDA_SPEC_ITEM(S) S,
+    static const int spec[] = {DDA_SPECIALIZED_LENGTHS(DDA_SPEC_ITEM)};
+#undef DDA_SPEC_ITEM
+    const int nspec = (int)(sizeof(spec) / sizeof(spec[0]));
+    // candidates: the default choice of dda_setup, then the k-th specialized length at or above
+    // 2n - 1 on every axis, k = 0 .. n_cand - 1 (each padding once)
+    std::vector<std::array<int, 3>> cand{{default_pad(grid[0]), default_pad(grid[1]), default_pad(grid[2])}};
+    for (int k = 0; k < n_cand; ++k) {
+        std::array<int, 3> c3{};
+        bool ok = true;
+        for (int a = 0; a < 3 && ok; ++a) {
+            int rank = -1;
+            for (int i = 0; i < nspec && rank < k; ++i)
+                if (spec[i] >= 2 * grid[a] - 1) {
+                    ++rank;
+                    if (rank == k) c3[a] = spec[i];
+                }
+            ok = rank == k;
+        }
+        if (ok && std::find(cand.begin(), cand.end(), c3) == cand.end()) cand.push_back(c3);
+    }
+    float best = 3.4e38f;
+    int best_pad[3] = {0, 0, 0};
+    std::string why;
+    for (const auto &c3 : cand) {
+        dda_setup_opts o{};
+        for (int a = 0; a < 3; ++a) o.pad[a] = c3[a];
+        Ctx *c = nullptr;
+        dda_status st = setup(&c, grid, mask, m, kd, polarizability, &o, nullptr);
+        if (st == DDA_EINVAL) {  // a padding these kernels do not run (e.g. too many threads per line)
+            why = last_error();
+            clear_error();
+            continue;
+        }
+        if (st != DDA_OK) return st;
+        if (wrapped(*c)) {
+            destroy(c);
+            set_error("dda_tune_padding: homogeneous particles only");
+            return DDA_ENOTSUP;
+        }
+        int32_t tiles[2];
+        st = tune<double>(*c, n_rhs, reps, tiles);
+        double2 *x = nullptr, *y = nullptr;
+        const size_t bytes = (size_t)3 * n_rhs * c->N * sizeof(double2);
+        if (st == DDA_OK) st = device_alloc((void **)&x, bytes);
+        if (st == DDA_OK) st = device_alloc((void **)&y, bytes);
+        if (st == DDA_OK && hipMemset(x, 0, bytes) != hipSuccess) st = DDA_EHIP;
+        float k[5], tot = 0;
+        std::vector<double> ar(n_rhs, 0.0), ai(n_rhs, 0.0);
+        if (st == DDA_OK) st = matvec_timed<double>(*c, n_rhs, ar, ai, x, y, reps, k, &tot);
+        if (x) (void)hipFree(x);
+        if (y) (void)hipFree(y);
+        const int L[3] = {c->Lx, c->Ly, c->Lz};
+        destroy(c);
+        if (st != DDA_OK) return st;
+        if (tot < best) {
+            best = tot;
+            for (int a = 0; a < 3; ++a) best_pad[a] = L[a];
+        }
+    }
+    if (best_pad[0] == 0) {
+        set_error("dda_tune_padding: no candidate padding could be set up: " + why);
+        return DDA_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a) pad_out[a] = best_pad[a];
+    if (ms_out) *ms_out = best;
+    return DDA_OK;
 }
 
 dda_status dda_get_tiles(const dda_ctx *h, int32_t precision, int32_t tiles[2]) {

@@ -63,6 +63,9 @@ static int smallest_pad(int n) {
     return L;
 }
 
+// the padded length dda_setup chooses for an axis of n cells
+int default_pad(int n) { return smallest_pad(n); }
+
 // lines per block (a power of two, returned as its log2): up to DDA_MAX_THREADS threads,
 // preferably a whole number of waves, LDS within DDA_LDS_CAP
 static int pick_lines_log2(int tpl, int line_bytes, int ndim, int want, int maxt = DDA_MAX_THREADS) {

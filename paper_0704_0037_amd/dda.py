@@ -78,6 +78,9 @@ _SIGS = {
                                                     ct.POINTER(ct.c_int32)]),
     "dda_rhs": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p]),
     "dda_matvec": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
+    "dda_tune_padding": (ct.c_int, [ct.POINTER(ct.c_int32), ct.POINTER(ct.c_uint8), ct.POINTER(ct.c_double),
+                                     ct.c_double, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
+                                     ct.POINTER(ct.c_int32), ct.POINTER(ct.c_float)]),
     "dda_matvec_noalloc": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
     "dda_matvec_f32": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_void_p, ct.c_void_p]),
     "dda_matvec_batch": (ct.c_int, [ct.c_void_p, ct.POINTER(Beam), ct.c_int32, ct.c_void_p, ct.c_void_p]),
@@ -432,6 +435,20 @@ class Context:
 
 def _info_dict(inf):
     return {f: getattr(inf, f) for f, _ in SolveInfo._fields_ if f != "res_hist"}
+
+
+def tune_padding(mask, m, kd, polarizability=POL_LDR, n_rhs=1, reps=5, n_cand=3):
+    """dda_tune_padding: the fastest padded grid (Lx, Ly, Lz) for this particle, and its product
+    time in milliseconds; pass the grid as Context(..., pad=...)."""
+    mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+    nz, ny, nx = mask.shape
+    grid = (ct.c_int32 * 3)(nx, ny, nz)
+    mm = (ct.c_double * 2)(complex(m).real, complex(m).imag)
+    out = (ct.c_int32 * 3)()
+    ms = ct.c_float()
+    _check(lib().dda_tune_padding(grid, mask.ctypes.data_as(ct.POINTER(ct.c_uint8)), mm, float(kd), int(polarizability),
+                                  int(n_rhs), int(reps), int(n_cand), out, ct.byref(ms)), "dda_tune_padding")
+    return tuple(out), ms.value
 
 
 def solve_many(contexts, beams, tol=1e-5, solver=QMR, maxit=0, check_every=0, graph=0, x_out=None,

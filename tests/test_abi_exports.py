@@ -120,3 +120,10 @@ def test_newer_entry_points_check_arguments_without_a_gpu():
     assert L.dda_checkpoint_save(None, None, b"/nonexistent/ckpt") == dda.EINVAL
     assert L.dda_checkpoint_load(None, None, b"/nonexistent/ckpt") == dda.EINVAL
     assert b"dda_checkpoint_load" in L.dda_last_error()
+    # the padded-grid tuner and the no-allocation product refuse bad arguments before any device call
+    pad = (ctypes.c_int32 * 3)()
+    assert L.dda_tune_padding(grid, mask, m, 0.4, 0, 1, 3, 0, pad, None) == dda.EINVAL  # n_cand < 1
+    assert L.dda_tune_padding(grid, None, m, 0.4, 0, 1, 3, 2, pad, None) == dda.EINVAL
+    assert b"dda_tune_padding" in L.dda_last_error()
+    assert L.dda_matvec_noalloc(None, None, None, None) == dda.EINVAL
+    assert b"dda_matvec_noalloc" in L.dda_last_error()

@@ -77,6 +77,22 @@ def test_lines_per_block_does_not_change_result():
         assert np.array_equal(y, ys[0])
 
 
+def test_padding_tuner_picks_a_candidate_and_keeps_the_product():
+    """dda_tune_padding times the default padding and the specialized lengths above 2n - 1: what it
+    returns is one of them, and a context set up with it gives the product of the default one to
+    rounding (any padding >= 2n - 1 computes the same circulant sums)."""
+    dda = _dda()
+    mask = inputs.sphere_mask(30)  # default 60^3; specialized candidates 60, 64, 72
+    pad, ms = dda.tune_padding(mask, 1.4, 0.4, n_cand=3, reps=3)
+    assert pad in [(60, 60, 60), (64, 64, 64), (72, 72, 72)] and ms > 0
+    x = torch.from_numpy(inputs.random_vector(int(mask.sum()), seed=5)).cuda()
+    with dda.Context(mask, 1.4, 0.4) as c0, dda.Context(mask, 1.4, 0.4, pad=pad) as c1:
+        assert c1.padded_grid() == pad
+        y0 = c0.matvec(inputs.X_POL, x).cpu().numpy()
+        y1 = c1.matvec(inputs.X_POL, x).cpu().numpy()
+    assert np.abs(y1 - y0).max() < 1e-13 * np.abs(y0).max()
+
+
 def test_rhs_and_polarizability_match_oracle():
     dda = _dda()
     mask = _random_mask((6, 7, 5), 21)
