@@ -413,6 +413,22 @@ def forms(ctx, w, beams, theta, dda, inputs, torch, over_budget, cpu=None):
             "iterations": [int(i["iters"]) for i in infos], "fp64_finish": sum(int(i["outer"]) for i in i32),
             "res_true_max": max(i["res_true"] for i in infos),
             "res_true_max_fp32_products": max(i["res_true"] for i in i32)}
+        # the padded-grid autotuner: the default padding against the next specialized lengths
+        if not over_budget("tuned_padding"):
+            (tuned, ttune) = _timed(torch, lambda: [dda.tune_padding(x.mask, x.m, x.kd, n_cand=2, reps=3)[0] for x in ws])
+            changed = [i for i, (c, p) in enumerate(zip(cs, tuned)) if c.padded_grid() != p]
+            ct = [dda.Context(ws[i].mask, ws[i].m, ws[i].kd, pad=tuned[i]) if i in changed else cs[i]
+                  for i in range(len(cs))]
+            for i in changed:
+                ct[i].tune(dda.FP64)
+                ct[i].solve([inputs.X_POL], tol=1e-1)
+            _, tseq_t = _timed(torch, lambda: [c.solve([inputs.X_POL], tol=1e-5) for c in ct])
+            (_, it_, _), tm_t = _timed(torch, lambda: dda.solve_many(ct, pol, tol=1e-5))
+            for i in changed:
+                ct[i].close()
+            res["many_particles"]["tuned_padding"] = {
+                "tuner_s": ttune, "changed": {ws[i].name: [cs[i].padded_grid()[0], tuned[i][0]] for i in changed},
+                "sequential_fp64_s": tseq_t, "concurrent_fp64_s": tm_t, "speedup_vs_default_sequential": tseq / tm_t}
     finally:
         for c in cs:
             c.close()
@@ -457,26 +473,36 @@ def deep_m2(dda, inputs, torch):
     return out
 
 
-def solver_study(dda, inputs, torch, n=64, tol=1e-5):
+def solver_study(dda, inputs, torch, n=64, tol=1e-5, cgnr_maxit=20000):
     """The four solvers on one strongly scattering sphere (x = 20, m = 1.8, the case of the paper's
-    residual-history figure, Sec. 4) on an n^3 grid: iterations, products, time and the relative
-    residual at log-spaced iterations."""
+    residual-history figure, Sec. 4; its Table 1 runs it on a 128^3 grid) on an n^3 grid:
+    iterations, products, time, the relative residual at log-spaced iterations and the first
+    iteration below 2e-3, 1e-3 and tol (Sec. 4 compares the iterations to reach 1e-3 and 2e-3 with
+    those to reach 1e-5).  CGNR stops after cgnr_maxit iterations."""
     os.environ.setdefault("DDA_PROGRESS", "30")
     mask = inputs.sphere_mask(n)
     N = int(mask.sum())
     kd = inputs.kd_for_size_parameter(20.0, N)
     out = {"workload": f"sphere{n}, x = 20, m = 1.8, kd = {kd:.4f}, x-pol, tol {tol:g}", "n_dipoles": N}
+    marks_eps = (2e-3, 1e-3, tol)
     with dda.Context(mask, 1.8, kd) as ctx:
+        out["padded_grid"] = list(ctx.padded_grid())
         ctx.tune(dda.FP64)
         for name, solver in (("qmr", dda.QMR), ("bicg", dda.BICG), ("bicgstab", dda.BICGSTAB), ("cgnr", dda.CGNR)):
-            (x, info, st), dt = _timed(torch, lambda: ctx.solve([inputs.X_POL], tol=tol, solver=solver, maxit=200000,
-                                                                 history=200001, raise_on_fail=False))
-            h = info[0]["res_hist"]
+            maxit = cgnr_maxit if solver == dda.CGNR else 200000
+            (x, info, st), dt = _timed(torch, lambda: ctx.solve([inputs.X_POL], tol=tol, solver=solver, maxit=maxit,
+                                                                 history=maxit + 1, raise_on_fail=False))
+            h = np.asarray(info[0]["res_hist"])
             marks = sorted({min(len(h) - 1, int(round(v))) for v in np.geomspace(1, max(1, len(h) - 1), 12)})
-            out[name] = {"s": dt, "status": st, "iterations": info[0]["iters"], "matvecs": info[0]["matvecs"],
-                         "res_true": info[0]["res_true"], "Cext": ctx.cross_sections(inputs.X_POL, x[0].contiguous())[0],
-                         "res_hist": {str(i): h[i] for i in marks}}
-            log(f"solver study {name}: {out[name]['iterations']} iterations, {dt:.2f} s")
+            below = {f"{e:g}": (int(np.argmax(h <= e)) if np.any(h <= e) else None) for e in marks_eps}
+            rec = {"s": dt, "status": st, "iterations": info[0]["iters"], "matvecs": info[0]["matvecs"],
+                   "res_true": info[0]["res_true"], "Cext": ctx.cross_sections(inputs.X_POL, x[0].contiguous())[0],
+                   "first_iteration_below": below, "res_hist": {str(i): float(h[i]) for i in marks}}
+            if below[f"{tol:g}"] and below["0.001"] and below["0.002"]:
+                rec["fewer_iterations_to_1e-3"] = below[f"{tol:g}"] / below["0.001"]
+                rec["fewer_iterations_to_2e-3"] = below[f"{tol:g}"] / below["0.002"]
+            out[name] = rec
+            log(f"solver study {name}: {rec['iterations']} iterations, {dt:.2f} s, first below {below}")
     return out
 
 
@@ -557,6 +583,7 @@ def main():
                     help="only: the 256^3 sphere's product on a batch of both polarizations, per-kernel HIP-event "
                          "times over --reps products (a short run for counter profiles)")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--study-n", type=int, default=64, help="grid side of the sphere in --solver-study")
     ap.add_argument("--budget-s", type=float, default=540.0,
                     help="wall-clock budget of the whole run: a form that would not fit is skipped (and named)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
@@ -566,7 +593,7 @@ def main():
         return
     t_start = time.perf_counter()
     # expected seconds of the long forms (measured on one MI355X), used to stay inside the budget
-    expected = {"fp32_relaxed_m2": 330.0, "learned_guess": 75.0, "cpu_baseline": 150.0}
+    expected = {"fp32_relaxed_m2": 330.0, "learned_guess": 75.0, "tuned_padding": 15.0}
 
     def over_budget(name):
         late = time.perf_counter() - t_start + expected.get(name, 0.0) > args.budget_s
@@ -585,7 +612,7 @@ def main():
         print(json.dumps(deep_m2(dda, inputs, torch)), flush=True)
         return
     if args.solver_study:
-        print(json.dumps(solver_study(dda, inputs, torch)), flush=True)
+        print(json.dumps(solver_study(dda, inputs, torch, n=args.study_n)), flush=True)
         return
     if args.materials_study:
         print(json.dumps(materials_study(dda, inputs, torch)), flush=True)
