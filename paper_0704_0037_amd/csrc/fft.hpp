@@ -56,7 +56,8 @@ template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_
 struct FftPlan {
     int L;                   // transform length
     int npass;               // number of passes (1 for L = 1, which uses radix 1); 0 = length not supported
-    int tpl;                 // threads per line = L / smallest radix
+    int tpl;                 // threads per line = L / largest radix (butterflies of the widest pass)
+    int tpl1;                // threads per line for one butterfly per thread in every pass = L / smallest radix
     int tw_off;              // offset of the table exp(-2 pi i m / L), m < L, in the twiddle buffer
     int radix[kMaxPass];
     int ns[kMaxPass];        // product of the radices of the preceding passes
@@ -64,8 +65,12 @@ struct FftPlan {
 
 // Radix schedule for length L (5-smooth): 8s first, the leftover power of two as 16 (or 4*4 when
 // maxr = 8), 4 or 2, then 5s and 3s; reversed for the inverse of a pass pair whose middle stays in
-// registers.  Larger radices mean fewer passes over LDS.  Used on the host to plan and on the
-// device to specialize kernels for a length known at compile time.
+// registers.  Larger radices mean fewer passes over LDS.  A line gets tpl = L / (largest radix)
+// threads, one per butterfly of its widest pass; a pass of smaller radix has more butterflies
+// than threads, and each thread takes ceil(L / (R tpl)) of them, so no lane idles through the
+// radix-8 passes that do most of the arithmetic.  tpl1 = L / (smallest radix) threads give one
+// butterfly per thread in every pass (the fused z pass runs that way).  Used on the host to plan
+// and on the device to specialize kernels for a length known at compile time.
 __host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
     FftPlan p{};
     int r[kMaxPass] = {};
@@ -97,18 +102,24 @@ __host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
             r[i] = r[n - 1 - i];
             r[n - 1 - i] = t;
         }
-    int ns = 1, rmin = 1 << 30;
+    int ns = 1, rmin = 1 << 30, rmax = 0;
     for (int i = 0; i < n; ++i) {
         p.radix[i] = r[i];
         p.ns[i] = ns;
         ns *= r[i];
         rmin = rmin < r[i] ? rmin : r[i];
+        rmax = rmax > r[i] ? rmax : r[i];
     }
     p.L = L;
     p.npass = n;
-    p.tpl = L / rmin;
+    p.tpl = L / rmax;
+    p.tpl1 = L / rmin;
     return p;
 }
+
+// bound on the butterflies a thread takes in a pass of radix R when a line has L / (largest
+// radix) threads and no radix exceeds maxr
+__host__ __device__ constexpr int bfly_per_thread(int R, int maxr) { return (maxr + R - 1) / R; }
 
 // The plan a kernel uses: the compile-time plan for LC > 0 (all indices fold to constants), else
 // the runtime plan passed as an argument.  tw_off always comes from the runtime plan.
@@ -404,56 +415,73 @@ template <bool WAVE> __device__ __forceinline__ void lds_sync() {
     }
 }
 
-// lines of a compile-time plan fit in one wavefront when its threads-per-line divides 64
-template <int LC, int MAXR> __host__ __device__ constexpr bool wave_lines() {
-    if constexpr (LC > 0) return 64 % make_plan(LC, MAXR, false).tpl == 0;
+// lines of a compile-time plan fit in one wavefront when its threads-per-line divides 64 (tpl1
+// for callers with one butterfly per thread)
+template <int LC, int MAXR, bool ONE = false> __host__ __device__ constexpr bool wave_lines() {
+    if constexpr (LC > 0) return 64 % (ONE ? make_plan(LC, MAXR, false).tpl1 : make_plan(LC, MAXR, false).tpl) == 0;
     else return false;
+}
+
+// One in-place pass of radix R over an LDS line: thread j loads butterflies j, j + tpl, ... (< L/R)
+// into registers, the block syncs, then it stores them.  NB bounds the butterflies per thread.
+template <int DIR, int R, int NB, bool WAVE, typename C, class TW, class LD, class ST>
+__device__ __forceinline__ void lds_pass(int j, int L, int tpl, int Ns, TW tw, LD ld, ST st) {
+    C a[NB][R];
+    const int nb = L / R;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        if (j + b * tpl < nb) bfly_load<DIR, R>(a[b], j + b * tpl, L, Ns, tw, ld);
+    lds_sync<WAVE>();
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        if (j + b * tpl < nb) bfly_store<R>(a[b], j + b * tpl, Ns, st);
+    lds_sync<WAVE>();
 }
 
 // Passes [p0, p1) in place on the LDS line `ln` (stride-skewed).  Every thread of the block
 // must call this (it may contain barriers).  LC > 0 selects the plan make_plan(LC, MAXR, REV)
 // known at compile time: passes are then unrolled with constant radices and strides, and when a
 // line fits in a wave the passes sync only that wave; LC = 0 runs the runtime plan `pl`.
-template <int DIR, int MAXR, int LC, bool REV, typename C, class TW>
+// ONE: the caller runs tpl1 threads per line (one butterfly per thread in every pass) instead of
+// tpl.
+template <int DIR, int MAXR, int LC, bool REV, bool ONE, typename C, class TW>
 __device__ __forceinline__ void lds_passes_tw(C *ln, const FftPlan &pl, int p0, int p1, int j, TW tw) {
     auto ld = [&](int i) { return ln[pidx(i)]; };
     auto st = [&](int i, C v) { ln[pidx(i)] = v; };
     if constexpr (LC > 0) {
         constexpr FftPlan P = make_plan(LC, MAXR, REV);
-        constexpr bool W = wave_lines<LC, MAXR>();
+        constexpr int T = ONE ? P.tpl1 : P.tpl;
+        constexpr bool W = 64 % T == 0;
         static_for<1, P.npass>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             constexpr int R = P.radix[p], Ns = P.ns[p];
-            if (p >= p0 && p < p1) {
-                const bool act = j < LC / R;
-                C a[R];
-                if (act) bfly_load<DIR, R>(a, j, LC, Ns, tw, ld);
-                lds_sync<W>();
-                if (act) bfly_store<R>(a, j, Ns, st);
-                lds_sync<W>();
-            }
+            constexpr int NB = (LC / R + T - 1) / T;
+            if (p >= p0 && p < p1) lds_pass<DIR, R, NB, W, C>(j, LC, T, Ns, tw, ld, st);
         });
     } else {
         for (int p = p0; p < p1; ++p) {
-            const int R = pl.radix[p], Ns = pl.ns[p];
-            const bool act = j < pl.L / R;
-            C a[MAXR];
-            if (act) load_rt<DIR, MAXR>(a, R, j, pl.L, Ns, tw, ld);
-            __syncthreads();
-            if (act) store_rt<MAXR>(a, R, j, Ns, st);
-            __syncthreads();
+            const int R = pl.radix[p], Ns = pl.ns[p], L = pl.L, T = ONE ? pl.tpl1 : pl.tpl;
+            constexpr int M = ONE ? 1 : MAXR;  // butterflies per thread bound
+            switch (R) {
+                case 2: lds_pass<DIR, 2, bfly_per_thread(2, M), false, C>(j, L, T, Ns, tw, ld, st); break;
+                case 3: lds_pass<DIR, 3, bfly_per_thread(3, M), false, C>(j, L, T, Ns, tw, ld, st); break;
+                case 4: lds_pass<DIR, 4, bfly_per_thread(4, M), false, C>(j, L, T, Ns, tw, ld, st); break;
+                case 5: lds_pass<DIR, 5, bfly_per_thread(5, M), false, C>(j, L, T, Ns, tw, ld, st); break;
+                case 8: if constexpr (MAXR >= 8) lds_pass<DIR, 8, bfly_per_thread(8, M), false, C>(j, L, T, Ns, tw, ld, st); break;
+                default: if constexpr (MAXR >= 16) lds_pass<DIR, 16, 1, false, C>(j, L, T, Ns, tw, ld, st); break;
+            }
         }
     }
 }
 
-template <int DIR, int MAXR, int LC, bool REV, typename C>
+template <int DIR, int MAXR, int LC, bool REV, bool ONE = false, typename C>
 __device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
                                            const C *__restrict__ tw) {
-    lds_passes_tw<DIR, MAXR, LC, REV>(ln, pl, p0, p1, j, tw);
+    lds_passes_tw<DIR, MAXR, LC, REV, ONE>(ln, pl, p0, p1, j, tw);
 }
-template <int DIR, int MAXR, int LC, bool REV, typename C>
+template <int DIR, int MAXR, int LC, bool REV, bool ONE = false, typename C>
 __device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j, TwStaged<C> tw) {
-    lds_passes_tw<DIR, MAXR, LC, REV>(ln, pl, p0, p1, j, tw);
+    lds_passes_tw<DIR, MAXR, LC, REV, ONE>(ln, pl, p0, p1, j, tw);
 }
 
 // true when every pass of the compile-time plan of length L is radix 8 (its twiddle bases fit in

@@ -84,18 +84,18 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
     const cplx<RX> *xc = x + (size_t)c * N;
     {   // pass 0 from global, lines along lanes' j (x contiguous)
         const int line = t / TPL, j = t % TPL, y = y0 + line;
-        if (j < L / R0) {
-            const int *grow = gmap + ((size_t)z * ny + (y < ny ? y : 0)) * nx;
-            const bool yok = y < ny;
-            int rx0, rx1, id0;
-            const bool run = row_run(rows, z * ny + (y < ny ? y : 0), rx0, rx1, id0);
+        const int *grow = gmap + ((size_t)z * ny + (y < ny ? y : 0)) * nx;
+        const bool yok = y < ny;
+        int rx0, rx1, id0;
+        const bool run = row_run(rows, z * ny + (y < ny ? y : 0), rx0, rx1, id0);
+        for (int jb = j; jb < L / R0; jb += TPL) {
             C a[kMaxRadix];
             if (run)
-                load_rt<-1, kMaxRadix, true>(a, R0, j, L, 1, tw, [&](int i) -> C {
+                load_rt<-1, kMaxRadix, true>(a, R0, jb, L, 1, tw, [&](int i) -> C {
                     return (yok && i >= rx0 && i < rx1) ? ccast<C>(xc[id0 + i - rx0]) : czero<C>();
                 });
             else
-                load_rt<-1, kMaxRadix, true>(a, R0, j, L, 1, tw, [&](int i) -> C {
+                load_rt<-1, kMaxRadix, true>(a, R0, jb, L, 1, tw, [&](int i) -> C {
                     if (yok && i < nx) {
                         const int id = grow[i];
                         if (id >= 0) return ccast<C>(xc[id]);
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
                     return czero<C>();
                 });
             C *ln = lds + line * S;
-            store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+            store_rt<kMaxRadix>(a, R0, jb, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
     }
     constexpr bool W = wave_lines<LC, kMaxRadix>();
@@ -114,11 +114,11 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
     if (NP >= 2) {  // last pass to global, lanes over lines (y contiguous in B1)
         const int line = t & (NL - 1), j = t >> lnl, y = y0 + line;
         const int Rp = RL, Ns = NSL;
-        if (j < L / Rp) {
+        for (int jb = j; jb < L / Rp; jb += TPL) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;
-            load_rt<-1, kMaxRadix>(a, Rp, j, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            if (y < ny) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) { st_stream(&dstc[(size_t)i * ny + y], v); });
+            load_rt<-1, kMaxRadix>(a, Rp, jb, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
+            if (y < ny) store_rt<kMaxRadix>(a, Rp, jb, Ns, [&](int i, C v) { st_stream(&dstc[(size_t)i * ny + y], v); });
         }
     } else {
         for (int e = t; e < NL * L; e += blockDim.x) {
@@ -154,14 +154,14 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
     const int t = threadIdx.x;
     {
         const int line = t / TPL, j = t % TPL, z = z0 + line;
-        if (j < L / R0) {
-            const bool zok = z < nz;
-            const C *src = B1 + (((size_t)c * nz + (zok ? z : 0)) * Lx + kx) * ny;
+        const bool zok = z < nz;
+        const C *src = B1 + (((size_t)c * nz + (zok ? z : 0)) * Lx + kx) * ny;
+        for (int jb = j; jb < L / R0; jb += TPL) {
             C a[kMaxRadix];
-            load_rt<-1, kMaxRadix, true>(a, R0, j, L, 1, tw,
+            load_rt<-1, kMaxRadix, true>(a, R0, jb, L, 1, tw,
                                    [&](int i) -> C { return (zok && i < ny) ? ld_stream(&src[i]) : czero<C>(); });
             C *ln = lds + line * S;
-            store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+            store_rt<kMaxRadix>(a, R0, jb, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
     }
     constexpr bool W = wave_lines<LC, kMaxRadix>();
@@ -178,11 +178,11 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
     if (NP >= 2) {
         const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
         const int Rp = RL, Ns = NSL;
-        if (j < L / Rp) {
+        for (int jb = j; jb < L / Rp; jb += TPL) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;
-            load_rt<-1, kMaxRadix>(a, Rp, j, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            if (z < nz) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) { st_stream(&dst[(size_t)i * kystride + z], v); });
+            load_rt<-1, kMaxRadix>(a, Rp, jb, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
+            if (z < nz) store_rt<kMaxRadix>(a, Rp, jb, Ns, [&](int i, C v) { st_stream(&dst[(size_t)i * kystride + z], v); });
         }
     } else {
         for (int e = t; e < NL * L; e += blockDim.x) {
@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     const FftPlan pf = plan_of<LC, kMaxRadixZ, false>(pf_rt);
     const FftPlan pi = plan_of<LC, kMaxRadixZ, true>(pi_rt);
     const int NPZ = pf.npass, RQ = pi.radix[NPZ - 1], NQ = pi.ns[NPZ - 1];
-    const int L = pf.L, TPL = pf.tpl, S = lds_line_stride(L);
+    const int L = pf.L, TPL = pf.tpl1, S = lds_line_stride(L);  // one butterfly per thread in every pass
     const int np = pf.npass;
     const int R0 = pf.radix[0];
     const int Ri = pi.radix[0];  // == pf.radix[np - 1]
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
         else return tw;
     }();
     C *ln = lcol + comp * S;
-    constexpr bool W = wave_lines<LC, kMaxRadixZ>();
+    constexpr bool W = wave_lines<LC, kMaxRadixZ, true>();
     constexpr int ngroups = 4 / DDA_ZMUL_SLOTS;
     const bool act = j < qi;
     // G[comp][d] for d = x, y, z: row comp of the symmetric tensor is (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             C a[kMaxRadixZ];
             if constexpr (OWN) {
                 if (np >= 2) {
-                    lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np - 1, j, twp);
+                    lds_passes<-1, kMaxRadixZ, LC, false, true>(ln, pf_rt, 1, np - 1, j, twp);
                     const int NsL = L / Ri;  // Ns of the last forward pass
                     if (act) load_rt<-1, kMaxRadixZ>(a, Ri, j, L, NsL, twp, [&](int i) { return ln[pidx(i)]; });
                     lds_sync<W>();
@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                 }
                 __syncthreads();  // the multiply reads the other two lines and the staged tensor
             } else {
-                lds_passes<-1, kMaxRadixZ, LC, false>(ln, pf_rt, 1, np, j, twp);  // natural order in LDS afterwards
+                lds_passes<-1, kMaxRadixZ, LC, false, true>(ln, pf_rt, 1, np, j, twp);  // natural order in LDS afterwards
                 if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
             }
             if (act) {
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             } else {
                 if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
                 lds_sync<W>();
-                lds_passes<+1, kMaxRadixZ, LC, true>(ln, pi_rt, 1, np - 1, j, twp);
+                lds_passes<+1, kMaxRadixZ, LC, true, true>(ln, pi_rt, 1, np - 1, j, twp);
                 if (j < L / RQ) {
                     load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, twp, [&](int i) { return ln[pidx(i)]; });
                     if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) st_stream(&line[i], v); });
@@ -409,13 +409,13 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
 #endif
     {   // pass 0 from global, lanes over lines (z contiguous in B2)
         const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
-        if (j < L / R0) {
-            const bool zok = z < nz;
+        const bool zok = z < nz;
+        for (int jb = j; jb < L / R0; jb += TPL) {
             C a[kMaxRadix];
-            load_rt<+1, kMaxRadix>(a, R0, j, L, 1, tw,
+            load_rt<+1, kMaxRadix>(a, R0, jb, L, 1, tw,
                                    [&](int i) -> C { return zok ? ld_stream(&src[(size_t)i * kystride + z]) : czero<C>(); });
             C *ln = lds + line * S;
-            store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+            store_rt<kMaxRadix>(a, R0, jb, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
     }
     __syncthreads();
@@ -424,11 +424,11 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
     C *dst = B1 + (((size_t)c * nz + (z < nz ? z : 0)) * Lx + kx) * ny;
     if (NP >= 2) {
         const int Rp = RL, Ns = NSL;
-        if (j < L / Rp) {
+        for (int jb = j; jb < L / Rp; jb += TPL) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;
-            load_rt<+1, kMaxRadix>(a, Rp, j, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            if (z < nz) store_rt<kMaxRadix>(a, Rp, j, Ns, [&](int i, C v) {
+            load_rt<+1, kMaxRadix>(a, Rp, jb, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
+            if (z < nz) store_rt<kMaxRadix>(a, Rp, jb, Ns, [&](int i, C v) {
                 if (i < ny) st_stream(&dst[i], v);
             });
         }
@@ -492,13 +492,13 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     const C *src = B1 + ((size_t)c * nz + z) * (size_t)L * ny;
     {   // pass 0 from global, lanes over lines (y contiguous in B1)
         const int line = t & (NL - 1), j = t >> lnl, y = y0 + line;
-        if (j < L / R0) {
-            const bool yok = y < ny;
+        const bool yok = y < ny;
+        for (int jb = j; jb < L / R0; jb += TPL) {
             C a[kMaxRadix];
-            load_rt<+1, kMaxRadix>(a, R0, j, L, 1, tw,
+            load_rt<+1, kMaxRadix>(a, R0, jb, L, 1, tw,
                                    [&](int i) -> C { return yok ? ld_stream(&src[(size_t)i * ny + y]) : czero<C>(); });
             C *ln = lds + line * S;
-            store_rt<kMaxRadix>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+            store_rt<kMaxRadix>(a, R0, jb, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }
     }
     __syncthreads();
@@ -524,11 +524,11 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     };
     if (NP >= 2) {
         const int Rp = RL, Ns = NSL;
-        if (j < L / Rp) {
+        for (int jb = j; jb < L / Rp; jb += TPL) {
             C a[kMaxRadix];
             const C *ln = lds + line * S;
-            load_rt<+1, kMaxRadix>(a, Rp, j, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            store_rt<kMaxRadix>(a, Rp, j, Ns, emit);
+            load_rt<+1, kMaxRadix>(a, Rp, jb, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
+            store_rt<kMaxRadix>(a, Rp, jb, Ns, emit);
         }
     } else {
         for (int i = j; i < nx; i += TPL) emit(i, lds[line * S + pidx(i)]);

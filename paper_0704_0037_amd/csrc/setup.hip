@@ -41,13 +41,14 @@ static bool five_smooth(int L) {
 }
 
 // Padded length of an axis of n cells: at least 2n - 1 (the circulant embedding of the Toeplitz
-// interaction), 5-smooth, with at most 64 threads per line (the z pass runs one column of three
-// lines per block); a length with compile-time specialized kernels is preferred when it costs at
-// most 25 % more than the smallest admissible one.
+// interaction), 5-smooth, with at most 64 threads per line in the z pass (L / its smallest radix:
+// one butterfly per thread in every pass, one column of three lines per block); a length with
+// compile-time specialized kernels is preferred when it costs at most 25 % more than the smallest
+// admissible one.
 static bool admissible(int L) {
     if (!five_smooth(L)) return false;
     const FftPlan p = make_plan(L, kMaxRadixZ, false);
-    return p.npass > 0 && p.tpl <= 64;
+    return p.npass > 0 && p.tpl1 <= 64;
 }
 static int smallest_pad(int n) {
     int L = std::max(1, 2 * n - 1);
@@ -145,23 +146,23 @@ __global__ void __launch_bounds__(DDA_MAX_THREADS) k_fft_axis(double2 *__restric
     C *base = buf + (size_t)(ok ? u0 + gline : 0) * su + (size_t)v * sv;
     {
         const int R0 = pl.radix[0];
-        if (gj < L / R0) {
+        for (int jb = gj; jb < L / R0; jb += TPL) {
             C a[kMaxRadix];
-            load_rt<-1, kMaxRadix>(a, R0, gj, L, 1, tw,
+            load_rt<-1, kMaxRadix>(a, R0, jb, L, 1, tw,
                                    [&](int i) -> C { return ok ? base[(size_t)i * sp] : czero<C>(); });
             C *ln = lds + gline * S;
-            store_rt<kMaxRadix>(a, R0, gj, 1, [&](int i, C val) { ln[pidx(i)] = val; });
+            store_rt<kMaxRadix>(a, R0, jb, 1, [&](int i, C val) { ln[pidx(i)] = val; });
         }
     }
     __syncthreads();
     lds_passes<-1, kMaxRadix, 0, false>(lds + (t / TPL) * S, pl, 1, pl.npass - 1, t % TPL, tw);
     if (pl.npass >= 2) {
         const int p = pl.npass - 1, Rp = pl.radix[p], Ns = pl.ns[p];
-        if (gj < L / Rp) {
+        for (int jb = gj; jb < L / Rp; jb += TPL) {
             C a[kMaxRadix];
             const C *ln = lds + gline * S;
-            load_rt<-1, kMaxRadix>(a, Rp, gj, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            if (ok) store_rt<kMaxRadix>(a, Rp, gj, Ns, [&](int i, C val) { base[(size_t)i * sp] = val; });
+            load_rt<-1, kMaxRadix>(a, Rp, jb, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
+            if (ok) store_rt<kMaxRadix>(a, Rp, jb, Ns, [&](int i, C val) { base[(size_t)i * sp] = val; });
         }
     } else if (ok) {
         for (int i = gj; i < L; i += TPL) base[(size_t)i * sp] = lds[gline * S + pidx(i)];
@@ -625,7 +626,7 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
     };
     const bool tiles_ok = tiles(c->tl64, 16, max_threads<double>()) && tiles(c->tl32, 8, max_threads<float>());
     c->nc_z = 1;
-    if (DDA_ZMUL_SLOTS * 3 * c->pzf.tpl > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 || !tiles_ok) {
+    if (DDA_ZMUL_SLOTS * 3 * c->pzf.tpl1 > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 || !tiles_ok) {
         set_error("dda_setup: padded size too large for one workgroup per line");
         delete c;
         return DDA_EINVAL;
