@@ -544,21 +544,26 @@ def materials_study(dda, inputs, torch, n=256, reps=10):
     return out
 
 
-def product_only(dda, inputs, torch, reps):
-    """The 256^3 sphere's fp64 product on a batch of both polarizations: tile schedule tuned for that
-    batch, then `reps` products with HIP events around every kernel; ms per launch and the fraction
-    of the HBM peak from the algorithmic bytes."""
-    w = inputs.c2_sphere256()
-    n = w.grid[0]
+def product_only(dda, inputs, torch, reps, n=256):
+    """The fp64 product on a batch of both polarizations: tile schedule tuned for that batch, then
+    `reps` products with HIP events around every kernel; ms per launch and the fraction of the HBM
+    peak from the algorithmic bytes.  n = 256: the 256^3 sphere of the benchmark; other n: an n^3
+    sphere with m = 1.3 and kd = 0.3 (the sizes of the many-particle workload)."""
+    if n == 256:
+        w = inputs.c2_sphere256()
+        name, mask, m, kd = w.name, w.mask, w.m, w.kd
+    else:
+        name, mask, m, kd = f"sphere{n}_m1.3_kd0.3", inputs.sphere_mask(n), 1.3, 0.3
     beams = [inputs.X_POL, inputs.Y_POL]
-    with dda.Context(w.mask, w.m, w.kd) as ctx:
+    with dda.Context(mask, m, kd) as ctx:
         L, N = ctx.padded_grid()[0], ctx.n
         tiles = ctx.tune(dda.FP64, n_rhs=len(beams))
         x = torch.from_numpy(inputs.random_vector(N, seed=1, n_rhs=len(beams))).cuda()
         y = torch.empty_like(x)
         kms, tot = ctx.matvec_timed(beams, x, y, reps=reps)
     ab = alg_bytes(n, N, L, 16, len(beams))
-    return {"workload": f"{w.name}, fp64, batch of {len(beams)}", "tiles": tiles, "reps": reps, "total_ms": tot,
+    return {"workload": f"{name}, fp64, batch of {len(beams)}", "padded": L, "n_dipoles": N, "tiles": tiles,
+            "reps": reps, "total_ms": tot,
             "kernels": {k: {"ms": kms[i], "frac": ab[k] / kms[i] / 1e6 / HBM_PEAK_GBS} for i, k in enumerate(KERNELS)},
             "product_frac": sum(ab.values()) / tot / 1e6 / HBM_PEAK_GBS}
 
@@ -584,6 +589,7 @@ def main():
                          "times over --reps products (a short run for counter profiles)")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--study-n", type=int, default=64, help="grid side of the sphere in --solver-study")
+    ap.add_argument("--product-n", type=int, nargs="+", default=[256], help="sphere sizes of --product-only")
     ap.add_argument("--budget-s", type=float, default=540.0,
                     help="wall-clock budget of the whole run: a form that would not fit is skipped (and named)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
@@ -618,7 +624,8 @@ def main():
         print(json.dumps(materials_study(dda, inputs, torch)), flush=True)
         return
     if args.product_only:
-        print(json.dumps(product_only(dda, inputs, torch, args.reps)), flush=True)
+        for n in args.product_n:
+            print(json.dumps(product_only(dda, inputs, torch, args.reps, n)), flush=True)
         return
 
     if args.calibration_copy:
