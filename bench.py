@@ -398,7 +398,8 @@ def forms(ctx, w, beams, theta, dda, inputs, torch, over_budget, cpu=None):
             c.solve([inputs.X_POL], tol=1e-1, precision=dda.FP32_PRODUCT)
         pol = [inputs.X_POL] * len(cs)
         dda.solve_many(cs, pol, tol=1e-1, pack=True)  # warm: the batches' buffers and kernels
-        _, tseq = _timed(torch, lambda: [c.solve([inputs.X_POL], tol=1e-5) for c in cs])
+        each = [_timed(torch, lambda c=c: c.solve([inputs.X_POL], tol=1e-5))[1] for c in cs]
+        tseq = sum(each)
         (_, infos, st), tm = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5))
         (_, ip, sp), tp = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5, pack=True))
         (_, i32, st32), tm32 = _timed(torch, lambda: dda.solve_many(cs, pol, tol=1e-5, precision=dda.FP32_PRODUCT))
@@ -410,6 +411,8 @@ def forms(ctx, w, beams, theta, dda, inputs, torch, over_budget, cpu=None):
             "packed_fp64_s": tp, "packed": "particles sharing a padded length packed into one batch each "
                                            "(one launch per pass over the batch, pack=True)",
             "speedup": tseq / tm, "speedup_fp32_products": tseq / tm32, "speedup_packed": tseq / tp,
+            "slowest_particle_s": max(each), "five_slowest_particles_s": sorted(each)[-5:],
+            "slowest_particle": ws[int(np.argmax(each))].name,
             "iterations": [int(i["iters"]) for i in infos], "fp64_finish": sum(int(i["outer"]) for i in i32),
             "res_true_max": max(i["res_true"] for i in infos),
             "res_true_max_fp32_products": max(i["res_true"] for i in i32)}

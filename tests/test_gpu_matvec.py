@@ -65,6 +65,38 @@ def test_matvec_matches_oracle(name, mask, m, kd, pad):
         assert _rel_err(y, ref) < 1e-12, (name, ctx.padded_grid(), _rel_err(y, ref))
 
 
+SPECIALIZED = [32, 48, 60, 64, 72, 80, 96, 120, 128, 160, 192, 256, 320, 384, 512]
+
+
+@pytest.mark.parametrize("L", SPECIALIZED)
+def test_every_specialized_length_matches_oracle(L):
+    """Each length with compile-time kernels (its radix schedule, its threads per line and its
+    butterflies per thread in the passes of smaller radix) on every axis: a ragged particle padded to
+    L along one axis at a time (L^3 up to 192), two batched beams, fp64 against the oracle at 1e-12
+    and fp32 at 2e-5.  384 (radices 8, 4, 4, 3) is an x and y length only: the z pass runs one
+    thread per butterfly of its radix-3 pass, 128 per line, above its 64, and setup refuses it."""
+    dda = _dda()
+    mask = _random_mask((7, 9, 11), 40 + L, 0.5)  # [nz][ny][nx]
+    m, kd = 1.4 + 0.02j, 0.5
+    pads = [(L, L, L)] if L <= 192 else [(L, 24, 16), (24, L, 16)] + ([(24, 24, L)] if L != 384 else [])
+    if L == 384:
+        with pytest.raises(dda.DDAError) as e:
+            dda.Context(mask, m, kd, pad=(24, 24, L))
+        assert e.value.status == dda.EINVAL
+    beams = [inputs.X_POL, inputs.Y_POL]
+    for pad in pads:
+        with dda.Context(mask, m, kd, pad=pad, fp32=True) as ctx:
+            assert ctx.padded_grid() == pad
+            x = inputs.random_vector(ctx.n, seed=L, n_rhs=2)
+            y = ctx.matvec_batch(beams, torch.from_numpy(x).cuda()).cpu().numpy()
+            for r, b in enumerate(beams):
+                ref = _oracle_y(mask, m, kd, b, x[r])
+                assert _rel_err(y[r], ref) < 1e-12, (pad, r, _rel_err(y[r], ref))
+            y32 = ctx.matvec_f32(beams[0], torch.from_numpy(x[0].astype(np.complex64)).cuda()).cpu().numpy()
+            ref = _oracle_y(mask, m, kd, beams[0], x[0])
+            assert _rel_err(y32, ref) < 2e-5, (pad, _rel_err(y32, ref))
+
+
 def test_lines_per_block_does_not_change_result():
     dda = _dda()
     mask = inputs.sphere_mask(10)
