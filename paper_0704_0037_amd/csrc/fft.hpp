@@ -117,6 +117,16 @@ __host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
     return p;
 }
 
+// threads per line of the fused z pass: one butterfly per thread in every pass when that fits
+// in 64 (tpl1), else L / (largest radix) with several butterflies per thread in the passes of
+// smaller radix (384 = 8 4 4 3: 48 threads, not 128)
+__host__ __device__ constexpr int zmul_tpl(const FftPlan &p) { return p.tpl1 <= 64 ? p.tpl1 : p.tpl; }
+// threads per component line in the z-pass block: zmul_tpl, or a whole wave for the lengths with
+// several butterflies per thread (their lines then sync the wave only, and the multiply's code
+// path is uniform per wave; lanes past zmul_tpl idle).  Measured: 7 % faster at 384 (48 of 64
+// lanes), but 20-30 % slower at 120 and 160 than lines packed across waves.
+__host__ __device__ constexpr int zmul_ct(const FftPlan &p) { return p.tpl1 > 64 ? 64 : zmul_tpl(p); }
+
 // bound on the butterflies a thread takes in a pass of radix R when a line has L / (largest
 // radix) threads and no radix exceeds maxr
 __host__ __device__ constexpr int bfly_per_thread(int R, int maxr) { return (maxr + R - 1) / R; }
@@ -415,10 +425,9 @@ template <bool WAVE> __device__ __forceinline__ void lds_sync() {
     }
 }
 
-// lines of a compile-time plan fit in one wavefront when its threads-per-line divides 64 (tpl1
-// for callers with one butterfly per thread)
-template <int LC, int MAXR, bool ONE = false> __host__ __device__ constexpr bool wave_lines() {
-    if constexpr (LC > 0) return 64 % (ONE ? make_plan(LC, MAXR, false).tpl1 : make_plan(LC, MAXR, false).tpl) == 0;
+// lines of a compile-time plan fit in one wavefront when its threads-per-line divides 64
+template <int LC, int MAXR> __host__ __device__ constexpr bool wave_lines() {
+    if constexpr (LC > 0) return 64 % make_plan(LC, MAXR, false).tpl == 0;
     else return false;
 }
 

@@ -209,10 +209,16 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                                                           FftPlan pi_rt, const cplx<R> *__restrict__ twall,
                                                           const int *__restrict__ done) {
     using C = cplx<R>;
-    const FftPlan pf = plan_of<LC, kMaxRadixZ, false>(pf_rt);
-    const FftPlan pi = plan_of<LC, kMaxRadixZ, true>(pi_rt);
+    // MB lengths (384 = 8 4 4 3; 360, 480 at run time) run the forward plan largest radix last and
+    // the inverse largest first, so the multiply still has one butterfly per thread
+    constexpr bool FLIP = LC > 0 && make_plan(LC, kMaxRadixZ, false).tpl1 > 64;
+    const FftPlan pf = plan_of<LC, kMaxRadixZ, FLIP>(pf_rt);
+    const FftPlan pi = plan_of<LC, kMaxRadixZ, !FLIP>(pi_rt);
     const int NPZ = pf.npass, RQ = pi.radix[NPZ - 1], NQ = pi.ns[NPZ - 1];
-    const int L = pf.L, TPL = pf.tpl1, S = lds_line_stride(L);  // one butterfly per thread in every pass
+    // one butterfly per thread in every pass, or (MB) L / (largest radix) threads per line with
+    // several butterflies per thread in the passes of smaller radix
+    const bool MB = pf.tpl1 > 64;
+    const int L = pf.L, TPL = zmul_tpl(pf), S = lds_line_stride(L);
     const int np = pf.npass;
     const int R0 = pf.radix[0];
     const int Ri = pi.radix[0];  // == pf.radix[np - 1]
@@ -226,7 +232,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     C *lds = reinterpret_cast<C *>(smem_raw);
     const C *tw = twall + pf_rt.tw_off;
     const int t = threadIdx.x;
-    const int lslot = t / (3 * TPL), comp = (t / TPL) % 3, j = t % TPL;
+    const int CT = zmul_ct(pf);  // threads per component line in the block (>= TPL)
+    const int lslot = t / (3 * CT), comp = (t / CT) % 3, u = t % CT;
+    const int j0 = u < TPL ? u : L;  // lanes past TPL take no butterfly
     const int kxo = oct % (hx + 1), kyo = oct / (hx + 1);
     const int nmx = (kxo == 0 || 2 * kxo == Lx) ? 1 : 2;  // distinct x mirrors of this column
     const int nmy = (kyo == 0 || 2 * kyo == Ly) ? 1 : 2;
@@ -244,14 +252,14 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
         for (int e = t; e < LC / 8; e += blockDim.x) tws[e] = tw[e];
         __syncthreads();
     }
-    const auto twp = [&] {
+    const auto twp0 = [&] {
         if constexpr (TWL) return TwStaged<C>{tws, tw};
         else return tw;
     }();
     C *ln = lcol + comp * S;
-    constexpr bool W = wave_lines<LC, kMaxRadixZ, true>();
+    constexpr bool W = LC > 0 && 64 % zmul_ct(make_plan(LC, kMaxRadixZ, false)) == 0;  // a line within one wave
     constexpr int ngroups = 4 / DDA_ZMUL_SLOTS;
-    const bool act = j < qi;
+    const bool act = j0 < qi;
     // G[comp][d] for d = x, y, z: row comp of the symmetric tensor is (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
     const int g0 = comp == 0 ? 0 : comp == 1 ? 1 : 2;
     const int g1 = comp == 0 ? 1 : comp == 1 ? 3 : 4;
@@ -272,6 +280,18 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     for (int q = next_round(0); q < Q; q = next_round(q + 1)) {
         const int rhs = q / ngroups, grp = q % ngroups;
         {
+            // several butterflies per thread: the butterfly index and the twiddle table are opaque
+            // to the compiler from round to round, so the many per-thread LDS addresses and twiddle
+            // loads are formed inside each round instead of being held in registers across rounds
+            // (which spills)
+            auto twp = twp0;
+            int j = j0;
+            if constexpr (!TWL) {
+                if (MB) {
+                    __asm__ volatile("" : "+s"(twp));
+                    __asm__ volatile("" : "+v"(j));
+                }
+            }
             const int slot = grp * DDA_ZMUL_SLOTS + lslot;  // mirror 0..3 of the octant column
             const bool mxs = slot & 1, mys = slot & 2;
             const bool ok = (!mxs || nmx == 2) && (!mys || nmy == 2);  // slot holds a distinct column
@@ -281,13 +301,22 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
 #else
             C *line = B2 + (((size_t)(ok ? ky : 0) * Lx + (ok ? kx : 0)) * (3 * nrhs) + rhs * 3 + comp) * nz;
 #endif
-            if (j < q0) {
+            for (int jb = j; jb < q0; jb += TPL) {
                 C a[kMaxRadixZ];
-                load_rt<-1, kMaxRadixZ, true>(a, R0, j, L, 1, twp,
+                load_rt<-1, kMaxRadixZ, true>(a, R0, jb, L, 1, twp,
                                         [&](int i) -> C { return (ok && i < nz) ? ld_stream(&line[i]) : czero<C>(); });
-                store_rt<kMaxRadixZ>(a, R0, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
+                store_rt<kMaxRadixZ>(a, R0, jb, 1, [&](int i, C v) { ln[pidx(i)] = v; });
             }
             lds_sync<W>();
+            // LDS passes [p0, p1) of the forward (inverse) plan, one or several butterflies per thread
+            auto fpasses = [&](int p0, int p1) {
+                if (MB) lds_passes<-1, kMaxRadixZ, LC, FLIP, false>(ln, pf_rt, p0, p1, j, twp);
+                else lds_passes<-1, kMaxRadixZ, LC, FLIP, true>(ln, pf_rt, p0, p1, j, twp);
+            };
+            auto ipasses = [&](int p0, int p1) {
+                if (MB) lds_passes<+1, kMaxRadixZ, LC, !FLIP, false>(ln, pi_rt, p0, p1, j, twp);
+                else lds_passes<+1, kMaxRadixZ, LC, !FLIP, true>(ln, pi_rt, p0, p1, j, twp);
+            };
             // own-component path (double precision): all forward passes but the last through LDS;
             // the last one keeps this thread's outputs (its own component at kz = j + r qi) in
             // registers and also stores them, in natural order, for the two other components
@@ -295,7 +324,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             C a[kMaxRadixZ];
             if constexpr (OWN) {
                 if (np >= 2) {
-                    lds_passes<-1, kMaxRadixZ, LC, false, true>(ln, pf_rt, 1, np - 1, j, twp);
+                    fpasses(1, np - 1);
                     const int NsL = L / Ri;  // Ns of the last forward pass
                     if (act) load_rt<-1, kMaxRadixZ>(a, Ri, j, L, NsL, twp, [&](int i) { return ln[pidx(i)]; });
                     lds_sync<W>();
@@ -306,7 +335,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                 }
                 __syncthreads();  // the multiply reads the other two lines and the staged tensor
             } else {
-                lds_passes<-1, kMaxRadixZ, LC, false, true>(ln, pf_rt, 1, np, j, twp);  // natural order in LDS afterwards
+                fpasses(1, np);  // natural order in LDS afterwards
                 if constexpr (W) __syncthreads();  // the multiply reads all three lines and the staged tensor
             }
             if (act) {
@@ -318,8 +347,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                 const R s2 = comp == 0 ? sx : comp == 1 ? sy : (R)1;
                 auto mul = [&](auto radix_tag) {
                     constexpr int RI = decltype(radix_tag)::value;
-                    // the component is uniform per wave: one code path per component; on the
-                    // own-component path each reads only the two other lines
+                    // one code path per component (a wave holds one component when its lines do
+                    // not straddle waves); on the own-component path each reads only the two
+                    // other lines
                     auto rows = [&](auto comp_tag) {
                         constexpr int CP = decltype(comp_tag)::value;
 #pragma unroll
@@ -358,10 +388,10 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             } else {
                 if (act) store_rt<kMaxRadixZ>(a, Ri, j, 1, [&](int i, C v) { ln[pidx(i)] = v; });
                 lds_sync<W>();
-                lds_passes<+1, kMaxRadixZ, LC, true, true>(ln, pi_rt, 1, np - 1, j, twp);
-                if (j < L / RQ) {
-                    load_rt<+1, kMaxRadixZ>(a, RQ, j, L, NQ, twp, [&](int i) { return ln[pidx(i)]; });
-                    if (ok) store_rt<kMaxRadixZ>(a, RQ, j, NQ, [&](int i, C v) { if (i < nz) st_stream(&line[i], v); });
+                ipasses(1, np - 1);
+                for (int jb = j; jb < L / RQ; jb += TPL) {
+                    load_rt<+1, kMaxRadixZ>(a, RQ, jb, L, NQ, twp, [&](int i) { return ln[pidx(i)]; });
+                    if (ok) store_rt<kMaxRadixZ>(a, RQ, jb, NQ, [&](int i, C v) { if (i < nz) st_stream(&line[i], v); });
                 }
             }
             lds_sync<W>();  // the slot's lines are rewritten by the next round

@@ -41,14 +41,13 @@ static bool five_smooth(int L) {
 }
 
 // Padded length of an axis of n cells: at least 2n - 1 (the circulant embedding of the Toeplitz
-// interaction), 5-smooth, with at most 64 threads per line in the z pass (L / its smallest radix:
-// one butterfly per thread in every pass, one column of three lines per block); a length with
-// compile-time specialized kernels is preferred when it costs at most 25 % more than the smallest
-// admissible one.
+// interaction), 5-smooth, with at most 64 threads per line in the z pass (one column of three
+// lines per block; zmul_tpl); a length with compile-time specialized kernels is preferred when it
+// costs at most 25 % more than the smallest admissible one.
 static bool admissible(int L) {
     if (!five_smooth(L)) return false;
     const FftPlan p = make_plan(L, kMaxRadixZ, false);
-    return p.npass > 0 && p.tpl1 <= 64;
+    return p.npass > 0 && zmul_tpl(p) <= 64;
 }
 static int smallest_pad(int n) {
     int L = std::max(1, 2 * n - 1);
@@ -599,8 +598,12 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
         f.tw_off = inv.tw_off = off_of(L);
         return f.npass > 0 && inv.npass > 0;
     };
-    if (!plans(c->Lx, kMaxRadix, c->pxf, c->pxi) || !plans(c->Ly, kMaxRadix, c->pyf, c->pyi) ||
-        !plans(c->Lz, kMaxRadixZ, c->pzf, c->pzi)) {
+    // the z pass of a length whose smallest radix would need more than 64 threads per line runs
+    // its forward plan largest radix last (and the inverse largest first)
+    const bool zflip = make_plan(c->Lz, kMaxRadixZ, false).tpl1 > 64;
+    bool zok = plans(c->Lz, kMaxRadixZ, c->pzf, c->pzi);
+    if (zok && zflip) std::swap(c->pzf, c->pzi);
+    if (!plans(c->Lx, kMaxRadix, c->pxf, c->pxi) || !plans(c->Ly, kMaxRadix, c->pyf, c->pyi) || !zok) {
         set_error("dda_setup: unsupported padded size");
         delete c;
         return DDA_EINVAL;
@@ -626,7 +629,7 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
     };
     const bool tiles_ok = tiles(c->tl64, 16, max_threads<double>()) && tiles(c->tl32, 8, max_threads<float>());
     c->nc_z = 1;
-    if (DDA_ZMUL_SLOTS * 3 * c->pzf.tpl1 > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 || !tiles_ok) {
+    if (DDA_ZMUL_SLOTS * 3 * zmul_ct(c->pzf) > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 || !tiles_ok) {
         set_error("dda_setup: padded size too large for one workgroup per line");
         delete c;
         return DDA_EINVAL;

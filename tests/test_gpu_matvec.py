@@ -68,21 +68,18 @@ def test_matvec_matches_oracle(name, mask, m, kd, pad):
 SPECIALIZED = [32, 48, 60, 64, 72, 80, 96, 120, 128, 160, 192, 256, 320, 384, 512]
 
 
-@pytest.mark.parametrize("L", SPECIALIZED)
+@pytest.mark.parametrize("L", SPECIALIZED + [360, 480])
 def test_every_specialized_length_matches_oracle(L):
     """Each length with compile-time kernels (its radix schedule, its threads per line and its
     butterflies per thread in the passes of smaller radix) on every axis: a ragged particle padded to
     L along one axis at a time (L^3 up to 192), two batched beams, fp64 against the oracle at 1e-12
-    and fp32 at 2e-5.  384 (radices 8, 4, 4, 3) is an x and y length only: the z pass runs one
-    thread per butterfly of its radix-3 pass, 128 per line, above its 64, and setup refuses it."""
+    and fp32 at 2e-5.  384 (radices 8, 4, 4, 3), and the runtime-planned 360 and 480, take several
+    butterflies per thread in the z pass too (one per thread would need more than 64 threads per
+    line)."""
     dda = _dda()
     mask = _random_mask((7, 9, 11), 40 + L, 0.5)  # [nz][ny][nx]
     m, kd = 1.4 + 0.02j, 0.5
-    pads = [(L, L, L)] if L <= 192 else [(L, 24, 16), (24, L, 16)] + ([(24, 24, L)] if L != 384 else [])
-    if L == 384:
-        with pytest.raises(dda.DDAError) as e:
-            dda.Context(mask, m, kd, pad=(24, 24, L))
-        assert e.value.status == dda.EINVAL
+    pads = [(L, L, L)] if L <= 192 else [(L, 24, 16), (24, L, 16), (24, 24, L)]
     beams = [inputs.X_POL, inputs.Y_POL]
     for pad in pads:
         with dda.Context(mask, m, kd, pad=pad, fp32=True) as ctx:
@@ -95,6 +92,16 @@ def test_every_specialized_length_matches_oracle(L):
             y32 = ctx.matvec_f32(beams[0], torch.from_numpy(x[0].astype(np.complex64)).cuda()).cpu().numpy()
             ref = _oracle_y(mask, m, kd, beams[0], x[0])
             assert _rel_err(y32, ref) < 2e-5, (pad, _rel_err(y32, ref))
+
+
+def test_spheres_of_161_to_192_cells_pad_to_384():
+    """2n - 1 in 321..383: the smallest admissible length is 360 (n <= 180) or 384, and the
+    specialized 384 is taken (it was 512 while the z pass needed one thread per butterfly of its
+    radix-3 pass)."""
+    dda = _dda()
+    for n in (161, 175, 192):
+        with dda.Context(inputs.sphere_mask(n), 1.3, 0.3) as ctx:
+            assert ctx.padded_grid() == (384, 384, 384), (n, ctx.padded_grid())
 
 
 def test_lines_per_block_does_not_change_result():
