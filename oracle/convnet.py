@@ -67,11 +67,13 @@ TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0,
 
 
 def num_params():
+    """Number of network parameters (bookkeeping, no arithmetic of the method)."""
     return sum(27 * ci * co + co for ci, co, *_ in LAYERS)
 
 
 def unflatten(p):
-    """Flat canonical vector -> list of (W [27][co][ci], b [co]) float64."""
+    """Flat canonical vector -> list of (W [27][co][ci], b [co]) float64 (bookkeeping; the GPU
+    parameter layout is checked against it by the network's parity tests)."""
     p = np.asarray(p, dtype=np.float64)
     out, o = [], 0
     for ci, co, *_ in LAYERS:
@@ -85,11 +87,13 @@ def unflatten(p):
 
 
 def flatten(layers):
+    """Inverse of unflatten (bookkeeping)."""
     return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in layers])
 
 
 def init_params(seed):
-    """He-normal weights (std sqrt(2 / (27 cin))), zero biases; the head is scaled by 0.1."""
+    """He-normal weights (std sqrt(2 / (27 cin))), zero biases; the head is scaled by 0.1
+    (seeded initial values, no arithmetic of the method)."""
     rng = np.random.default_rng(seed)
     layers = []
     for li, (ci, co, *_) in enumerate(LAYERS):
@@ -101,7 +105,10 @@ def init_params(seed):
 
 
 def bf16(x):
-    """Round to bfloat16 (nearest even), returned as float64."""
+    """Round to bfloat16 (nearest even), returned as float64.
+
+    pinned by: test_oracle_convnet.py::test_bf16_rounding_and_rounded_gradient_close_to_exact.
+    """
     f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
     u = f.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
@@ -110,7 +117,11 @@ def bf16(x):
 
 # ------------------------------------------------------------------------------ operators
 def conv3d(x, W):
-    """3x3x3 zero-padded cross-correlation: x [D][H][W][ci], W [27][co][ci] -> [D][H][W][co]."""
+    """3x3x3 zero-padded cross-correlation: x [D][H][W][ci], W [27][co][ci] -> [D][H][W][co].
+
+    pinned by: test_oracle_convnet.py::test_conv_matches_scipy_correlate and
+        test_conv_brute_force_and_single_tap_shift.
+    """
     D, H, Wd, _ = x.shape
     xp = np.pad(x, ((1, 1), (1, 1), (1, 1), (0, 0)))
     y = np.zeros((D, H, Wd, W.shape[1]))
@@ -120,7 +131,10 @@ def conv3d(x, W):
 
 
 def conv3d_weight_grad(x, g):
-    """d/dW of sum(g * conv3d(x, W)): [27][co][ci]."""
+    """d/dW of sum(g * conv3d(x, W)): [27][co][ci].
+
+    pinned by: test_oracle_convnet.py::test_gradient_matches_finite_differences.
+    """
     D, H, Wd, _ = x.shape
     xp = np.pad(x, ((1, 1), (1, 1), (1, 1), (0, 0)))
     gf = g.reshape(-1, g.shape[-1])
@@ -132,34 +146,55 @@ def conv3d_weight_grad(x, g):
 
 
 def conv3d_input_grad(g, W):
-    """d/dx of sum(g * conv3d(x, W)): the correlation with the flipped, transposed kernel."""
+    """d/dx of sum(g * conv3d(x, W)): the correlation with the flipped, transposed kernel.
+
+    pinned by: test_oracle_convnet.py::test_pool_up_adjoint_and_conv_adjoints.
+    """
     Wt = np.stack([W[26 - t].T for t in range(27)])  # [27][ci][co]
     return conv3d(g, Wt)
 
 
 def pool(x):
+    """2x2x2 average pooling.
+
+    pinned by: test_oracle_convnet.py::test_pool_up_adjoint_and_conv_adjoints.
+    """
     D, H, Wd, C = x.shape
     return x.reshape(D // 2, 2, H // 2, 2, Wd // 2, 2, C).mean(axis=(1, 3, 5))
 
 
 def up(x):
+    """Nearest-neighbour 2x up-sampling along each axis.
+
+    pinned by: test_oracle_convnet.py::test_pool_up_adjoint_and_conv_adjoints.
+    """
     return x.repeat(2, axis=0).repeat(2, axis=1).repeat(2, axis=2)
 
 
 def pool_adjoint(g):
-    """d/dx of sum(g * pool(x))."""
+    """d/dx of sum(g * pool(x)).
+
+    pinned by: test_oracle_convnet.py::test_pool_up_adjoint_and_conv_adjoints (adjoint identity <g,
+        pool x> = <pool* g, x>).
+    """
     return up(g) / 8.0
 
 
 def up_adjoint(g):
-    """d/dx of sum(g * up(x))."""
+    """d/dx of sum(g * up(x)).
+
+    pinned by: test_oracle_convnet.py::test_pool_up_adjoint_and_conv_adjoints.
+    """
     D, H, Wd, C = g.shape
     return g.reshape(D // 2, 2, H // 2, 2, Wd // 2, 2, C).sum(axis=(1, 3, 5))
 
 
 # ------------------------------------------------------------------------------ network
 def forward(params, feat, bf16_round=False):
-    """Activations of one sample (feat [G][G][G][16], the 16 input channels) as a dict; 'out' is the prediction."""
+    """Activations of one sample (feat [G][G][G][16], the 16 input channels) as a dict; 'out' is the prediction.
+
+    pinned by: test_oracle_convnet.py::test_gradient_matches_finite_differences.
+    """
     r = bf16 if bf16_round else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(r(W), np.asarray(b, dtype=np.float64)) for W, b in unflatten(params)]
     a = {"f": r(feat)}
@@ -187,6 +222,7 @@ def loss_and_grad(params, feats, targets, masks, bf16_round=False):
     """Masked mean-square loss over a batch and its gradient w.r.t. the flat parameters.
 
     feats [B][G][G][G][16], targets [B][G][G][G][6], masks [B][G][G][G] (0/1).
+    pinned by: test_oracle_convnet.py::test_gradient_matches_finite_differences.
     """
     r = bf16 if bf16_round else (lambda a: np.asarray(a, dtype=np.float64))
     layers = [(r(W), b) for W, b in unflatten(params)]
@@ -229,12 +265,19 @@ def loss_and_grad(params, feats, targets, masks, bf16_round=False):
 
 # ---------------------------------------------------------------------- DDA coupling
 def box_offset(grid, G):
+    """Offset (x, y, z) of a grid of `grid` cells centred in the G^3 box.
+
+    pinned by: test_oracle_convnet.py::test_features_target_guess_against_dda_oracle.
+    """
     nx, ny, nz = grid
     return (G - nx) // 2, (G - ny) // 2, (G - nz) // 2
 
 
 def box_positions(grid, G):
-    """Particle-frame positions of every box cell, [G][G][G][3] (x, y, z)."""
+    """Particle-frame positions of every box cell, [G][G][G][3] (x, y, z).
+
+    pinned by: test_oracle_convnet.py::test_features_target_guess_against_dda_oracle.
+    """
     nx, ny, nz = grid
     ox, oy, oz = box_offset(grid, G)
     c = np.arange(G) + 0.5
@@ -243,7 +286,10 @@ def box_positions(grid, G):
 
 
 def box_mask(mask, G):
-    """mask [nz][ny][nx] placed in the G^3 box."""
+    """mask [nz][ny][nx] placed in the G^3 box.
+
+    pinned by: test_oracle_convnet.py::test_features_target_guess_against_dda_oracle.
+    """
     nz, ny, nx = mask.shape
     ox, oy, oz = box_offset((nx, ny, nz), G)
     out = np.zeros((G, G, G))
@@ -252,6 +298,11 @@ def box_mask(mask, G):
 
 
 def features(mask, m, kd, prop, pol, G):
+    """The network's 16 input channels on the G^3 box for a particle and a beam.
+
+    pinned by: test_oracle_convnet.py::test_features_target_guess_against_dda_oracle (against the
+        DDA oracle's incident field and polarizability).
+    """
     nz, ny, nx = mask.shape
     mk = box_mask(mask, G)
     r = box_positions((nx, ny, nz), G)
@@ -272,7 +323,10 @@ def features(mask, m, kd, prop, pol, G):
 
 
 def dipole_cells(mask, G):
-    """Flat box indices (z, y, x order) of the dipoles, in the dipole order of the lattice."""
+    """Flat box indices (z, y, x order) of the dipoles, in the dipole order of the lattice.
+
+    pinned by: test_oracle_convnet.py::test_features_target_guess_against_dda_oracle.
+    """
     nz, ny, nx = mask.shape
     ox, oy, oz = box_offset((nx, ny, nz), G)
     z, y, x = np.nonzero(mask)
@@ -280,7 +334,11 @@ def dipole_cells(mask, G):
 
 
 def target(mask, kd, beta, prop, pol, x, G):
-    """x (N, 3) solution -> [G][G][G][6] target (Re/Im of x / beta - E_inc at the dipoles)."""
+    """x (N, 3) solution -> [G][G][G][6] target (Re/Im of x / beta - E_inc at the dipoles).
+
+    pinned by: test_oracle_convnet.py::test_features_target_guess_against_dda_oracle (target and
+        guess invert each other).
+    """
     from . import dda as odda
     pos, _ = odda.dipoles(mask)
     Einc = odda.incident_field(pos, kd, prop, pol)
@@ -293,7 +351,10 @@ def target(mask, kd, beta, prop, pol, x, G):
 
 
 def guess(mask, kd, beta, prop, pol, out, G):
-    """Network output [G][G][G][6] -> initial guess x0 (N, 3) = beta (E_inc + delta)."""
+    """Network output [G][G][G][6] -> initial guess x0 (N, 3) = beta (E_inc + delta).
+
+    pinned by: test_oracle_convnet.py::test_features_target_guess_against_dda_oracle.
+    """
     from . import dda as odda
     pos, _ = odda.dipoles(mask)
     Einc = odda.incident_field(pos, kd, prop, pol)

@@ -70,6 +70,8 @@ def ldr_s(prop, pol):
 
     Reading: for a complex (e.g. circular) polarization the squared modulus of each
     component is used; for linear polarization this is the usual sum (a_mu e_mu)^2.
+    pinned by: test_oracle_ldr.py (the lattice dispersion relation along an axis, S = 0, a face
+        diagonal, S = 1/2, and a body diagonal, S = 1/3).
     """
     a = np.asarray(prop, dtype=np.float64)
     e = np.asarray(pol, dtype=np.complex128)
@@ -107,7 +109,12 @@ def alpha_cldr(m, k, prop):
 
 
 def beta_of_alpha(alpha):
-    """beta with beta*beta = alpha (Sec. 2, text before eq. 2); principal square root."""
+    """beta with beta*beta = alpha (Sec. 2, text before eq. 2); principal square root.
+
+    pinned by: test_oracle_physics.py::test_inhomogeneous_symmetrized_system_equals_equation_1 and
+        test_tensor_polarizability_symmetrized_system_equals_equation_1 (the beta-symmetrized system
+        solves eq. 1).
+    """
     return np.sqrt(complex(alpha))
 
 
@@ -204,7 +211,11 @@ def matvec_rows(pos, k, beta, x, rows, chunk=1 << 18):
 
 
 def matvec(pos, k, beta, x, chunk=256):
-    """Full direct-sum matvec of eq. (3), processed in row chunks (O(N^2) work)."""
+    """Full direct-sum matvec of eq. (3), processed in row chunks (O(N^2) work).
+
+    pinned by: test_oracle_physics.py::test_direct_sum_equals_dense (row by row) and
+        test_direct_sum_equals_library_fft_convolution (numpy FFT convolution on the lattice).
+    """
     N = pos.shape[0]
     b = np.broadcast_to(np.asarray(beta, dtype=np.complex128), (N,))
     bx = b[:, None] * x
@@ -223,7 +234,12 @@ def matvec(pos, k, beta, x, chunk=256):
 # ------------------------------------------------------------------- incident field
 def incident_field(pos, k, prop, pol, w0=0.0, center=(0.0, 0.0, 0.0)):
     """Incident field at the dipoles (right-hand side of eq. 1): the plane wave
-    E_inc(r) = e exp(i k a.r), or for w0 > 0 the focused beam of gaussian_beam_field."""
+    E_inc(r) = e exp(i k a.r), or for w0 > 0 the focused beam of gaussian_beam_field.
+
+    pinned by: test_oracle_scattering.py::test_single_dipole_is_rayleigh_scatterer (dipole radiation
+        pattern of the driven dipole) and test_sphere16_against_mie_and_paper_accuracy (Mie within
+        the paper's error envelope).
+    """
     if w0 > 0:
         return gaussian_beam_field(pos, k, prop, pol, w0, center)
     a = np.asarray(prop, dtype=np.float64)
@@ -238,7 +254,11 @@ def gaussian_beam_nodes(k, w0, r_max):
     directions): t on [0, t_max], sin t_max = min(1, 12 / (k w0)) (the spectrum exp(-w0^2 |q|^2 / 4)
     is below 3e-16 beyond), Gauss-Legendre with n_t = ceil(k sin(t_max) r_max) + 24 nodes; azimuths
     by the periodic trapezoid rule on n_phi = 2 ceil(k sin(t_max) r_max) + 16 points; r_max bounds
-    |r - center| over the dipoles.  Returns (t, weight of t, phi, weight of phi)."""
+    |r - center| over the dipoles.  Returns (t, weight of t, phi, weight of phi).
+
+    pinned by: test_oracle_physics.py::test_gaussian_beam_quadrature_is_converged and
+        test_gaussian_beam_focal_value_closed_form.
+    """
     st = min(1.0, 12.0 / (k * w0))
     t_max = math.asin(st)
     kr = int(math.ceil(k * st * r_max))
@@ -285,7 +305,11 @@ def gaussian_beam_field(pos, k, prop, pol, w0, center):
 
 
 def rhs(pos, k, beta, prop, pol, w0=0.0, center=(0.0, 0.0, 0.0)):
-    """Right-hand side of eq. (3): b_i = beta_i E_inc,i."""
+    """Right-hand side of eq. (3): b_i = beta_i E_inc,i.
+
+    pinned by: test_oracle_physics.py::test_inhomogeneous_symmetrized_system_equals_equation_1 (b =
+        beta E_inc turns eq. 1 into eq. 3).
+    """
     N = pos.shape[0]
     if np.ndim(beta) == 2:  # diagonal tensor per dipole
         return np.asarray(beta, dtype=np.complex128) * incident_field(pos, k, prop, pol, w0, center)
@@ -295,6 +319,7 @@ def rhs(pos, k, beta, prop, pol, w0=0.0, center=(0.0, 0.0, 0.0)):
 
 # ---------------------------------------------------------------------------- solvers
 def _flat(v):
+    """Flat view (bookkeeping, no arithmetic of the method)."""
     return v.reshape(-1)
 
 
@@ -564,7 +589,11 @@ def cgnr(apply_A, b, tol, maxit=100000, x0=None):
 
 
 def solve_dense(pos, k, beta, b):
-    """Exact solution of eq. (3) by dense LU (numpy.linalg.solve); for small systems only."""
+    """Exact solution of eq. (3) by dense LU (numpy.linalg.solve); for small systems only.
+
+    pinned by: a library routine (numpy.linalg.solve) on the assembled matrix;
+        test_oracle_solvers.py checks QMR, Bi-CG, Bi-CGSTAB and CGNR against it.
+    """
     A = interaction_matrix(pos, k, beta)
     return np.linalg.solve(A, _flat(b)).reshape(b.shape)
 
@@ -597,6 +626,8 @@ def csca_exact(pos, k, P):
     Csca = k^4 sum_ij P_i^H M(r_i - r_j) P_j, M(r) = integral over the unit sphere of
     (I - n n) exp(i k n.r) dOmega = 4 pi [ (2/3 j0 - 1/3 j2)(kr) I + j2(kr) r^ r^ ], M(0) = 8pi/3 I.
     Independent of the far-field route; used only to check the optical theorem.
+    pinned by: test_oracle_scattering.py::test_optical_theorem (Cext = Csca + Cabs for the exact
+        dense solution).
     """
     N = pos.shape[0]
     tot = 0.0
@@ -640,7 +671,12 @@ def farfield(pos, k, P, n):
 
 def sphere_quadrature(prop, n_theta, n_phi):
     """Directions and weights integrating over the unit sphere: Gauss-Legendre in mu = cos(theta)
-    about the propagation direction, uniform in phi.  Returns (n (M, 3), w (M,), mu (M,))."""
+    about the propagation direction, uniform in phi.  Returns (n (M, 3), w (M,), mu (M,)).
+
+    pinned by:
+        test_oracle_physics.py::test_asymmetry_quadrature_reproduces_the_exact_scattering_cross_sect
+        ion.
+    """
     a = np.asarray(prop, dtype=np.float64)
     a = a / np.linalg.norm(a)
     t = np.array([1.0, 0.0, 0.0]) if abs(a[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
@@ -723,7 +759,11 @@ def romberg_adaptive(f, a, b, eps, n_min=2, n_max=10):
 def _orientation_rows(pos, m, k, mus, n_gamma, polarizability, mask=None):
     """Mean (Cext, Cabs, Csca) over the 2^n_gamma equispaced gamma and the x and y incident
     polarizations, at each cos(beta) in mus.  Orientation R = Ry(beta) Rz(gamma) (alpha = 0); the
-    particle-frame beam is R^T applied to the laboratory vectors."""
+    particle-frame beam is R^T applied to the laboratory vectors.
+
+    pinned by: test_oracle_physics.py::test_orientation_average_of_an_isotropic_dipole and
+        test_orientation_average_invariant_under_a_lattice_rotation (through orientation_average).
+    """
     ng = 2 ** n_gamma
     rows = np.zeros((len(mus), 3))
     for i, mu in enumerate(mus):
@@ -850,7 +890,11 @@ def orientation_average_mueller(mask, m, k, n_beta, n_gamma, n_alpha, theta, pol
 
 
 def beam_frame(prop, pol):
-    """(e1, e2, e3): e3 = propagation, e1 = (real) polarization, e2 = e3 x e1."""
+    """(e1, e2, e3): e3 = propagation, e1 = (real) polarization, e2 = e3 x e1.
+
+    pinned by: test_oracle_scattering.py::test_s11_one_polarization_equals_two and
+        test_mueller_formula_equals_the_stokes_transfer_of_the_amplitude_matrix.
+    """
     e3 = np.asarray(prop, dtype=np.float64)
     e1 = np.real(np.asarray(pol, dtype=np.complex128))
     e2 = np.cross(e3, e1)
@@ -858,7 +902,11 @@ def beam_frame(prop, pol):
 
 
 def scattering_directions(prop, pol, theta, phi):
-    """Directions and unit vectors theta^, phi^ in the scattering plane at azimuth phi."""
+    """Directions and unit vectors theta^, phi^ in the scattering plane at azimuth phi.
+
+    pinned by: test_oracle_scattering.py::test_single_dipole_is_rayleigh_scatterer and
+        test_symmetry_plane_kills_off_diagonal_blocks.
+    """
     e1, e2, e3 = beam_frame(prop, pol)
     th = np.asarray(theta, dtype=np.float64)
     st, ct = np.sin(th), np.cos(th)
@@ -875,6 +923,8 @@ def amplitude_matrix(F1, F2, t_hat, p_hat, phi):
     Incident parallel/perpendicular to the scattering plane: e_par = cos(phi) e1 + sin(phi) e2,
     e_perp = sin(phi) e1 - cos(phi) e2; by linearity F_par, F_perp follow from F1, F2.
     S2 = theta^.F_par, S4 = -phi^.F_par, S3 = theta^.F_perp, S1 = -phi^.F_perp.
+    pinned by: test_oracle_scattering.py::test_mueller_formula_equals_the_stokes_transfer_of_the_amp
+        litude_matrix and test_forward_scattering_theorem.
     """
     cp, sp = math.cos(phi), math.sin(phi)
     Fpar = cp * F1 + sp * F2
@@ -914,7 +964,10 @@ def mueller_from_amplitudes(S1, S2, S3, S4):
 
 
 def rotation_about(axis, angle):
-    """Rotation matrix by `angle` about the unit vector `axis` (Rodrigues)."""
+    """Rotation matrix by `angle` about the unit vector `axis` (Rodrigues).
+
+    pinned by: test_oracle_physics.py::test_orientation_average_invariant_under_a_lattice_rotation.
+    """
     a = np.asarray(axis, dtype=np.float64)
     K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
     return np.eye(3) + math.sin(angle) * K + (1 - math.cos(angle)) * (K @ K)
@@ -928,6 +981,9 @@ def mueller(pos, k, prop, pol, P1, P2, theta, phi):
     propagation direction (the paper uses the sphere's symmetry to run one polarization only,
     Sec. 3.1): then F2(n) = R F1(R^-1 n) with R the +90-degree rotation taking e1 to e2.
     Returns (len(theta), 4, 4).
+    pinned by: test_oracle_scattering.py::test_mueller_formula_equals_the_stokes_transfer_of_the_amp
+        litude_matrix (Stokes definitions), test_single_dipole_is_rayleigh_scatterer and
+        test_sphere16_against_mie_and_paper_accuracy (every element against Mie).
     """
     n, t_hat, p_hat = scattering_directions(prop, pol, theta, phi)
     F1 = farfield(pos, k, P1, n)
@@ -941,11 +997,18 @@ def mueller(pos, k, prop, pol, P1, P2, theta, phi):
 
 
 def efficiency(C, n_dipoles):
-    """Q = C / (pi a_eq^2), a_eq = (3N/4pi)^(1/3) d (volume-equivalent radius, Sec. 3.1)."""
+    """Q = C / (pi a_eq^2), a_eq = (3N/4pi)^(1/3) d (volume-equivalent radius, Sec. 3.1).
+
+    pinned by: test_oracle_scattering.py::test_sphere16_against_mie_and_paper_accuracy (Qext against
+        Mie within the paper's envelope).
+    """
     a_eq = (3.0 * n_dipoles / (4.0 * math.pi)) ** (1.0 / 3.0)
     return C / (math.pi * a_eq * a_eq)
 
 
 def size_parameter(k, n_dipoles):
-    """Volume-equivalent size parameter x = k a_eq."""
+    """Volume-equivalent size parameter x = k a_eq.
+
+    pinned by: test_oracle_scattering.py::test_sphere16_against_mie_and_paper_accuracy.
+    """
     return k * (3.0 * n_dipoles / (4.0 * math.pi)) ** (1.0 / 3.0)

@@ -21,12 +21,20 @@ import numpy as np
 
 
 def n_terms(x):
-    """Number of series terms: x + 4 x^(1/3) + 2 (Wiscombe's criterion, as used in BHMIE)."""
+    """Number of series terms: x + 4 x^(1/3) + 2 (Wiscombe's criterion, as used in BHMIE).
+
+    pinned by: test_oracle_scattering.py::test_mie_bhmie_printed_example (printed values of the
+        textbook's program) and test_mie_energy_and_forward_theorem.
+    """
     return int(round(x + 4.0 * x ** (1.0 / 3.0) + 2.0))
 
 
 def coefficients(x, m):
-    """Mie coefficients a_n, b_n for n = 1..nstop (arrays of length nstop)."""
+    """Mie coefficients a_n, b_n for n = 1..nstop (arrays of length nstop).
+
+    pinned by: test_oracle_scattering.py::test_mie_bhmie_printed_example, test_mie_rayleigh_limit
+        and test_mie_extinction_paradox.
+    """
     m = complex(m)
     mx = m * x
     nstop = n_terms(x)
@@ -56,7 +64,11 @@ def coefficients(x, m):
 
 
 def efficiencies(x, m):
-    """(Qext, Qsca, Qabs) of a sphere with size parameter x and refractive index m."""
+    """(Qext, Qsca, Qabs) of a sphere with size parameter x and refractive index m.
+
+    pinned by: test_oracle_scattering.py::test_mie_bhmie_printed_example (Qext, Qsca, Qback as
+        printed), test_mie_rayleigh_limit, test_mie_energy_and_forward_theorem.
+    """
     a, b = coefficients(x, m)
     n = np.arange(1, len(a) + 1)
     qsca = 2.0 / x ** 2 * float(np.sum((2 * n + 1) * (np.abs(a) ** 2 + np.abs(b) ** 2)))
@@ -65,7 +77,11 @@ def efficiencies(x, m):
 
 
 def amplitudes(x, m, theta):
-    """Amplitude functions S1(theta), S2(theta) (Bohren & Huffman convention)."""
+    """Amplitude functions S1(theta), S2(theta) (Bohren & Huffman convention).
+
+    pinned by: test_oracle_scattering.py::test_mie_bhmie_printed_example (Qback from S1(180 deg))
+        and test_mie_energy_and_forward_theorem (Qext = 4 Re S(0) / x^2).
+    """
     a, b = coefficients(x, m)
     mu = np.cos(np.asarray(theta, dtype=np.float64))
     S1 = np.zeros(mu.shape, dtype=np.complex128)
@@ -85,7 +101,12 @@ def amplitudes(x, m, theta):
 
 
 def s11(x, m, theta):
-    """Unnormalized S11 = (|S1|^2 + |S2|^2) / 2."""
+    """Unnormalized S11 = (|S1|^2 + |S2|^2) / 2.
+
+    pinned by:
+        test_oracle_scattering.py::test_mie_mueller_rayleigh_limit_and_single_amplitude_pair_identit
+        y.
+    """
     S1, S2 = amplitudes(x, m, theta)
     return 0.5 * (np.abs(S1) ** 2 + np.abs(S2) ** 2)
 
@@ -94,7 +115,12 @@ def mueller(x, m, theta):
     """Nonzero elements of a sphere's Mueller matrix (Bohren & Huffman eq. 4.77, unnormalized):
     S11 = (|S2|^2 + |S1|^2)/2, S12 = (|S2|^2 - |S1|^2)/2, S33 = Re(S2 S1^*), S34 = Im(S2 S1^*);
     by the sphere's symmetry S22 = S11, S21 = S12, S44 = S33, S43 = -S34 and the rest vanish.
-    Returns (len(theta), 4, 4)."""
+    Returns (len(theta), 4, 4).
+
+    pinned by:
+        test_oracle_scattering.py::test_mie_mueller_rayleigh_limit_and_single_amplitude_pair_identit
+        y (Rayleigh limit and S11^2 = S12^2 + S33^2 + S34^2).
+    """
     S1, S2 = amplitudes(x, m, theta)
     M = np.zeros(S1.shape + (4, 4))
     M[..., 0, 0] = M[..., 1, 1] = 0.5 * (np.abs(S2) ** 2 + np.abs(S1) ** 2)
@@ -106,7 +132,11 @@ def mueller(x, m, theta):
 
 
 def asymmetry(x, m):
-    """Asymmetry parameter <cos theta> from the series (Bohren & Huffman eq. 4.62)."""
+    """Asymmetry parameter <cos theta> from the series (Bohren & Huffman eq. 4.62).
+
+    pinned by: test_oracle_scattering.py::test_mie_bhmie_printed_example (g as printed) and
+        test_oracle_physics.py::test_sphere_asymmetry_near_mie.
+    """
     a, b = coefficients(x, m)
     qext, qsca, _ = efficiencies(x, m)
     n = np.arange(1, len(a) + 1)
