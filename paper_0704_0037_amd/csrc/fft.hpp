@@ -1,6 +1,6 @@
 // Stockham FFT building blocks for lines held in LDS (gfx950, wave64).
 //
-// A length-L transform is split into passes of radix 2, 3, 4, 5, 8 or 16.  Pass p with radix R
+// A length-L transform is split into passes of radix 2, 3, 4, 5, 6, 8 or 16.  Pass p with radix R
 // and stride Ns (product of the radices before it) does L/R butterflies; butterfly j reads the
 // elements j + r*L/R (r < R), multiplies element r by W^(r*k) with W = exp(-+2 pi i/(Ns*R)) and
 // k = j mod Ns, does an R-point DFT and writes output r to (j - k)*R + k + r*Ns (self-sorting,
@@ -63,9 +63,9 @@ struct FftPlan {
     int ns[kMaxPass];        // product of the radices of the preceding passes
 };
 
-// Radix schedule for length L (5-smooth): 8s first, the leftover power of two as 16 (or 4*4 when
-// maxr = 8), 4 or 2, then 5s and 3s; reversed for the inverse of a pass pair whose middle stays in
-// registers.  Larger radices mean fewer passes over LDS.  A line gets tpl = L / (largest radix)
+// Radix schedule for length L (5-smooth): 8s first, the leftover power of two as 16 (maxr 16), as
+// a 6 together with one factor 3, as 4*4, 4 or 2, then 5s and 3s; reversed for the inverse of a
+// pass pair whose middle stays in registers.  Larger radices mean fewer passes over LDS.  A line gets tpl = L / (largest radix)
 // threads, one per butterfly of its widest pass; a pass of smaller radix has more butterflies
 // than threads, and each thread takes ceil(L / (R tpl)) of them, so no lane idles through the
 // radix-8 passes that do most of the arithmetic.  tpl1 = L / (smallest radix) threads give one
@@ -86,15 +86,17 @@ __host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
         const int n8 = p2 / 3, left = p2 % 3;
         if (n8 + 2 + n3 + n5 > kMaxPass) return p;
         for (int i = 0; i < n8; ++i) r[n++] = 8;
+        int m3 = n3;
         if (left == 1) {
             if (n8 > 0 && maxr >= 16) r[n - 1] = 16;
+            else if (m3 > 0 && maxr >= 6) { r[n++] = 6; --m3; }  // the odd 2 with a 3 (384 = 8 8 6)
             else if (n8 > 0) { r[n - 1] = 4; r[n++] = 4; }
             else r[n++] = 2;
         } else if (left == 2) {
             r[n++] = 4;
         }
         for (int i = 0; i < n5; ++i) r[n++] = 5;
-        for (int i = 0; i < n3; ++i) r[n++] = 3;
+        for (int i = 0; i < m3; ++i) r[n++] = 3;
     }
     if (reverse)
         for (int i = 0; i < n / 2; ++i) {
@@ -198,6 +200,31 @@ template <int DIR, typename C> __device__ __forceinline__ void dft5(C *a) {
     a[3] = csub(t2, u2);
 }
 
+// 6 = 3 x 2: two-point DFTs of (a_i, a_(i+3)), the second output times w6^i, then three-point DFTs;
+// output k2 + 2 k1 is the three-point DFT k1 of branch k2 (w6^((i + 3m)(k2 + 2k1)) =
+// w6^(i k2) w3^(i k1) (-1)^(m k2))
+template <int DIR, typename C> __device__ __forceinline__ void dft6(C *a) {
+    using R = decltype(C::x);
+    const R h = (R)0.5, s3 = (R)0.86602540378443864676;  // cos, sin of pi / 3
+    C t0[3], t1[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        t0[i] = cadd(a[i], a[i + 3]);
+        t1[i] = csub(a[i], a[i + 3]);
+    }
+    // w6 = exp(DIR 2 pi i / 6) = h + DIR i s3; w6^2 = -h + DIR i s3
+    const R sd = DIR < 0 ? -s3 : s3;
+    t1[1] = mk<C>(t1[1].x * h - t1[1].y * sd, t1[1].x * sd + t1[1].y * h);
+    t1[2] = mk<C>(-t1[2].x * h - t1[2].y * sd, t1[2].x * sd - t1[2].y * h);
+    dft3<DIR>(t0);
+    dft3<DIR>(t1);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        a[2 * k1] = t0[k1];
+        a[2 * k1 + 1] = t1[k1];
+    }
+}
+
 // multiply by exp(DIR * 2 pi i m / 16) for the few m the radix-16 split needs
 template <int DIR, typename C> __device__ __forceinline__ C rot16(C v, int m) {
     using R = decltype(C::x);
@@ -265,6 +292,7 @@ template <int DIR, int RADIX, typename C> __device__ __forceinline__ void dftR(C
     else if constexpr (RADIX == 3) dft3<DIR>(a);
     else if constexpr (RADIX == 4) dft4<DIR>(a);
     else if constexpr (RADIX == 5) dft5<DIR>(a);
+    else if constexpr (RADIX == 6) dft6<DIR>(a);
     else if constexpr (RADIX == 8) dft8<DIR>(a);
     else if constexpr (RADIX == 16) dft16<DIR>(a);
 }
@@ -361,6 +389,7 @@ __device__ __forceinline__ void load_rt(C *a, int R, int j, int L, int Ns, const
         case 3: bfly_load<DIR, 3, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         case 4: bfly_load<DIR, 4, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         case 5: bfly_load<DIR, 5, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 6: bfly_load<DIR, 6, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         case 8: if constexpr (MAXR >= 8) bfly_load<DIR, 8, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         default: if constexpr (MAXR >= 16) bfly_load<DIR, 16, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
     }
@@ -374,6 +403,7 @@ __device__ __forceinline__ void load_rt(C *a, int R, int j, int L, int Ns, TwSta
         case 3: bfly_load<DIR, 3, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         case 4: bfly_load<DIR, 4, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         case 5: bfly_load<DIR, 5, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
+        case 6: bfly_load<DIR, 6, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         case 8: if constexpr (MAXR >= 8) bfly_load<DIR, 8, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
         default: if constexpr (MAXR >= 16) bfly_load<DIR, 16, C, LD, UPPER_ZERO>(a, j, L, Ns, tw, ld); break;
     }
@@ -387,6 +417,7 @@ __device__ __forceinline__ void regs_rt(C *a, int R, int j, int L, int Ns, const
         case 3: bfly_regs<DIR, 3>(a, j, L, Ns, tw); break;
         case 4: bfly_regs<DIR, 4>(a, j, L, Ns, tw); break;
         case 5: bfly_regs<DIR, 5>(a, j, L, Ns, tw); break;
+        case 6: bfly_regs<DIR, 6>(a, j, L, Ns, tw); break;
         case 8: if constexpr (MAXR >= 8) bfly_regs<DIR, 8>(a, j, L, Ns, tw); break;
         default: if constexpr (MAXR >= 16) bfly_regs<DIR, 16>(a, j, L, Ns, tw); break;
     }
@@ -400,6 +431,7 @@ __device__ __forceinline__ void store_rt(const C *a, int R, int j, int Ns, ST st
         case 3: bfly_store<3>(a, j, Ns, st); break;
         case 4: bfly_store<4>(a, j, Ns, st); break;
         case 5: bfly_store<5>(a, j, Ns, st); break;
+        case 6: bfly_store<6>(a, j, Ns, st); break;
         case 8: if constexpr (MAXR >= 8) bfly_store<8>(a, j, Ns, st); break;
         default: if constexpr (MAXR >= 16) bfly_store<16>(a, j, Ns, st); break;
     }
@@ -476,6 +508,7 @@ __device__ __forceinline__ void lds_passes_tw(C *ln, const FftPlan &pl, int p0, 
                 case 3: lds_pass<DIR, 3, bfly_per_thread(3, M), false, C>(j, L, T, Ns, tw, ld, st); break;
                 case 4: lds_pass<DIR, 4, bfly_per_thread(4, M), false, C>(j, L, T, Ns, tw, ld, st); break;
                 case 5: lds_pass<DIR, 5, bfly_per_thread(5, M), false, C>(j, L, T, Ns, tw, ld, st); break;
+                case 6: lds_pass<DIR, 6, bfly_per_thread(6, M), false, C>(j, L, T, Ns, tw, ld, st); break;
                 case 8: if constexpr (MAXR >= 8) lds_pass<DIR, 8, bfly_per_thread(8, M), false, C>(j, L, T, Ns, tw, ld, st); break;
                 default: if constexpr (MAXR >= 16) lds_pass<DIR, 16, 1, false, C>(j, L, T, Ns, tw, ld, st); break;
             }

@@ -379,6 +379,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                     case 3: mul(std::integral_constant<int, 3>{}); break;
                     case 4: mul(std::integral_constant<int, 4>{}); break;
                     case 5: mul(std::integral_constant<int, 5>{}); break;
+                    case 6: mul(std::integral_constant<int, 6>{}); break;
                     default: mul(std::integral_constant<int, 8>{}); break;
                 }
             }

@@ -73,9 +73,9 @@ def test_every_specialized_length_matches_oracle(L):
     """Each length with compile-time kernels (its radix schedule, its threads per line and its
     butterflies per thread in the passes of smaller radix) on every axis: a ragged particle padded to
     L along one axis at a time (L^3 up to 192), two batched beams, fp64 against the oracle at 1e-12
-    and fp32 at 2e-5.  384 (radices 8, 4, 4, 3), and the runtime-planned 360 and 480, take several
-    butterflies per thread in the z pass too (one per thread would need more than 64 threads per
-    line)."""
+    and fp32 at 2e-5.  48 and 384 use the radix-6 pass (8 6, 8 8 6); the runtime-planned 360 and 480
+    take several butterflies per thread in the z pass too (one per thread would need more than 64
+    threads per line)."""
     dda = _dda()
     mask = _random_mask((7, 9, 11), 40 + L, 0.5)  # [nz][ny][nx]
     m, kd = 1.4 + 0.02j, 0.5
