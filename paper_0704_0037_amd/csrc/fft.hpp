@@ -64,8 +64,9 @@ struct FftPlan {
 };
 
 // Radix schedule for length L (5-smooth): 8s first, the leftover power of two as 16 (maxr 16), as
-// a 6 together with one factor 3, as 4*4, 4 or 2, then 5s and 3s; reversed for the inverse of a
-// pass pair whose middle stays in registers.  Larger radices mean fewer passes over LDS.  A line gets tpl = L / (largest radix)
+// a 6 together with one factor 3 (only where a radix-3 pass would need more than 64 threads per
+// line), as 4*4, 4 or 2, then 5s and 3s; reversed for the inverse of a pass pair whose middle
+// stays in registers.  Larger radices mean fewer passes over LDS.  A line gets tpl = L / (largest radix)
 // threads, one per butterfly of its widest pass; a pass of smaller radix has more butterflies
 // than threads, and each thread takes ceil(L / (R tpl)) of them, so no lane idles through the
 // radix-8 passes that do most of the arithmetic.  tpl1 = L / (smallest radix) threads give one
@@ -89,7 +90,7 @@ __host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
         int m3 = n3;
         if (left == 1) {
             if (n8 > 0 && maxr >= 16) r[n - 1] = 16;
-            else if (m3 > 0 && maxr >= 6) { r[n++] = 6; --m3; }  // the odd 2 with a 3 (384 = 8 8 6)
+            else if (m3 > 0 && maxr >= 6 && L / 3 > 64) { r[n++] = 6; --m3; }  // 384 = 8 8 6: 64 threads, not 128
             else if (n8 > 0) { r[n - 1] = 4; r[n++] = 4; }
             else r[n++] = 2;
         } else if (left == 2) {

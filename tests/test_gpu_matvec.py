@@ -68,12 +68,12 @@ def test_matvec_matches_oracle(name, mask, m, kd, pad):
 SPECIALIZED = [32, 48, 60, 64, 72, 80, 96, 120, 128, 160, 192, 256, 320, 384, 512]
 
 
-@pytest.mark.parametrize("L", SPECIALIZED + [360, 480])
+@pytest.mark.parametrize("L", SPECIALIZED + [240, 360, 480])
 def test_every_specialized_length_matches_oracle(L):
     """Each length with compile-time kernels (its radix schedule, its threads per line and its
     butterflies per thread in the passes of smaller radix) on every axis: a ragged particle padded to
     L along one axis at a time (L^3 up to 192), two batched beams, fp64 against the oracle at 1e-12
-    and fp32 at 2e-5.  48 and 384 use the radix-6 pass (8 6, 8 8 6); the runtime-planned 360 and 480
+    and fp32 at 2e-5.  384 and the runtime-planned 240 use the radix-6 pass (8 8 6, 8 6 5); 360 and 480
     take several butterflies per thread in the z pass too (one per thread would need more than 64
     threads per line)."""
     dda = _dda()
