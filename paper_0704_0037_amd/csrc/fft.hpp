@@ -31,11 +31,8 @@ template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_
 #define DDA_SPECIALIZED_LENGTHS(X) \
     X(32) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
 
-#ifndef DDA_ZMUL_SLOTS
-#define DDA_ZMUL_SLOTS 1      // mirror columns processed side by side in a z-pass block (1, 2 or 4)
-#endif
 #ifndef DDA_ZMUL_THREADS
-#define DDA_ZMUL_THREADS (DDA_ZMUL_SLOTS * 3 * 64)  // block-size bound of the fused z-pass kernel
+#define DDA_ZMUL_THREADS (3 * 64)  // block-size bound of the fused z-pass kernel
 #endif
 #ifndef DDA_TW_DERIVED
 #define DDA_TW_DERIVED 1  // radix-8 twiddles w^3, w^5, w^6, w^7 formed from w, w^2, w^4 (0: all from the table)
@@ -72,7 +69,8 @@ struct FftPlan {
 // radix-8 passes that do most of the arithmetic.  tpl1 = L / (smallest radix) threads give one
 // butterfly per thread in every pass (the fused z pass runs that way).  Used on the host to plan
 // and on the device to specialize kernels for a length known at compile time.
-__host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
+// order: 0 the schedule above, 1 reversed, 2 ascending by radix (largest last), 3 descending
+__host__ __device__ constexpr FftPlan make_plan(int L, int maxr, int order) {
     FftPlan p{};
     int r[kMaxPass] = {};
     int n = 0;
@@ -99,12 +97,19 @@ __host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
         for (int i = 0; i < n5; ++i) r[n++] = 5;
         for (int i = 0; i < m3; ++i) r[n++] = 3;
     }
-    if (reverse)
+    if (order == 1)
         for (int i = 0; i < n / 2; ++i) {
             const int t = r[i];
             r[i] = r[n - 1 - i];
             r[n - 1 - i] = t;
         }
+    if (order >= 2)
+        for (int i = 1; i < n; ++i)  // insertion sort
+            for (int k = i; k > 0 && (order == 2 ? r[k - 1] > r[k] : r[k - 1] < r[k]); --k) {
+                const int t = r[k];
+                r[k] = r[k - 1];
+                r[k - 1] = t;
+            }
     int ns = 1, rmin = 1 << 30, rmax = 0;
     for (int i = 0; i < n; ++i) {
         p.radix[i] = r[i];
@@ -123,12 +128,30 @@ __host__ __device__ constexpr FftPlan make_plan(int L, int maxr, bool reverse) {
 // threads per line of the fused z pass: one butterfly per thread in every pass when that fits
 // in 64 (tpl1), else L / (largest radix) with several butterflies per thread in the passes of
 // smaller radix (384 = 8 4 4 3: 48 threads, not 128)
-__host__ __device__ constexpr int zmul_tpl(const FftPlan &p) { return p.tpl1 <= 64 ? p.tpl1 : p.tpl; }
-// threads per component line in the z-pass block: zmul_tpl, or a whole wave for the lengths with
-// several butterflies per thread (their lines then sync the wave only, and the multiply's code
-// path is uniform per wave; lanes past zmul_tpl idle).  Measured: 7 % faster at 384 (48 of 64
-// lanes), but 20-30 % slower at 120 and 160 than lines packed across waves.
-__host__ __device__ constexpr int zmul_ct(const FftPlan &p) { return p.tpl1 > 64 ? 64 : zmul_tpl(p); }
+// z-pass mode of a length.  One butterfly per thread in every pass (tpl1 threads per line, one
+// column per round) where that fits in 64 threads and a line fills a good part of a wave;
+// otherwise ("multi") L / (largest radix) threads per line, the forward plan with its largest
+// radix last, several butterflies per thread in the other passes, each component in a wave of
+// its own, and 64 / lanes columns per round (lanes = tpl rounded up to a power of two, at least
+// 16): a short line alone would leave most of a wave idle through a round's whole chain of
+// passes.  Measured per 2-vector z pass against one column per round: 48 -41 %, 64 -57 %, 96
+// -23 %, 120 -19 %, 192 -7 %, 256 -11 %; but 160 (20 of 32 lanes busy) +16 % and 72 (9 of 16)
+// +0 %, which keep one column per round.
+__host__ __device__ constexpr int zmul_pow2_lanes(int tpl) {
+    int w = 16;
+    while (w < tpl) w *= 2;
+    return w;
+}
+__host__ __device__ constexpr bool zmul_multi(const FftPlan &p) {
+    return p.tpl1 > 64 ||
+           (p.npass > 1 && p.tpl <= 32 && (4 * p.tpl >= 3 * zmul_pow2_lanes(p.tpl) || p.tpl <= 8));
+}
+__host__ __device__ constexpr int zmul_tpl(const FftPlan &p) { return zmul_multi(p) ? p.tpl : p.tpl1; }
+// lanes per line (a power of two) and lines (columns) per wave in the multi mode
+__host__ __device__ constexpr int zmul_lanes(const FftPlan &p) { return zmul_multi(p) ? zmul_pow2_lanes(p.tpl) : p.tpl1; }
+__host__ __device__ constexpr int zmul_slots(const FftPlan &p) { return zmul_multi(p) ? 64 / zmul_lanes(p) : 1; }
+// threads per component in the block: a whole wave in the multi mode
+__host__ __device__ constexpr int zmul_ct(const FftPlan &p) { return zmul_multi(p) ? 64 : p.tpl1; }
 
 // bound on the butterflies a thread takes in a pass of radix R when a line has L / (largest
 // radix) threads and no radix exceeds maxr
@@ -136,7 +159,7 @@ __host__ __device__ constexpr int bfly_per_thread(int R, int maxr) { return (max
 
 // The plan a kernel uses: the compile-time plan for LC > 0 (all indices fold to constants), else
 // the runtime plan passed as an argument.  tw_off always comes from the runtime plan.
-template <int LC, int MAXR, bool REV>
+template <int LC, int MAXR, int REV>
 __device__ __forceinline__ FftPlan plan_of(const FftPlan &rt) {
     if constexpr (LC > 0) {
         constexpr FftPlan P = make_plan(LC, MAXR, REV);  // evaluated by the compiler
@@ -486,7 +509,7 @@ __device__ __forceinline__ void lds_pass(int j, int L, int tpl, int Ns, TW tw, L
 // line fits in a wave the passes sync only that wave; LC = 0 runs the runtime plan `pl`.
 // ONE: the caller runs tpl1 threads per line (one butterfly per thread in every pass) instead of
 // tpl.
-template <int DIR, int MAXR, int LC, bool REV, bool ONE, typename C, class TW>
+template <int DIR, int MAXR, int LC, int REV, bool ONE, typename C, class TW>
 __device__ __forceinline__ void lds_passes_tw(C *ln, const FftPlan &pl, int p0, int p1, int j, TW tw) {
     auto ld = [&](int i) { return ln[pidx(i)]; };
     auto st = [&](int i, C v) { ln[pidx(i)] = v; };
@@ -517,12 +540,12 @@ __device__ __forceinline__ void lds_passes_tw(C *ln, const FftPlan &pl, int p0, 
     }
 }
 
-template <int DIR, int MAXR, int LC, bool REV, bool ONE = false, typename C>
+template <int DIR, int MAXR, int LC, int REV, bool ONE = false, typename C>
 __device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
                                            const C *__restrict__ tw) {
     lds_passes_tw<DIR, MAXR, LC, REV, ONE>(ln, pl, p0, p1, j, tw);
 }
-template <int DIR, int MAXR, int LC, bool REV, bool ONE = false, typename C>
+template <int DIR, int MAXR, int LC, int REV, bool ONE = false, typename C>
 __device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j, TwStaged<C> tw) {
     lds_passes_tw<DIR, MAXR, LC, REV, ONE>(ln, pl, p0, p1, j, tw);
 }

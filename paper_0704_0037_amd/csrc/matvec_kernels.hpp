@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
 // The (up to) four columns (kx, ky) with kx in {kxo, Lx - kxo}, ky in {kyo, Ly - kyo} share one
 // octant column (kxo, kyo) of the tensor.  A block owns one octant column: it stages the column's
 // six kz-runs in LDS once and then runs, for every right-hand side, its mirror columns through
-// the z pass, DDA_ZMUL_SLOTS of them side by side per round.  The tensor is read once per batch.
+// the z pass, zmul_slots of them side by side per round.  The tensor is read once per batch.
 //
 // Within a column, thread (comp, j) owns butterfly j of the line of one component (one wave per
 // line at L = 512).  After the forward passes the three transformed lines sit in LDS in natural
@@ -209,15 +209,16 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
                                                           FftPlan pi_rt, const cplx<R> *__restrict__ twall,
                                                           const int *__restrict__ done) {
     using C = cplx<R>;
-    // MB lengths (384 = 8 4 4 3; 360, 480 at run time) run the forward plan largest radix last and
-    // the inverse largest first, so the multiply still has one butterfly per thread
-    constexpr bool FLIP = LC > 0 && make_plan(LC, kMaxRadixZ, false).tpl1 > 64;
-    const FftPlan pf = plan_of<LC, kMaxRadixZ, FLIP>(pf_rt);
-    const FftPlan pi = plan_of<LC, kMaxRadixZ, !FLIP>(pi_rt);
+    // multi-mode lengths run the forward plan sorted with its largest radix last and the inverse
+    // sorted largest first, so the multiply and the passes next to it keep one butterfly per thread
+    constexpr bool FLIP = LC > 0 && zmul_multi(make_plan(LC, kMaxRadixZ, false));
+    constexpr int FO = FLIP ? 2 : 0, IO = FLIP ? 3 : 1;  // plan orders (make_plan) of the two transforms
+    const FftPlan pf = plan_of<LC, kMaxRadixZ, FO>(pf_rt);
+    const FftPlan pi = plan_of<LC, kMaxRadixZ, IO>(pi_rt);
     const int NPZ = pf.npass, RQ = pi.radix[NPZ - 1], NQ = pi.ns[NPZ - 1];
     // one butterfly per thread in every pass, or (MB) L / (largest radix) threads per line with
     // several butterflies per thread in the passes of smaller radix
-    const bool MB = pf.tpl1 > 64;
+    const bool MB = zmul_multi(pf);
     const int L = pf.L, TPL = zmul_tpl(pf), S = lds_line_stride(L);
     const int np = pf.npass;
     const int R0 = pf.radix[0];
@@ -232,9 +233,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     C *lds = reinterpret_cast<C *>(smem_raw);
     const C *tw = twall + pf_rt.tw_off;
     const int t = threadIdx.x;
-    const int CT = zmul_ct(pf);  // threads per component line in the block (>= TPL)
-    const int lslot = t / (3 * CT), comp = (t / CT) % 3, u = t % CT;
-    const int j0 = u < TPL ? u : L;  // lanes past TPL take no butterfly
+    const int CT = zmul_ct(pf), LW = zmul_lanes(pf), SL = zmul_slots(pf);
+    const int comp = t / CT, u = t % CT, lslot = u / LW, jj = u % LW;  // component, column slot, lane
+    const int j0 = jj < TPL ? jj : L;  // lanes past TPL take no butterfly
     const int kxo = oct % (hx + 1), kyo = oct / (hx + 1);
     const int nmx = (kxo == 0 || 2 * kxo == Lx) ? 1 : 2;  // distinct x mirrors of this column
     const int nmy = (kyo == 0 || 2 * kyo == Ly) ? 1 : 2;
@@ -247,7 +248,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     // all-radix-8 lengths: the twiddle bases of every pass staged after the lines (no global
     // twiddle loads inside the rounds)
     constexpr bool TWL = LC > 0 && all_radix8(LC, kMaxRadixZ);
-    C *tws = lds + 6 * hz1 + DDA_ZMUL_SLOTS * 3 * S;
+    C *tws = lds + 6 * hz1 + SL * 3 * S;
     if constexpr (TWL) {
         for (int e = t; e < LC / 8; e += blockDim.x) tws[e] = tw[e];
         __syncthreads();
@@ -257,8 +258,8 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
         else return tw;
     }();
     C *ln = lcol + comp * S;
-    constexpr bool W = LC > 0 && 64 % zmul_ct(make_plan(LC, kMaxRadixZ, false)) == 0;  // a line within one wave
-    constexpr int ngroups = 4 / DDA_ZMUL_SLOTS;
+    constexpr bool W = LC > 0 && 64 % zmul_lanes(make_plan(LC, kMaxRadixZ, false)) == 0;  // a line within one wave
+    const int ngroups = 4 / SL;
     const bool act = j0 < qi;
     // G[comp][d] for d = x, y, z: row comp of the symmetric tensor is (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
     const int g0 = comp == 0 ? 0 : comp == 1 ? 1 : 2;
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     const int Q = nrhs * ngroups;
     auto next_round = [&](int q) {
         for (; q < Q; ++q) {
-            const int rhs = q / ngroups, slot0 = (q % ngroups) * DDA_ZMUL_SLOTS;
+            const int rhs = q / ngroups, slot0 = (q % ngroups) * SL;
             if (done && done[rhs]) continue;
             if (((slot0 & 1) && nmx == 1) || ((slot0 & 2) && nmy == 1)) continue;
             break;
@@ -286,13 +287,11 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             // (which spills)
             auto twp = twp0;
             int j = j0;
-            if constexpr (!TWL) {
-                if (MB) {
-                    __asm__ volatile("" : "+s"(twp));
-                    __asm__ volatile("" : "+v"(j));
-                }
+            if (MB) {
+                if constexpr (!TWL) __asm__ volatile("" : "+s"(twp));
+                __asm__ volatile("" : "+v"(j));
             }
-            const int slot = grp * DDA_ZMUL_SLOTS + lslot;  // mirror 0..3 of the octant column
+            const int slot = grp * SL + lslot;  // mirror 0..3 of the octant column
             const bool mxs = slot & 1, mys = slot & 2;
             const bool ok = (!mxs || nmx == 2) && (!mys || nmy == 2);  // slot holds a distinct column
             const int kx = mxs ? Lx - kxo : kxo, ky = mys ? Ly - kyo : kyo;
@@ -310,12 +309,12 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             lds_sync<W>();
             // LDS passes [p0, p1) of the forward (inverse) plan, one or several butterflies per thread
             auto fpasses = [&](int p0, int p1) {
-                if (MB) lds_passes<-1, kMaxRadixZ, LC, FLIP, false>(ln, pf_rt, p0, p1, j, twp);
-                else lds_passes<-1, kMaxRadixZ, LC, FLIP, true>(ln, pf_rt, p0, p1, j, twp);
+                if (MB) lds_passes<-1, kMaxRadixZ, LC, FO, false>(ln, pf_rt, p0, p1, j, twp);
+                else lds_passes<-1, kMaxRadixZ, LC, FO, true>(ln, pf_rt, p0, p1, j, twp);
             };
             auto ipasses = [&](int p0, int p1) {
-                if (MB) lds_passes<+1, kMaxRadixZ, LC, !FLIP, false>(ln, pi_rt, p0, p1, j, twp);
-                else lds_passes<+1, kMaxRadixZ, LC, !FLIP, true>(ln, pi_rt, p0, p1, j, twp);
+                if (MB) lds_passes<+1, kMaxRadixZ, LC, IO, false>(ln, pi_rt, p0, p1, j, twp);
+                else lds_passes<+1, kMaxRadixZ, LC, IO, true>(ln, pi_rt, p0, p1, j, twp);
             };
             // own-component path (double precision): all forward passes but the last through LDS;
             // the last one keeps this thread's outputs (its own component at kz = j + r qi) in
@@ -400,10 +399,10 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     }
 }
 
-// LDS elements of the z-pass block: the tensor column, DDA_ZMUL_SLOTS slots of three lines and,
+// LDS elements of the z-pass block: the tensor column, zmul_slots slots of three lines and,
 // for all-radix-8 lengths, the staged twiddle bases
 __host__ __device__ constexpr size_t zmul_lds_elems(int Lz) {
-    return (size_t)6 * (Lz / 2 + 1) + (size_t)DDA_ZMUL_SLOTS * 3 * lds_line_stride(Lz) +
+    return (size_t)6 * (Lz / 2 + 1) + (size_t)zmul_slots(make_plan(Lz, kMaxRadixZ, false)) * 3 * lds_line_stride(Lz) +
            (all_radix8(Lz, kMaxRadixZ) ? (size_t)Lz / 8 : 0);
 }
 

@@ -92,7 +92,7 @@ dda_status matvec_device_impl(Ctx &c, const cplx<RX> *x, cplx<RX> *y, int nrhs, 
 #undef DDA_ARGS
     if (ev) DDA_HIP_CHECK(hipEventRecord(ev[2], s));
     const int zblocks = (c.Lx / 2 + 1) * (c.Ly / 2 + 1);  // one block per octant column
-#define DDA_ARGS dim3((zblocks + 7) / 8 * 8), dim3(DDA_ZMUL_SLOTS * 3 * zmul_ct(c.pzf)), lz_bytes, s, w.B2, gh, c.nz, \
+#define DDA_ARGS dim3((zblocks + 7) / 8 * 8), dim3(3 * zmul_ct(c.pzf)), lz_bytes, s, w.B2, gh, c.nz, \
                  c.Lx, c.Ly, nrhs, c.pzf, c.pzi, tw, done
 #define DDA_BYTES lz_bytes
     DDA_DISPATCH(c.Lz, k_zmul, DDA_BYTES, DDA_ARGS)

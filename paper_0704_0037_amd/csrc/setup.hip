@@ -598,11 +598,15 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
         f.tw_off = inv.tw_off = off_of(L);
         return f.npass > 0 && inv.npass > 0;
     };
-    // the z pass of a length whose smallest radix would need more than 64 threads per line runs
-    // its forward plan largest radix last (and the inverse largest first)
-    const bool zflip = make_plan(c->Lz, kMaxRadixZ, false).tpl1 > 64;
+    // the z pass of a multi-mode length (zmul_multi) runs its forward plan sorted largest radix
+    // last (and the inverse largest first)
+    const bool zflip = zmul_multi(make_plan(c->Lz, kMaxRadixZ, false));
     bool zok = plans(c->Lz, kMaxRadixZ, c->pzf, c->pzi);
-    if (zok && zflip) std::swap(c->pzf, c->pzi);
+    if (zok && zflip) {  // sorted: the forward plan's largest radix last, the inverse's first
+        c->pzf = make_plan(c->Lz, kMaxRadixZ, 2);
+        c->pzi = make_plan(c->Lz, kMaxRadixZ, 3);
+        c->pzf.tw_off = c->pzi.tw_off = off_of(c->Lz);
+    }
     if (!plans(c->Lx, kMaxRadix, c->pxf, c->pxi) || !plans(c->Ly, kMaxRadix, c->pyf, c->pyi) || !zok) {
         set_error("dda_setup: unsupported padded size");
         delete c;
@@ -629,7 +633,7 @@ dda_status setup(Ctx **out, const int32_t grid[3], const uint8_t *mask, const do
     };
     const bool tiles_ok = tiles(c->tl64, 16, max_threads<double>()) && tiles(c->tl32, 8, max_threads<float>());
     c->nc_z = 1;
-    if (DDA_ZMUL_SLOTS * 3 * zmul_ct(c->pzf) > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 || !tiles_ok) {
+    if (3 * zmul_ct(c->pzf) > DDA_ZMUL_THREADS || zmul_lds_elems(c->Lz) * 16 > 160 * 1024 || !tiles_ok) {
         set_error("dda_setup: padded size too large for one workgroup per line");
         delete c;
         return DDA_EINVAL;
