@@ -233,7 +233,8 @@ dda_status dda_matvec_f32(dda_ctx *ctx, const dda_beam *beam, const void *x, voi
  * contexts) race and must be ordered by the caller.  Homogeneous contexts only.
  *   x, y   device complex128 [3][N]; must not overlap
  * Errors: DDA_EINVAL (null pointers, overlap, or a particle whose intermediates exceed 128 MiB:
- * 48 (nz Lx ny + nz Lx Ly) bytes plus alignment), DDA_ENOTSUP (several materials or CLDR),
+ * 48 (nz Lx ny' + nz' Lx Ly) bytes plus alignment, ny' and nz' being ny and nz rounded up to a
+ * multiple of 16), DDA_ENOTSUP (several materials or CLDR),
  * DDA_EHIP.
  */
 dda_status dda_matvec_noalloc(dda_ctx *ctx, const dda_beam *beam, const void *x, void *y);

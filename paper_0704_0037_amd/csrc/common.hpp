@@ -38,6 +38,12 @@ template <int DIR, typename C> __host__ __device__ __forceinline__ C mul_i(C a) 
 }
 template <typename C> __host__ __device__ __forceinline__ C czero() { return mk<C>(0, 0); }
 
+// Pitch (elements) of the rows of the product's intermediates along their contiguous axis (y in
+// B1, z in B2): the cell count rounded up to 16, so that every row starts on a 256-byte boundary
+// and the tiles of lines that the transposing passes store side by side fill whole 128-byte
+// segments whatever the particle's size.
+__host__ __device__ constexpr int row_pitch(int n) { return (n + 15) & ~15; }
+
 // Streaming (non-temporal) global load and store of one complex value: the FFT passes read and
 // write each intermediate element exactly once, so they bypass cache retention
 template <typename C> __device__ __forceinline__ C ld_stream(const C *p) {

@@ -18,8 +18,8 @@ void clear_error();
 // Work buffers of one precision, sized for `nrhs` right-hand sides.
 template <typename R> struct Work {
     int nrhs = 0;
-    cplx<R> *B1 = nullptr;   // [3 nrhs][nz][Lx][ny]
-    cplx<R> *B2 = nullptr;   // [Ly][Lx][3 nrhs][nz]
+    cplx<R> *B1 = nullptr;   // [3 nrhs][nz][Lx][row_pitch(ny)]
+    cplx<R> *B2 = nullptr;   // [Lx][3 nrhs][Ly][row_pitch(nz)]
     cplx<R> *scale = nullptr;  // [nrhs] alpha / (Lx Ly Lz)
     cplx<R> *dots = nullptr;   // per-block partial sums of the matvec epilogue
     size_t ndots = 0;

@@ -153,6 +153,12 @@ __host__ __device__ constexpr int zmul_slots(const FftPlan &p) { return zmul_mul
 // threads per component in the block: a whole wave in the multi mode
 __host__ __device__ constexpr int zmul_ct(const FftPlan &p) { return zmul_multi(p) ? 64 : p.tpl1; }
 
+__host__ __device__ constexpr int pow2_at_least(int n) {
+    int w = 1;
+    while (w < n) w *= 2;
+    return w;
+}
+
 // bound on the butterflies a thread takes in a pass of radix R when a line has L / (largest
 // radix) threads and no radix exceeds maxr
 __host__ __device__ constexpr int bfly_per_thread(int R, int maxr) { return (maxr + R - 1) / R; }
@@ -509,14 +515,16 @@ __device__ __forceinline__ void lds_pass(int j, int L, int tpl, int Ns, TW tw, L
 // line fits in a wave the passes sync only that wave; LC = 0 runs the runtime plan `pl`.
 // ONE: the caller runs tpl1 threads per line (one butterfly per thread in every pass) instead of
 // tpl.
-template <int DIR, int MAXR, int LC, int REV, bool ONE, typename C, class TW>
+// P2: the caller gives each line a power-of-two group of lanes (threads past the line's butterfly
+// count idle), so a line whose group divides 64 lies within one wave.
+template <int DIR, int MAXR, int LC, int REV, bool ONE, bool P2, typename C, class TW>
 __device__ __forceinline__ void lds_passes_tw(C *ln, const FftPlan &pl, int p0, int p1, int j, TW tw) {
     auto ld = [&](int i) { return ln[pidx(i)]; };
     auto st = [&](int i, C v) { ln[pidx(i)] = v; };
     if constexpr (LC > 0) {
         constexpr FftPlan P = make_plan(LC, MAXR, REV);
         constexpr int T = ONE ? P.tpl1 : P.tpl;
-        constexpr bool W = 64 % T == 0;
+        constexpr bool W = 64 % (P2 ? pow2_at_least(T) : T) == 0;
         static_for<1, P.npass>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             constexpr int R = P.radix[p], Ns = P.ns[p];
@@ -540,14 +548,14 @@ __device__ __forceinline__ void lds_passes_tw(C *ln, const FftPlan &pl, int p0, 
     }
 }
 
-template <int DIR, int MAXR, int LC, int REV, bool ONE = false, typename C>
+template <int DIR, int MAXR, int LC, int REV, bool ONE = false, bool P2 = false, typename C>
 __device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j,
                                            const C *__restrict__ tw) {
-    lds_passes_tw<DIR, MAXR, LC, REV, ONE>(ln, pl, p0, p1, j, tw);
+    lds_passes_tw<DIR, MAXR, LC, REV, ONE, P2>(ln, pl, p0, p1, j, tw);
 }
-template <int DIR, int MAXR, int LC, int REV, bool ONE = false, typename C>
+template <int DIR, int MAXR, int LC, int REV, bool ONE = false, bool P2 = false, typename C>
 __device__ __forceinline__ void lds_passes(C *ln, const FftPlan &pl, int p0, int p1, int j, TwStaged<C> tw) {
-    lds_passes_tw<DIR, MAXR, LC, REV, ONE>(ln, pl, p0, p1, j, tw);
+    lds_passes_tw<DIR, MAXR, LC, REV, ONE, P2>(ln, pl, p0, p1, j, tw);
 }
 
 // true when every pass of the compile-time plan of length L is radix 8 (its twiddle bases fit in

@@ -63,8 +63,8 @@ __global__ void k_put_scale(double2 *p, double re, double im) { *p = make_double
 
 // bytes of scratch the product of one vector on this context needs: B1, B2, scale (256-aligned)
 size_t noalloc_bytes(const Ctx &c) {
-    const size_t b1 = (size_t)3 * c.nz * c.Lx * c.ny * sizeof(double2);
-    const size_t b2 = (size_t)3 * c.nz * c.Lx * c.Ly * sizeof(double2);
+    const size_t b1 = (size_t)3 * c.nz * c.Lx * row_pitch(c.ny) * sizeof(double2);
+    const size_t b2 = (size_t)3 * row_pitch(c.nz) * c.Lx * c.Ly * sizeof(double2);
     return round256(b1) + round256(b2) + round256(sizeof(double2));
 }
 
@@ -105,9 +105,9 @@ extern "C" dda_status dda_matvec_noalloc(dda_ctx *h, const dda_beam *beam, const
     Work<double> wk;
     wk.nrhs = 1;
     wk.B1 = reinterpret_cast<double2 *>(p);
-    p += round256((size_t)3 * c->nz * c->Lx * c->ny * sizeof(double2));
+    p += round256((size_t)3 * c->nz * c->Lx * row_pitch(c->ny) * sizeof(double2));
     wk.B2 = reinterpret_cast<double2 *>(p);
-    p += round256((size_t)3 * c->nz * c->Lx * c->Ly * sizeof(double2));
+    p += round256((size_t)3 * row_pitch(c->nz) * c->Lx * c->Ly * sizeof(double2));
     wk.scale = reinterpret_cast<double2 *>(p);
     double ar, ai;
     polarizability(*c, *beam, ar, ai);

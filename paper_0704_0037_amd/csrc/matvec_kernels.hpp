@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
     lds_sync<W>();
     lds_passes<-1, kMaxRadix, LC, false>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
     if constexpr (W) __syncthreads();  // the store mapping below crosses waves
-    C *dstc = B1 + ((size_t)c * nz + z) * (size_t)L * ny;
+    const int nyp = row_pitch(ny);
+    C *dstc = B1 + ((size_t)c * nz + z) * (size_t)L * nyp;
     if (NP >= 2) {  // last pass to global, lanes over lines (y contiguous in B1)
         const int line = t & (NL - 1), j = t >> lnl, y = y0 + line;
         const int Rp = RL, Ns = NSL;
@@ -118,12 +119,12 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_x(const int *__restric
             C a[kMaxRadix];
             const C *ln = lds + line * S;
             load_rt<-1, kMaxRadix>(a, Rp, jb, L, Ns, tw, [&](int i) { return ln[pidx(i)]; });
-            if (y < ny) store_rt<kMaxRadix>(a, Rp, jb, Ns, [&](int i, C v) { st_stream(&dstc[(size_t)i * ny + y], v); });
+            if (y < ny) store_rt<kMaxRadix>(a, Rp, jb, Ns, [&](int i, C v) { st_stream(&dstc[(size_t)i * nyp + y], v); });
         }
     } else {
         for (int e = t; e < NL * L; e += blockDim.x) {
             const int line = e & (NL - 1), i = e >> lnl, y = y0 + line;
-            if (y < ny) dstc[(size_t)i * ny + y] = lds[line * S + pidx(i)];
+            if (y < ny) dstc[(size_t)i * nyp + y] = lds[line * S + pidx(i)];
         }
     }
 }
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
     {
         const int line = t / TPL, j = t % TPL, z = z0 + line;
         const bool zok = z < nz;
-        const C *src = B1 + (((size_t)c * nz + (zok ? z : 0)) * Lx + kx) * ny;
+        const C *src = B1 + (((size_t)c * nz + (zok ? z : 0)) * Lx + kx) * row_pitch(ny);
         for (int jb = j; jb < L / R0; jb += TPL) {
             C a[kMaxRadix];
             load_rt<-1, kMaxRadix, true>(a, R0, jb, L, 1, tw,
@@ -168,12 +169,13 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fwd_y(const cplx<R> *__res
     lds_sync<W>();
     lds_passes<-1, kMaxRadix, LC, false>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
     if constexpr (W) __syncthreads();  // the store mapping below crosses waves
+    const int nzp = row_pitch(nz);
 #if DDA_B2_COLMAJOR
-    const size_t kystride = (size_t)nz;
-    C *dst = B2 + ((size_t)kx * ncomp + c) * (size_t)L * nz;
+    const size_t kystride = (size_t)nzp;
+    C *dst = B2 + ((size_t)kx * ncomp + c) * (size_t)L * nzp;
 #else
-    const size_t kystride = (size_t)Lx * ncomp * nz;
-    C *dst = B2 + ((size_t)kx * ncomp + c) * nz;
+    const size_t kystride = (size_t)Lx * ncomp * nzp;
+    C *dst = B2 + ((size_t)kx * ncomp + c) * nzp;
 #endif
     if (NP >= 2) {
         const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
@@ -228,6 +230,7 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
     const int per_xcd = gridDim.x / 8;
     const int oct = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int hx = Lx / 2, hy = Ly / 2, hz = L / 2, hz1 = hz + 1;
+    const int nzp = row_pitch(nz);
     if (oct >= (hx + 1) * (hy + 1)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
@@ -296,9 +299,9 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             const bool ok = (!mxs || nmx == 2) && (!mys || nmy == 2);  // slot holds a distinct column
             const int kx = mxs ? Lx - kxo : kxo, ky = mys ? Ly - kyo : kyo;
 #if DDA_B2_COLMAJOR
-            C *line = B2 + (((size_t)(ok ? kx : 0) * (3 * nrhs) + rhs * 3 + comp) * Ly + (ok ? ky : 0)) * nz;
+            C *line = B2 + (((size_t)(ok ? kx : 0) * (3 * nrhs) + rhs * 3 + comp) * Ly + (ok ? ky : 0)) * nzp;
 #else
-            C *line = B2 + (((size_t)(ok ? ky : 0) * Lx + (ok ? kx : 0)) * (3 * nrhs) + rhs * 3 + comp) * nz;
+            C *line = B2 + (((size_t)(ok ? ky : 0) * Lx + (ok ? kx : 0)) * (3 * nrhs) + rhs * 3 + comp) * nzp;
 #endif
             for (int jb = j; jb < q0; jb += TPL) {
                 C a[kMaxRadixZ];
@@ -309,11 +312,11 @@ __global__ void __launch_bounds__(DDA_ZMUL_THREADS, DDA_ZMUL_WAVES_PER_EU) k_zmu
             lds_sync<W>();
             // LDS passes [p0, p1) of the forward (inverse) plan, one or several butterflies per thread
             auto fpasses = [&](int p0, int p1) {
-                if (MB) lds_passes<-1, kMaxRadixZ, LC, FO, false>(ln, pf_rt, p0, p1, j, twp);
+                if (MB) lds_passes<-1, kMaxRadixZ, LC, FO, false, true>(ln, pf_rt, p0, p1, j, twp);
                 else lds_passes<-1, kMaxRadixZ, LC, FO, true>(ln, pf_rt, p0, p1, j, twp);
             };
             auto ipasses = [&](int p0, int p1) {
-                if (MB) lds_passes<+1, kMaxRadixZ, LC, IO, false>(ln, pi_rt, p0, p1, j, twp);
+                if (MB) lds_passes<+1, kMaxRadixZ, LC, IO, false, true>(ln, pi_rt, p0, p1, j, twp);
                 else lds_passes<+1, kMaxRadixZ, LC, IO, true>(ln, pi_rt, p0, p1, j, twp);
             };
             // own-component path (double precision): all forward passes but the last through LDS;
@@ -430,12 +433,13 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
     const int c = b / Lx;
     if (done && done[c / 3]) return;
     const int t = threadIdx.x;
+    const int nzp = row_pitch(nz);
 #if DDA_B2_COLMAJOR
-    const size_t kystride = (size_t)nz;
-    const C *src = B2 + ((size_t)kx * ncomp + c) * (size_t)L * nz;
+    const size_t kystride = (size_t)nzp;
+    const C *src = B2 + ((size_t)kx * ncomp + c) * (size_t)L * nzp;
 #else
-    const size_t kystride = (size_t)Lx * ncomp * nz;
-    const C *src = B2 + ((size_t)kx * ncomp + c) * nz;
+    const size_t kystride = (size_t)Lx * ncomp * nzp;
+    const C *src = B2 + ((size_t)kx * ncomp + c) * nzp;
 #endif
     {   // pass 0 from global, lanes over lines (z contiguous in B2)
         const int line = t & (NL - 1), j = t >> lnl, z = z0 + line;
@@ -451,7 +455,7 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_y(const cplx<R> *__res
     __syncthreads();
     lds_passes<+1, kMaxRadix, LC, true>(lds + (t / TPL) * S, pl_rt, 1, NP - 1, t % TPL, tw);
     const int line = t / TPL, j = t % TPL, z = z0 + line;
-    C *dst = B1 + (((size_t)c * nz + (z < nz ? z : 0)) * Lx + kx) * ny;
+    C *dst = B1 + (((size_t)c * nz + (z < nz ? z : 0)) * Lx + kx) * row_pitch(ny);
     if (NP >= 2) {
         const int Rp = RL, Ns = NSL;
         for (int jb = j; jb < L / Rp; jb += TPL) {
@@ -519,14 +523,15 @@ __global__ void __launch_bounds__(max_threads<R>()) k_inv_x(const int *__restric
     gmap += (size_t)(c / 3) * gstride;
     rows += (size_t)(c / 3) * rstride;
     const int t = threadIdx.x;
-    const C *src = B1 + ((size_t)c * nz + z) * (size_t)L * ny;
+    const int nyp = row_pitch(ny);
+    const C *src = B1 + ((size_t)c * nz + z) * (size_t)L * nyp;
     {   // pass 0 from global, lanes over lines (y contiguous in B1)
         const int line = t & (NL - 1), j = t >> lnl, y = y0 + line;
         const bool yok = y < ny;
         for (int jb = j; jb < L / R0; jb += TPL) {
             C a[kMaxRadix];
             load_rt<+1, kMaxRadix>(a, R0, jb, L, 1, tw,
-                                   [&](int i) -> C { return yok ? ld_stream(&src[(size_t)i * ny + y]) : czero<C>(); });
+                                   [&](int i) -> C { return yok ? ld_stream(&src[(size_t)i * nyp + y]) : czero<C>(); });
             C *ln = lds + line * S;
             store_rt<kMaxRadix>(a, R0, jb, 1, [&](int i, C v) { ln[pidx(i)] = v; });
         }

@@ -283,8 +283,8 @@ template <typename R> dda_status ensure_work(Ctx &c, int nrhs) {
     free_work(w);
     const size_t nc = (size_t)3 * nrhs;
     dda_status st;
-    if ((st = device_alloc((void **)&w.B1, nc * c.nz * (size_t)c.Lx * c.ny * sizeof(cplx<R>))) != DDA_OK) return st;
-    if ((st = device_alloc((void **)&w.B2, nc * c.nz * (size_t)c.Lx * c.Ly * sizeof(cplx<R>))) != DDA_OK) return st;
+    if ((st = device_alloc((void **)&w.B1, nc * c.nz * (size_t)c.Lx * row_pitch(c.ny) * sizeof(cplx<R>))) != DDA_OK) return st;
+    if ((st = device_alloc((void **)&w.B2, nc * row_pitch(c.nz) * (size_t)c.Lx * c.Ly * sizeof(cplx<R>))) != DDA_OK) return st;
     if ((st = device_alloc((void **)&w.scale, (size_t)nrhs * sizeof(cplx<R>))) != DDA_OK) return st;
     w.ndots = max_dots_per_rhs(c) * nrhs;  // enough for any tile schedule (the tuner may change it)
     if ((st = device_alloc((void **)&w.dots, w.ndots * sizeof(cplx<R>))) != DDA_OK) return st;
