@@ -29,7 +29,7 @@ constexpr int kMaxPass = 12;
 template <typename R> constexpr int max_threads() { return sizeof(R) == 8 ? DDA_MAX_THREADS_F64 : 2 * DDA_MAX_THREADS; }
 // padded lengths with kernels specialized at compile time (5-smooth sizes the workloads use most)
 #define DDA_SPECIALIZED_LENGTHS(X) \
-    X(32) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+    X(32) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128) X(160) X(192) X(200) X(256) X(320) X(384) X(512)
 
 #ifndef DDA_ZMUL_THREADS
 #define DDA_ZMUL_THREADS (3 * 64)  // block-size bound of the fused z-pass kernel

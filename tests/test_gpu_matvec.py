@@ -65,7 +65,7 @@ def test_matvec_matches_oracle(name, mask, m, kd, pad):
         assert _rel_err(y, ref) < 1e-12, (name, ctx.padded_grid(), _rel_err(y, ref))
 
 
-SPECIALIZED = [32, 48, 60, 64, 72, 80, 96, 120, 128, 160, 192, 256, 320, 384, 512]
+SPECIALIZED = [32, 48, 60, 64, 72, 80, 96, 120, 128, 160, 192, 200, 256, 320, 384, 512]
 
 
 @pytest.mark.parametrize("L", SPECIALIZED + [240, 360, 480])
