@@ -3,10 +3,10 @@
 // (the quantities the paper compares with Mie theory, Sec. 3.1).
 //
 // Far field: F(n) = -i k^3 (I - n n) sum_j P_j exp(-i k n.r_j).  A block takes up to 256
-// directions (one per thread) and a range of grid lines (y, z); the dipoles of one line are
-// staged in LDS and every thread walks them, advancing its phase factor along x by one
-// multiplication per cell (a direct sincos restarts the recurrence after a gap in the line and
-// at the start of every line, so at most nx - 1 products accumulate rounding).
+// directions (one per thread) and a range of grid lines (y, z); every thread walks the dipoles
+// of each line (read wave-uniformly through the scalar cache), advancing its phase factor along
+// x by one multiplication per cell (a direct sincos restarts the recurrence after a gap in the
+// line and at the start of every line, so at most nx - 1 products accumulate rounding).
 #include <cmath>
 #include <string>
 #include <vector>
@@ -74,16 +74,16 @@ __global__ void __launch_bounds__(kRoThreads) k_xsec(const double2 *__restrict__
     }
 }
 
-// F partial sums (without the -i k^3 (I - nn) beta factor) for directions [d0, d0+256) over the
-// lines [l0, l1) of chunk blockIdx.y; writes part[(d * nchunk + chunk) * 3 + c].
+// F partial sums (without the -i k^3 (I - nn) beta factor) for the directions of this block
+// (one per lane) over the lines [l0, l1) of chunk blockIdx.y; writes part[(d * nchunk + chunk) * 3 + c].
+// Every lane of a wave walks the same dipoles, so their polarizations and cell indices are
+// wave-uniform: they come through the scalar data cache into scalar registers, which the fp64
+// multiply-adds read directly (no LDS staging, no block barriers).
 __global__ void __launch_bounds__(kRoThreads) k_farfield(const double2 *__restrict__ x, const int *__restrict__ lin,
                                                          const int *__restrict__ line_start, int N, int nx, int ny,
                                                          int nz, int lines_per_chunk, const double *__restrict__ dirs,
-                                                         int ndir, double k, double2 *__restrict__ part, int seg) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double2 *sp = reinterpret_cast<double2 *>(smem_raw);  // [3][seg]
-    int *sx = reinterpret_cast<int *>(sp + 3 * seg);       // [seg]
-    const int d = blockIdx.x * kRoThreads + threadIdx.x;
+                                                         int ndir, double k, double2 *__restrict__ part) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = d < ndir;
     const int chunk = blockIdx.y, nchunk = gridDim.y;
     double nxd = 0, nyd = 0, nzd = 0;
@@ -98,43 +98,46 @@ __global__ void __launch_bounds__(kRoThreads) k_farfield(const double2 *__restri
     const int nlines = ny * nz;
     const int l0 = chunk * lines_per_chunk;
     const int l1 = min(nlines, l0 + lines_per_chunk);
+    const double2 *x1 = x + N, *x2 = x + 2 * (size_t)N;
     for (int L = l0; L < l1; ++L) {
         const int s = line_start[L], e = line_start[L + 1];
-        if (e == s) continue;  // uniform across the block
+        const int base = L * nx;  // lin = base + ix on this line
         const double py = (L % ny) + 0.5 - 0.5 * ny;
         const double pz = (L / ny) + 0.5 - 0.5 * nz;
         double2 ph = make_double2(1, 0);
         int xprev = -2;
-        for (int s0 = s; s0 < e; s0 += seg) {  // stage the line through LDS in segments
-            const int cnt = min(seg, e - s0);
-            __syncthreads();
-            for (int q = threadIdx.x; q < cnt; q += kRoThreads) {
-                sp[q] = x[s0 + q];
-                sp[seg + q] = x[(size_t)N + s0 + q];
-                sp[2 * seg + q] = x[2 * (size_t)N + s0 + q];
-                sx[q] = lin[s0 + q] % nx;
+        auto step = [&](int ix, double2 v0, double2 v1, double2 v2) {
+            if (ix == xprev + 1) {
+                ph = make_double2(ph.x * cw - ph.y * sw, ph.x * sw + ph.y * cw);
+            } else {
+                const double px = ix + 0.5 - 0.5 * nx;
+                double sn, cs;
+                sincos(-k * (nxd * px + nyd * py + nzd * pz), &sn, &cs);
+                ph = make_double2(cs, sn);
             }
-            __syncthreads();
-            if (!active) continue;
-            for (int q = 0; q < cnt; ++q) {
-                const int ix = sx[q];
-                if (ix == xprev + 1) {
-                    ph = make_double2(ph.x * cw - ph.y * sw, ph.x * sw + ph.y * cw);
-                } else {
-                    const double px = ix + 0.5 - 0.5 * nx;
-                    double sn, cs;
-                    sincos(-k * (nxd * px + nyd * py + nzd * pz), &sn, &cs);
-                    ph = make_double2(cs, sn);
-                }
-                xprev = ix;
+            xprev = ix;
+            const double2 v[3] = {v0, v1, v2};
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double2 v = sp[c * seg + q];
-                    acc[c].x += v.x * ph.x - v.y * ph.y;
-                    acc[c].y += v.x * ph.y + v.y * ph.x;
-                }
+            for (int c = 0; c < 3; ++c) {
+                acc[c].x += v[c].x * ph.x - v[c].y * ph.y;
+                acc[c].y += v[c].x * ph.y + v[c].y * ph.x;
             }
+        };
+        int q = s;
+        for (; q + 4 <= e; q += 4) {  // four dipoles' loads in flight together
+            int ix[4];
+            double2 a[4], b[4], cc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ix[u] = lin[q + u] - base;
+                a[u] = x[q + u];
+                b[u] = x1[q + u];
+                cc[u] = x2[q + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) step(ix[u], a[u], b[u], cc[u]);
         }
+        for (; q < e; ++q) step(lin[q] - base, x[q], x1[q], x2[q]);
     }
     if (active)
         for (int c = 0; c < 3; ++c) part[((size_t)d * nchunk + chunk) * 3 + c] = acc[c];
@@ -187,7 +190,10 @@ static dda_status farfield_sums(Ctx &c, const double2 *x, int ndir, const double
     dda_status st;
     if ((st = ensure_lines(c)) != DDA_OK) return st;
     const int nlines = c.ny * c.nz;
-    const int dtiles = (ndir + kRoThreads - 1) / kRoThreads;
+    // directions in whole waves, at most four waves a block, blocks as even as the count allows
+    const int waves = (ndir + 63) / 64;
+    const int dtiles = (waves + kRoThreads / 64 - 1) / (kRoThreads / 64);
+    const int bthreads = 64 * ((waves + dtiles - 1) / dtiles);
     // enough chunks to fill the GPU several times over, at least a few lines each
     int nchunk = std::max(1, std::min(nlines, 2048 / std::max(1, dtiles)));
     const int lpc = (nlines + nchunk - 1) / nchunk;
@@ -198,10 +204,8 @@ static dda_status farfield_sums(Ctx &c, const double2 *x, int ndir, const double
     double2 *sums = c.red + npart;
     double *ddirs = (double *)(sums + (size_t)ndir * 3);
     DDA_HIP_CHECK(hipMemcpyAsync(ddirs, dirs, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    const int seg = std::min(c.nx, 1024);
-    const size_t lds = (size_t)seg * (3 * sizeof(double2) + sizeof(int));
-    hipLaunchKernelGGL(k_farfield, dim3(dtiles, nchunk), dim3(kRoThreads), lds, c.stream, x, c.lin, c.line_start,
-                       (int)c.N, c.nx, c.ny, c.nz, lpc, ddirs, ndir, c.kd, part, seg);
+    hipLaunchKernelGGL(k_farfield, dim3(dtiles, nchunk), dim3(bthreads), 0, c.stream, x, c.lin, c.line_start,
+                       (int)c.N, c.nx, c.ny, c.nz, lpc, ddirs, ndir, c.kd, part);
     hipLaunchKernelGGL(k_ff_sum, dim3((ndir * 3 + 255) / 256), dim3(256), 0, c.stream, part, ndir, nchunk, sums);
     DDA_HIP_CHECK(hipGetLastError());
     out.resize((size_t)ndir * 3);
