@@ -68,13 +68,15 @@ def test_matvec_matches_oracle(name, mask, m, kd, pad):
 SPECIALIZED = [32, 48, 60, 64, 72, 80, 96, 120, 128, 160, 192, 200, 256, 320, 384, 512]
 
 
-@pytest.mark.parametrize("L", SPECIALIZED + [240, 360, 480])
+@pytest.mark.parametrize("L", SPECIALIZED + [100, 150, 240, 270, 360, 480])
 def test_every_specialized_length_matches_oracle(L):
     """Each length with compile-time kernels (its radix schedule, its threads per line and its
     butterflies per thread in the passes of smaller radix) on every axis: a ragged particle padded to
     L along one axis at a time (L^3 up to 192), two batched beams, fp64 against the oracle at 1e-12
-    and fp32 at 2e-5.  384 and the runtime-planned 240 use the radix-6 pass (8 8 6, 8 6 5); 360 and 480
-    take several butterflies per thread in the z pass too (one per thread would need more than 64
+    and fp32 at 2e-5.  The lengths after the specialized ones run the plan as a run-time argument:
+    100 (4 5 5, one column per round in the z pass), 150 (2 5 5 3) and 270 (2 5 3 3 3, five passes);
+    240 uses the radix-6 pass (8 6 5), like the specialized 384 (8 8 6); 150, 270, 360 and 480 take
+    several butterflies per thread in the z pass too (one per thread would need more than 64
     threads per line)."""
     dda = _dda()
     mask = _random_mask((7, 9, 11), 40 + L, 0.5)  # [nz][ny][nx]
